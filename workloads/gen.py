@@ -1,0 +1,329 @@
+"""Seeded synthetic inputs for the batched segment-QP workloads.
+
+This module only draws numbers: it holds none of the method's arithmetic (no
+Bezier operators, no constraint lifting, no solver).  Both the FP64 CPU
+oracle and the HIP path consume what it returns.
+
+The paper (Sec. IV, Figs. 4-5) measures on its own MuJoCo scenes and on the
+ARCHER robot, not on a public suite, and never states the reachable-polytope
+matrices of Theorem 2.  The generators below are synthetic stand-ins with the
+paper's shapes: about 50,000 candidate edges (Sec. IV-A) and a few hundred
+box obstacles (Figs. 4-5).
+
+Seeding: instance ``i`` of workload ``cfg`` draws from
+``default_rng(SeedSequence(1000 + cfg, spawn_key=(0, i)))`` and the shared
+environment (obstacles, polytopes) from ``spawn_key=(1,)``, so any subset of
+a batch regenerates exactly.
+
+Conventions shared with the consumers (documented in include/rbp.h):
+
+* ``vec(P)`` is point-major: ``y[3*k + c]`` is coordinate ``c`` of control
+  point ``k``.
+* Reachable rows are stored in the literal form ``H vec(P) <= h0 + G x0``.
+  They are drawn in the displacement frame ``H vec(P - 1 (x) P0) <= h0 + G' x0``
+  (dynamics do not depend on where the segment starts) and stored with
+  ``G = G' + H (1 (x) [I3 0])`` so the stored rows stay affine in ``x0``.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Dict, Optional, Sequence
+
+import numpy as np
+
+DIM = 3
+T_DEFAULT = 1.0
+VMAX = 3.0
+AMAX = 5.0
+# reachable-row offsets for the cluttered-environment batches: shifted from
+# U[1,3] so that about 30% of the edges come out infeasible
+H0_CLUTTER = (1.3, 3.3)
+
+
+def instance_rng(cfg: int, i: int) -> np.random.Generator:
+    return np.random.default_rng(np.random.SeedSequence(1000 + cfg, spawn_key=(0, int(i))))
+
+
+def env_rng(cfg: int) -> np.random.Generator:
+    return np.random.default_rng(np.random.SeedSequence(1000 + cfg, spawn_key=(1,)))
+
+
+@dataclass
+class SegmentBatch:
+    """A batch of segment problems in the layout the C ABI consumes.
+
+    Shared polytope table: polytope ``j`` owns faces ``poly_off[j]:poly_off[j+1]``
+    of ``A_face`` (F x 3) and ``b_face`` (F).  Instance ``i`` uses polytope
+    ``poly_idx[i]``, has degree ``degree[i]`` and ``reach_off[i+1]-reach_off[i]``
+    reachable rows whose dense coefficients sit in
+    ``H[H_off[i]:H_off[i+1]]`` (row-major, ``3*(degree+1)`` columns), with
+    ``h0``/``G`` rows at the same row offsets.
+    """
+
+    name: str
+    degree: np.ndarray          # int32 [N]
+    T: np.ndarray               # float64 [N]
+    vmax: float
+    amax: float
+    poly_off: np.ndarray        # int32 [n_poly+1]
+    A_face: np.ndarray          # float64 [F, 3]
+    b_face: np.ndarray          # float64 [F]
+    poly_idx: np.ndarray        # int32 [N]
+    reach_off: np.ndarray       # int64 [N+1]
+    H_off: np.ndarray           # int64 [N+1]
+    H: np.ndarray               # float64 [sum r_i * 3(p_i+1)]
+    h0: np.ndarray              # float64 [R]
+    G: np.ndarray               # float64 [R, 6]
+    x0: np.ndarray              # float64 [N, 6]
+    goal: np.ndarray            # float64 [N, 3]
+    meta: Dict[str, object] = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return int(self.degree.shape[0])
+
+    def reach_rows(self, i: int) -> int:
+        return int(self.reach_off[i + 1] - self.reach_off[i])
+
+    def instance(self, i: int) -> dict:
+        """Plain per-instance view (numpy arrays, FP64)."""
+        p = int(self.degree[i])
+        j = int(self.poly_idx[i])
+        f0, f1 = int(self.poly_off[j]), int(self.poly_off[j + 1])
+        r0, r1 = int(self.reach_off[i]), int(self.reach_off[i + 1])
+        h0_, h1_ = int(self.H_off[i]), int(self.H_off[i + 1])
+        return dict(
+            p=p, T=float(self.T[i]), vmax=float(self.vmax), amax=float(self.amax),
+            A_face=self.A_face[f0:f1].copy(), b_face=self.b_face[f0:f1].copy(),
+            H=self.H[h0_:h1_].reshape(r1 - r0, 3 * (p + 1)).copy(),
+            h0=self.h0[r0:r1].copy(), G=self.G[r0:r1].copy(),
+            x0=self.x0[i].copy(), goal=self.goal[i].copy(),
+        )
+
+    def subset(self, idx: Sequence[int]) -> "SegmentBatch":
+        idx = np.asarray(idx, dtype=np.int64)
+        r = self.reach_off[idx + 1] - self.reach_off[idx]
+        hsz = self.H_off[idx + 1] - self.H_off[idx]
+        reach_off = np.zeros(len(idx) + 1, np.int64)
+        reach_off[1:] = np.cumsum(r)
+        H_off = np.zeros(len(idx) + 1, np.int64)
+        H_off[1:] = np.cumsum(hsz)
+        H = np.concatenate([self.H[self.H_off[i]:self.H_off[i + 1]] for i in idx]) if len(idx) else np.zeros(0)
+        h0 = np.concatenate([self.h0[self.reach_off[i]:self.reach_off[i + 1]] for i in idx]) if len(idx) else np.zeros(0)
+        G = np.concatenate([self.G[self.reach_off[i]:self.reach_off[i + 1]] for i in idx]) if len(idx) else np.zeros((0, 6))
+        return SegmentBatch(
+            name=f"{self.name}[subset]", degree=self.degree[idx].copy(), T=self.T[idx].copy(),
+            vmax=self.vmax, amax=self.amax, poly_off=self.poly_off, A_face=self.A_face,
+            b_face=self.b_face, poly_idx=self.poly_idx[idx].copy(), reach_off=reach_off,
+            H_off=H_off, H=H, h0=h0, G=G.reshape(-1, 6), x0=self.x0[idx].copy(),
+            goal=self.goal[idx].copy(), meta=dict(self.meta, subset=idx.tolist()[:16]),
+        )
+
+
+# ---------------------------------------------------------------------------
+# building blocks (draws only)
+# ---------------------------------------------------------------------------
+
+def _reach_block(rng: np.random.Generator, r: int, p: int, h0_lo: float = 1.0, h0_hi: float = 3.0):
+    """r reachable rows over 3(p+1) coefficients: unit-norm Gaussian rows,
+    h0 ~ U[h0_lo, h0_hi], G' ~ N(0, 0.1^2); G returned in the literal
+    (absolute) form."""
+    ncol = 3 * (p + 1)
+    H = rng.standard_normal((r, ncol))
+    H /= np.linalg.norm(H, axis=1, keepdims=True)
+    h0 = rng.uniform(h0_lo, h0_hi, size=r)
+    Gp = rng.normal(0.0, 0.1, size=(r, 6))
+    G = Gp.copy()
+    # displacement frame -> literal frame: add H (1 (x) [I3 0]) to the x0 map
+    G[:, :3] += H.reshape(r, p + 1, 3).sum(axis=1)
+    return H, h0, G
+
+
+def _box_polytope(rng: np.random.Generator, n_faces: int, centre: np.ndarray):
+    """A bounded polytope containing ``centre``: 6 axis faces with half-widths
+    U[0.5,2] plus ``n_faces-6`` Gaussian-normal cuts at offset n.c + U[0.5,2]."""
+    w = rng.uniform(0.5, 2.0, size=3)
+    A = np.concatenate([np.eye(3), -np.eye(3)])
+    b = np.concatenate([centre + w, -(centre - w)])
+    k = n_faces - 6
+    if k > 0:
+        nrm = rng.standard_normal((k, 3))
+        nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+        off = nrm @ centre + rng.uniform(0.5, 2.0, size=k)
+        A = np.concatenate([A, nrm])
+        b = np.concatenate([b, off])
+    return A, b, w
+
+
+def _inside(A: np.ndarray, b: np.ndarray, pts: np.ndarray) -> np.ndarray:
+    return np.all(pts @ A.T <= b, axis=-1)
+
+
+def _finalize(name, degree, T, poly_A, poly_b, poly_idx, Hs, h0s, Gs, x0, goal, meta):
+    poly_off = np.zeros(len(poly_A) + 1, np.int32)
+    poly_off[1:] = np.cumsum([a.shape[0] for a in poly_A])
+    reach_off = np.zeros(len(Hs) + 1, np.int64)
+    reach_off[1:] = np.cumsum([h.shape[0] for h in Hs])
+    H_off = np.zeros(len(Hs) + 1, np.int64)
+    H_off[1:] = np.cumsum([h.size for h in Hs])
+    return SegmentBatch(
+        name=name, degree=np.asarray(degree, np.int32), T=np.asarray(T, np.float64),
+        vmax=VMAX, amax=AMAX, poly_off=poly_off,
+        A_face=np.ascontiguousarray(np.concatenate(poly_A)),
+        b_face=np.ascontiguousarray(np.concatenate(poly_b)),
+        poly_idx=np.asarray(poly_idx, np.int32), reach_off=reach_off, H_off=H_off,
+        H=np.ascontiguousarray(np.concatenate([h.ravel() for h in Hs])),
+        h0=np.ascontiguousarray(np.concatenate(h0s)),
+        G=np.ascontiguousarray(np.concatenate(Gs).reshape(-1, 6)),
+        x0=np.ascontiguousarray(np.asarray(x0, np.float64).reshape(-1, 6)),
+        goal=np.ascontiguousarray(np.asarray(goal, np.float64).reshape(-1, 3)), meta=meta,
+    )
+
+
+# ---------------------------------------------------------------------------
+# workload 0: 64 independent degree-7 segments, each in its own axis box
+# ---------------------------------------------------------------------------
+
+def gen_cfg0(n: int = 64, indices: Optional[Sequence[int]] = None, p: int = 7, r: int = 32) -> SegmentBatch:
+    idx = range(n) if indices is None else indices
+    poly_A, poly_b, Hs, h0s, Gs, x0s, goals = [], [], [], [], [], [], []
+    for i in idx:
+        rng = instance_rng(0, i)
+        c = rng.uniform(0.0, 10.0, size=3)
+        w = rng.uniform(0.5, 2.0, size=3)
+        pos0 = c + 0.9 * w * rng.uniform(-1.0, 1.0, size=3)
+        g = c + 0.9 * w * rng.uniform(-1.0, 1.0, size=3)
+        v0 = rng.uniform(-1.0, 1.0, size=3)
+        H, h0, G = _reach_block(rng, r, p)
+        poly_A.append(np.concatenate([np.eye(3), -np.eye(3)]))
+        poly_b.append(np.concatenate([c + w, -(c - w)]))
+        Hs.append(H); h0s.append(h0); Gs.append(G)
+        x0s.append(np.concatenate([pos0, v0])); goals.append(g)
+    m = len(x0s)
+    return _finalize("seg64_p7_box", [p] * m, [T_DEFAULT] * m, poly_A, poly_b, np.arange(m),
+                     Hs, h0s, Gs, x0s, goals, dict(cfg=0))
+
+
+# ---------------------------------------------------------------------------
+# cluttered environment shared by workloads 1, 2 and 4
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Environment:
+    obs_lo: np.ndarray
+    obs_hi: np.ndarray
+    centres: np.ndarray
+    halfw: np.ndarray
+    poly_A: list
+    poly_b: list
+    knn: np.ndarray
+
+
+def make_environment(cfg: int, n_obst: int = 200, n_poly: int = 2000, faces=(8, 24), k_nn: int = 4) -> Environment:
+    rng = env_rng(cfg)
+    oc = rng.uniform(0.0, 10.0, size=(n_obst, 3))
+    osz = rng.uniform(0.2, 1.5, size=(n_obst, 3))
+    lo, hi = oc - osz / 2, oc + osz / 2
+    centres, halfw, pA, pb = [], [], [], []
+    for _ in range(n_poly):
+        while True:
+            c = rng.uniform(0.0, 10.0, size=3)
+            if not np.any(np.all((c >= lo) & (c <= hi), axis=1)):
+                break
+        nf = int(rng.integers(faces[0], faces[1] + 1))
+        A, b, w = _box_polytope(rng, nf, c)
+        centres.append(c); halfw.append(w); pA.append(A); pb.append(b)
+    centres = np.asarray(centres)
+    d2 = ((centres[:, None, :] - centres[None, :, :]) ** 2).sum(-1)
+    np.fill_diagonal(d2, np.inf)
+    knn = np.argsort(d2, axis=1)[:, :k_nn]
+    return Environment(lo, hi, centres, np.asarray(halfw), pA, pb, knn)
+
+
+_ENV_CACHE: Dict[tuple, Environment] = {}
+
+
+def environment(cfg: int, **kw) -> Environment:
+    key = (cfg, tuple(sorted(kw.items())))
+    if key not in _ENV_CACHE:
+        _ENV_CACHE[key] = make_environment(cfg, **kw)
+    return _ENV_CACHE[key]
+
+
+def _sample_in(rng, A, b, c, w, tries: int = 8, batch: int = 64):
+    for _ in range(tries):
+        cand = c + w * rng.uniform(-1.0, 1.0, size=(batch, 3))
+        ok = _inside(A, b, cand)
+        if ok.any():
+            return cand[int(np.argmax(ok))]
+    return c.copy()
+
+
+def _edge(rng, env: Environment, p: int, r: int):
+    j = int(rng.integers(0, len(env.poly_A)))
+    A, b = env.poly_A[j], env.poly_b[j]
+    c, w = env.centres[j], env.halfw[j]
+    pos0 = _sample_in(rng, A, b, c, w)
+    goal = None
+    for nb in rng.permutation(env.knn[j]):
+        An, bn = env.poly_A[nb], env.poly_b[nb]
+        for _ in range(4):
+            cand = c + w * rng.uniform(-1.0, 1.0, size=(256, 3))
+            ok = _inside(A, b, cand) & _inside(An, bn, cand)
+            if ok.any():
+                goal = cand[int(np.argmax(ok))]
+                break
+        if goal is not None:
+            break
+    if goal is None:                       # no overlap with any near neighbour
+        goal = _sample_in(rng, A, b, c, w)
+    v0 = rng.uniform(-1.0, 1.0, size=3)
+    H, h0, G = _reach_block(rng, r, p, *H0_CLUTTER)
+    return j, np.concatenate([pos0, v0]), goal, H, h0, G
+
+
+def gen_cfg1(n: int = 50_000, indices: Optional[Sequence[int]] = None, cfg: int = 1) -> SegmentBatch:
+    """Edge-evaluation batch: degree-7 segments, start polytope from a shared
+    table of 2,000 free-space polytopes (8-24 faces) placed among 200 box
+    obstacles; the goal lies where the start polytope meets one of its 4
+    nearest neighbours."""
+    env = environment(cfg)
+    idx = range(n) if indices is None else indices
+    pidx, Hs, h0s, Gs, x0s, goals = [], [], [], [], [], []
+    for i in idx:
+        rng = instance_rng(cfg, i)
+        j, x0, g, H, h0, G = _edge(rng, env, 7, 32)
+        pidx.append(j); Hs.append(H); h0s.append(h0); Gs.append(G); x0s.append(x0); goals.append(g)
+    m = len(x0s)
+    return _finalize("edges50k_p7_clutter", [7] * m, [T_DEFAULT] * m, env.poly_A, env.poly_b, pidx,
+                     Hs, h0s, Gs, x0s, goals, dict(cfg=cfg))
+
+
+def gen_cfg2(n: int = 200_000, indices: Optional[Sequence[int]] = None) -> SegmentBatch:
+    """Uneven sizes: degree U{3..9}, 6-40 faces per polytope, 16-128 reachable rows."""
+    env = environment(2, faces=(6, 40))
+    idx = range(n) if indices is None else indices
+    deg, pidx, Hs, h0s, Gs, x0s, goals = [], [], [], [], [], [], []
+    for i in idx:
+        rng = instance_rng(2, i)
+        p = int(rng.integers(3, 10))
+        r = int(rng.integers(16, 129))
+        j, x0, g, H, h0, G = _edge(rng, env, p, r)
+        deg.append(p); pidx.append(j); Hs.append(H); h0s.append(h0); Gs.append(G); x0s.append(x0); goals.append(g)
+    m = len(x0s)
+    return _finalize("uneven200k_p3to9", deg, [T_DEFAULT] * m, env.poly_A, env.poly_b, pidx,
+                     Hs, h0s, Gs, x0s, goals, dict(cfg=2))
+
+
+def upstream_grads(cfg: int, n: int, ncol: int = 24, indices: Optional[Sequence[int]] = None) -> np.ndarray:
+    """Upstream gradient on P* for the differentiation workload: N(0,1) per
+    entry, seeded per instance (stream spawn_key=(2, i))."""
+    idx = range(n) if indices is None else indices
+    out = np.empty((len(idx), ncol))
+    for k, i in enumerate(idx):
+        rng = np.random.default_rng(np.random.SeedSequence(1000 + cfg, spawn_key=(2, int(i))))
+        out[k] = rng.standard_normal(ncol)
+    return out
+
+
+GENERATORS = {0: gen_cfg0, 1: gen_cfg1, 2: gen_cfg2}
