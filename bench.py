@@ -1,0 +1,256 @@
+"""Throughput of the batched segment-QP path on one MI355X.
+
+A step is one pass of the whole path over the 50,000-edge cluttered
+environment batch (degree-7 segments, 8-24 faces, 32 reachable rows, about
+30% infeasible): the forward solve (FP32 ADMM warm start + FP64 active-set
+polish, rbp_solve_batch) followed by the implicit-KKT backward
+(rbp_backward), inputs resident in HBM.  The value counts instances that end
+SOLVED with a scaled KKT residual <= 1e-6 or INFEASIBLE with a verified
+certificate.  Printed as one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_VALU_TFLOPS = 78.6     # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz (FP64, and FP32 without packing)
+PEAK_HBM_GBS = 8000.0
+KKT_OK = 1e-6
+
+
+def instance_sizes(b):
+    p = b.degree.astype(np.int64)
+    nf = np.diff(b.poly_off.astype(np.int64))[b.poly_idx]
+    r = np.diff(b.reach_off)
+    return p, nf, r
+
+
+def algorithmic_flops(b, iters):
+    """Flops per instance of the forward kernel, from the instance sizes and
+    the measured iteration counts (ADMM iterations, polish steps)."""
+    p, nf, r = instance_sizes(b)
+    n = 3 * (p - 1)
+    F = (p - 1) * nf
+    m = F + 6 * p - 3 + r
+    nnz_diff = 3 * (2 * p - 2) + 3 * (3 * (p - 1) - 2)
+    nnz = 3 * F + nnz_diff + r * n                         # free columns
+    nnz_full = 3 * F + 6 * p + 9 * (p - 1) + r * 3 * (p + 1)
+    admm_it = 4 * nnz + 2 * n * n + 10 * m
+    setup = 2 * r * n * n + 2 * n ** 3 + r * 3 * (p - 1) * p + 2 * r * 3 * (p + 1) + 2 * n * n
+    polish_step = 2 * nnz_full + 4 * n * n + n * (p - 1) + (n * n) // 4
+    final = 2 * nnz_full + n * n + 2 * (3 * (p + 1)) ** 2
+    K = iters[:, 0].astype(np.int64)
+    S = iters[:, 1].astype(np.int64)
+    return setup + K * admm_it + S * polish_step + final
+
+
+def algorithmic_bytes(b, q_mean=8):
+    """HBM bytes per instance of the forward kernel: problem data read once,
+    outputs and stored active set written once."""
+    p, nf, r = instance_sizes(b)
+    reads = 8 * r * 3 * (p + 1) + 48 * r + 8 * r + 72 + 8 + 44 + 32 * nf
+    writes = 24 * (p + 1) + 16 + 4 + 8 + 4 + 16 * q_mean
+    return reads + writes
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("rbp_kernels.hip", "rbp_api.cpp", "rbp_internal.hpp", "rbp_consts.hpp"):
+        with open(os.path.join(ROOT, "paper_2411_13507_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(n_inst):
+    """HBM bytes per solve launch measured by rocprofv3 (FETCH_SIZE +
+    WRITE_SIZE, scaled by the copy-kernel calibration), if taken on the
+    current kernel sources; None otherwise."""
+    path = os.path.join(ROOT, "profiles", "solve_edges50k_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_hash") != kernel_source_hash() or rec.get("instances") != n_inst:
+        return None
+    return float(rec["bytes_per_launch"])
+
+
+def _oracle_fwd_bwd(args):
+    from oracle import segment
+    inst, gbar = args
+    r = segment.solve(inst)
+    if segment.is_solved(r):
+        segment.gradients(r, gbar).combined(1.0)
+    return r.status
+
+
+def cpu_baseline(b, gbar, n_sample=2000):
+    """The FP64 oracle (phase-1 LP + active set + gradients) on the first
+    ``n_sample`` instances, over a process pool on the host cores."""
+    import multiprocessing as mp
+    cores = min(16, os.cpu_count() or 1)
+    insts = [(b.instance(i), gbar[i]) for i in range(n_sample)]
+    t = time.perf_counter()
+    with mp.get_context("fork").Pool(cores) as pool:
+        pool.map(_oracle_fwd_bwd, insts, chunksize=16)
+    dt = time.perf_counter() - t
+    return {"value": n_sample / dt, "unit": "solves/s", "cores": cores, "kind": "oracle",
+            "sample": f"first {n_sample} of the 50,000 edges, forward + gradients, {dt:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=50_000)
+    ap.add_argument("--admm-iters", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); instances are independent, "
+              "so a multi-GPU run would shard the batch with no communication.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2411_13507_amd import _lib
+    from paper_2411_13507_amd.api import SegmentBatchGPU
+    from workloads import gen
+
+    b = gen.generate(1, args.n)
+    gbar = gen.upstream_grads(4, b.n) if b.n <= 50_000 else np.random.default_rng(4).standard_normal((b.n, 24))
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    gb = SegmentBatchGPU(b, device="cuda:0")
+    x0 = torch.as_tensor(b.x0, device=dev)
+    goal = torch.as_tensor(b.goal, device=dev)
+    gP = torch.as_tensor(gbar.ravel(), device=dev)
+    gC = torch.ones(b.n, dtype=torch.float64, device=dev)
+    opts = _lib.default_opts()
+    opts.admm_iters = args.admm_iters
+    out = gb.alloc_outputs()
+    grads = None
+
+    def step():
+        nonlocal grads
+        gb.solve(x0, goal, opts=opts, out=out)
+        grads = gb.backward(gP, gC, out=grads)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / max(args.steps, 1)
+    st = out.status.cpu().numpy()
+    kkt = out.kkt.cpu().numpy()
+    iters = out.iters.cpu().numpy()
+    n_ok = int(((st == 0) & (kkt <= KKT_OK)).sum())
+    n_inf = int((st == 1).sum())
+    counted = n_ok + n_inf
+    value = counted / dt
+
+    # forward kernel alone, HIP events on the launch stream
+    fopts = _lib.default_opts()
+    fopts.admm_iters = args.admm_iters
+    fopts.store_for_backward = 0
+    stream = torch.cuda.current_stream(dev)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    for _ in range(2):
+        gb.solve(x0, goal, opts=fopts, out=out)
+    for e0, e1 in evs:
+        e0.record(stream)
+        gb.solve(x0, goal, opts=fopts, out=out)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    t_solve = float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs])) / 1e3
+    # backward kernel alone
+    gb.solve(x0, goal, opts=opts, out=out)
+    bevs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    for e0, e1 in bevs:
+        e0.record(stream)
+        gb.backward(gP, gC, out=grads)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    t_bwd = float(np.mean([e0.elapsed_time(e1) for e0, e1 in bevs])) / 1e3
+
+    flops = float(algorithmic_flops(b, iters).sum())
+    nbytes = float(algorithmic_bytes(b).sum())
+    achieved = flops / t_solve / 1e12
+    traffic = traffic_from_profile(b.n)
+
+    plain = None
+    if not args.no_plain:
+        sub = b.subset(range(1000))
+        pb = SegmentBatchGPU(sub, device="cuda:0")
+        popts = _lib.default_opts()
+        popts.plain = 1
+        popts.store_for_backward = 0
+        sx0 = torch.as_tensor(sub.x0, device=dev)
+        sg = torch.as_tensor(sub.goal, device=dev)
+        pout = pb.alloc_outputs()
+        pb.solve(sx0, sg, opts=popts, out=pout)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        pb.solve(sx0, sg, opts=popts, out=pout)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t
+        pst = pout.status.cpu().numpy()
+        pk = pout.kkt.cpu().numpy()
+        pc = int(((pst == 0) & (pk <= KKT_OK)).sum() + (pst == 1).sum())
+        plain = {"solves_per_s": pc / tp, "sample": "first 1000 edges, FP64 iterations, one launch per instance",
+                 "s_per_1000": tp}
+        pb.close()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(b, gbar)
+
+    rec = {
+        "metric": "segment-QP solves/s at KKT res <=1e-6, fwd+bwd (fwd, plain and % roofline alongside)",
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32+fp64",
+        "data": "synthetic",
+        "config": {"workload": "edges50k_p7_clutter", "instances": b.n, "degree": 7, "faces": "8-24",
+                   "reach_rows": 32, "admm_iters": args.admm_iters,
+                   "obstacles": 200, "polytopes": 2000},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_VALU_TFLOPS, "traffic": traffic,
+                     "kernel": "solve_kernel<float,7>", "launch_ms": t_solve * 1e3,
+                     "flops_per_launch": flops},
+        "hbm": {"algorithmic_bytes_per_launch": nbytes, "achieved_GBs": nbytes / t_solve / 1e9,
+                "frac": nbytes / t_solve / 1e9 / PEAK_HBM_GBS},
+        "fwd_solves_per_s": counted / t_solve,
+        "bwd_ms": t_bwd * 1e3,
+        "counts": {"solved_kkt_ok": n_ok, "infeasible_certified": n_inf, "other": int(b.n - counted)},
+        "polish_steps_mean": float(iters[:, 1].mean()),
+        "plain": plain,
+        "vs_plain": (value / plain["solves_per_s"]) if plain else None,
+        "fwd_vs_plain": ((counted / t_solve) / plain["solves_per_s"]) if plain else None,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

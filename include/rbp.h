@@ -1,0 +1,187 @@
+/*
+ * rbp.h -- batched reachable-Bezier-polytope segment QPs on AMD MI355X (gfx950).
+ *
+ * One instance is one candidate graph edge of the Bezier-graph planner
+ * (Csomay-Shanklin, Compton, Ames, "Dynamically Feasible Path Planning in
+ * Cluttered Environments via Reachable Bezier Polytopes", Sec. II-B and III):
+ * a degree-p Bezier curve on [0, T] in R^3, control points P_0..P_p,
+ *
+ *   minimise    int_0^T |b''(t)|^2 dt        (closed-form Bernstein Hessian)
+ *   subject to  A_f P_k <= b_f          for every control point k
+ *                                        (free-space polytope; by the
+ *                                        convex-hull property, Property 1,
+ *                                        the whole curve stays inside)
+ *               |p/T (P_{k+1} - P_k)|      <= vmax   componentwise
+ *               |p(p-1)/T^2 Delta^2 P_k|   <= amax   componentwise
+ *               H vec(P) <= h0 + G x0        (reachable Bezier polytope,
+ *                                             Theorem 2, affine in x0)
+ *               P_0 = x0[0:3],  P_p = goal   (the edge joins two waypoints)
+ *
+ * vec(P) is point-major: element 3k + c is coordinate c of control point k.
+ *
+ * Conventions for every entry point:
+ *   - All array arguments are DEVICE pointers (hipMalloc'd memory or torch
+ *     tensors on the GPU), row-major and contiguous, unless stated otherwise.
+ *   - Calls are enqueued on the given HIP stream and are asynchronous with
+ *     respect to the host, except rbp_build_batch, which copies the index
+ *     arrays to the host to validate them and synchronises the stream.
+ *   - The caller owns every buffer it passes.  A batch owns its internal
+ *     state (packed offsets, work order, stored forward state) until
+ *     rbp_destroy_batch.  The problem arrays named in rbp_problem_desc are
+ *     read, not copied: they must stay valid and unchanged while the batch
+ *     is used.
+ *   - A batch is not re-entrant: do not run two calls on one batch
+ *     concurrently on different streams.
+ *   - Return value: RBP_OK (0) or a negative RBP_E_* code; nothing throws
+ *     across this interface.  Per-instance outcomes are reported in
+ *     status_out (RBP_SOLVED ... RBP_INVALID_INPUT).
+ */
+#ifndef RBP_H_
+#define RBP_H_
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* call results */
+#define RBP_OK 0
+#define RBP_E_INVALID (-1) /* null pointer or out-of-range scalar argument        */
+#define RBP_E_SHAPE (-2)   /* inconsistent offsets, degree or size out of range    */
+#define RBP_E_ALLOC (-3)   /* device allocation failed                             */
+#define RBP_E_DEVICE (-4)  /* a HIP runtime call or kernel launch failed           */
+#define RBP_E_STATE (-5)   /* backward without a stored forward pass               */
+
+/* per-instance status */
+#define RBP_SOLVED 0         /* optimum found, scaled KKT residual <= kkt_tol      */
+#define RBP_INFEASIBLE 1     /* Farkas certificate verified in FP64                */
+#define RBP_MAXITER 2        /* reserved                                           */
+#define RBP_POLISH_FAILED 3  /* active-set polish hit its step cap, or its
+                                infeasibility certificate did not verify          */
+#define RBP_NUMERICAL 4      /* polished point misses the KKT tolerance            */
+#define RBP_INVALID_INPUT 5  /* non-finite input, T <= 0 or a zero face normal     */
+
+#define RBP_MIN_DEGREE 3
+#define RBP_MAX_DEGREE 9
+#define RBP_MAX_FACES 64     /* faces per polytope                                 */
+#define RBP_MAX_REACH 128    /* reachable rows per instance                        */
+
+/*
+ * Problem description (device pointers).  N instances share a table of
+ * n_poly free-space polytopes (the keep-in regions of the paper's convex
+ * decomposition); instance i uses polytope poly_idx[i].
+ */
+typedef struct rbp_problem_desc {
+  int32_t n_instances;        /* N >= 0                                          */
+  int32_t n_poly;             /* polytopes in the table (>= 1 when N > 0)        */
+  const int32_t* degree;      /* [N] Bezier degree p, RBP_MIN..RBP_MAX_DEGREE    */
+  const double* T;            /* [N] segment duration, > 0                       */
+  const int32_t* poly_off;    /* [n_poly+1] polytope j owns faces
+                                 poly_off[j] .. poly_off[j+1]-1, poly_off[0] = 0,
+                                 1..RBP_MAX_FACES faces each                      */
+  const double* A_face;       /* [F][3] outward face normals (non-zero)          */
+  const double* b_face;       /* [F] face offsets: A_face[f] . x <= b_face[f]    */
+  const int32_t* poly_idx;    /* [N] polytope of each instance                   */
+  const int64_t* reach_off;   /* [N+1] reachable-row offsets, reach_off[0] = 0,
+                                 r_i = reach_off[i+1]-reach_off[i] in 0..128      */
+  const int64_t* H_off;       /* [N+1] element offsets into H; instance i holds
+                                 r_i x 3(p_i+1) doubles, row-major                */
+  const double* H;            /* reachable-polytope rows over vec(P)             */
+  const double* h0;           /* [R] right-hand sides, R = reach_off[N]          */
+  const double* G;            /* [R][6] dependence of the right-hand side on x0  */
+  double vmax;                /* velocity bound, > 0                             */
+  double amax;                /* acceleration bound, > 0                         */
+} rbp_problem_desc;
+
+typedef struct rbp_solve_opts {
+  int32_t admm_iters;         /* FP32 ADMM iterations before the polish (>= 0)   */
+  float rho;                  /* ADMM penalty (> 0)                               */
+  float alpha;                /* ADMM relaxation, in (0, 2)                       */
+  int32_t max_polish_steps;   /* FP64 active-set step cap; 0 = 8 n + 64          */
+  double feas_tol;            /* polish primal tolerance, relative (> 0)         */
+  double kkt_tol;             /* SOLVED requires scaled KKT residual <= this     */
+  int32_t store_for_backward; /* keep the active set for rbp_backward             */
+  int32_t plain;              /* 1: FP64 iterations, one kernel launch per
+                                 instance (the unbatched baseline)                */
+} rbp_solve_opts;
+
+/* Sizes of the variable-length outputs of a batch (host struct). */
+typedef struct rbp_batch_sizes {
+  int32_t n_instances;
+  int32_t max_degree;
+  int64_t points_total;       /* sum_i (p_i + 1): P_out holds 3 * points_total   */
+  int64_t faces_total;        /* sum_i n_f(poly_idx[i]): length of grad_b        */
+} rbp_batch_sizes;
+
+typedef struct rbp_batch rbp_batch;
+
+/* Fills *o with the defaults: admm_iters 10, rho 0.1, alpha 1.6,
+ * max_polish_steps 0, feas_tol 1e-11, kkt_tol 1e-6, store_for_backward 1,
+ * plain 0. */
+void rbp_default_opts(rbp_solve_opts* o);
+
+/*
+ * Validates the description (index arrays are copied to the host; the call
+ * synchronises `stream`), computes per-instance output offsets and a work
+ * order, uploads the per-degree constant tables to the current device and
+ * allocates the forward state.  On success *out owns the new batch.
+ * Errors: RBP_E_INVALID (null pointers, vmax/amax <= 0), RBP_E_SHAPE (offsets
+ * not monotone, sizes or degrees out of range, H_off inconsistent with the
+ * degrees and row counts), RBP_E_ALLOC, RBP_E_DEVICE.
+ */
+int rbp_build_batch(const rbp_problem_desc* desc, hipStream_t stream, rbp_batch** out);
+
+/* Output sizes of a built batch.  Errors: RBP_E_INVALID. */
+int rbp_batch_get_sizes(const rbp_batch* batch, rbp_batch_sizes* out);
+
+/*
+ * Forward pass over all instances: FP32 ADMM warm start, then the FP64
+ * active-set polish (Sec. III-B's per-edge QP, here with the segment cost).
+ *   x0      [N][6]   start state (position, velocity); P_0 = x0[0:3]
+ *   goal    [N][3]   end waypoint; P_p = goal
+ *   b_face  [F] or NULL: replaces desc->b_face for this call (and backward)
+ *   opts    host pointer or NULL (defaults)
+ *   P_out   [3 * points_total]: instance i at 3 * sum_{i'<i}(p_i'+1);
+ *           NaN unless SOLVED
+ *   cost_out   [N] optimal cost; +inf if INFEASIBLE, NaN on other failures
+ *   status_out [N] RBP_SOLVED ... RBP_INVALID_INPUT
+ *   kkt_out    [N] max of the scaled primal, dual and complementarity
+ *              residuals of the polished point (NaN unless SOLVED/NUMERICAL)
+ *   iters_out  [N][2] or NULL: ADMM iterations, polish steps
+ * Errors: RBP_E_INVALID (null required pointer, bad option), RBP_E_DEVICE.
+ */
+int rbp_solve_batch(rbp_batch* batch, const double* x0, const double* goal, const double* b_face,
+                    const rbp_solve_opts* opts, double* P_out, double* cost_out,
+                    int32_t* status_out, double* kkt_out, int32_t* iters_out, hipStream_t stream);
+
+/*
+ * Vector-Jacobian product of the last forward pass (which must have run with
+ * store_for_backward) for the loss  l = sum_i grad_P_i . P*_i + grad_cost_i f*_i,
+ * by implicit differentiation of the KKT system on the polished active set.
+ *   grad_P    [3 * points_total] or NULL (zero)
+ *   grad_cost [N] or NULL (zero)
+ *   grad_x0   [N][6], grad_goal [N][3]
+ *   grad_b    [faces_total]: d l / d b_face for the faces of instance i's
+ *             polytope, at sum_{i'<i} n_f(i'); callers with a shared table
+ *             scatter-add these into it
+ *   flags_out [N] or NULL: 1 when the active rows are (nearly) linearly
+ *             dependent, so the derivative is not unique
+ * Instances that are not SOLVED get zero gradients.
+ * Errors: RBP_E_INVALID, RBP_E_STATE (no stored forward), RBP_E_DEVICE.
+ */
+int rbp_backward(rbp_batch* batch, const double* grad_P, const double* grad_cost, double* grad_x0,
+                 double* grad_goal, double* grad_b, int32_t* flags_out, hipStream_t stream);
+
+/* Releases the batch and its device state (no-op for NULL).  Synchronises the
+ * batch's last stream first. */
+void rbp_destroy_batch(rbp_batch* batch);
+
+/* Static string for a call result or per-instance status code. */
+const char* rbp_status_string(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RBP_H_ */

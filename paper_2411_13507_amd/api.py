@@ -1,0 +1,154 @@
+"""Python face of the C ABI: device memory and streams come from PyTorch,
+every step of the computation runs in librbp.so."""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_handle(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _dev(a, dtype, device) -> torch.Tensor:
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).to(device).contiguous()
+
+
+@dataclass
+class SolveResult:
+    P: torch.Tensor          # [3 * points_total] float64
+    cost: torch.Tensor       # [N]
+    status: torch.Tensor     # [N] int32
+    kkt: torch.Tensor        # [N]
+    iters: torch.Tensor      # [N, 2] int32
+
+
+@dataclass
+class Gradients:
+    x0: torch.Tensor         # [N, 6]
+    goal: torch.Tensor       # [N, 3]
+    b_inst: torch.Tensor     # [faces_total] per-instance face gradients
+    flags: torch.Tensor      # [N] int32
+
+
+class SegmentBatchGPU:
+    """A built batch of segment problems resident on one GPU.
+
+    ``problem`` is any object with the array attributes of the C description
+    (degree, T, poly_off, A_face, b_face, poly_idx, reach_off, H_off, H, h0,
+    G, vmax, amax), for instance a ``workloads.gen.SegmentBatch``.
+    """
+
+    def __init__(self, problem, device: str = "cuda"):
+        if not torch.cuda.is_available():
+            raise _lib.RbpError("no GPU visible: the batched segment-QP library runs only on the GPU")
+        self.device = torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device(self.device.type, torch.cuda.current_device())
+        L = _lib.load()
+        f64, i32, i64 = torch.float64, torch.int32, torch.int64
+        d = self.device
+        self.degree = _dev(problem.degree, i32, d)
+        self.T = _dev(problem.T, f64, d)
+        self.poly_off = _dev(problem.poly_off, i32, d)
+        self.A_face = _dev(problem.A_face, f64, d)
+        self.b_face = _dev(problem.b_face, f64, d)
+        self.poly_idx = _dev(problem.poly_idx, i32, d)
+        self.reach_off = _dev(problem.reach_off, i64, d)
+        self.H_off = _dev(problem.H_off, i64, d)
+        self.H = _dev(problem.H, f64, d)
+        self.h0 = _dev(problem.h0, f64, d)
+        self.G = _dev(np.asarray(problem.G).reshape(-1), f64, d)
+        self.N = int(self.degree.numel())
+        desc = _lib.ProblemDesc(
+            self.N, int(self.poly_off.numel()) - 1,
+            _ptr(self.degree), _ptr(self.T), _ptr(self.poly_off), _ptr(self.A_face), _ptr(self.b_face),
+            _ptr(self.poly_idx), _ptr(self.reach_off), _ptr(self.H_off), _ptr(self.H), _ptr(self.h0),
+            _ptr(self.G), float(problem.vmax), float(problem.amax),
+        )
+        h = ctypes.c_void_p()
+        with torch.cuda.device(d):
+            _lib.check(L.rbp_build_batch(ctypes.byref(desc), _stream_handle(d), ctypes.byref(h)), "rbp_build_batch")
+        self._h = h
+        sz = _lib.BatchSizes()
+        _lib.check(L.rbp_batch_get_sizes(h, ctypes.byref(sz)), "rbp_batch_get_sizes")
+        self.points_total = int(sz.points_total)
+        self.faces_total = int(sz.faces_total)
+        self.max_degree = int(sz.max_degree)
+        deg = np.asarray(problem.degree, np.int64)
+        self.pt_off = np.concatenate([[0], np.cumsum(deg + 1)])
+        nf = np.diff(np.asarray(problem.poly_off, np.int64))[np.asarray(problem.poly_idx, np.int64)]
+        self.face_off = np.concatenate([[0], np.cumsum(nf)])
+        # face-table index of every per-instance face gradient (for scatter-add)
+        po = np.asarray(problem.poly_off, np.int64)[np.asarray(problem.poly_idx, np.int64)]
+        self.face_index = torch.as_tensor(
+            np.concatenate([np.arange(a, a + k) for a, k in zip(po, nf)]) if len(nf) else np.zeros(0, np.int64),
+            dtype=torch.int64, device=d)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            _lib.load().rbp_destroy_batch(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def alloc_outputs(self) -> SolveResult:
+        d, N = self.device, self.N
+        return SolveResult(
+            P=torch.empty(3 * self.points_total, dtype=torch.float64, device=d),
+            cost=torch.empty(N, dtype=torch.float64, device=d),
+            status=torch.empty(N, dtype=torch.int32, device=d),
+            kkt=torch.empty(N, dtype=torch.float64, device=d),
+            iters=torch.zeros((N, 2), dtype=torch.int32, device=d),
+        )
+
+    def solve(self, x0: torch.Tensor, goal: torch.Tensor, b_face: Optional[torch.Tensor] = None,
+              opts: Optional[_lib.SolveOpts] = None, out: Optional[SolveResult] = None) -> SolveResult:
+        """Forward pass (rbp_solve_batch) on the current torch stream."""
+        o = out or self.alloc_outputs()
+        opts = opts or _lib.default_opts()
+        for t, shape in ((x0, (self.N, 6)), (goal, (self.N, 3))):
+            if t.dtype != torch.float64 or not t.is_contiguous() or tuple(t.shape) != shape or t.device != self.device:
+                raise ValueError(f"expected contiguous float64 {shape} on {self.device}")
+        if b_face is not None and (b_face.dtype != torch.float64 or not b_face.is_contiguous()
+                                   or b_face.numel() != self.b_face.numel()):
+            raise ValueError("b_face must be a contiguous float64 tensor shaped like the face table")
+        rc = _lib.load().rbp_solve_batch(
+            self._h, _ptr(x0), _ptr(goal), _ptr(b_face), ctypes.byref(opts), _ptr(o.P), _ptr(o.cost),
+            _ptr(o.status), _ptr(o.kkt), _ptr(o.iters), _stream_handle(self.device))
+        _lib.check(rc, "rbp_solve_batch")
+        return o
+
+    def backward(self, grad_P: Optional[torch.Tensor] = None, grad_cost: Optional[torch.Tensor] = None,
+                 out: Optional[Gradients] = None) -> Gradients:
+        """Implicit-KKT vector-Jacobian product of the last forward pass."""
+        d, N = self.device, self.N
+        g = out or Gradients(
+            x0=torch.empty((N, 6), dtype=torch.float64, device=d),
+            goal=torch.empty((N, 3), dtype=torch.float64, device=d),
+            b_inst=torch.empty(self.faces_total, dtype=torch.float64, device=d),
+            flags=torch.empty(N, dtype=torch.int32, device=d),
+        )
+        rc = _lib.load().rbp_backward(
+            self._h, _ptr(grad_P), _ptr(grad_cost), _ptr(g.x0), _ptr(g.goal), _ptr(g.b_inst), _ptr(g.flags),
+            _stream_handle(d))
+        _lib.check(rc, "rbp_backward")
+        return g
+
+    def P_of(self, P_flat: torch.Tensor, i: int) -> torch.Tensor:
+        a, b = self.pt_off[i], self.pt_off[i + 1]
+        return P_flat[3 * a:3 * b].view(-1, 3)

@@ -1,0 +1,296 @@
+// C ABI of the batched segment-QP library (see include/rbp.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <numeric>
+#include <vector>
+
+#include "../../include/rbp.h"
+#include "rbp_internal.hpp"
+
+struct rbp_batch {
+  int device = 0;
+  rbp_problem_desc desc{};
+  int32_t N = 0, pmax = 3, rmax = 0, nfmax = 1;
+  int32_t uniform_degree = 0;   // common degree of all instances, 0 if mixed
+  int64_t pt_total = 0, face_total = 0;
+  int64_t* d_pt_off = nullptr;
+  int64_t* d_face_off = nullptr;
+  int32_t* d_order = nullptr;
+  // forward state kept for backward
+  int32_t nmax = 0;
+  int32_t* st_q = nullptr;
+  int32_t* st_id = nullptr;
+  int32_t* st_side = nullptr;
+  double* st_lam = nullptr;
+  double* fw_P = nullptr;
+  int32_t* fw_status = nullptr;
+  double* fw_x0 = nullptr;
+  double* fw_goal = nullptr;
+  double* fw_bface = nullptr;   // copy of the b_face actually used
+  int64_t F_total = 0;
+  bool has_forward = false;
+  hipStream_t last_stream = nullptr;
+};
+
+namespace {
+
+std::mutex g_const_mu;
+std::vector<int> g_const_done;
+
+int ensure_constants(int device) {
+  std::lock_guard<std::mutex> lk(g_const_mu);
+  if (std::find(g_const_done.begin(), g_const_done.end(), device) != g_const_done.end()) return RBP_OK;
+  if (rbp::upload_constants(device) != hipSuccess) return RBP_E_DEVICE;
+  g_const_done.push_back(device);
+  return RBP_OK;
+}
+
+template <typename T>
+int dalloc(T** p, size_t n) {
+  *p = nullptr;
+  if (n == 0) n = 1;
+  if (hipMalloc(reinterpret_cast<void**>(p), n * sizeof(T)) != hipSuccess) { *p = nullptr; return RBP_E_ALLOC; }
+  return RBP_OK;
+}
+
+void free_batch(rbp_batch* b) {
+  if (!b) return;
+  void* ptrs[] = {b->d_pt_off, b->d_face_off, b->d_order, b->st_q, b->st_id, b->st_side,
+                  b->st_lam, b->fw_P, b->fw_status, b->fw_x0, b->fw_goal, b->fw_bface};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  delete b;
+}
+
+template <typename T>
+int d2h(std::vector<T>& dst, const T* src, size_t n, hipStream_t s) {
+  dst.resize(n);
+  if (n == 0) return RBP_OK;
+  if (hipMemcpyAsync(dst.data(), src, n * sizeof(T), hipMemcpyDeviceToHost, s) != hipSuccess) return RBP_E_DEVICE;
+  return RBP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void rbp_default_opts(rbp_solve_opts* o) {
+  if (!o) return;
+  o->admm_iters = 10;
+  o->rho = 0.1f;
+  o->alpha = 1.6f;
+  o->max_polish_steps = 0;
+  o->feas_tol = 1e-11;
+  o->kkt_tol = 1e-6;
+  o->store_for_backward = 1;
+  o->plain = 0;
+}
+
+const char* rbp_status_string(int code) {
+  switch (code) {
+    case 0: return "ok / solved";
+    case RBP_INFEASIBLE: return "infeasible (verified certificate)";
+    case RBP_MAXITER: return "iteration limit";
+    case RBP_POLISH_FAILED: return "polish failed";
+    case RBP_NUMERICAL: return "numerical: KKT tolerance missed";
+    case RBP_INVALID_INPUT: return "invalid instance input";
+    case RBP_E_INVALID: return "invalid argument";
+    case RBP_E_SHAPE: return "inconsistent shapes or offsets";
+    case RBP_E_ALLOC: return "device allocation failed";
+    case RBP_E_DEVICE: return "HIP runtime error";
+    case RBP_E_STATE: return "no stored forward pass";
+    default: return "unknown code";
+  }
+}
+
+int rbp_build_batch(const rbp_problem_desc* d, hipStream_t stream, rbp_batch** out) {
+  if (!d || !out) return RBP_E_INVALID;
+  *out = nullptr;
+  const int32_t N = d->n_instances;
+  if (N < 0 || d->n_poly < 0) return RBP_E_INVALID;
+  if (!(d->vmax > 0.0) || !(d->amax > 0.0)) return RBP_E_INVALID;
+  if (N > 0) {
+    if (d->n_poly < 1) return RBP_E_SHAPE;
+    if (!d->degree || !d->T || !d->poly_off || !d->A_face || !d->b_face || !d->poly_idx ||
+        !d->reach_off || !d->H_off || !d->H || !d->h0 || !d->G)
+      return RBP_E_INVALID;
+  }
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return RBP_E_DEVICE;
+  if (int rc = ensure_constants(dev)) return rc;
+
+  std::vector<int32_t> deg, pidx, poff;
+  std::vector<int64_t> roff, hoff;
+  int rc = RBP_OK;
+  if (N > 0) {
+    if ((rc = d2h(deg, d->degree, N, stream)) || (rc = d2h(pidx, d->poly_idx, N, stream)) ||
+        (rc = d2h(poff, d->poly_off, size_t(d->n_poly) + 1, stream)) ||
+        (rc = d2h(roff, d->reach_off, size_t(N) + 1, stream)) || (rc = d2h(hoff, d->H_off, size_t(N) + 1, stream)))
+      return rc;
+    if (hipStreamSynchronize(stream) != hipSuccess) return RBP_E_DEVICE;
+  }
+  auto* b = new (std::nothrow) rbp_batch();
+  if (!b) return RBP_E_ALLOC;
+  b->device = dev;
+  b->desc = *d;
+  b->N = N;
+  std::vector<int64_t> pt_off(size_t(N) + 1, 0), face_off(size_t(N) + 1, 0);
+  std::vector<int32_t> order(N);
+  if (N > 0) {
+    if (poff[0] != 0) { free_batch(b); return RBP_E_SHAPE; }
+    for (int j = 0; j < d->n_poly; ++j) {
+      const int64_t nf = int64_t(poff[j + 1]) - poff[j];
+      if (nf < 1 || nf > RBP_MAX_FACES) { free_batch(b); return RBP_E_SHAPE; }
+    }
+    if (roff[0] != 0 || hoff[0] != 0) { free_batch(b); return RBP_E_SHAPE; }
+    std::vector<int64_t> cost(N);
+    for (int i = 0; i < N; ++i) {
+      const int p = deg[i];
+      if (p < RBP_MIN_DEGREE || p > RBP_MAX_DEGREE) { free_batch(b); return RBP_E_SHAPE; }
+      if (pidx[i] < 0 || pidx[i] >= d->n_poly) { free_batch(b); return RBP_E_SHAPE; }
+      const int64_t r = roff[i + 1] - roff[i];
+      if (r < 0 || r > RBP_MAX_REACH) { free_batch(b); return RBP_E_SHAPE; }
+      if (hoff[i + 1] - hoff[i] != r * 3 * (p + 1)) { free_batch(b); return RBP_E_SHAPE; }
+      const int nf = poff[pidx[i] + 1] - poff[pidx[i]];
+      b->pmax = std::max<int32_t>(b->pmax, p);
+      b->rmax = std::max<int32_t>(b->rmax, int32_t(r));
+      b->nfmax = std::max<int32_t>(b->nfmax, nf);
+      pt_off[i + 1] = pt_off[i] + (p + 1);
+      face_off[i + 1] = face_off[i] + nf;
+      cost[i] = int64_t(3 * (p - 1)) * ((p - 1) * nf + 6 * p + r);
+    }
+    b->F_total = poff[d->n_poly];
+    b->uniform_degree = deg[0];
+    for (int i = 1; i < N; ++i)
+      if (deg[i] != deg[0]) { b->uniform_degree = 0; break; }
+    // work order: most expensive first so that the tail of the launch is short
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return cost[a] > cost[c]; });
+  }
+  b->pt_total = pt_off[N];
+  b->face_total = face_off[N];
+  b->nmax = 3 * (b->pmax - 1);
+  const size_t n1 = size_t(N);
+  if ((rc = dalloc(&b->d_pt_off, n1 + 1)) || (rc = dalloc(&b->d_face_off, n1 + 1)) ||
+      (rc = dalloc(&b->d_order, n1)) || (rc = dalloc(&b->st_q, n1)) ||
+      (rc = dalloc(&b->st_id, n1 * b->nmax)) || (rc = dalloc(&b->st_side, n1 * b->nmax)) ||
+      (rc = dalloc(&b->st_lam, n1 * b->nmax)) || (rc = dalloc(&b->fw_P, size_t(3 * b->pt_total))) ||
+      (rc = dalloc(&b->fw_status, n1)) || (rc = dalloc(&b->fw_x0, 6 * n1)) ||
+      (rc = dalloc(&b->fw_goal, 3 * n1)) || (rc = dalloc(&b->fw_bface, size_t(std::max<int64_t>(b->F_total, 1))))) {
+    free_batch(b);
+    return rc;
+  }
+  if (hipMemcpyAsync(b->d_pt_off, pt_off.data(), (n1 + 1) * sizeof(int64_t), hipMemcpyHostToDevice, stream) ||
+      hipMemcpyAsync(b->d_face_off, face_off.data(), (n1 + 1) * sizeof(int64_t), hipMemcpyHostToDevice, stream) ||
+      (N > 0 && hipMemcpyAsync(b->d_order, order.data(), n1 * sizeof(int32_t), hipMemcpyHostToDevice, stream)) ||
+      hipStreamSynchronize(stream)) {
+    free_batch(b);
+    return RBP_E_DEVICE;
+  }
+  b->last_stream = stream;
+  *out = b;
+  return RBP_OK;
+}
+
+int rbp_batch_get_sizes(const rbp_batch* b, rbp_batch_sizes* out) {
+  if (!b || !out) return RBP_E_INVALID;
+  out->n_instances = b->N;
+  out->max_degree = b->pmax;
+  out->points_total = b->pt_total;
+  out->faces_total = b->face_total;
+  return RBP_OK;
+}
+
+int rbp_solve_batch(rbp_batch* b, const double* x0, const double* goal, const double* b_face,
+                    const rbp_solve_opts* opts_in, double* P_out, double* cost_out, int32_t* status_out,
+                    double* kkt_out, int32_t* iters_out, hipStream_t stream) {
+  if (!b) return RBP_E_INVALID;
+  rbp_solve_opts o;
+  rbp_default_opts(&o);
+  if (opts_in) o = *opts_in;
+  if (o.admm_iters < 0 || !(o.rho > 0.0f) || !(o.alpha > 0.0f) || !(o.alpha < 2.0f) || o.max_polish_steps < 0 ||
+      !(o.feas_tol > 0.0) || !(o.kkt_tol > 0.0))
+    return RBP_E_INVALID;
+  b->has_forward = false;
+  if (b->N == 0) return RBP_OK;
+  if (!x0 || !goal || !P_out || !cost_out || !status_out || !kkt_out) return RBP_E_INVALID;
+  const rbp_problem_desc& d = b->desc;
+  const double* bf = b_face ? b_face : d.b_face;
+
+  rbp::SolveArgs a{};
+  a.N = b->N;
+  a.degree = d.degree; a.T = d.T; a.poly_off = d.poly_off; a.A_face = d.A_face; a.b_face = bf;
+  a.poly_idx = d.poly_idx; a.reach_off = d.reach_off; a.H_off = d.H_off; a.H = d.H; a.h0 = d.h0; a.G = d.G;
+  a.vmax = d.vmax; a.amax = d.amax;
+  a.x0 = x0; a.goal = goal; a.pt_off = b->d_pt_off;
+  a.P_out = P_out; a.cost_out = cost_out; a.status_out = status_out; a.kkt_out = kkt_out; a.iters_out = iters_out;
+  a.store = o.store_for_backward ? 1 : 0;
+  a.st_q = b->st_q; a.st_id = b->st_id; a.st_side = b->st_side; a.st_lam = b->st_lam;
+  a.admm_iters = o.admm_iters; a.rho = o.rho; a.alpha = o.alpha;
+  a.max_steps = o.max_polish_steps; a.feas_tol = o.feas_tol; a.kkt_tol = o.kkt_tol;
+  a.dims = rbp::make_dims(b->pmax, b->rmax, b->nfmax);
+  hipError_t e = hipSuccess;
+  if (o.plain) {
+    a.order = nullptr;
+    for (int i = 0; i < b->N && e == hipSuccess; ++i) {
+      a.inst_base = i;
+      e = rbp::launch_solve(a, 1, stream, true, b->uniform_degree);
+    }
+  } else {
+    a.order = b->d_order;
+    a.inst_base = 0;
+    e = rbp::launch_solve(a, b->N, stream, false, b->uniform_degree);
+  }
+  if (e != hipSuccess) return RBP_E_DEVICE;
+  b->last_stream = stream;
+  if (o.store_for_backward) {
+    const size_t n1 = size_t(b->N);
+    if (hipMemcpyAsync(b->fw_P, P_out, size_t(3 * b->pt_total) * sizeof(double), hipMemcpyDeviceToDevice, stream) ||
+        hipMemcpyAsync(b->fw_status, status_out, n1 * sizeof(int32_t), hipMemcpyDeviceToDevice, stream) ||
+        hipMemcpyAsync(b->fw_x0, x0, 6 * n1 * sizeof(double), hipMemcpyDeviceToDevice, stream) ||
+        hipMemcpyAsync(b->fw_goal, goal, 3 * n1 * sizeof(double), hipMemcpyDeviceToDevice, stream) ||
+        (b->F_total > 0 &&
+         hipMemcpyAsync(b->fw_bface, bf, size_t(b->F_total) * sizeof(double), hipMemcpyDeviceToDevice, stream)))
+      return RBP_E_DEVICE;
+    b->has_forward = true;
+  }
+  return RBP_OK;
+}
+
+int rbp_backward(rbp_batch* b, const double* grad_P, const double* grad_cost, double* grad_x0, double* grad_goal,
+                 double* grad_b, int32_t* flags_out, hipStream_t stream) {
+  if (!b) return RBP_E_INVALID;
+  if (!b->has_forward) return RBP_E_STATE;
+  if (b->N == 0) return RBP_OK;
+  if (!grad_x0 || !grad_goal || !grad_b) return RBP_E_INVALID;
+  const rbp_problem_desc& d = b->desc;
+  rbp::BackArgs a{};
+  a.N = b->N;
+  a.degree = d.degree; a.T = d.T; a.poly_off = d.poly_off; a.A_face = d.A_face; a.b_face = b->fw_bface;
+  a.poly_idx = d.poly_idx; a.reach_off = d.reach_off; a.H_off = d.H_off; a.H = d.H; a.G = d.G;
+  a.vmax = d.vmax; a.amax = d.amax;
+  a.x0 = b->fw_x0; a.goal = b->fw_goal; a.pt_off = b->d_pt_off; a.face_off = b->d_face_off;
+  a.P_sol = b->fw_P; a.status = b->fw_status;
+  a.st_q = b->st_q; a.st_id = b->st_id; a.st_side = b->st_side; a.st_lam = b->st_lam;
+  a.grad_P = grad_P; a.grad_cost = grad_cost;
+  a.grad_x0 = grad_x0; a.grad_goal = grad_goal; a.grad_b = grad_b; a.flags = flags_out;
+  a.dims = rbp::make_dims(b->pmax, b->rmax, b->nfmax);
+  if (rbp::launch_backward(a, stream) != hipSuccess) return RBP_E_DEVICE;
+  b->last_stream = stream;
+  return RBP_OK;
+}
+
+void rbp_destroy_batch(rbp_batch* b) {
+  if (!b) return;
+  (void)hipSetDevice(b->device);
+  if (b->last_stream) (void)hipStreamSynchronize(b->last_stream);
+  else (void)hipDeviceSynchronize();
+  free_batch(b);
+}
+
+}  // extern "C"

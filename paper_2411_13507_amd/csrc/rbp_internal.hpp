@@ -1,0 +1,111 @@
+// Internal interface between the C ABI (rbp_api.cpp) and the kernels
+// (rbp_kernels.hip).  Not part of the public header.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "rbp_consts.hpp"
+
+namespace rbp {
+
+// Per-instance row numbering used by the solver, the stored active sets and
+// the backward pass (p = degree, nf = faces of the instance's polytope,
+// r = reachable rows):
+//   faces  : id = s*nf + j           s = 0..p-2 (control point s+1), j < nf
+//   vel    : id = F + 3k + c         k = 0..p-1, c = 0..2   (F = (p-1) nf)
+//   acc    : id = F + 3p + 3k + c    k = 0..p-2
+//   reach  : id = F + 6p - 3 + l     l < r
+// Face and reachable rows are one-sided (upper bound); difference rows are
+// two-sided.  An active constraint is (id, side) with side = +1 (upper) or
+// -1 (lower).
+
+struct LdsDims {
+  int nmax;    // 3 (pmax - 1)
+  int ncol;    // 3 (pmax + 1)
+  int r_cap;   // max reachable rows
+  int nf_cap;  // max faces
+  int m_cap;   // max rows
+  // byte offsets
+  int o_Hd, o_Af, o_rowval, o_ybuf, o_vec, o_scal, o_acte, o_lam, o_actid, o_actside, o_region;
+  int o_Hf, o_Aff, o_vbuf, o_xb1, o_xb2, o_Kx;   // ADMM part of region
+  int o_Q1, o_R;                                  // polish part of region
+  int bytes;
+};
+
+struct SolveArgs {
+  int N;
+  const int32_t* degree;
+  const double* T;
+  const int32_t* poly_off;
+  const double* A_face;
+  const double* b_face;
+  const int32_t* poly_idx;
+  const int64_t* reach_off;
+  const int64_t* H_off;
+  const double* H;
+  const double* h0;
+  const double* G;
+  double vmax, amax;
+  const double* x0;
+  const double* goal;
+  const int64_t* pt_off;     // per-instance offset in control points (sum of p+1)
+  const int32_t* order;      // work order (nullable): block b solves order[b]
+  int inst_base;             // added to the block index (single-instance launches)
+  double* P_out;
+  double* cost_out;
+  int32_t* status_out;
+  double* kkt_out;
+  int32_t* iters_out;        // nullable, 2 per instance: ADMM iterations, polish steps
+  // state kept for the backward pass
+  int store;
+  int32_t* st_q;             // active count per instance
+  int32_t* st_id;            // [N * nmax] row ids
+  int32_t* st_side;          // [N * nmax] sides
+  double* st_lam;            // [N * nmax] multipliers
+  // options
+  int admm_iters;
+  float rho, alpha;
+  int max_steps;
+  double feas_tol;
+  double kkt_tol;
+  LdsDims dims;
+};
+
+struct BackArgs {
+  int N;
+  const int32_t* degree;
+  const double* T;
+  const int32_t* poly_off;
+  const double* A_face;
+  const double* b_face;
+  const int32_t* poly_idx;
+  const int64_t* reach_off;
+  const int64_t* H_off;
+  const double* H;
+  const double* G;
+  double vmax, amax;
+  const double* x0;
+  const double* goal;
+  const int64_t* pt_off;
+  const int64_t* face_off;   // per-instance offset of its faces in grad_b
+  const double* P_sol;       // forward solution (control points)
+  const int32_t* status;
+  const int32_t* st_q;
+  const int32_t* st_id;
+  const int32_t* st_side;
+  const double* st_lam;
+  const double* grad_P;      // nullable
+  const double* grad_cost;   // nullable
+  double* grad_x0;
+  double* grad_goal;
+  double* grad_b;
+  int32_t* flags;            // nullable: 1 when the active rows are (near) dependent
+  LdsDims dims;
+};
+
+LdsDims make_dims(int pmax, int r_cap, int nf_cap);
+hipError_t upload_constants(int device);
+hipError_t launch_solve(const SolveArgs& a, int n_blocks, hipStream_t s, bool fp64_iters, int pfix);
+hipError_t launch_backward(const BackArgs& a, hipStream_t s);
+
+}  // namespace rbp

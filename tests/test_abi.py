@@ -1,0 +1,89 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry
+point that include/rbp.h declares, and rejects bad arguments before any
+device work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2411_13507_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "rbp.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rbp_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("librbp.so not built")
+    return _lib.load()
+
+
+def test_header_symbols_exported(lib):
+    names = declared_symbols()
+    assert set(names) == set(_lib.EXPORTED), names
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_default_opts(lib):
+    o = _lib.default_opts()
+    assert o.admm_iters == 10 and abs(o.rho - 0.1) < 1e-7 and abs(o.alpha - 1.6) < 1e-6
+    assert o.max_polish_steps == 0 and o.store_for_backward == 1 and o.plain == 0
+    assert o.feas_tol == 1e-11 and o.kkt_tol == 1e-6
+
+
+def test_status_strings(lib):
+    for code in (0, 1, 2, 3, 4, 5, -1, -2, -3, -4, -5):
+        s = lib.rbp_status_string(code).decode()
+        assert s and s != "unknown code"
+    assert lib.rbp_status_string(1234).decode() == "unknown code"
+
+
+def test_null_arguments_rejected(lib):
+    out = ctypes.c_void_p()
+    assert lib.rbp_build_batch(None, None, ctypes.byref(out)) == _lib.RBP_E_INVALID
+    d = _lib.ProblemDesc()
+    d.n_instances = 1
+    d.vmax = 3.0
+    d.amax = 5.0
+    d.n_poly = 1
+    # null device pointers with N > 0
+    assert lib.rbp_build_batch(ctypes.byref(d), None, ctypes.byref(out)) == _lib.RBP_E_INVALID
+    d.vmax = 0.0
+    assert lib.rbp_build_batch(ctypes.byref(d), None, ctypes.byref(out)) == _lib.RBP_E_INVALID
+    d.vmax, d.n_instances = 3.0, -1
+    assert lib.rbp_build_batch(ctypes.byref(d), None, ctypes.byref(out)) == _lib.RBP_E_INVALID
+    o = _lib.default_opts()
+    z = [None] * 7
+    assert lib.rbp_solve_batch(None, None, None, None, ctypes.byref(o), *z) == _lib.RBP_E_INVALID
+    assert lib.rbp_backward(None, *([None] * 7)) == _lib.RBP_E_INVALID
+    sz = _lib.BatchSizes()
+    assert lib.rbp_batch_get_sizes(None, ctypes.byref(sz)) == _lib.RBP_E_INVALID
+    lib.rbp_destroy_batch(None)
+
+
+def test_no_cpu_fallback():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("GPU present")
+    from paper_2411_13507_amd.api import SegmentBatchGPU
+    from workloads import gen
+    with pytest.raises(_lib.RbpError):
+        SegmentBatchGPU(gen.gen_cfg0(2))
+
+
+def test_missing_library_is_an_error(tmp_path):
+    saved = _lib._LIB
+    try:
+        _lib._LIB = None
+        with pytest.raises(_lib.RbpError):
+            _lib.load(str(tmp_path / "missing.so"))
+    finally:
+        _lib._LIB = saved

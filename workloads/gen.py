@@ -27,6 +27,7 @@ Conventions shared with the consumers (documented in include/rbp.h):
 from __future__ import annotations
 
 from dataclasses import dataclass, field
+import os
 from typing import Dict, Optional, Sequence
 
 import numpy as np
@@ -159,7 +160,7 @@ def _inside(A: np.ndarray, b: np.ndarray, pts: np.ndarray) -> np.ndarray:
     return np.all(pts @ A.T <= b, axis=-1)
 
 
-def _finalize(name, degree, T, poly_A, poly_b, poly_idx, Hs, h0s, Gs, x0, goal, meta):
+def _finalize(name, degree, T, poly_A, poly_b, poly_idx, Hs, h0s, Gs, x0, goal, meta, vmax=VMAX, amax=AMAX):
     poly_off = np.zeros(len(poly_A) + 1, np.int32)
     poly_off[1:] = np.cumsum([a.shape[0] for a in poly_A])
     reach_off = np.zeros(len(Hs) + 1, np.int64)
@@ -168,7 +169,7 @@ def _finalize(name, degree, T, poly_A, poly_b, poly_idx, Hs, h0s, Gs, x0, goal, 
     H_off[1:] = np.cumsum([h.size for h in Hs])
     return SegmentBatch(
         name=name, degree=np.asarray(degree, np.int32), T=np.asarray(T, np.float64),
-        vmax=VMAX, amax=AMAX, poly_off=poly_off,
+        vmax=vmax, amax=amax, poly_off=poly_off,
         A_face=np.ascontiguousarray(np.concatenate(poly_A)),
         b_face=np.ascontiguousarray(np.concatenate(poly_b)),
         poly_idx=np.asarray(poly_idx, np.int32), reach_off=reach_off, H_off=H_off,
@@ -327,3 +328,69 @@ def upstream_grads(cfg: int, n: int, ncol: int = 24, indices: Optional[Sequence[
 
 
 GENERATORS = {0: gen_cfg0, 1: gen_cfg1, 2: gen_cfg2}
+
+
+def concat(parts) -> SegmentBatch:
+    """Join batches that share one polytope table (same workload)."""
+    parts = [p for p in parts if p.n > 0] or list(parts)[:1]
+    first = parts[0]
+    reach = np.concatenate([[0]] + [np.diff(p.reach_off) for p in parts]).cumsum()
+    hsz = np.concatenate([[0]] + [np.diff(p.H_off) for p in parts]).cumsum()
+    return SegmentBatch(
+        name=first.name, degree=np.concatenate([p.degree for p in parts]),
+        T=np.concatenate([p.T for p in parts]), vmax=first.vmax, amax=first.amax,
+        poly_off=first.poly_off, A_face=first.A_face, b_face=first.b_face,
+        poly_idx=np.concatenate([p.poly_idx for p in parts]),
+        reach_off=reach.astype(np.int64), H_off=hsz.astype(np.int64),
+        H=np.concatenate([p.H for p in parts]), h0=np.concatenate([p.h0 for p in parts]),
+        G=np.concatenate([p.G for p in parts]).reshape(-1, 6),
+        x0=np.concatenate([p.x0 for p in parts]), goal=np.concatenate([p.goal for p in parts]),
+        meta=dict(first.meta),
+    )
+
+
+def _gen_chunk(args):
+    cfg, idx = args
+    if cfg == 0:
+        return gen_cfg0(indices=idx)
+    if cfg in (1, 4):
+        return gen_cfg1(indices=idx, cfg=1)
+    return gen_cfg2(indices=idx)
+
+
+def generate(cfg: int, n: int, workers: Optional[int] = None) -> SegmentBatch:
+    """Workload ``cfg`` with ``n`` instances, drawn in parallel processes.
+    Every instance has its own seed, so the result equals the serial one."""
+    workers = workers or min(16, os.cpu_count() or 1)
+    if workers <= 1 or n < 2000:
+        return _gen_chunk((cfg, list(range(n))))
+    chunks = [list(c) for c in np.array_split(np.arange(n), workers * 4) if len(c)]
+    import multiprocessing as mp
+    with mp.get_context("fork").Pool(workers) as pool:
+        parts = pool.map(_gen_chunk, [(cfg, c) for c in chunks])
+    out = concat(parts)
+    out.name = parts[0].name
+    return out
+
+
+def from_instances(insts, name: str = "custom") -> SegmentBatch:
+    """Pack per-instance dicts (the layout of ``SegmentBatch.instance``) into
+    a batch; each instance gets its own polytope."""
+    return _finalize(name, [d["p"] for d in insts], [d["T"] for d in insts],
+                     [np.asarray(d["A_face"], float) for d in insts],
+                     [np.asarray(d["b_face"], float) for d in insts], np.arange(len(insts)),
+                     [np.asarray(d["H"], float).reshape(-1, 3 * (d["p"] + 1)) for d in insts],
+                     [np.asarray(d["h0"], float) for d in insts],
+                     [np.asarray(d["G"], float).reshape(-1, 6) for d in insts],
+                     [np.asarray(d["x0"], float) for d in insts],
+                     [np.asarray(d["goal"], float) for d in insts], dict(cfg=-1),
+                     vmax=insts[0]["vmax"], amax=insts[0]["amax"]) if insts else _empty(name)
+
+
+def _empty(name):
+    return SegmentBatch(name=name, degree=np.zeros(0, np.int32), T=np.zeros(0), vmax=VMAX, amax=AMAX,
+                        poly_off=np.zeros(2, np.int32) + np.array([0, 6], np.int32),
+                        A_face=np.concatenate([np.eye(3), -np.eye(3)]), b_face=np.ones(6),
+                        poly_idx=np.zeros(0, np.int32), reach_off=np.zeros(1, np.int64),
+                        H_off=np.zeros(1, np.int64), H=np.zeros(0), h0=np.zeros(0), G=np.zeros((0, 6)),
+                        x0=np.zeros((0, 6)), goal=np.zeros((0, 3)))
