@@ -64,7 +64,7 @@ def algorithmic_bytes(b, q_mean=8):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("rbp_kernels.hip", "rbp_api.cpp", "rbp_internal.hpp", "rbp_consts.hpp"):
+    for f in ("rbp_kernels.hip", "rbp_api.cpp", "rbp_internal.hpp", "rbp_consts.hpp", "rbp_wave.hpp"):
         with open(os.path.join(ROOT, "paper_2411_13507_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -146,12 +146,32 @@ def main():
         gb.solve(x0, goal, opts=opts, out=out)
         grads = gb.backward(gP, gC, out=grads)
 
+    step()                                   # allocates the gradient buffers
+    torch.cuda.synchronize()
+    # capture one step (per-degree solve launches, state copies, backward) in a
+    # HIP graph on torch's stream; replay it as the timed step
+    launch = "hipgraph"
+    run = step
+    try:
+        cur = torch.cuda.current_stream(dev)
+        side = torch.cuda.Stream(device=dev)
+        side.wait_stream(cur)
+        with torch.cuda.stream(side):
+            step()
+        cur.wait_stream(side)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            step()
+        run = graph.replay
+    except Exception as exc:                 # capture refused: time the eager launches
+        launch = f"eager (capture failed: {type(exc).__name__})"
+        run = step
     for _ in range(args.warmup):
-        step()
+        run()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        step()
+        run()
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / max(args.steps, 1)
     st = out.status.cpu().numpy()
@@ -233,7 +253,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "edges50k_p7_clutter", "instances": b.n, "degree": 7, "faces": "8-24",
                    "reach_rows": 32, "admm_iters": args.admm_iters,
-                   "obstacles": 200, "polytopes": 2000},
+                   "obstacles": 200, "polytopes": 2000, "launch": launch},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_VALU_TFLOPS, "traffic": traffic,
                      "kernel": "solve_kernel<float,7>", "launch_ms": t_solve * 1e3,

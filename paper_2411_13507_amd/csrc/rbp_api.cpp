@@ -16,7 +16,10 @@ struct rbp_batch {
   int device = 0;
   rbp_problem_desc desc{};
   int32_t N = 0, pmax = 3, rmax = 0, nfmax = 1;
-  int32_t uniform_degree = 0;   // common degree of all instances, 0 if mixed
+  // work order grouped by degree: order[deg_start[p] .. deg_start[p]+deg_count[p]) have degree p
+  int32_t deg_start[RBP_MAX_DEGREE + 1] = {};
+  int32_t deg_count[RBP_MAX_DEGREE + 1] = {};
+  std::vector<int32_t> degree_host;
   int64_t pt_total = 0, face_total = 0;
   int64_t* d_pt_off = nullptr;
   int64_t* d_face_off = nullptr;
@@ -165,12 +168,18 @@ int rbp_build_batch(const rbp_problem_desc* d, hipStream_t stream, rbp_batch** o
       cost[i] = int64_t(3 * (p - 1)) * ((p - 1) * nf + 6 * p + r);
     }
     b->F_total = poff[d->n_poly];
-    b->uniform_degree = deg[0];
-    for (int i = 1; i < N; ++i)
-      if (deg[i] != deg[0]) { b->uniform_degree = 0; break; }
-    // work order: most expensive first so that the tail of the launch is short
+    // work order: grouped by degree (one specialised launch each), most
+    // expensive first within a group so that the tail of each launch is short
     std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return cost[a] > cost[c]; });
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
+      return deg[a] != deg[c] ? deg[a] < deg[c] : cost[a] > cost[c];
+    });
+    for (int k = 0; k < N; ++k) {
+      const int p = deg[order[k]];
+      if (b->deg_count[p] == 0) b->deg_start[p] = k;
+      ++b->deg_count[p];
+    }
+    b->degree_host = deg;
   }
   b->pt_total = pt_off[N];
   b->face_total = face_off[N];
@@ -233,18 +242,22 @@ int rbp_solve_batch(rbp_batch* b, const double* x0, const double* goal, const do
   a.st_q = b->st_q; a.st_id = b->st_id; a.st_side = b->st_side; a.st_lam = b->st_lam;
   a.admm_iters = o.admm_iters; a.rho = o.rho; a.alpha = o.alpha;
   a.max_steps = o.max_polish_steps; a.feas_tol = o.feas_tol; a.kkt_tol = o.kkt_tol;
-  a.dims = rbp::make_dims(b->pmax, b->rmax, b->nfmax);
+  a.dims = rbp::make_dims(b->pmax, b->rmax, b->nfmax, o.plain ? 8 : 4);
   hipError_t e = hipSuccess;
   if (o.plain) {
     a.order = nullptr;
     for (int i = 0; i < b->N && e == hipSuccess; ++i) {
       a.inst_base = i;
-      e = rbp::launch_solve(a, 1, stream, true, b->uniform_degree);
+      e = rbp::launch_solve(a, 1, stream, true, b->degree_host[i]);
     }
   } else {
     a.order = b->d_order;
-    a.inst_base = 0;
-    e = rbp::launch_solve(a, b->N, stream, false, b->uniform_degree);
+    for (int p = RBP_MIN_DEGREE; p <= RBP_MAX_DEGREE && e == hipSuccess; ++p) {
+      if (b->deg_count[p] == 0) continue;
+      a.inst_base = b->deg_start[p];
+      a.N = b->deg_start[p] + b->deg_count[p];
+      e = rbp::launch_solve(a, b->deg_count[p], stream, false, p);
+    }
   }
   if (e != hipSuccess) return RBP_E_DEVICE;
   b->last_stream = stream;
@@ -279,7 +292,7 @@ int rbp_backward(rbp_batch* b, const double* grad_P, const double* grad_cost, do
   a.st_q = b->st_q; a.st_id = b->st_id; a.st_side = b->st_side; a.st_lam = b->st_lam;
   a.grad_P = grad_P; a.grad_cost = grad_cost;
   a.grad_x0 = grad_x0; a.grad_goal = grad_goal; a.grad_b = grad_b; a.flags = flags_out;
-  a.dims = rbp::make_dims(b->pmax, b->rmax, b->nfmax);
+  a.dims = rbp::make_dims(b->pmax, b->rmax, b->nfmax, 8);
   if (rbp::launch_backward(a, stream) != hipSuccess) return RBP_E_DEVICE;
   b->last_stream = stream;
   return RBP_OK;

@@ -33,7 +33,7 @@ struct LdsDims {
 };
 
 struct SolveArgs {
-  int N;
+  int N;                     // solve: end of the launch's range in the work order
   const int32_t* degree;
   const double* T;
   const int32_t* poly_off;
@@ -50,7 +50,7 @@ struct SolveArgs {
   const double* goal;
   const int64_t* pt_off;     // per-instance offset in control points (sum of p+1)
   const int32_t* order;      // work order (nullable): block b solves order[b]
-  int inst_base;             // added to the block index (single-instance launches)
+  int inst_base;             // first work-order position of the launch (block b -> inst_base + b)
   double* P_out;
   double* cost_out;
   int32_t* status_out;
@@ -103,7 +103,7 @@ struct BackArgs {
   LdsDims dims;
 };
 
-LdsDims make_dims(int pmax, int r_cap, int nf_cap);
+LdsDims make_dims(int pmax, int r_cap, int nf_cap, int real_bytes);
 hipError_t upload_constants(int device);
 hipError_t launch_solve(const SolveArgs& a, int n_blocks, hipStream_t s, bool fp64_iters, int pfix);
 hipError_t launch_backward(const BackArgs& a, hipStream_t s);

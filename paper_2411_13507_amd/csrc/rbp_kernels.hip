@@ -30,6 +30,7 @@
 #include <cstdint>
 
 #include "rbp_internal.hpp"
+#include "rbp_wave.hpp"
 
 namespace rbp {
 
@@ -44,34 +45,12 @@ constexpr int kSolved = 0, kInfeasible = 1, kMaxIter = 2, kPolishFailed = 3, kNu
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
-__device__ __forceinline__ double wsum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-  return v;
-}
-__device__ __forceinline__ double wmax(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
-  return v;
-}
+__device__ __forceinline__ double wsum(double v) { return wave::sum(v); }
+__device__ __forceinline__ double wmax(double v) { return wave::max(v); }
 __device__ __forceinline__ bool wany(bool b) { return __ballot(b) != 0ull; }
-// arg-max with the lowest id on ties; result identical in every lane
-__device__ __forceinline__ void wargmax(double& v, int& id) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    const double ov = __shfl_xor(v, o, kWave);
-    const int oid = __shfl_xor(id, o, kWave);
-    if (ov > v || (ov == v && oid < id)) { v = ov; id = oid; }
-  }
-}
-__device__ __forceinline__ void wargmin(double& v, int& id) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    const double ov = __shfl_xor(v, o, kWave);
-    const int oid = __shfl_xor(id, o, kWave);
-    if (ov < v || (ov == v && oid < id)) { v = ov; id = oid; }
-  }
-}
+// arg-max / arg-min with the lowest id on ties; identical in every lane
+__device__ __forceinline__ void wargmax(double& v, int& id) { wave::argmax(v, id); }
+__device__ __forceinline__ void wargmin(double& v, int& id) { wave::argmin(v, id); }
 __device__ __forceinline__ double sel3(int c, double a, double b, double d) {
   return c == 0 ? a : (c == 1 ? b : d);
 }
@@ -299,7 +278,7 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
   // ======================================================================
   // ADMM in precision Real
   // ======================================================================
-  const Real rho = Real(A.rho), alpha = Real(A.alpha);
+  const Real rho = Real(A.rho), alpha = Real(A.alpha), irho = Real(1) / Real(A.rho);
   // face Gram (3x3 symmetric) of unit face normals
   double g00, g01, g02, g11, g12, g22;
   {
@@ -426,7 +405,7 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
   }
   auto upd = [&](Real& z, Real& y, Real zh, Real lo, Real hi) {
     const Real zrl = alpha * zh + (Real(1) - alpha) * z;
-    Real zn = zrl + y / rho;
+    Real zn = zrl + y * irho;
     zn = zn < lo ? lo : (zn > hi ? hi : zn);
     y += rho * (zrl - zn);
     z = zn;
@@ -651,7 +630,7 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
   auto solve_lambda = [&]() {
     double w = (lane < q) ? (L.acte[lane] - L.actc[lane]) : 0.0;
     for (int k = 0; k < q; ++k) {
-      const double wk = __shfl(w, k, kWave) / L.Rm[k * N + k];
+      const double wk = wave::bcast(w, k) / L.Rm[k * N + k];
       if (lane == k) w = wk;
       else if (lane > k && lane < q) w -= L.Rm[k * N + lane] * wk;
     }
@@ -663,7 +642,7 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
       u -= w;
     }
     for (int k = q - 1; k >= 0; --k) {
-      const double lk = __shfl(u, k, kWave) / L.Rm[k * N + k];
+      const double lk = wave::bcast(u, k) / L.Rm[k * N + k];
       if (lane == k) u = lk;
       else if (lane < k) u -= L.Rm[lane * N + k] * lk;
     }
@@ -684,7 +663,7 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
     for (int sl = 0; sl < 2; ++sl)
       if (sc_r[sl] > 0.0f && double(sc_r[sl]) > best) { best = sc_r[sl]; key = 2 * (RB + lane + kWave * sl) + 1; }
     wargmax(best, key);
-    if (!(best > 0.0)) break;
+    if (!(best > 0.0) || key < 0 || (key >> 1) >= m) break;
     const int id = key >> 1, side = (key & 1) ? 1 : -1;
     // owner clears its proposal and publishes the full-row bound and constant
     {
@@ -802,7 +781,7 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
     double dummy;
     eval_rows(best, key, dummy, false);
     if (!(best > 0.0)) { status = kSolved; break; }
-    if (steps >= max_steps) { status = kPolishFailed; break; }
+    if (steps >= max_steps || key < 0 || (key >> 1) >= m) { status = kPolishFailed; break; }
     const int id = key >> 1, side = (key & 1) ? 1 : -1;
     // owner publishes violation, full-row bound and constant
     {
@@ -845,7 +824,7 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
       // r = R^-1 c
       double rv = (lane < q) ? L.vC[lane] : 0.0;
       for (int k = q - 1; k >= 0; --k) {
-        const double rk = __shfl(rv, k, kWave) / L.Rm[k * N + k];
+        const double rk = wave::bcast(rv, k) / L.Rm[k * N + k];
         if (lane == k) rv = rk;
         else if (lane < k) rv -= L.Rm[lane * N + k] * rk;
       }
@@ -996,32 +975,16 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
   }
 }
 
-// PFIX = 3..9: every instance of the launch has that degree; PFIX = 0: mixed
-// degrees, dispatched per instance.
-template <typename Real, int PFIX>
+// One launch per degree P: block b solves order[inst_base + b]; instances
+// are grouped by degree in the work order.
+template <typename Real, int P>
 __global__ __launch_bounds__(64) void solve_kernel(SolveArgs A) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
   const int b = blockIdx.x + A.inst_base;
   if (b >= A.N) return;
   const int inst = A.order ? A.order[b] : b;
-  const int p = A.degree[inst];
-  if (PFIX != 0) {
-    if (p == PFIX) solve_instance<(PFIX ? PFIX : 3), Real>(A, inst, smem);
-    else if (threadIdx.x == 0) A.status_out[inst] = kInvalid;
-    return;
-  }
-  switch (p) {
-    case 3: solve_instance<3, Real>(A, inst, smem); break;
-    case 4: solve_instance<4, Real>(A, inst, smem); break;
-    case 5: solve_instance<5, Real>(A, inst, smem); break;
-    case 6: solve_instance<6, Real>(A, inst, smem); break;
-    case 7: solve_instance<7, Real>(A, inst, smem); break;
-    case 8: solve_instance<8, Real>(A, inst, smem); break;
-    case 9: solve_instance<9, Real>(A, inst, smem); break;
-    default:
-      if (threadIdx.x == 0) A.status_out[inst] = kInvalid;
-      break;
-  }
+  if (A.degree[inst] == P) solve_instance<P, Real>(A, inst, smem);
+  else if (threadIdx.x == 0) A.status_out[inst] = kInvalid;
 }
 
 // ==========================================================================
@@ -1135,7 +1098,7 @@ __device__ void backward_instance(const BackArgs& A, const int inst, char* smem)
   __syncthreads();
   double om = cv;
   for (int k = q - 1; k >= 0; --k) {
-    const double ok = __shfl(om, k, kWave) / L.Rm[k * N + k];
+    const double ok = wave::bcast(om, k) / L.Rm[k * N + k];
     if (lane == k) om = ok;
     else if (lane < k) om -= L.Rm[lane * N + k] * ok;
   }
@@ -1209,7 +1172,7 @@ __global__ __launch_bounds__(64) void backward_kernel(BackArgs A) {
 
 }  // namespace
 
-LdsDims make_dims(int pmax, int r_cap, int nf_cap) {
+LdsDims make_dims(int pmax, int r_cap, int nf_cap, int real_bytes) {
   LdsDims d{};
   d.nmax = 3 * (pmax - 1);
   d.ncol = 3 * (pmax + 1);
@@ -1229,16 +1192,17 @@ LdsDims make_dims(int pmax, int r_cap, int nf_cap) {
   d.o_actid = take(d.nmax * 4);
   d.o_actside = take(d.nmax * 4);
   d.o_region = o;
-  // iteration scratch sized for 8-byte reals (covers both precisions)
+  // iteration scratch in the precision of the iterations
   const int hs = ((d.r_cap + 3) & ~3) + 4;
+  const int rb = real_bytes;
   int a = d.o_region;
   auto take_r = [&](int bytes) { const int at = a; a += (bytes + 15) & ~15; return at; };
-  d.o_Hf = take_r(d.nmax * hs * 8);
-  d.o_Aff = take_r(d.nf_cap * 4 * 8);
-  d.o_vbuf = take_r(d.m_cap * 8);
-  d.o_xb1 = take_r(d.nmax * 8);
-  d.o_xb2 = take_r(d.nmax * 8);
-  d.o_Kx = take_r(d.nmax * d.nmax * 8);
+  d.o_Hf = take_r(d.nmax * hs * rb);
+  d.o_Aff = take_r(d.nf_cap * 4 * rb);
+  d.o_vbuf = take_r(d.m_cap * rb);
+  d.o_xb1 = take_r(d.nmax * rb);
+  d.o_xb2 = take_r(d.nmax * rb);
+  d.o_Kx = take_r(d.nmax * d.nmax * rb);
   int b = d.o_region;
   auto take_p = [&](int bytes) { const int at = b; b += (bytes + 15) & ~15; return at; };
   d.o_Q1 = take_p(d.nmax * d.nmax * 8);
@@ -1268,7 +1232,7 @@ static void launch_solve_t(const SolveArgs& a, int n_blocks, hipStream_t s, int 
     case 7: hipLaunchKernelGGL((solve_kernel<Real, 7>), g, blk, sh, s, a); break;
     case 8: hipLaunchKernelGGL((solve_kernel<Real, 8>), g, blk, sh, s, a); break;
     case 9: hipLaunchKernelGGL((solve_kernel<Real, 9>), g, blk, sh, s, a); break;
-    default: hipLaunchKernelGGL((solve_kernel<Real, 0>), g, blk, sh, s, a); break;
+    default: break;
   }
 }
 

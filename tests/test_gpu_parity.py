@@ -187,3 +187,43 @@ def test_maximum_sizes(gpu_available):
     b = gen.from_instances(insts)
     _, out = gpu_solve(b)
     check(b, out, label="max-size")
+
+
+def test_graph_capture_replays_match_eager(gpu_available):
+    """solve + backward captured in one graph on torch's stream; every replay
+    (with eager work and synchronisations in between) must equal the eager
+    results bitwise."""
+    from paper_2411_13507_amd.api import SegmentBatchGPU
+    b = gen.gen_cfg2(indices=range(160))
+    gb = SegmentBatchGPU(b)
+    dev = gb.device
+    x0 = torch.as_tensor(b.x0, device=dev)
+    goal = torch.as_tensor(b.goal, device=dev)
+    gP = torch.as_tensor(np.random.default_rng(5).standard_normal(3 * gb.points_total), device=dev)
+    gC = torch.ones(b.n, dtype=torch.float64, device=dev)
+    out = gb.alloc_outputs()
+    gb.solve(x0, goal, out=out)
+    gr = gb.backward(gP, gC)
+    torch.cuda.synchronize()
+    ref = [t.clone() for t in (out.P, out.cost, out.status, out.kkt, gr.x0, gr.goal, gr.b_inst)]
+    side = torch.cuda.Stream(device=dev)
+    side.wait_stream(torch.cuda.current_stream(dev))
+    with torch.cuda.stream(side):
+        gb.solve(x0, goal, out=out)
+        gb.backward(gP, gC, out=gr)
+    torch.cuda.current_stream(dev).wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        gb.solve(x0, goal, out=out)
+        gb.backward(gP, gC, out=gr)
+    for rep in range(4):
+        for t in (out.P, out.cost, out.kkt, gr.x0, gr.goal, gr.b_inst):
+            t.fill_(-7.0)
+        graph.replay()
+        torch.cuda.synchronize()
+        got = (out.P, out.cost, out.status, out.kkt, gr.x0, gr.goal, gr.b_inst)
+        for a, r in zip(got, ref):
+            assert torch.equal(torch.nan_to_num(a, nan=1.5), torch.nan_to_num(r, nan=1.5)), rep
+        # eager work between replays
+        gb.solve(x0 + 0.0, goal, out=gb.alloc_outputs())
+        torch.cuda.synchronize()
