@@ -178,6 +178,65 @@ int rbp_backward(rbp_batch* batch, const double* grad_P, const double* grad_cost
  * batch's last stream first. */
 void rbp_destroy_batch(rbp_batch* batch);
 
+/*
+ * Multi-segment paths.  A path is S segments of one degree (7) and duration T
+ * joined with continuous position, velocity and acceleration (equal
+ * durations: C0, C1 and C2 conditions on the control points); start and goal
+ * pinned.  Segment s keeps its control points in polytope poly_idx[s] and
+ * satisfies its reachable rows  H_s vec(P^s) <= h0_s + G_s x0_s,  where x0_s is
+ * the path's start state for the first segment and the join state
+ * (P^s_0, p/T (P^s_1 - P^s_0)) for the others.  Device pointers throughout.
+ */
+#define RBP_CHAIN_DEGREE 7
+#define RBP_CHAIN_MAX_SEGMENTS 12
+
+typedef struct rbp_chain_desc {
+  int32_t n_chains;           /* N >= 0                                          */
+  int32_t n_poly;             /* polytopes in the table                          */
+  int32_t degree;             /* RBP_CHAIN_DEGREE                                */
+  int32_t reserved;           /* 0                                               */
+  double T;                   /* segment duration, > 0                           */
+  double vmax, amax;          /* > 0                                             */
+  const int64_t* seg_off;     /* [N+1] path c owns segments seg_off[c]..seg_off[c+1]-1,
+                                 1..RBP_CHAIN_MAX_SEGMENTS each                   */
+  const int32_t* poly_off;    /* [n_poly+1] as in rbp_problem_desc               */
+  const double* A_face;       /* [F][3]                                          */
+  const double* b_face;       /* [F]                                             */
+  const int32_t* poly_idx;    /* [n_seg] polytope of each segment                */
+  const int64_t* reach_off;   /* [n_seg+1] reachable-row offsets, 0..128 rows    */
+  const int64_t* H_off;       /* [n_seg+1] element offsets, r x 3(p+1) each      */
+  const double* H;
+  const double* h0;           /* [R]                                             */
+  const double* G;            /* [R][6]                                          */
+} rbp_chain_desc;
+
+typedef struct rbp_chains rbp_chains;
+
+/* Validates (index arrays copied to the host, stream synchronised) and builds
+ * a path batch.  Errors as rbp_build_batch; degree other than 7 or more than
+ * RBP_CHAIN_MAX_SEGMENTS segments is RBP_E_SHAPE. */
+int rbp_build_chains(const rbp_chain_desc* desc, hipStream_t stream, rbp_chains** out);
+
+/* points_total = sum over paths of S (p+1): P_out holds 3 points_total
+ * doubles, path c at 3 (p+1) seg_off[c]; faces_total is 0. */
+int rbp_chains_get_sizes(const rbp_chains* chains, rbp_batch_sizes* out);
+
+/*
+ * Forward pass over all paths: FP32 ADMM warm start with a banded KKT matrix
+ * in LDS, FP64 dual active-set polish with banded Cholesky solves.
+ *   x0 [N][6], goal [N][3]; opts as for rbp_solve_batch (plain and
+ *   store_for_backward are ignored);
+ *   P_out [3 points_total]: the control points of every segment (NaN unless
+ *   SOLVED); cost_out, status_out, kkt_out [N]; iters_out [N][2] or NULL.
+ * Errors: RBP_E_INVALID, RBP_E_DEVICE.
+ */
+int rbp_solve_chains(rbp_chains* chains, const double* x0, const double* goal, const rbp_solve_opts* opts,
+                     double* P_out, double* cost_out, int32_t* status_out, double* kkt_out,
+                     int32_t* iters_out, hipStream_t stream);
+
+/* Releases a path batch (no-op for NULL). */
+void rbp_destroy_chains(rbp_chains* chains);
+
 /* Static string for a call result or per-instance status code. */
 const char* rbp_status_string(int code);
 

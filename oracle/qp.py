@@ -62,10 +62,8 @@ def phase1(A, u, E, e, y_bound: float, tau: float = TAU) -> Phase1:
     out = Phase1(s=s, y=None)
     if s < 0:
         y = res.x[:n].copy()
-        # put the pinned coordinates exactly on their values
-        for r in range(E.shape[0]):
-            j = int(np.argmax(np.abs(E[r])))
-            y[j] = e[r] / E[r, j]
+        # project onto {E y = e} so the equalities hold to rounding
+        y -= E.T @ np.linalg.solve(E @ E.T, E @ y - e)
         viol = float(np.max((An @ y - un)))
         out.y = y
         out.feasible = True
@@ -114,6 +112,18 @@ def _eqp(Q2, A, E, e, u, W):
     return sol[:n], sol[n:]
 
 
+def initial_working_set(A, u, E, y0) -> List[int]:
+    """Rows tight at the phase-1 point, kept linearly independent of the
+    equality rows and of each other (none when the point is interior)."""
+    slack = u - A @ y0
+    W0: List[int] = []
+    for i in np.where(slack <= 1e-12 * (1 + np.abs(u)))[0]:
+        C = np.vstack([E, A[W0 + [int(i)]]])
+        if np.linalg.matrix_rank(C) == C.shape[0]:
+            W0.append(int(i))
+    return W0
+
+
 def active_set(Q, A, u, E, e, y0, W0=(), max_iter: Optional[int] = None) -> QPResult:
     """Primal active-set method (N&W Alg. 16.3) for min y^T Q y, A y <= u,
     E y = e, from a feasible ``y0`` with working set ``W0`` (inequality rows
@@ -131,14 +141,14 @@ def active_set(Q, A, u, E, e, y0, W0=(), max_iter: Optional[int] = None) -> QPRe
         x, lam = _eqp(Q2, A, E, e, u, W)
         p = x - y
         pn = np.max(np.abs(p))
-        if pn <= 1e-12 * (1.0 + np.max(np.abs(y))):
+        if pn <= 1e-10 * (1.0 + np.max(np.abs(y))):
             alpha, block = 1.0, -1
         else:
             Ap = A @ p
             slack = u - A @ y
             alpha, block = 1.0, -1
             inW = np.zeros(m, bool); inW[W] = True
-            cand = np.where((~inW) & (Ap > 1e-14 * anorm * pn))[0]
+            cand = np.where((~inW) & (Ap > 1e-12 * anorm * pn))[0]
             if cand.size:
                 ratios = np.maximum(slack[cand], 0.0) / Ap[cand]
                 rmin = ratios.min()

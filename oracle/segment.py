@@ -55,14 +55,7 @@ def solve(inst: dict, tau: float = _qp.TAU) -> SegmentResult:
         st = _qp.INFEASIBLE if ph.certified else _qp.UNCERTIFIED
         return SegmentResult(st, ph.s, ph.certified, np.full((q.p + 1, 3), np.nan), np.inf,
                              None, None, None, {}, q)
-    # working set at the phase-1 point: rows tight there (none when strictly feasible)
-    slack = q.u - q.A @ ph.y
-    tight = [int(i) for i in np.where(slack <= 1e-12 * (1 + np.abs(q.u)))[0]]
-    W0 = []
-    for i in tight:
-        C = np.vstack([q.E, q.A[W0 + [i]]])
-        if np.linalg.matrix_rank(C) == C.shape[0]:
-            W0.append(i)
+    W0 = _qp.initial_working_set(q.A, q.u, q.E, ph.y)
     r = _qp.active_set(q.Q, q.A, q.u, q.E, q.e, ph.y, W0)
     if r.status == _qp.SOLVED:
         st = _qp.SOLVED if ph.certified else _qp.UNCERTIFIED

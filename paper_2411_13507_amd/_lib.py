@@ -14,6 +14,7 @@ SOLVED, INFEASIBLE, MAXITER, POLISH_FAILED, NUMERICAL, INVALID_INPUT = 0, 1, 2, 
 EXPORTED = (
     "rbp_default_opts", "rbp_build_batch", "rbp_batch_get_sizes", "rbp_solve_batch",
     "rbp_backward", "rbp_destroy_batch", "rbp_status_string",
+    "rbp_build_chains", "rbp_chains_get_sizes", "rbp_solve_chains", "rbp_destroy_chains",
 )
 
 _p = ctypes.c_void_p
@@ -25,6 +26,15 @@ class ProblemDesc(ctypes.Structure):
         ("degree", _p), ("T", _p), ("poly_off", _p), ("A_face", _p), ("b_face", _p),
         ("poly_idx", _p), ("reach_off", _p), ("H_off", _p), ("H", _p), ("h0", _p), ("G", _p),
         ("vmax", ctypes.c_double), ("amax", ctypes.c_double),
+    ]
+
+
+class ChainDesc(ctypes.Structure):
+    _fields_ = [
+        ("n_chains", ctypes.c_int32), ("n_poly", ctypes.c_int32), ("degree", ctypes.c_int32),
+        ("reserved", ctypes.c_int32), ("T", ctypes.c_double), ("vmax", ctypes.c_double),
+        ("amax", ctypes.c_double), ("seg_off", _p), ("poly_off", _p), ("A_face", _p), ("b_face", _p),
+        ("poly_idx", _p), ("reach_off", _p), ("H_off", _p), ("H", _p), ("h0", _p), ("G", _p),
     ]
 
 
@@ -71,6 +81,14 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.rbp_backward.restype = ctypes.c_int
     L.rbp_destroy_batch.argtypes = [_p]
     L.rbp_destroy_batch.restype = None
+    L.rbp_build_chains.argtypes = [ctypes.POINTER(ChainDesc), _p, ctypes.POINTER(_p)]
+    L.rbp_build_chains.restype = ctypes.c_int
+    L.rbp_chains_get_sizes.argtypes = [_p, ctypes.POINTER(BatchSizes)]
+    L.rbp_chains_get_sizes.restype = ctypes.c_int
+    L.rbp_solve_chains.argtypes = [_p, _p, _p, ctypes.POINTER(SolveOpts), _p, _p, _p, _p, _p, _p]
+    L.rbp_solve_chains.restype = ctypes.c_int
+    L.rbp_destroy_chains.argtypes = [_p]
+    L.rbp_destroy_chains.restype = None
     L.rbp_status_string.argtypes = [ctypes.c_int]
     L.rbp_status_string.restype = ctypes.c_char_p
     _LIB = L

@@ -152,3 +152,77 @@ class SegmentBatchGPU:
     def P_of(self, P_flat: torch.Tensor, i: int) -> torch.Tensor:
         a, b = self.pt_off[i], self.pt_off[i + 1]
         return P_flat[3 * a:3 * b].view(-1, 3)
+
+
+class ChainBatchGPU:
+    """A built batch of multi-segment paths (degree-7 segments joined with
+    continuous position, velocity and acceleration) on one GPU.
+
+    ``problem`` has the array attributes of the C path description
+    (seg_off, poly_off, A_face, b_face, poly_idx, reach_off, H_off, H, h0, G)
+    and scalars degree, T, vmax, amax, e.g. ``workloads.gen.ChainBatch``.
+    """
+
+    def __init__(self, problem, device: str = "cuda"):
+        if not torch.cuda.is_available():
+            raise _lib.RbpError("no GPU visible: the path solver runs only on the GPU")
+        self.device = torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device(self.device.type, torch.cuda.current_device())
+        L = _lib.load()
+        f64, i32, i64 = torch.float64, torch.int32, torch.int64
+        d = self.device
+        self.seg_off = _dev(problem.seg_off, i64, d)
+        self.poly_off = _dev(problem.poly_off, i32, d)
+        self.A_face = _dev(problem.A_face, f64, d)
+        self.b_face = _dev(problem.b_face, f64, d)
+        self.poly_idx = _dev(problem.poly_idx, i32, d)
+        self.reach_off = _dev(problem.reach_off, i64, d)
+        self.H_off = _dev(problem.H_off, i64, d)
+        self.H = _dev(problem.H, f64, d)
+        self.h0 = _dev(problem.h0, f64, d)
+        self.G = _dev(np.asarray(problem.G).reshape(-1), f64, d)
+        self.N = int(self.seg_off.numel()) - 1
+        self.degree = int(problem.degree)
+        desc = _lib.ChainDesc(
+            self.N, int(self.poly_off.numel()) - 1, self.degree, 0, float(problem.T), float(problem.vmax),
+            float(problem.amax), _ptr(self.seg_off), _ptr(self.poly_off), _ptr(self.A_face), _ptr(self.b_face),
+            _ptr(self.poly_idx), _ptr(self.reach_off), _ptr(self.H_off), _ptr(self.H), _ptr(self.h0), _ptr(self.G))
+        h = ctypes.c_void_p()
+        with torch.cuda.device(d):
+            _lib.check(L.rbp_build_chains(ctypes.byref(desc), _stream_handle(d), ctypes.byref(h)), "rbp_build_chains")
+        self._h = h
+        sz = _lib.BatchSizes()
+        _lib.check(L.rbp_chains_get_sizes(h, ctypes.byref(sz)), "rbp_chains_get_sizes")
+        self.points_total = int(sz.points_total)
+        self.seg_off_host = np.asarray(problem.seg_off, np.int64)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            _lib.load().rbp_destroy_chains(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, x0: torch.Tensor, goal: torch.Tensor, opts: Optional[_lib.SolveOpts] = None,
+              out: Optional[SolveResult] = None) -> SolveResult:
+        d, N = self.device, self.N
+        o = out or SolveResult(
+            P=torch.empty(3 * self.points_total, dtype=torch.float64, device=d),
+            cost=torch.empty(N, dtype=torch.float64, device=d),
+            status=torch.empty(N, dtype=torch.int32, device=d),
+            kkt=torch.empty(N, dtype=torch.float64, device=d),
+            iters=torch.zeros((N, 2), dtype=torch.int32, device=d))
+        for t, shape in ((x0, (N, 6)), (goal, (N, 3))):
+            if t.dtype != torch.float64 or not t.is_contiguous() or tuple(t.shape) != shape or t.device != d:
+                raise ValueError(f"expected contiguous float64 {shape} on {d}")
+        opts = opts or _lib.default_opts()
+        rc = _lib.load().rbp_solve_chains(self._h, _ptr(x0), _ptr(goal), ctypes.byref(opts), _ptr(o.P),
+                                          _ptr(o.cost), _ptr(o.status), _ptr(o.kkt), _ptr(o.iters),
+                                          _stream_handle(d))
+        _lib.check(rc, "rbp_solve_chains")
+        return o

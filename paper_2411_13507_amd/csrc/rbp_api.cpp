@@ -298,6 +298,144 @@ int rbp_backward(rbp_batch* b, const double* grad_P, const double* grad_cost, do
   return RBP_OK;
 }
 
+struct rbp_chains {
+  int device = 0;
+  rbp_chain_desc desc{};
+  int32_t N = 0, s_max = 1, nf_max = 1, r_max = 0;
+  int64_t pt_total = 0;
+  int32_t* d_order = nullptr;
+  hipStream_t last_stream = nullptr;
+};
+
+namespace {
+std::vector<int> g_chain_const_done;
+int ensure_chain_constants(int device) {
+  std::lock_guard<std::mutex> lk(g_const_mu);
+  if (std::find(g_chain_const_done.begin(), g_chain_const_done.end(), device) != g_chain_const_done.end())
+    return RBP_OK;
+  if (rbp::upload_chain_constants(device) != hipSuccess) return RBP_E_DEVICE;
+  g_chain_const_done.push_back(device);
+  return RBP_OK;
+}
+constexpr int kChainQCap = 48;   // working-set capacity of the path polish
+}  // namespace
+
+int rbp_build_chains(const rbp_chain_desc* d, hipStream_t stream, rbp_chains** out) {
+  if (!d || !out) return RBP_E_INVALID;
+  *out = nullptr;
+  const int32_t N = d->n_chains;
+  if (N < 0 || d->n_poly < 0 || !(d->T > 0.0) || !(d->vmax > 0.0) || !(d->amax > 0.0)) return RBP_E_INVALID;
+  if (d->degree != RBP_CHAIN_DEGREE) return RBP_E_SHAPE;
+  if (N > 0 && (!d->seg_off || !d->poly_off || !d->A_face || !d->b_face || !d->poly_idx || !d->reach_off ||
+                !d->H_off || !d->H || !d->h0 || !d->G))
+    return RBP_E_INVALID;
+  if (N > 0 && d->n_poly < 1) return RBP_E_SHAPE;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return RBP_E_DEVICE;
+  if (int rc = ensure_chain_constants(dev)) return rc;
+  std::vector<int64_t> soff;
+  int rc = RBP_OK;
+  if (N > 0) {
+    if ((rc = d2h(soff, d->seg_off, size_t(N) + 1, stream))) return rc;
+    if (hipStreamSynchronize(stream) != hipSuccess) return RBP_E_DEVICE;
+    if (soff[0] != 0) return RBP_E_SHAPE;
+  }
+  const int64_t nseg = N > 0 ? soff[N] : 0;
+  std::vector<int32_t> pidx, poff;
+  std::vector<int64_t> roff, hoff;
+  if (N > 0) {
+    if ((rc = d2h(pidx, d->poly_idx, size_t(nseg), stream)) || (rc = d2h(poff, d->poly_off, size_t(d->n_poly) + 1, stream)) ||
+        (rc = d2h(roff, d->reach_off, size_t(nseg) + 1, stream)) || (rc = d2h(hoff, d->H_off, size_t(nseg) + 1, stream)))
+      return rc;
+    if (hipStreamSynchronize(stream) != hipSuccess) return RBP_E_DEVICE;
+  }
+  auto* c = new (std::nothrow) rbp_chains();
+  if (!c) return RBP_E_ALLOC;
+  c->device = dev;
+  c->desc = *d;
+  c->N = N;
+  const int p = d->degree;
+  std::vector<int32_t> order(N);
+  if (N > 0) {
+    if (poff[0] != 0 || roff[0] != 0 || hoff[0] != 0) { delete c; return RBP_E_SHAPE; }
+    for (int j = 0; j < d->n_poly; ++j) {
+      const int nf = poff[j + 1] - poff[j];
+      if (nf < 1 || nf > RBP_MAX_FACES) { delete c; return RBP_E_SHAPE; }
+    }
+    for (int i = 0; i < N; ++i) {
+      const int64_t S = soff[i + 1] - soff[i];
+      if (S < 1 || S > RBP_CHAIN_MAX_SEGMENTS) { delete c; return RBP_E_SHAPE; }
+      c->s_max = std::max<int32_t>(c->s_max, int32_t(S));
+    }
+    for (int64_t s = 0; s < nseg; ++s) {
+      if (pidx[s] < 0 || pidx[s] >= d->n_poly) { delete c; return RBP_E_SHAPE; }
+      const int64_t r = roff[s + 1] - roff[s];
+      if (r < 0 || r > RBP_MAX_REACH || hoff[s + 1] - hoff[s] != r * 3 * (p + 1)) { delete c; return RBP_E_SHAPE; }
+      c->r_max = std::max<int32_t>(c->r_max, int32_t(r));
+      c->nf_max = std::max<int32_t>(c->nf_max, poff[pidx[s] + 1] - poff[pidx[s]]);
+    }
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+      return soff[a + 1] - soff[a] > soff[b + 1] - soff[b];
+    });
+  }
+  c->pt_total = int64_t(p + 1) * nseg;
+  if ((rc = dalloc(&c->d_order, size_t(std::max(N, 1))))) { delete c; return rc; }
+  if (N > 0 && (hipMemcpyAsync(c->d_order, order.data(), size_t(N) * 4, hipMemcpyHostToDevice, stream) ||
+                hipStreamSynchronize(stream))) {
+    (void)hipFree(c->d_order);
+    delete c;
+    return RBP_E_DEVICE;
+  }
+  c->last_stream = stream;
+  *out = c;
+  return RBP_OK;
+}
+
+int rbp_chains_get_sizes(const rbp_chains* c, rbp_batch_sizes* out) {
+  if (!c || !out) return RBP_E_INVALID;
+  out->n_instances = c->N;
+  out->max_degree = c->desc.degree;
+  out->points_total = c->pt_total;
+  out->faces_total = 0;
+  return RBP_OK;
+}
+
+int rbp_solve_chains(rbp_chains* c, const double* x0, const double* goal, const rbp_solve_opts* opts_in,
+                     double* P_out, double* cost_out, int32_t* status_out, double* kkt_out, int32_t* iters_out,
+                     hipStream_t stream) {
+  if (!c) return RBP_E_INVALID;
+  rbp_solve_opts o;
+  rbp_default_opts(&o);
+  if (opts_in) o = *opts_in;
+  if (o.admm_iters < 0 || !(o.rho > 0.0f) || !(o.alpha > 0.0f) || !(o.alpha < 2.0f) || o.max_polish_steps < 0 ||
+      !(o.feas_tol > 0.0) || !(o.kkt_tol > 0.0))
+    return RBP_E_INVALID;
+  if (c->N == 0) return RBP_OK;
+  if (!x0 || !goal || !P_out || !cost_out || !status_out || !kkt_out) return RBP_E_INVALID;
+  const rbp_chain_desc& d = c->desc;
+  rbp::ChainArgs a{};
+  a.N = c->N; a.P = d.degree; a.T = d.T; a.vmax = d.vmax; a.amax = d.amax;
+  a.seg_off = d.seg_off; a.poly_off = d.poly_off; a.A_face = d.A_face; a.b_face = d.b_face;
+  a.poly_idx = d.poly_idx; a.reach_off = d.reach_off; a.H_off = d.H_off; a.H = d.H; a.h0 = d.h0; a.G = d.G;
+  a.x0 = x0; a.goal = goal; a.order = c->d_order;
+  a.P_out = P_out; a.cost_out = cost_out; a.status_out = status_out; a.kkt_out = kkt_out; a.iters_out = iters_out;
+  a.admm_iters = o.admm_iters; a.rho = o.rho; a.alpha = o.alpha; a.max_steps = o.max_polish_steps;
+  a.feas_tol = o.feas_tol; a.kkt_tol = o.kkt_tol;
+  a.dims = rbp::make_chain_dims(d.degree, c->s_max, c->nf_max, c->r_max, kChainQCap);
+  if (rbp::launch_chains(a, stream) != hipSuccess) return RBP_E_DEVICE;
+  c->last_stream = stream;
+  return RBP_OK;
+}
+
+void rbp_destroy_chains(rbp_chains* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  if (c->last_stream) (void)hipStreamSynchronize(c->last_stream);
+  if (c->d_order) (void)hipFree(c->d_order);
+  delete c;
+}
+
 void rbp_destroy_batch(rbp_batch* b) {
   if (!b) return;
   (void)hipSetDevice(b->device);

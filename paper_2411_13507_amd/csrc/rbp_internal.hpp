@@ -103,7 +103,49 @@ struct BackArgs {
   LdsDims dims;
 };
 
+// ---- multi-segment paths (rbp_chain.hip)
+struct ChainDims {
+  int s_cap, nf_cap, r_cap, q_cap, nf_pts_cap, ng_cap, n_cap, m_cap;
+  int o_segi, o_seg64, o_Af, o_bfs, o_fan, o_rb, o_rn, o_Pseg, o_gfull, o_G1b, o_L1b, o_qv, o_x, o_scal,
+      o_cand, o_bits;
+  int o_Kb, o_zr, o_yr, o_accp, o_Pf, o_xt, o_Cs, o_Wm;          // ADMM part of the region
+  int o_LS, o_beta, o_acte, o_u, o_cvec, o_actid;                 // polish part of the region
+  int bytes;
+};
+
+struct ChainArgs {
+  int N;
+  int P;
+  double T, vmax, amax;
+  const int64_t* seg_off;
+  const int32_t* poly_off;
+  const double* A_face;
+  const double* b_face;
+  const int32_t* poly_idx;
+  const int64_t* reach_off;
+  const int64_t* H_off;
+  const double* H;
+  const double* h0;
+  const double* G;
+  const double* x0;
+  const double* goal;
+  const int32_t* order;
+  double* P_out;
+  double* cost_out;
+  int32_t* status_out;
+  double* kkt_out;
+  int32_t* iters_out;
+  int admm_iters;
+  float rho, alpha;
+  int max_steps;
+  double feas_tol, kkt_tol;
+  ChainDims dims;
+};
+
 LdsDims make_dims(int pmax, int r_cap, int nf_cap, int real_bytes);
+ChainDims make_chain_dims(int p, int s_cap, int nf_cap, int r_cap, int q_cap);
+hipError_t upload_chain_constants(int device);
+hipError_t launch_chains(const ChainArgs& a, hipStream_t s);
 hipError_t upload_constants(int device);
 hipError_t launch_solve(const SolveArgs& a, int n_blocks, hipStream_t s, bool fp64_iters, int pfix);
 hipError_t launch_backward(const BackArgs& a, hipStream_t s);

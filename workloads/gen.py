@@ -39,6 +39,8 @@ AMAX = 5.0
 # reachable-row offsets for the cluttered-environment batches: shifted from
 # U[1,3] so that about 30% of the edges come out infeasible
 H0_CLUTTER = (1.3, 3.3)
+# reachable-row offsets of the chain segments
+H0_CHAIN = (2.0, 4.0)
 
 
 def instance_rng(cfg: int, i: int) -> np.random.Generator:
@@ -394,3 +396,110 @@ def _empty(name):
                         poly_idx=np.zeros(0, np.int32), reach_off=np.zeros(1, np.int64),
                         H_off=np.zeros(1, np.int64), H=np.zeros(0), h0=np.zeros(0), G=np.zeros((0, 6)),
                         x0=np.zeros((0, 6)), goal=np.zeros((0, 3)))
+
+
+# ---------------------------------------------------------------------------
+# workload 3: multi-segment chains through a corridor of overlapping polytopes
+# ---------------------------------------------------------------------------
+
+@dataclass
+class ChainBatch:
+    """N chains; chain c has segments seg_off[c]..seg_off[c+1]-1.  Segment s
+    uses polytope poly_idx[s] of the shared table and reachable rows
+    reach_off[s]..reach_off[s+1]-1 (coefficients at H_off[s], 3(p+1) columns)."""
+
+    name: str
+    degree: int
+    T: float
+    vmax: float
+    amax: float
+    seg_off: np.ndarray        # int64 [N+1]
+    poly_off: np.ndarray       # int32 [n_poly+1]
+    A_face: np.ndarray         # [F,3]
+    b_face: np.ndarray         # [F]
+    poly_idx: np.ndarray       # int32 [n_seg]
+    reach_off: np.ndarray      # int64 [n_seg+1]
+    H_off: np.ndarray          # int64 [n_seg+1]
+    H: np.ndarray
+    h0: np.ndarray
+    G: np.ndarray              # [R, 6]
+    x0: np.ndarray             # [N, 6] start state of the chain
+    goal: np.ndarray           # [N, 3]
+
+    @property
+    def n(self) -> int:
+        return int(self.seg_off.shape[0] - 1)
+
+    def chain(self, c: int) -> dict:
+        s0, s1 = int(self.seg_off[c]), int(self.seg_off[c + 1])
+        p = self.degree
+        segs = []
+        for s in range(s0, s1):
+            j = int(self.poly_idx[s])
+            f0, f1 = int(self.poly_off[j]), int(self.poly_off[j + 1])
+            r0, r1 = int(self.reach_off[s]), int(self.reach_off[s + 1])
+            segs.append(dict(A_face=self.A_face[f0:f1].copy(), b_face=self.b_face[f0:f1].copy(),
+                             H=self.H[self.H_off[s]:self.H_off[s + 1]].reshape(r1 - r0, 3 * (p + 1)).copy(),
+                             h0=self.h0[r0:r1].copy(), G=self.G[r0:r1].copy()))
+        return dict(p=p, T=self.T, vmax=self.vmax, amax=self.amax, x0=self.x0[c].copy(),
+                    goal=self.goal[c].copy(), segments=segs)
+
+
+def _overlap_point(rng, A1, b1, c1, w1, A2, b2, tries=6):
+    for _ in range(tries):
+        cand = c1 + w1 * rng.uniform(-1.0, 1.0, size=(256, 3))
+        ok = _inside(A1, b1, cand) & _inside(A2, b2, cand)
+        if ok.any():
+            return cand[int(np.argmax(ok))]
+    return None
+
+
+def gen_cfg3(n: int = 8192, indices: Optional[Sequence[int]] = None, p: int = 7, r: int = 32) -> ChainBatch:
+    """Chains of S ~ U{4..12} degree-7 segments; polytope centres follow a
+    random walk with steps U[0.8, 1.5] m (a step is redrawn until consecutive
+    polytopes overlap); start inside the first polytope, goal inside the last."""
+    idx = range(n) if indices is None else indices
+    seg_off = [0]
+    polys_A, polys_b, pidx, Hs, h0s, Gs, x0s, goals = [], [], [], [], [], [], [], []
+    for i in idx:
+        rng = instance_rng(3, i)
+        S = int(rng.integers(4, 13))
+        c = rng.uniform(2.0, 8.0, size=3)
+        nf = int(rng.integers(8, 25))
+        A, b, w = _box_polytope(rng, nf, c)
+        chain = [(A, b, c, w)]
+        while len(chain) < S:
+            for _ in range(50):
+                d = rng.standard_normal(3)
+                d *= rng.uniform(0.8, 1.5) / np.linalg.norm(d)
+                c2 = chain[-1][2] + d
+                nf2 = int(rng.integers(8, 25))
+                A2, b2, w2 = _box_polytope(rng, nf2, c2)
+                if _overlap_point(rng, chain[-1][0], chain[-1][1], chain[-1][2], chain[-1][3], A2, b2) is not None:
+                    chain.append((A2, b2, c2, w2))
+                    break
+            else:
+                raise RuntimeError("corridor step not found")
+        start = _sample_in(rng, chain[0][0], chain[0][1], chain[0][2], chain[0][3])
+        goal = _sample_in(rng, chain[-1][0], chain[-1][1], chain[-1][2], chain[-1][3])
+        v0 = rng.uniform(-1.0, 1.0, size=3)
+        for (A_, b_, _, _) in chain:
+            pidx.append(len(polys_A))
+            polys_A.append(A_); polys_b.append(b_)
+            H, h0, G = _reach_block(rng, r, p, *H0_CHAIN)
+            Hs.append(H); h0s.append(h0); Gs.append(G)
+        seg_off.append(seg_off[-1] + S)
+        x0s.append(np.concatenate([start, v0])); goals.append(goal)
+    poly_off = np.zeros(len(polys_A) + 1, np.int32)
+    poly_off[1:] = np.cumsum([a.shape[0] for a in polys_A])
+    reach_off = np.zeros(len(Hs) + 1, np.int64)
+    reach_off[1:] = np.cumsum([h.shape[0] for h in Hs])
+    H_off = np.zeros(len(Hs) + 1, np.int64)
+    H_off[1:] = np.cumsum([h.size for h in Hs])
+    return ChainBatch(name="chains8k_p7", degree=p, T=T_DEFAULT, vmax=VMAX, amax=AMAX,
+                      seg_off=np.asarray(seg_off, np.int64), poly_off=poly_off,
+                      A_face=np.concatenate(polys_A), b_face=np.concatenate(polys_b),
+                      poly_idx=np.asarray(pidx, np.int32), reach_off=reach_off, H_off=H_off,
+                      H=np.concatenate([h.ravel() for h in Hs]), h0=np.concatenate(h0s),
+                      G=np.concatenate(Gs).reshape(-1, 6), x0=np.asarray(x0s).reshape(-1, 6),
+                      goal=np.asarray(goals).reshape(-1, 3))
