@@ -107,6 +107,59 @@ def cpu_baseline(b, gbar, n_sample=2000):
             "sample": f"first {n_sample} of the 50,000 edges, forward + gradients, {dt:.1f} s wall"}
 
 
+def time_launches(fn, reps, stream):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for e0, e1 in evs:
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+    torch.cuda.synchronize()
+    return float(np.median([e0.elapsed_time(e1) for e0, e1 in evs])) / 1e3
+
+
+def extra_workloads(reps=3):
+    """Forward throughput of the uneven batch (200,000 segments, degree 3-9,
+    6-40 faces, 16-128 reachable rows; one launch per degree) and of the
+    path batch (8,192 paths of 4-12 joined degree-7 segments)."""
+    import torch
+    from paper_2411_13507_amd.api import ChainBatchGPU, SegmentBatchGPU
+    from workloads import gen
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream(dev)
+    out = {}
+    b = gen.generate(2, 200_000)
+    gb = SegmentBatchGPU(b, device="cuda:0")
+    x0, goal = torch.as_tensor(b.x0, device=dev), torch.as_tensor(b.goal, device=dev)
+    res = gb.alloc_outputs()
+    t = time_launches(lambda: gb.solve(x0, goal, out=res), reps, stream)
+    st = res.status.cpu().numpy()
+    kk = res.kkt.cpu().numpy()
+    ok = int(((st == 0) & (kk <= KKT_OK)).sum() + (st == 1).sum())
+    out["uneven200k_p3to9"] = {"fwd_ms": t * 1e3, "solves_per_s": ok / t, "instances": b.n,
+                               "status_counts": np.bincount(st, minlength=6).tolist()}
+    gb.close()
+    del b, gb, res
+    c = gen.generate_chains(8192)
+    cb = ChainBatchGPU(c, device="cuda:0")
+    x0, goal = torch.as_tensor(c.x0, device=dev), torch.as_tensor(c.goal, device=dev)
+    holder = {}
+    t = time_launches(lambda: holder.__setitem__("r", cb.solve(x0, goal, out=holder.get("r"))), reps, stream)
+    r = holder["r"]
+    st = r.status.cpu().numpy()
+    kk = r.kkt.cpu().numpy()
+    ok = int(((st == 0) & (kk <= KKT_OK)).sum() + (st == 1).sum())
+    nseg = int(c.seg_off[-1])
+    out["chains8k_p7"] = {"fwd_ms": t * 1e3, "paths_per_s": ok / t, "paths": c.n, "segments": nseg,
+                          "segment_solves_per_s": ok / t * nseg / c.n,
+                          "status_counts": np.bincount(st, minlength=6).tolist(),
+                          "polish_steps_mean": float(r.iters.cpu().numpy()[:, 1].mean())}
+    cb.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,7 +169,19 @@ def main():
     ap.add_argument("--admm-iters", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a 1 GiB device-to-device copy (HBM counter calibration) and exit")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        x = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": x.numel() * 8, "copy_bytes_written": y.numel() * 8, "launches": 3}))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); instances are independent, "
               "so a multi-GPU run would shard the batch with no communication.", file=sys.stderr)
@@ -234,6 +299,10 @@ def main():
                  "s_per_1000": tp}
         pb.close()
 
+    extras = None
+    if not args.no_extras:
+        extras = extra_workloads()
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(b, gbar)
@@ -268,6 +337,7 @@ def main():
         "vs_plain": (value / plain["solves_per_s"]) if plain else None,
         "fwd_vs_plain": ((counted / t_solve) / plain["solves_per_s"]) if plain else None,
         "cpu_baseline": cpu,
+        "other_workloads": extras,
     }
     print(json.dumps(rec), flush=True)
 

@@ -227,3 +227,18 @@ def test_graph_capture_replays_match_eager(gpu_available):
         # eager work between replays
         gb.solve(x0 + 0.0, goal, out=gb.alloc_outputs())
         torch.cuda.synchronize()
+
+
+def test_autotune_picks_a_candidate_and_results_do_not_change(gpu_available, tmp_path, monkeypatch):
+    from paper_2411_13507_amd import autotune
+    monkeypatch.setattr(autotune, "CACHE", str(tmp_path / "tune.json"))
+    b = gen.gen_cfg1(indices=range(600))
+    o = autotune.tune(b, sample=600, reps=2)
+    assert (o.admm_iters, round(o.rho, 6)) in {(k, round(r, 6)) for k, r in autotune.CANDIDATES}
+    assert autotune.cached(b) is not None
+    _, tuned = gpu_solve(b, o)
+    _, default = gpu_solve(b)
+    assert np.array_equal(tuned["status"], default["status"])
+    ok = default["status"] == 0
+    assert np.nanmax(np.abs(tuned["P"] - default["P"])) <= 1e-9
+    check(b, tuned, label="autotuned")

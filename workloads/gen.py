@@ -503,3 +503,43 @@ def gen_cfg3(n: int = 8192, indices: Optional[Sequence[int]] = None, p: int = 7,
                       H=np.concatenate([h.ravel() for h in Hs]), h0=np.concatenate(h0s),
                       G=np.concatenate(Gs).reshape(-1, 6), x0=np.asarray(x0s).reshape(-1, 6),
                       goal=np.asarray(goals).reshape(-1, 3))
+
+
+def concat_chains(parts) -> ChainBatch:
+    """Join path batches (each part has its own polytopes)."""
+    first = parts[0]
+    seg_off, poly_off, pidx, reach_off, H_off = [np.zeros(1, np.int64)], [np.zeros(1, np.int64)], [], \
+        [np.zeros(1, np.int64)], [np.zeros(1, np.int64)]
+    npoly = nseg = nf_tot = nr_tot = nh_tot = 0
+    for pt in parts:
+        seg_off.append(pt.seg_off[1:] + nseg)
+        poly_off.append(pt.poly_off[1:].astype(np.int64) + nf_tot)
+        pidx.append(pt.poly_idx.astype(np.int64) + npoly)
+        reach_off.append(pt.reach_off[1:] + nr_tot)
+        H_off.append(pt.H_off[1:] + nh_tot)
+        nseg += int(pt.seg_off[-1]); npoly += len(pt.poly_off) - 1
+        nf_tot += int(pt.poly_off[-1]); nr_tot += int(pt.reach_off[-1]); nh_tot += int(pt.H_off[-1])
+    return ChainBatch(
+        name=first.name, degree=first.degree, T=first.T, vmax=first.vmax, amax=first.amax,
+        seg_off=np.concatenate(seg_off), poly_off=np.concatenate(poly_off).astype(np.int32),
+        A_face=np.concatenate([p.A_face for p in parts]), b_face=np.concatenate([p.b_face for p in parts]),
+        poly_idx=np.concatenate(pidx).astype(np.int32), reach_off=np.concatenate(reach_off),
+        H_off=np.concatenate(H_off), H=np.concatenate([p.H for p in parts]),
+        h0=np.concatenate([p.h0 for p in parts]), G=np.concatenate([p.G for p in parts]).reshape(-1, 6),
+        x0=np.concatenate([p.x0 for p in parts]), goal=np.concatenate([p.goal for p in parts]))
+
+
+def _gen_chain_chunk(idx):
+    return gen_cfg3(indices=idx)
+
+
+def generate_chains(n: int = 8192, workers: Optional[int] = None) -> ChainBatch:
+    """The path workload drawn in parallel processes (equal to the serial draw)."""
+    workers = workers or min(16, os.cpu_count() or 1)
+    if workers <= 1 or n < 256:
+        return gen_cfg3(indices=list(range(n)))
+    chunks = [list(c) for c in np.array_split(np.arange(n), workers * 4) if len(c)]
+    import multiprocessing as mp
+    with mp.get_context("fork").Pool(workers) as pool:
+        parts = pool.map(_gen_chain_chunk, chunks)
+    return concat_chains(parts)
