@@ -317,7 +317,7 @@ int ensure_chain_constants(int device) {
   g_chain_const_done.push_back(device);
   return RBP_OK;
 }
-constexpr int kChainQCap = 48;   // working-set capacity of the path polish
+constexpr int kChainQCap = 64;   // working-set capacity of the path polish (one entry per lane)
 }  // namespace
 
 int rbp_build_chains(const rbp_chain_desc* d, hipStream_t stream, rbp_chains** out) {

@@ -50,7 +50,7 @@ struct CLds {
   static constexpr int NP = P + 1, NC = 3 * (P + 1), BW = 3 * (P + 1) - 1;
   int *nf, *nr, *f0, *rowoff;
   int64_t *r0, *hb;
-  double *Af, *bfs, *rb, *Pseg, *gfull, *G1b, *L1b, *qv, *xu, *x, *scal;
+  double *Af, *bfs, *rb, *Pseg, *gfull, *G1b, *L1b, *L1r, *qv, *xu, *x, *scal;
   float *fan, *rn;
   int* cand;
   unsigned* actbits;
@@ -80,6 +80,7 @@ __device__ CLds<P> ccarve(char* s, const ChainDims& D) {
   L.gfull = (double*)(s + D.o_gfull);
   L.G1b = (double*)(s + D.o_G1b);
   L.L1b = (double*)(s + D.o_L1b);
+  L.L1r = (double*)(s + D.o_L1r);
   L.qv = (double*)(s + D.o_qv);
   L.xu = L.qv + 3 * D.nf_pts_cap;
   L.x = (double*)(s + D.o_x);
@@ -357,11 +358,16 @@ __device__ void chain_instance(const ChainArgs& A, const int ch, char* smem) {
     __syncthreads();
   }
   // banded solves with G1 (x) I3: lane = free point, 3 coordinates per lane
-  auto gsolve = [&](const double* rhs, double* out) {
-    double y0 = 0, y1 = 0, y2 = 0;
+  // G = L L^T on the points (the same banded factor for each coordinate):
+  // forward half-solve leaves y = L^-1 rhs in registers (lane = point),
+  // backward half-solve writes L^-T y; reciprocal diagonal in L1r
+  for (int i = lane; i < NF; i += kWave) L.L1r[i] = 1.0 / L.L1b[i * (P + 1)];
+  __syncthreads();
+  auto gfwd = [&](const double* rhs, double& y0, double& y1, double& y2) {
+    y0 = 0; y1 = 0; y2 = 0;
     if (lane < NF) { y0 = rhs[3 * lane]; y1 = rhs[3 * lane + 1]; y2 = rhs[3 * lane + 2]; }
     for (int i = 0; i < NF; ++i) {
-      const double dinv = 1.0 / L.L1b[i * (P + 1)];
+      const double dinv = L.L1r[i];
       const double a0 = wave::bcast(y0, i) * dinv, a1 = wave::bcast(y1, i) * dinv, a2 = wave::bcast(y2, i) * dinv;
       if (lane == i) { y0 = a0; y1 = a1; y2 = a2; }
       else if (lane > i && lane <= i + P && lane < NF) {
@@ -369,8 +375,10 @@ __device__ void chain_instance(const ChainArgs& A, const int ch, char* smem) {
         y0 -= l * a0; y1 -= l * a1; y2 -= l * a2;
       }
     }
+  };
+  auto gbwd = [&](double y0, double y1, double y2, double* out) {
     for (int i = NF - 1; i >= 0; --i) {
-      const double dinv = 1.0 / L.L1b[i * (P + 1)];
+      const double dinv = L.L1r[i];
       const double a0 = wave::bcast(y0, i) * dinv, a1 = wave::bcast(y1, i) * dinv, a2 = wave::bcast(y2, i) * dinv;
       if (lane == i) { y0 = a0; y1 = a1; y2 = a2; }
       else if (lane < i && lane >= i - P) {
@@ -380,6 +388,11 @@ __device__ void chain_instance(const ChainArgs& A, const int ch, char* smem) {
     }
     if (lane < NF) { out[3 * lane] = y0; out[3 * lane + 1] = y1; out[3 * lane + 2] = y2; }
     __syncthreads();
+  };
+  auto gsolve = [&](const double* rhs, double* out) {
+    double y0, y1, y2;
+    gfwd(rhs, y0, y1, y2);
+    gbwd(y0, y1, y2, out);
   };
   // linear term from the pinned goal: q = G1[free, goal] * dg; unconstrained minimiser
   for (int e = lane; e < n; e += kWave) {
@@ -912,17 +925,23 @@ __device__ void chain_instance(const ChainArgs& A, const int ch, char* smem) {
       double rv = ls_backward(ls_forward(cv, q), q);   // r = S^-1 c
       if (lane >= q) rv = 0.0;
       n_times(rv, L.w);                       // w = N r
-      gsolve(L.w, L.zv);                      // G^-1 w
-      for (int e = lane; e < n; e += kWave) L.zv[e] = L.u[e] - L.zv[e];
+      // d = n+ - N r; z = G^-1 d and zz = d^T G^-1 d = |L^-1 d|^2, a sum of
+      // squares that is small exactly when n+ lies in the span of N
+      for (int e = lane; e < n; e += kWave) L.zv[e] = L.np[e] - L.w[e];
       __syncthreads();
-      const double zz = nplus_dot(q, L.zv);
+      double f0, f1, f2;
+      gfwd(L.zv, f0, f1, f2);
+      const double zz = wave::sum(lane < NF ? f0 * f0 + f1 * f1 + f2 * f2 : 0.0);
+      gbwd(f0, f1, f2, L.zv);
       const double nu = nplus_dot(q, L.u);
       const double rmax = wave::max(lane < q ? fabs(rv) : 0.0);
       double t1 = __builtin_huge_val();
       int kd = lane;
       if (lane < q && rv > 1e-13 * rmax) t1 = lamr / rv;
       wave::argmin(t1, kd);
-      const bool zfull = zz > 1e-20 * fmax(nu, 1e-300) && zz > 0.0;
+      // below this ratio the entering normal counts as dependent: the Schur
+      // solve for r carries a relative error of about cond(S) * 1e-16
+      const bool zfull = zz > 1e-14 * fmax(nu, 1e-300) && zz > 0.0;
       const double t2 = zfull ? splus / zz : __builtin_huge_val();
       if (!(t1 < 1e300) && !(t2 < 1e300)) {
         // Farkas vector: 1 on the entering constraint, -r_k >= 0 on the working set
@@ -1080,6 +1099,7 @@ ChainDims make_chain_dims(int p, int s_cap, int nf_cap, int r_cap, int q_cap) {
   d.o_gfull = take(3 * d.ng_cap * 8);
   d.o_G1b = take(d.ng_cap * NP * 8);
   d.o_L1b = take(d.nf_pts_cap * NP * 8);
+  d.o_L1r = take(d.nf_pts_cap * 8);
   d.o_qv = take(2 * 3 * d.nf_pts_cap * 8);
   d.o_x = take(d.n_cap * 8);
   d.o_scal = take(16 * 8);

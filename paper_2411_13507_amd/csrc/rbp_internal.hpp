@@ -26,7 +26,7 @@ struct LdsDims {
   int nf_cap;  // max faces
   int m_cap;   // max rows
   // byte offsets
-  int o_Hd, o_Af, o_rowval, o_ybuf, o_vec, o_scal, o_acte, o_lam, o_actid, o_actside, o_region;
+  int o_Hd, o_Af, o_rowval, o_ybuf, o_vec, o_scal, o_acte, o_lam, o_actid, o_actside, o_cst, o_Rd, o_region;
   int o_Hf, o_Aff, o_vbuf, o_xb1, o_xb2, o_Kx;   // ADMM part of region
   int o_Q1, o_R;                                  // polish part of region
   int bytes;
@@ -106,7 +106,7 @@ struct BackArgs {
 // ---- multi-segment paths (rbp_chain.hip)
 struct ChainDims {
   int s_cap, nf_cap, r_cap, q_cap, nf_pts_cap, ng_cap, n_cap, m_cap;
-  int o_segi, o_seg64, o_Af, o_bfs, o_fan, o_rb, o_rn, o_Pseg, o_gfull, o_G1b, o_L1b, o_qv, o_x, o_scal,
+  int o_segi, o_seg64, o_Af, o_bfs, o_fan, o_rb, o_rn, o_Pseg, o_gfull, o_G1b, o_L1b, o_L1r, o_qv, o_x, o_scal,
       o_cand, o_bits;
   int o_Kb, o_zr, o_yr, o_accp, o_Pf, o_xt, o_Cs, o_Wm;          // ADMM part of the region
   int o_LS, o_beta, o_acte, o_u, o_cvec, o_actid;                 // polish part of the region

@@ -61,6 +61,7 @@ struct Lds {
   int *actid, *actside;
   Real *HfT, *Aff, *vbuf, *xb1, *xb2, *Kx;
   double *Q1, *Rm;
+  double *cL1i, *cQ1, *cGd, *Rd;   // staged degree tables; reciprocal diagonal of R
 };
 
 template <typename Real>
@@ -90,6 +91,10 @@ __device__ Lds<Real> carve(char* s, const LdsDims& D) {
   L.Kx = (Real*)(s + D.o_Kx);
   L.Q1 = (double*)(s + D.o_Q1);
   L.Rm = (double*)(s + D.o_R);
+  L.cL1i = (double*)(s + D.o_cst);
+  L.cQ1 = L.cL1i + kMaxFree * kMaxFree;
+  L.cGd = L.cQ1 + kMaxPts * kMaxPts;
+  L.Rd = (double*)(s + D.o_Rd);
   return L;
 }
 
@@ -130,21 +135,32 @@ struct Inst {
   }
 };
 
-// whitening: (L^-1 a)_i for var i = 3s + c, a given on the free vars in ``a``
+// whitening: (L^-1 a)_i for var i = 3s + c, a given on the free vars in ``a``;
+// Li = rows of L1inv (stride kMaxFree, in LDS or constant memory).  Fixed
+// trip count so that every load issues before the first use.
 template <int P>
-__device__ __forceinline__ double whiten_at(const DegConst& K, double T15, const double* a, int i) {
+__device__ __forceinline__ double whiten_at(const double* Li, double T15, const double* a, int i) {
+  constexpr int NFP = P - 1;
   const int s = i / 3, c = i - 3 * (i / 3);
   double acc = 0.0;
-  for (int t = 0; t <= s; ++t) acc += K.L1inv[s][t] * a[3 * t + c];
+#pragma unroll
+  for (int t = 0; t < NFP; ++t) {
+    const double w = Li[kMaxFree * s + t], x = a[3 * t + c];
+    acc += (t <= s) ? w * x : 0.0;
+  }
   return T15 * acc;
 }
 // un-whitening: (L^-T v)_i
 template <int P>
-__device__ __forceinline__ double unwhiten_at(const DegConst& K, double T15, const double* v, int i) {
+__device__ __forceinline__ double unwhiten_at(const double* Li, double T15, const double* v, int i) {
   constexpr int NFP = P - 1;
   const int s = i / 3, c = i - 3 * (i / 3);
   double acc = 0.0;
-  for (int t = s; t < NFP; ++t) acc += K.L1inv[t][s] * v[3 * t + c];
+#pragma unroll
+  for (int t = 0; t < NFP; ++t) {
+    const double w = Li[kMaxFree * t + s], x = v[3 * t + c];
+    acc += (t >= s) ? w * x : 0.0;
+  }
   return T15 * acc;
 }
 
@@ -208,6 +224,12 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
     const int pt = lane / 3, c = lane - 3 * (lane / 3);
     L.ybuf[lane] = (pt == P) ? sel3(c, in.dg[0], in.dg[1], in.dg[2]) : 0.0;
   }
+  // degree tables read with lane-dependent indices
+  for (int e = lane; e < kMaxFree * kMaxFree; e += kWave) {
+    L.cL1i[e] = (&K.L1inv[0][0])[e];
+    L.cGd[e] = (&K.Gdiff[0][0])[e];
+  }
+  for (int e = lane; e < kMaxPts * kMaxPts; e += kWave) L.cQ1[e] = (&K.Q1[0][0])[e];
   __syncthreads();
 
   // ---- face rows: lane j < nf owns face j on every interior point
@@ -279,95 +301,89 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
   // ADMM in precision Real
   // ======================================================================
   const Real rho = Real(A.rho), alpha = Real(A.alpha), irho = Real(1) / Real(A.rho);
-  // face Gram (3x3 symmetric) of unit face normals
-  double g00, g01, g02, g11, g12, g22;
-  {
-    const double w = fl ? 1.0 / (fan * fan) : 0.0;
-    g00 = wsum(w * fa0 * fa0); g01 = wsum(w * fa0 * fa1); g02 = wsum(w * fa0 * fa2);
-    g11 = wsum(w * fa1 * fa1); g12 = wsum(w * fa1 * fa2); g22 = wsum(w * fa2 * fa2);
-  }
-  // stage FP-Real copies of the rows used by the iteration
-  for (int e = lane; e < r * N; e += kWave) {
-    const int l = e / N, i = e - N * (e / N);
-    L.HfT[i * HS + l] = Real(L.Hd[l * NC + 3 + i]);
-  }
-  if (fl) { L.Aff[4 * lane] = Real(fa0); L.Aff[4 * lane + 1] = Real(fa1); L.Aff[4 * lane + 2] = Real(fa2); }
-  // K = P + rho * A^T D^2 A (free variables): Hessian, difference rows and
-  // face blocks in closed form; reachable rows below on the matrix cores.
-  for (int e = lane; e < N * N; e += kWave) {
-    const int i = e / N, j = e - N * (e / N);
-    const int s = i / 3, c = i - 3 * s, t = j / 3, c2 = j - 3 * t;
-    double v = 0.0;
-    if (c == c2) v = in.iT3 * (2.0 * K.Q1[s + 1][t + 1] + double(A.rho) * K.Gdiff[s][t]);
-    if (s == t) {
-      const int a = c < c2 ? c : c2, b = c < c2 ? c2 : c;
-      const double gf = (a == 0) ? (b == 0 ? g00 : (b == 1 ? g01 : g02)) : (a == 1 ? (b == 1 ? g11 : g12) : g22);
-      v += double(A.rho) * in.iT3 / K.kappa[s] * gf;
-    }
-    L.Kx[e] = Real(v);
-  }
-  __syncthreads();
-  {
-    // Gram sum_l d_l^2 h_l h_l^T over reachable rows with v_mfma_f32_32x32x2f32:
-    // A = B^T = scaled rows, two rows per instruction (lanes 0-31: row 2t,
-    // lanes 32-63: row 2t+1; column = lane % 32).
-    floatx16 acc;
-#pragma unroll
-    for (int g = 0; g < 16; ++g) acc[g] = 0.0f;
-    const int col = lane & 31, half = lane >> 5;
-    for (int t = 0; 2 * t < r; ++t) {
-      const int l = 2 * t + half;
-      float a = 0.0f;
-      if (l < r && col < N) a = float(L.rowval[RB + l] * L.Hd[l * NC + 3 + col]);
-      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, a, acc, 0, 0, 0);
-    }
-#pragma unroll
-    for (int g = 0; g < 16; ++g) {
-      const int i = 8 * (g >> 2) + 4 * half + (g & 3);
-      if (i < N && col < N) L.Kx[i * N + col] += Real(A.rho * acc[g]);
-    }
-  }
-  // in-place symmetric sweep: after all pivots Kx = -K^{-1}
-  {
-    constexpr int EPL = (N * N + kWave - 1) / kWave;
-    for (int k = 0; k < N; ++k) {
-      __syncthreads();
-      const Real d = L.Kx[k * N + k];
-      Real nv[EPL];
-#pragma unroll
-      for (int u = 0; u < EPL; ++u) {
-        const int e = lane + kWave * u;
-        nv[u] = 0;
-        if (e < N * N) {
-          const int i = e / N, j = e - N * (e / N);
-          const Real aik = L.Kx[i * N + k], akj = L.Kx[k * N + j], aij = L.Kx[e];
-          if (i == k && j == k) nv[u] = Real(-1) / d;
-          else if (i == k) nv[u] = akj / d;
-          else if (j == k) nv[u] = aik / d;
-          else nv[u] = aij - aik * akj / d;
-        }
-      }
-      __syncthreads();
-#pragma unroll
-      for (int u = 0; u < EPL; ++u) {
-        const int e = lane + kWave * u;
-        if (e < N * N) L.Kx[e] = nv[u];
-      }
-    }
-    __syncthreads();
-  }
-  // var lane i < N: row i of M = K^{-1}, linear term q_i
+  const int K_admm = A.admm_iters;
+  // var lane i < N: row i of M = K^{-1} (K = P + rho A^T D^2 A on the free
+  // variables), linear term q_i
   Real Mrow[N];
   const bool vl = lane < N;
   const int vs = lane / 3, vc = lane - 3 * (lane / 3);
   double qd = 0.0;
-  if (vl) {
 #pragma unroll
-    for (int j = 0; j < N; ++j) Mrow[j] = -L.Kx[lane * N + j];
-    qd = 2.0 * in.iT3 * K.Q1[vs + 1][P] * sel3(vc, in.dg[0], in.dg[1], in.dg[2]);
-  } else {
+  for (int j = 0; j < N; ++j) Mrow[j] = 0;
+  if (K_admm > 0) {
+    // face Gram (3x3 symmetric) of unit face normals
+    double g00, g01, g02, g11, g12, g22;
+    {
+      const double w = fl ? 1.0 / (fan * fan) : 0.0;
+      g00 = wsum(w * fa0 * fa0); g01 = wsum(w * fa0 * fa1); g02 = wsum(w * fa0 * fa2);
+      g11 = wsum(w * fa1 * fa1); g12 = wsum(w * fa1 * fa2); g22 = wsum(w * fa2 * fa2);
+    }
+    // stage FP-Real copies of the rows used by the iteration
+    for (int e = lane; e < r * N; e += kWave) {
+      const int l = e / N, i = e - N * (e / N);
+      L.HfT[i * HS + l] = Real(L.Hd[l * NC + 3 + i]);
+    }
+    if (fl) { L.Aff[4 * lane] = Real(fa0); L.Aff[4 * lane + 1] = Real(fa1); L.Aff[4 * lane + 2] = Real(fa2); }
+    {
+      // Gram sum_l d_l^2 h_l h_l^T over reachable rows with v_mfma_f32_32x32x2f32:
+      // A = B^T = scaled rows, two rows per instruction (lanes 0-31: row 2t,
+      // lanes 32-63: row 2t+1; column = lane % 32).
+      floatx16 acc;
 #pragma unroll
-    for (int j = 0; j < N; ++j) Mrow[j] = 0;
+      for (int g = 0; g < 16; ++g) acc[g] = 0.0f;
+      const int col = lane & 31, half = lane >> 5;
+      for (int t = 0; 2 * t < r; ++t) {
+        const int l = 2 * t + half;
+        float av = 0.0f;
+        if (l < r && col < N) av = float(L.rowval[RB + l] * L.Hd[l * NC + 3 + col]);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, av, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int g = 0; g < 16; ++g) {
+        const int i = 8 * (g >> 2) + 4 * half + (g & 3);
+        if (i < N && col < N) L.Kx[i * N + col] = Real(A.rho * acc[g]);
+      }
+    }
+    __syncthreads();
+    // lane j < N assembles column j of K: Hessian and difference rows in
+    // closed form, face blocks from the face Gram, reachable rows from above
+    Real kc[N];
+    {
+      const double gfa = sel3(vc, g00, g01, g02), gfb = sel3(vc, g01, g11, g12), gfc = sel3(vc, g02, g12, g22);
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        const int si = i / 3, ci = i - 3 * (i / 3);
+        kc[i] = 0;
+        if (vl) {
+          double v = 0.0;
+          if (ci == vc)
+            v = in.iT3 * (2.0 * L.cQ1[kMaxPts * (si + 1) + vs + 1] + double(A.rho) * L.cGd[kMaxFree * si + vs]);
+          if (si == vs) v += double(A.rho) * in.iT3 / K.kappa[si] * (ci == 0 ? gfa : (ci == 1 ? gfb : gfc));
+          kc[i] = Real(v) + L.Kx[i * N + lane];
+        }
+      }
+    }
+    // Gauss-Jordan sweep on the register columns (K is symmetric positive
+    // definite: no pivoting); afterwards kc = column ``lane`` of -K^{-1}
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      Real pk[N];
+#pragma unroll
+      for (int i = 0; i < N; ++i) pk[i] = wave::bcast(kc[i], k);
+      const Real invd = Real(1) / pk[k];
+      const Real f = kc[k] * invd;
+      const bool isk = lane == k;
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        if (i == k) kc[i] = isk ? -invd : f;
+        else kc[i] = isk ? pk[i] * invd : kc[i] - pk[i] * f;
+      }
+    }
+    if (vl) {
+#pragma unroll
+      for (int j = 0; j < N; ++j) Mrow[j] = -kc[j];
+      qd = 2.0 * in.iT3 * L.cQ1[kMaxPts * (vs + 1) + P] * sel3(vc, in.dg[0], in.dg[1], in.dg[2]);
+    }
   }
   const Real qr = Real(qd);
   // scaled row data in Real
@@ -410,7 +426,6 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
     y += rho * (zrl - zn);
     z = zn;
   };
-  const int K_admm = A.admm_iters;
   for (int it = 0; it < K_admm; ++it) {
     // v = D (rho z - y), in row order
     if (fl) {
@@ -425,10 +440,30 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
     }
     __syncthreads();
     if (vl) {
-      Real t = 0;
+      // A^T v with four partial sums so that the LDS loads overlap
+      Real t0 = 0, t1 = 0, t2 = 0, t3 = 0;
       const int k = vs + 1;
-      for (int j = 0; j < nf; ++j) t += L.Aff[4 * j + vc] * L.vbuf[vs * nf + j];
-      for (int l = 0; l < r; ++l) t += L.HfT[lane * HS + l] * L.vbuf[RB + l];
+      const Real* vf = L.vbuf + vs * nf;
+      int j = 0;
+      for (; j + 4 <= nf; j += 4) {
+        t0 += L.Aff[4 * j + vc] * vf[j];
+        t1 += L.Aff[4 * j + 4 + vc] * vf[j + 1];
+        t2 += L.Aff[4 * j + 8 + vc] * vf[j + 2];
+        t3 += L.Aff[4 * j + 12 + vc] * vf[j + 3];
+      }
+      for (; j < nf; ++j) t0 += L.Aff[4 * j + vc] * vf[j];
+      const Real* hrow = L.HfT + lane * HS;
+      const Real* vr = L.vbuf + RB;
+      int l = 0;
+#pragma unroll 2
+      for (; l + 4 <= r; l += 4) {
+        t0 += hrow[l] * vr[l];
+        t1 += hrow[l + 1] * vr[l + 1];
+        t2 += hrow[l + 2] * vr[l + 2];
+        t3 += hrow[l + 3] * vr[l + 3];
+      }
+      for (; l < r; ++l) t0 += hrow[l] * vr[l];
+      Real t = (t0 + t1) + (t2 + t3);
       t += Real(in.sv) * (L.vbuf[F + 3 * (k - 1) + vc] - L.vbuf[F + 3 * k + vc]);
       const int AB = F + 3 * P;
       if (k >= 2) t += Real(in.sa) * L.vbuf[AB + 3 * (k - 2) + vc];
@@ -502,7 +537,11 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
   double v0 = 0.0;
   if (vl) {
     double acc = 0.0;
-    for (int t = 0; t <= vs; ++t) acc += K.L1inv[vs][t] * K.Q1[t + 1][P];
+#pragma unroll
+    for (int t = 0; t < NFP; ++t) {
+      const double w = L.cL1i[kMaxFree * vs + t] * L.cQ1[kMaxPts * (t + 1) + P];
+      acc += (t <= vs) ? w : 0.0;
+    }
     v0 = -in.T15 * 2.0 * in.iT3 * sel3(vc, in.dg[0], in.dg[1], in.dg[2]) * acc;
   }
 
@@ -520,7 +559,7 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
       L.vC[lane] = in.coef(id, pt, vc, L.Af, L.Hd);
     }
     __syncthreads();
-    if (vl) L.vA[lane] = double(side) * whiten_at<P>(K, in.T15, L.vC, lane);
+    if (vl) L.vA[lane] = double(side) * whiten_at<P>(L.cL1i, in.T15, L.vC, lane);
     __syncthreads();
   };
 
@@ -535,7 +574,11 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
     __syncthreads();
     if (vl) {
       double acc = L.vA[lane];
-      for (int k = 0; k < q; ++k) acc -= L.Q1[k * N + lane] * L.vC[k];
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        const double qk = L.Q1[k * N + lane], ck = L.vC[k];
+        acc -= (k < q) ? qk * ck : 0.0;
+      }
       L.vB[lane] = acc;
     }
     __syncthreads();
@@ -547,7 +590,11 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
     __syncthreads();
     if (vl) {
       double acc = L.vB[lane];
-      for (int k = 0; k < q; ++k) acc -= L.Q1[k * N + lane] * L.vE[k];
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        const double qk = L.Q1[k * N + lane], ek = L.vE[k];
+        acc -= (k < q) ? qk * ek : 0.0;
+      }
       L.vB[lane] = acc;
     }
     if (lane < q) L.vC[lane] += L.vE[lane];
@@ -560,6 +607,7 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
     if (lane < q) L.Rm[lane * N + q] = L.vC[lane];
     if (lane == 0) {
       L.Rm[q * N + q] = nz;
+      L.Rd[q] = 1.0 / nz;
       L.actid[q] = id; L.actside[q] = side; L.acte[q] = e_full; L.actc[q] = c_full;
     }
     int ol, bit;
@@ -623,6 +671,8 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
     }
     --q;
     if (lane >= q) lamr = 0.0;
+    if (lane < q) L.Rd[lane] = 1.0 / L.Rm[lane * N + lane];
+    __syncthreads();
   };
 
   // multipliers of the current working set at the minimiser on its face:
@@ -630,7 +680,7 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
   auto solve_lambda = [&]() {
     double w = (lane < q) ? (L.acte[lane] - L.actc[lane]) : 0.0;
     for (int k = 0; k < q; ++k) {
-      const double wk = wave::bcast(w, k) / L.Rm[k * N + k];
+      const double wk = wave::bcast(w, k) * L.Rd[k];
       if (lane == k) w = wk;
       else if (lane > k && lane < q) w -= L.Rm[k * N + lane] * wk;
     }
@@ -642,7 +692,7 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
       u -= w;
     }
     for (int k = q - 1; k >= 0; --k) {
-      const double lk = wave::bcast(u, k) / L.Rm[k * N + k];
+      const double lk = wave::bcast(u, k) * L.Rd[k];
       if (lane == k) u = lk;
       else if (lane < k) u -= L.Rm[lane * N + k] * lk;
     }
@@ -708,13 +758,21 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
   __syncthreads();
   if (lane < q) {
     double acc = 0.0;
-    for (int k = lane; k < q; ++k) acc += L.Rm[lane * N + k] * L.vD[k];
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      const double rk = L.Rm[lane * N + k], dk = L.vD[k];
+      acc += (k >= lane && k < q) ? rk * dk : 0.0;
+    }
     L.vE[lane] = acc;
   }
   __syncthreads();
   if (vl) {
     double acc = v0;
-    for (int k = 0; k < q; ++k) acc -= L.Q1[k * N + lane] * L.vE[k];
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      const double qk = L.Q1[k * N + lane], ek = L.vE[k];
+      acc -= (k < q) ? qk * ek : 0.0;
+    }
     vw = acc;
   }
   __syncthreads();
@@ -769,7 +827,7 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
   auto refresh_y = [&]() {
     if (vl) L.vD[lane] = vw;
     __syncthreads();
-    if (vl) L.ybuf[3 + lane] = unwhiten_at<P>(K, in.T15, L.vD, lane);
+    if (vl) L.ybuf[3 + lane] = unwhiten_at<P>(L.cL1i, in.T15, L.vD, lane);
     __syncthreads();
   };
 
@@ -824,7 +882,7 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
       // r = R^-1 c
       double rv = (lane < q) ? L.vC[lane] : 0.0;
       for (int k = q - 1; k >= 0; --k) {
-        const double rk = wave::bcast(rv, k) / L.Rm[k * N + k];
+        const double rk = wave::bcast(rv, k) * L.Rd[k];
         if (lane == k) rv = rk;
         else if (lane < k) rv -= L.Rm[lane * N + k] * rk;
       }
@@ -931,7 +989,8 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
   double qy = 0.0;
   if (lane < NC) {
     const int pt = lane / 3, c = lane - 3 * (lane / 3);
-    for (int b = 0; b <= P; ++b) qy += K.Q1[pt][b] * L.ybuf[3 * b + c];
+#pragma unroll
+    for (int b = 0; b <= P; ++b) qy += L.cQ1[kMaxPts * pt + b] * L.ybuf[3 * b + c];
     qy *= in.iT3;
     L.qbuf[lane] = qy;
   }
@@ -978,7 +1037,7 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
 // One launch per degree P: block b solves order[inst_base + b]; instances
 // are grouped by degree in the work order.
 template <typename Real, int P>
-__global__ __launch_bounds__(64) void solve_kernel(SolveArgs A) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void solve_kernel(SolveArgs A) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
   const int b = blockIdx.x + A.inst_base;
   if (b >= A.N) return;
@@ -1055,7 +1114,7 @@ __device__ void backward_instance(const BackArgs& A, const int inst, char* smem)
     const int id = L.actid[k], side = L.actside[k];
     if (vl) L.vC[lane] = in.coef(id, vs + 1, vc, L.Af, L.Hd);
     __syncthreads();
-    if (vl) L.vA[lane] = double(side) * whiten_at<P>(K, in.T15, L.vC, lane);
+    if (vl) L.vA[lane] = double(side) * whiten_at<P>(&K.L1inv[0][0], in.T15, L.vC, lane);
     __syncthreads();
     for (int pass = 0; pass < 2; ++pass) {
       if (lane < k) {
@@ -1088,7 +1147,7 @@ __device__ void backward_instance(const BackArgs& A, const int inst, char* smem)
   // whitened upstream gradient on the free variables
   if (vl) L.vD[lane] = L.qbuf[3 + lane];
   __syncthreads();
-  double gh = vl ? whiten_at<P>(K, in.T15, L.vD, lane) : 0.0;
+  double gh = vl ? whiten_at<P>(&K.L1inv[0][0], in.T15, L.vD, lane) : 0.0;
   if (vl) L.vA[lane] = gh;
   __syncthreads();
   // c = Q1^T gh ; omega = R^-1 c ; xi = gh - Q1 c ; w = L^-T xi
@@ -1108,7 +1167,7 @@ __device__ void backward_instance(const BackArgs& A, const int inst, char* smem)
     L.vB[lane] = acc;
   }
   __syncthreads();
-  if (vl) L.vC[lane] = unwhiten_at<P>(K, in.T15, L.vB, lane);   // w on the free vars
+  if (vl) L.vC[lane] = unwhiten_at<P>(&K.L1inv[0][0], in.T15, L.vB, lane);   // w on the free vars
   // combined row weights  Omega_k = omega_k - gf lam_k
   if (lane < q) L.vD[lane] = om - gf * L.lam[lane];
   __syncthreads();
@@ -1191,6 +1250,8 @@ LdsDims make_dims(int pmax, int r_cap, int nf_cap, int real_bytes) {
   d.o_lam = take(d.nmax * 8);
   d.o_actid = take(d.nmax * 4);
   d.o_actside = take(d.nmax * 4);
+  d.o_cst = take((2 * kMaxFree * kMaxFree + kMaxPts * kMaxPts) * 8);
+  d.o_Rd = take(d.nmax * 8);
   d.o_region = o;
   // iteration scratch in the precision of the iterations
   const int hs = ((d.r_cap + 3) & ~3) + 4;

@@ -111,6 +111,9 @@ __device__ __forceinline__ void argmax(double& v, int& id) { arg_reduce<true>(v,
 __device__ __forceinline__ void argmin(double& v, int& id) { arg_reduce<false>(v, id); }
 
 // value of lane k (k uniform across the wave)
+__device__ __forceinline__ float bcast(float v, int k) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
+}
 __device__ __forceinline__ double bcast(double v, int k) {
   const long long b = __double_as_longlong(v);
   const int lo = __builtin_amdgcn_readlane(int(b & 0xffffffffll), k);
