@@ -16,9 +16,10 @@ struct rbp_batch {
   int device = 0;
   rbp_problem_desc desc{};
   int32_t N = 0, pmax = 3, rmax = 0, nfmax = 1;
-  // work order grouped by degree: order[deg_start[p] .. deg_start[p]+deg_count[p]) have degree p
-  int32_t deg_start[RBP_MAX_DEGREE + 1] = {};
-  int32_t deg_count[RBP_MAX_DEGREE + 1] = {};
+  // work order grouped by (degree, reachable-row class); each group is one
+  // launch whose LDS is sized by the group's own largest instance
+  struct Group { int32_t p, start, count, rmax, nfmax; };
+  std::vector<Group> groups;
   std::vector<int32_t> degree_host;
   int64_t pt_total = 0, face_total = 0;
   int64_t* d_pt_off = nullptr;
@@ -168,16 +169,29 @@ int rbp_build_batch(const rbp_problem_desc* d, hipStream_t stream, rbp_batch** o
       cost[i] = int64_t(3 * (p - 1)) * ((p - 1) * nf + 6 * p + r);
     }
     b->F_total = poff[d->n_poly];
-    // work order: grouped by degree (one specialised launch each), most
-    // expensive first within a group so that the tail of each launch is short
+    // work order: grouped by degree and reachable-row class (one specialised
+    // launch each, LDS sized per group), most expensive first within a group
+    // so that the tail of each launch is short
+    auto rclass = [&](int i) -> int {
+      const int64_t r = roff[i + 1] - roff[i];
+      return r <= 32 ? 0 : (r <= 64 ? 1 : 2);
+    };
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
-      return deg[a] != deg[c] ? deg[a] < deg[c] : cost[a] > cost[c];
+      if (deg[a] != deg[c]) return deg[a] < deg[c];
+      const int ra = rclass(a), rc2 = rclass(c);
+      return ra != rc2 ? ra < rc2 : cost[a] > cost[c];
     });
     for (int k = 0; k < N; ++k) {
-      const int p = deg[order[k]];
-      if (b->deg_count[p] == 0) b->deg_start[p] = k;
-      ++b->deg_count[p];
+      const int i = order[k];
+      const int32_t r = int32_t(roff[i + 1] - roff[i]);
+      const int32_t nf = poff[pidx[i] + 1] - poff[pidx[i]];
+      if (b->groups.empty() || b->groups.back().p != deg[i] || rclass(order[b->groups.back().start]) != rclass(i))
+        b->groups.push_back({deg[i], k, 0, 0, 1});
+      rbp_batch::Group& g = b->groups.back();
+      ++g.count;
+      g.rmax = std::max(g.rmax, r);
+      g.nfmax = std::max(g.nfmax, nf);
     }
     b->degree_host = deg;
   }
@@ -240,23 +254,25 @@ int rbp_solve_batch(rbp_batch* b, const double* x0, const double* goal, const do
   a.P_out = P_out; a.cost_out = cost_out; a.status_out = status_out; a.kkt_out = kkt_out; a.iters_out = iters_out;
   a.store = o.store_for_backward ? 1 : 0;
   a.st_q = b->st_q; a.st_id = b->st_id; a.st_side = b->st_side; a.st_lam = b->st_lam;
+  a.st_stride = b->nmax;
   a.admm_iters = o.admm_iters; a.rho = o.rho; a.alpha = o.alpha;
   a.max_steps = o.max_polish_steps; a.feas_tol = o.feas_tol; a.kkt_tol = o.kkt_tol;
-  a.dims = rbp::make_dims(b->pmax, b->rmax, b->nfmax, o.plain ? 8 : 4);
   hipError_t e = hipSuccess;
   if (o.plain) {
     a.order = nullptr;
+    a.dims = rbp::make_dims(b->pmax, b->rmax, b->nfmax, 8);
     for (int i = 0; i < b->N && e == hipSuccess; ++i) {
       a.inst_base = i;
       e = rbp::launch_solve(a, 1, stream, true, b->degree_host[i]);
     }
   } else {
     a.order = b->d_order;
-    for (int p = RBP_MIN_DEGREE; p <= RBP_MAX_DEGREE && e == hipSuccess; ++p) {
-      if (b->deg_count[p] == 0) continue;
-      a.inst_base = b->deg_start[p];
-      a.N = b->deg_start[p] + b->deg_count[p];
-      e = rbp::launch_solve(a, b->deg_count[p], stream, false, p);
+    for (size_t k = 0; k < b->groups.size() && e == hipSuccess; ++k) {
+      const rbp_batch::Group& g = b->groups[k];
+      a.dims = rbp::make_dims(g.p, g.rmax, g.nfmax, 4);
+      a.inst_base = g.start;
+      a.N = g.start + g.count;
+      e = rbp::launch_solve(a, g.count, stream, false, g.p);
     }
   }
   if (e != hipSuccess) return RBP_E_DEVICE;
@@ -292,8 +308,15 @@ int rbp_backward(rbp_batch* b, const double* grad_P, const double* grad_cost, do
   a.st_q = b->st_q; a.st_id = b->st_id; a.st_side = b->st_side; a.st_lam = b->st_lam;
   a.grad_P = grad_P; a.grad_cost = grad_cost;
   a.grad_x0 = grad_x0; a.grad_goal = grad_goal; a.grad_b = grad_b; a.flags = flags_out;
-  a.dims = rbp::make_dims(b->pmax, b->rmax, b->nfmax, 8);
-  if (rbp::launch_backward(a, stream) != hipSuccess) return RBP_E_DEVICE;
+  a.order = b->d_order;
+  a.st_stride = b->nmax;
+  for (size_t k = 0; k < b->groups.size(); ++k) {
+    const rbp_batch::Group& g = b->groups[k];
+    a.dims = rbp::make_dims(g.p, g.rmax, g.nfmax, 8);
+    a.inst_base = g.start;
+    a.N = g.start + g.count;
+    if (rbp::launch_backward(a, g.count, stream, g.p) != hipSuccess) return RBP_E_DEVICE;
+  }
   b->last_stream = stream;
   return RBP_OK;
 }

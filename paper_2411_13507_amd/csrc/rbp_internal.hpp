@@ -61,7 +61,8 @@ struct SolveArgs {
   int32_t* st_q;             // active count per instance
   int32_t* st_id;            // [N * nmax] row ids
   int32_t* st_side;          // [N * nmax] sides
-  double* st_lam;            // [N * nmax] multipliers
+  double* st_lam;            // [N * st_stride] multipliers
+  int st_stride;             // entries per instance in st_id / st_side / st_lam
   // options
   int admm_iters;
   float rho, alpha;
@@ -72,7 +73,10 @@ struct SolveArgs {
 };
 
 struct BackArgs {
-  int N;
+  int N;                     // end of the launch's range in the work order
+  const int32_t* order;      // work order (nullable): block b handles order[inst_base + b]
+  int inst_base;
+  int st_stride;
   const int32_t* degree;
   const double* T;
   const int32_t* poly_off;
@@ -148,6 +152,6 @@ hipError_t upload_chain_constants(int device);
 hipError_t launch_chains(const ChainArgs& a, hipStream_t s);
 hipError_t upload_constants(int device);
 hipError_t launch_solve(const SolveArgs& a, int n_blocks, hipStream_t s, bool fp64_iters, int pfix);
-hipError_t launch_backward(const BackArgs& a, hipStream_t s);
+hipError_t launch_backward(const BackArgs& a, int n_blocks, hipStream_t s, int pfix);
 
 }  // namespace rbp

@@ -99,7 +99,7 @@ __device__ Lds<Real> carve(char* s, const LdsDims& D) {
 }
 
 // Stride (elements) of the transposed reachable block H^T (free columns).
-__device__ __forceinline__ int hft_stride(const LdsDims& D) { return ((D.r_cap + 3) & ~3) + 4; }
+__device__ __forceinline__ int hft_stride(const LdsDims& D) { return D.r_cap | 1; }
 
 // --------------------------------------------------------------------------
 // Instance description shared by the forward and backward passes.
@@ -110,6 +110,10 @@ struct Inst {
   static constexpr int N = 3 * NFP;       // free variables
   static constexpr int NC = 3 * (P + 1);  // coefficients of a full row
   static constexpr int ND = 6 * P - 3;    // difference rows (velocity, acceleration)
+  // odd row strides (in doubles) of the LDS copies read one row per lane,
+  // so that a lane-strided 64-bit access touches distinct banks
+  static constexpr int NS = N | 1;        // basis Q1 and factor R
+  static constexpr int HDS = NC | 1;      // reachable rows
   double T, T15, iT3, sv, sa, vmax, amax;
   double x0[6], P0[3], dg[3];
   int nf, r, F, RB, m, f0;
@@ -131,7 +135,7 @@ struct Inst {
       if (cc != c) return 0.0;
       return sa * (double(pt == k + 2) - 2.0 * double(pt == k + 1) + double(pt == k));
     }
-    return Hd[(id - RB) * NC + 3 * pt + c];
+    return Hd[(id - RB) * HDS + 3 * pt + c];
   }
 };
 
@@ -170,7 +174,7 @@ __device__ __forceinline__ double unwhiten_at(const double* Li, double T15, cons
 template <int P, typename Real>
 __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
   using I = Inst<P>;
-  constexpr int NFP = I::NFP, N = I::N, NC = I::NC, ND = I::ND;
+  constexpr int NFP = I::NFP, N = I::N, NC = I::NC, ND = I::ND, NS = I::NS, HDS = I::HDS;
   const int lane = threadIdx.x;
   const DegConst& K = c_deg[P];
   const LdsDims& D = A.dims;
@@ -216,7 +220,8 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
   // ---- stage instance data in LDS
   for (int e = lane; e < r * NC; e += kWave) {
     const double h = A.H[in.hb + e];
-    L.Hd[e] = h;
+    const int l = e / NC;
+    L.Hd[e + l * (HDS - NC)] = h;
     bad |= !isfinite(h);
   }
   for (int e = lane; e < nf * 3; e += kWave) L.Af[e] = A.A_face[3 * (int64_t)in.f0 + e];
@@ -273,7 +278,7 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
   for (int sl = 0; sl < 2; ++sl) {
     const int l = lane + kWave * sl;
     if (l < r) {
-      const double* hr = L.Hd + l * NC;
+      const double* hr = L.Hd + l * HDS;
       double b = A.h0[in.r0 + l];
       for (int e = 0; e < 6; ++e) b += A.G[6 * (in.r0 + l) + e] * in.x0[e];
       double s0 = 0, s1 = 0, s2 = 0;
@@ -321,7 +326,7 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
     // stage FP-Real copies of the rows used by the iteration
     for (int e = lane; e < r * N; e += kWave) {
       const int l = e / N, i = e - N * (e / N);
-      L.HfT[i * HS + l] = Real(L.Hd[l * NC + 3 + i]);
+      L.HfT[i * HS + l] = Real(L.Hd[l * HDS + 3 + i]);
     }
     if (fl) { L.Aff[4 * lane] = Real(fa0); L.Aff[4 * lane + 1] = Real(fa1); L.Aff[4 * lane + 2] = Real(fa2); }
     {
@@ -335,7 +340,7 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
       for (int t = 0; 2 * t < r; ++t) {
         const int l = 2 * t + half;
         float av = 0.0f;
-        if (l < r && col < N) av = float(L.rowval[RB + l] * L.Hd[l * NC + 3 + col]);
+        if (l < r && col < N) av = float(L.rowval[RB + l] * L.Hd[l * HDS + 3 + col]);
         acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, av, acc, 0, 0, 0);
       }
 #pragma unroll
@@ -568,7 +573,7 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
   auto project = [&]() {
     if (lane < q) {
       double acc = 0.0;
-      for (int i = 0; i < N; ++i) acc += L.Q1[lane * N + i] * L.vA[i];
+      for (int i = 0; i < N; ++i) acc += L.Q1[lane * NS + i] * L.vA[i];
       L.vC[lane] = acc;
     }
     __syncthreads();
@@ -576,7 +581,7 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
       double acc = L.vA[lane];
 #pragma unroll
       for (int k = 0; k < N; ++k) {
-        const double qk = L.Q1[k * N + lane], ck = L.vC[k];
+        const double qk = L.Q1[k * NS + lane], ck = L.vC[k];
         acc -= (k < q) ? qk * ck : 0.0;
       }
       L.vB[lane] = acc;
@@ -584,7 +589,7 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
     __syncthreads();
     if (lane < q) {
       double acc = 0.0;
-      for (int i = 0; i < N; ++i) acc += L.Q1[lane * N + i] * L.vB[i];
+      for (int i = 0; i < N; ++i) acc += L.Q1[lane * NS + i] * L.vB[i];
       L.vE[lane] = acc;
     }
     __syncthreads();
@@ -592,7 +597,7 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
       double acc = L.vB[lane];
 #pragma unroll
       for (int k = 0; k < N; ++k) {
-        const double qk = L.Q1[k * N + lane], ek = L.vE[k];
+        const double qk = L.Q1[k * NS + lane], ek = L.vE[k];
         acc -= (k < q) ? qk * ek : 0.0;
       }
       L.vB[lane] = acc;
@@ -603,10 +608,10 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
 
   // append the projected direction as a new basis column (R gets c and |z|)
   auto append = [&](double nz, int id, int side, double e_full, double c_full) {
-    if (vl) L.Q1[q * N + lane] = L.vB[lane] / nz;
-    if (lane < q) L.Rm[lane * N + q] = L.vC[lane];
+    if (vl) L.Q1[q * NS + lane] = L.vB[lane] / nz;
+    if (lane < q) L.Rm[lane * NS + q] = L.vC[lane];
     if (lane == 0) {
-      L.Rm[q * N + q] = nz;
+      L.Rm[q * NS + q] = nz;
       L.Rd[q] = 1.0 / nz;
       L.actid[q] = id; L.actside[q] = side; L.acte[q] = e_full; L.actc[q] = c_full;
     }
@@ -631,7 +636,7 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
     for (int u = 0; u < EPL; ++u) {
       const int e = lane + kWave * u;
       const int row = e / N, col = e - N * (e / N);
-      tmp[u] = (e < N * N && row < q && col >= kd && col < q - 1) ? L.Rm[row * N + col + 1] : 0.0;
+      tmp[u] = (e < N * N && row < q && col >= kd && col < q - 1) ? L.Rm[row * NS + col + 1] : 0.0;
     }
     int id_n = 0, sd_n = 0;
     double e_n = 0, c_n = 0;
@@ -644,7 +649,7 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
     for (int u = 0; u < EPL; ++u) {
       const int e = lane + kWave * u;
       const int row = e / N, col = e - N * (e / N);
-      if (e < N * N && row < q && col >= kd && col < q - 1) L.Rm[row * N + col] = tmp[u];
+      if (e < N * N && row < q && col >= kd && col < q - 1) L.Rm[row * NS + col] = tmp[u];
     }
     if (lane >= kd && lane < q - 1) {
       L.actid[lane] = id_n; L.actside[lane] = sd_n; L.acte[lane] = e_n; L.actc[lane] = c_n;
@@ -652,26 +657,26 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
     }
     __syncthreads();
     for (int j = kd; j < q - 1; ++j) {
-      const double a = L.Rm[j * N + j], b = L.Rm[(j + 1) * N + j];
+      const double a = L.Rm[j * NS + j], b = L.Rm[(j + 1) * NS + j];
       const double rr_ = hypot(a, b);
       const double cg = rr_ > 0.0 ? a / rr_ : 1.0, sg = rr_ > 0.0 ? b / rr_ : 0.0;
       double r1 = 0, r2 = 0, qa = 0, qb = 0;
-      if (lane >= j && lane < q - 1) { r1 = L.Rm[j * N + lane]; r2 = L.Rm[(j + 1) * N + lane]; }
-      if (vl) { qa = L.Q1[j * N + lane]; qb = L.Q1[(j + 1) * N + lane]; }
+      if (lane >= j && lane < q - 1) { r1 = L.Rm[j * NS + lane]; r2 = L.Rm[(j + 1) * NS + lane]; }
+      if (vl) { qa = L.Q1[j * NS + lane]; qb = L.Q1[(j + 1) * NS + lane]; }
       __syncthreads();
       if (lane >= j && lane < q - 1) {
-        L.Rm[j * N + lane] = cg * r1 + sg * r2;
-        L.Rm[(j + 1) * N + lane] = -sg * r1 + cg * r2;
+        L.Rm[j * NS + lane] = cg * r1 + sg * r2;
+        L.Rm[(j + 1) * NS + lane] = -sg * r1 + cg * r2;
       }
       if (vl) {
-        L.Q1[j * N + lane] = cg * qa + sg * qb;
-        L.Q1[(j + 1) * N + lane] = -sg * qa + cg * qb;
+        L.Q1[j * NS + lane] = cg * qa + sg * qb;
+        L.Q1[(j + 1) * NS + lane] = -sg * qa + cg * qb;
       }
       __syncthreads();
     }
     --q;
     if (lane >= q) lamr = 0.0;
-    if (lane < q) L.Rd[lane] = 1.0 / L.Rm[lane * N + lane];
+    if (lane < q) L.Rd[lane] = 1.0 / L.Rm[lane * NS + lane];
     __syncthreads();
   };
 
@@ -682,19 +687,19 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
     for (int k = 0; k < q; ++k) {
       const double wk = wave::bcast(w, k) * L.Rd[k];
       if (lane == k) w = wk;
-      else if (lane > k && lane < q) w -= L.Rm[k * N + lane] * wk;
+      else if (lane > k && lane < q) w -= L.Rm[k * NS + lane] * wk;
     }
     if (vl) L.vD[lane] = v0;
     __syncthreads();
     double u = 0.0;
     if (lane < q) {
-      for (int i = 0; i < N; ++i) u += L.Q1[lane * N + i] * L.vD[i];
+      for (int i = 0; i < N; ++i) u += L.Q1[lane * NS + i] * L.vD[i];
       u -= w;
     }
     for (int k = q - 1; k >= 0; --k) {
       const double lk = wave::bcast(u, k) * L.Rd[k];
       if (lane == k) u = lk;
-      else if (lane < k) u -= L.Rm[lane * N + k] * lk;
+      else if (lane < k) u -= L.Rm[lane * NS + k] * lk;
     }
     lamr = (lane < q) ? u : 0.0;
     __syncthreads();
@@ -760,7 +765,7 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
     double acc = 0.0;
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-      const double rk = L.Rm[lane * N + k], dk = L.vD[k];
+      const double rk = L.Rm[lane * NS + k], dk = L.vD[k];
       acc += (k >= lane && k < q) ? rk * dk : 0.0;
     }
     L.vE[lane] = acc;
@@ -770,7 +775,7 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
     double acc = v0;
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-      const double qk = L.Q1[k * N + lane], ek = L.vE[k];
+      const double qk = L.Q1[k * NS + lane], ek = L.vE[k];
       acc -= (k < q) ? qk * ek : 0.0;
     }
     vw = acc;
@@ -810,7 +815,7 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
     for (int sl = 0; sl < 2; ++sl) {
       const int l = lane + kWave * sl;
       if (l < r) {
-        const double* hr = L.Hd + l * NC;
+        const double* hr = L.Hd + l * HDS;
         double v = 0.0;
         for (int e = 0; e < NC; ++e) v += hr[e] * L.ybuf[e];
         if (write_vals) L.rowval[RB + l] = v;
@@ -857,7 +862,7 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
           e_full = dbd; c_full = double(side) * dcst;
         } else {
           const int sl = bit - NFP - 1;
-          const double* hr = L.Hd + (lane + kWave * sl) * NC;
+          const double* hr = L.Hd + (lane + kWave * sl) * HDS;
           val = 0.0;
           for (int e = 0; e < NC; ++e) val += hr[e] * L.ybuf[e];
           e_full = sl == 0 ? ru[0] : ru[1];
@@ -884,7 +889,7 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
       for (int k = q - 1; k >= 0; --k) {
         const double rk = wave::bcast(rv, k) * L.Rd[k];
         if (lane == k) rv = rk;
-        else if (lane < k) rv -= L.Rm[lane * N + k] * rk;
+        else if (lane < k) rv -= L.Rm[lane * NS + k] * rk;
       }
       const double rmax = wmax((lane < q) ? fabs(rv) : 0.0);
       double t1 = __builtin_huge_val();
@@ -1027,7 +1032,7 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
     if (A.store) A.st_q[inst] = q;
   }
   if (A.store && lane < q) {
-    const int64_t b = (int64_t)inst * D.nmax;
+    const int64_t b = (int64_t)inst * A.st_stride;
     A.st_id[b + lane] = L.actid[lane];
     A.st_side[b + lane] = L.actside[lane];
     A.st_lam[b + lane] = L.lam[lane];
@@ -1059,7 +1064,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void so
 template <int P>
 __device__ void backward_instance(const BackArgs& A, const int inst, char* smem) {
   using I = Inst<P>;
-  constexpr int NFP = I::NFP, N = I::N, NC = I::NC, ND = I::ND;
+  constexpr int NFP = I::NFP, N = I::N, NC = I::NC, ND = I::ND, NS = I::NS, HDS = I::HDS;
   const int lane = threadIdx.x;
   const DegConst& K = c_deg[P];
   const LdsDims& D = A.dims;
@@ -1090,9 +1095,9 @@ __device__ void backward_instance(const BackArgs& A, const int inst, char* smem)
     if (A.flags && lane == 0) A.flags[inst] = 0;
     return;
   }
-  for (int e = lane; e < r * NC; e += kWave) L.Hd[e] = A.H[in.hb + e];
+  for (int e = lane; e < r * NC; e += kWave) L.Hd[e + (e / NC) * (HDS - NC)] = A.H[in.hb + e];
   for (int e = lane; e < nf * 3; e += kWave) L.Af[e] = A.A_face[3 * (int64_t)in.f0 + e];
-  const int64_t sb = (int64_t)inst * D.nmax;
+  const int64_t sb = (int64_t)inst * A.st_stride;
   if (lane < q) {
     L.actid[lane] = A.st_id[sb + lane];
     L.actside[lane] = A.st_side[sb + lane];
@@ -1119,18 +1124,18 @@ __device__ void backward_instance(const BackArgs& A, const int inst, char* smem)
     for (int pass = 0; pass < 2; ++pass) {
       if (lane < k) {
         double acc = 0.0;
-        for (int i = 0; i < N; ++i) acc += L.Q1[lane * N + i] * L.vA[i];
+        for (int i = 0; i < N; ++i) acc += L.Q1[lane * NS + i] * L.vA[i];
         L.vE[lane] = acc;
       }
       __syncthreads();
       if (vl) {
         double acc = L.vA[lane];
-        for (int j = 0; j < k; ++j) acc -= L.Q1[j * N + lane] * L.vE[j];
+        for (int j = 0; j < k; ++j) acc -= L.Q1[j * NS + lane] * L.vE[j];
         L.vB[lane] = acc;
       }
       if (lane < k) {
-        if (pass == 0) L.Rm[lane * N + k] = L.vE[lane];
-        else L.Rm[lane * N + k] += L.vE[lane];
+        if (pass == 0) L.Rm[lane * NS + k] = L.vE[lane];
+        else L.Rm[lane * NS + k] += L.vE[lane];
       }
       __syncthreads();
       if (vl) L.vA[lane] = L.vB[lane];
@@ -1140,8 +1145,8 @@ __device__ void backward_instance(const BackArgs& A, const int inst, char* smem)
     const double nz = sqrt(zz);
     dep |= !(nz > 1e-10);
     const double nzs = nz > 1e-300 ? nz : 1e-300;
-    if (vl) L.Q1[k * N + lane] = L.vA[lane] / nzs;
-    if (lane == 0) L.Rm[k * N + k] = nzs;
+    if (vl) L.Q1[k * NS + lane] = L.vA[lane] / nzs;
+    if (lane == 0) L.Rm[k * NS + k] = nzs;
     __syncthreads();
   }
   // whitened upstream gradient on the free variables
@@ -1152,18 +1157,18 @@ __device__ void backward_instance(const BackArgs& A, const int inst, char* smem)
   __syncthreads();
   // c = Q1^T gh ; omega = R^-1 c ; xi = gh - Q1 c ; w = L^-T xi
   double cv = 0.0;
-  if (lane < q) for (int i = 0; i < N; ++i) cv += L.Q1[lane * N + i] * L.vA[i];
+  if (lane < q) for (int i = 0; i < N; ++i) cv += L.Q1[lane * NS + i] * L.vA[i];
   if (lane < q) L.vE[lane] = cv;
   __syncthreads();
   double om = cv;
   for (int k = q - 1; k >= 0; --k) {
-    const double ok = wave::bcast(om, k) / L.Rm[k * N + k];
+    const double ok = wave::bcast(om, k) / L.Rm[k * NS + k];
     if (lane == k) om = ok;
-    else if (lane < k) om -= L.Rm[lane * N + k] * ok;
+    else if (lane < k) om -= L.Rm[lane * NS + k] * ok;
   }
   if (vl) {
     double acc = L.vA[lane];
-    for (int k = 0; k < q; ++k) acc -= L.Q1[k * N + lane] * L.vE[k];
+    for (int k = 0; k < q; ++k) acc -= L.Q1[k * NS + lane] * L.vE[k];
     L.vB[lane] = acc;
   }
   __syncthreads();
@@ -1213,20 +1218,15 @@ __device__ void backward_instance(const BackArgs& A, const int inst, char* smem)
   if (A.flags && lane == 0) A.flags[inst] = dep ? 1 : 0;
 }
 
+// One launch per group of the work order (same degree P): block b handles
+// order[inst_base + b].
+template <int P>
 __global__ __launch_bounds__(64) void backward_kernel(BackArgs A) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
-  const int inst = blockIdx.x;
-  if (inst >= A.N) return;
-  switch (A.degree[inst]) {
-    case 3: backward_instance<3>(A, inst, smem); break;
-    case 4: backward_instance<4>(A, inst, smem); break;
-    case 5: backward_instance<5>(A, inst, smem); break;
-    case 6: backward_instance<6>(A, inst, smem); break;
-    case 7: backward_instance<7>(A, inst, smem); break;
-    case 8: backward_instance<8>(A, inst, smem); break;
-    case 9: backward_instance<9>(A, inst, smem); break;
-    default: break;
-  }
+  const int b = blockIdx.x + A.inst_base;
+  if (b >= A.N) return;
+  const int inst = A.order ? A.order[b] : b;
+  if (A.degree[inst] == P) backward_instance<P>(A, inst, smem);
 }
 
 }  // namespace
@@ -1240,7 +1240,7 @@ LdsDims make_dims(int pmax, int r_cap, int nf_cap, int real_bytes) {
   d.m_cap = (pmax - 1) * d.nf_cap + 6 * pmax - 3 + d.r_cap;
   int o = 0;
   auto take = [&](int bytes) { const int at = o; o += (bytes + 15) & ~15; return at; };
-  d.o_Hd = take(d.r_cap * d.ncol * 8);
+  d.o_Hd = take(d.r_cap * (d.ncol | 1) * 8);
   d.o_Af = take(d.nf_cap * 3 * 8);
   d.o_rowval = take(d.m_cap * 8);
   d.o_ybuf = take(2 * d.ncol * 8);
@@ -1254,7 +1254,7 @@ LdsDims make_dims(int pmax, int r_cap, int nf_cap, int real_bytes) {
   d.o_Rd = take(d.nmax * 8);
   d.o_region = o;
   // iteration scratch in the precision of the iterations
-  const int hs = ((d.r_cap + 3) & ~3) + 4;
+  const int hs = d.r_cap | 1;
   const int rb = real_bytes;
   int a = d.o_region;
   auto take_r = [&](int bytes) { const int at = a; a += (bytes + 15) & ~15; return at; };
@@ -1266,8 +1266,8 @@ LdsDims make_dims(int pmax, int r_cap, int nf_cap, int real_bytes) {
   d.o_Kx = take_r(d.nmax * d.nmax * rb);
   int b = d.o_region;
   auto take_p = [&](int bytes) { const int at = b; b += (bytes + 15) & ~15; return at; };
-  d.o_Q1 = take_p(d.nmax * d.nmax * 8);
-  d.o_R = take_p(d.nmax * d.nmax * 8);
+  d.o_Q1 = take_p(d.nmax * (d.nmax | 1) * 8);
+  d.o_R = take_p(d.nmax * (d.nmax | 1) * 8);
   d.bytes = a > b ? a : b;
   return d;
 }
@@ -1304,9 +1304,20 @@ hipError_t launch_solve(const SolveArgs& a, int n_blocks, hipStream_t s, bool fp
   return hipGetLastError();
 }
 
-hipError_t launch_backward(const BackArgs& a, hipStream_t s) {
-  if (a.N <= 0) return hipSuccess;
-  hipLaunchKernelGGL(backward_kernel, dim3(a.N), dim3(kWave), a.dims.bytes, s, a);
+hipError_t launch_backward(const BackArgs& a, int n_blocks, hipStream_t s, int pfix) {
+  if (n_blocks <= 0) return hipSuccess;
+  const dim3 g(n_blocks), blk(kWave);
+  const size_t sh = a.dims.bytes;
+  switch (pfix) {
+    case 3: hipLaunchKernelGGL((backward_kernel<3>), g, blk, sh, s, a); break;
+    case 4: hipLaunchKernelGGL((backward_kernel<4>), g, blk, sh, s, a); break;
+    case 5: hipLaunchKernelGGL((backward_kernel<5>), g, blk, sh, s, a); break;
+    case 6: hipLaunchKernelGGL((backward_kernel<6>), g, blk, sh, s, a); break;
+    case 7: hipLaunchKernelGGL((backward_kernel<7>), g, blk, sh, s, a); break;
+    case 8: hipLaunchKernelGGL((backward_kernel<8>), g, blk, sh, s, a); break;
+    case 9: hipLaunchKernelGGL((backward_kernel<9>), g, blk, sh, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -15,6 +15,9 @@ from workloads import gen
 
 pytestmark = pytest.mark.gpu
 
+SCHEDULE1_SKIP = (
+    "persistent claim schedule removed: its first GPU run (graph capture of solve + backward with schedule 1) went silent and was killed; the cause was not found, so the path is switched off and this case stays off the GPU")
+
 
 def gpu_solve(batch, opts=None, b_face=None, x0=None, goal=None):
     from paper_2411_13507_amd.api import SegmentBatchGPU
@@ -189,32 +192,35 @@ def test_maximum_sizes(gpu_available):
     check(b, out, label="max-size")
 
 
-def test_graph_capture_replays_match_eager(gpu_available):
+@pytest.mark.parametrize("schedule", [0, pytest.param(1, marks=pytest.mark.skip(reason=SCHEDULE1_SKIP))])
+def test_graph_capture_replays_match_eager(gpu_available, schedule):
     """solve + backward captured in one graph on torch's stream; every replay
     (with eager work and synchronisations in between) must equal the eager
-    results bitwise."""
+    results bitwise.  Schedule 1 also captures the kernel that zeroes the
+    claim counters."""
     from paper_2411_13507_amd.api import SegmentBatchGPU
     b = gen.gen_cfg2(indices=range(160))
     gb = SegmentBatchGPU(b)
+    so = opts(schedule=schedule) if schedule else None
     dev = gb.device
     x0 = torch.as_tensor(b.x0, device=dev)
     goal = torch.as_tensor(b.goal, device=dev)
     gP = torch.as_tensor(np.random.default_rng(5).standard_normal(3 * gb.points_total), device=dev)
     gC = torch.ones(b.n, dtype=torch.float64, device=dev)
     out = gb.alloc_outputs()
-    gb.solve(x0, goal, out=out)
+    gb.solve(x0, goal, out=out, opts=so)
     gr = gb.backward(gP, gC)
     torch.cuda.synchronize()
     ref = [t.clone() for t in (out.P, out.cost, out.status, out.kkt, gr.x0, gr.goal, gr.b_inst)]
     side = torch.cuda.Stream(device=dev)
     side.wait_stream(torch.cuda.current_stream(dev))
     with torch.cuda.stream(side):
-        gb.solve(x0, goal, out=out)
+        gb.solve(x0, goal, out=out, opts=so)
         gb.backward(gP, gC, out=gr)
     torch.cuda.current_stream(dev).wait_stream(side)
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
-        gb.solve(x0, goal, out=out)
+        gb.solve(x0, goal, out=out, opts=so)
         gb.backward(gP, gC, out=gr)
     for rep in range(4):
         for t in (out.P, out.cost, out.kkt, gr.x0, gr.goal, gr.b_inst):
@@ -225,7 +231,7 @@ def test_graph_capture_replays_match_eager(gpu_available):
         for a, r in zip(got, ref):
             assert torch.equal(torch.nan_to_num(a, nan=1.5), torch.nan_to_num(r, nan=1.5)), rep
         # eager work between replays
-        gb.solve(x0 + 0.0, goal, out=gb.alloc_outputs())
+        gb.solve(x0 + 0.0, goal, out=gb.alloc_outputs(), opts=so)
         torch.cuda.synchronize()
 
 
@@ -242,3 +248,21 @@ def test_autotune_picks_a_candidate_and_results_do_not_change(gpu_available, tmp
     ok = default["status"] == 0
     assert np.nanmax(np.abs(tuned["P"] - default["P"])) <= 1e-9
     check(b, tuned, label="autotuned")
+
+
+@pytest.mark.skip(reason=SCHEDULE1_SKIP)
+def test_persistent_schedule_matches_one_workgroup_per_instance(gpu_available):
+    """Resident workgroups that claim instances through an atomic counter
+    compute every instance exactly as one workgroup per instance does; a
+    second call (counters zeroed again) gives the same bits."""
+    b = gen.gen_cfg2(indices=range(1500))
+    print("case: 1500 uneven segments, persistent schedule", flush=True)
+    _, o0 = gpu_solve(b)
+    gb, o1 = gpu_solve(b, opts=opts(schedule=1))
+    for k in ("P", "cost", "status", "kkt", "iters"):
+        assert np.array_equal(o0[k], o1[k], equal_nan=True), k
+    res = gb.solve(torch.as_tensor(b.x0, device=gb.device), torch.as_tensor(b.goal, device=gb.device),
+                   opts=opts(schedule=1))
+    torch.cuda.synchronize()
+    assert np.array_equal(res.P.cpu().numpy(), o0["P"], equal_nan=True)
+    check(b, o1, idx=list(range(0, b.n, 5)), label="uneven-persistent")
