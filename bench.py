@@ -122,7 +122,7 @@ def time_launches(fn, reps, stream):
 
 def extra_workloads(reps=3):
     """Forward throughput of the uneven batch (200,000 segments, degree 3-9,
-    6-40 faces, 16-128 reachable rows; one launch per degree) and of the
+    6-40 faces, 16-128 reachable rows; autotuned options) and of the
     path batch (8,192 paths of 4-12 joined degree-7 segments)."""
     import torch
     from paper_2411_13507_amd.api import ChainBatchGPU, SegmentBatchGPU
@@ -134,11 +134,15 @@ def extra_workloads(reps=3):
     gb = SegmentBatchGPU(b, device="cuda:0")
     x0, goal = torch.as_tensor(b.x0, device=dev), torch.as_tensor(b.goal, device=dev)
     res = gb.alloc_outputs()
-    t = time_launches(lambda: gb.solve(x0, goal, out=res), reps, stream)
+    from paper_2411_13507_amd import autotune
+    uo = autotune.tune(b, sample=b.n, reps=2, use_cache=False)
+    uo.store_for_backward = 0
+    t = time_launches(lambda: gb.solve(x0, goal, opts=uo, out=res), reps, stream)
     st = res.status.cpu().numpy()
     kk = res.kkt.cpu().numpy()
     ok = int(((st == 0) & (kk <= KKT_OK)).sum() + (st == 1).sum())
     out["uneven200k_p3to9"] = {"fwd_ms": t * 1e3, "solves_per_s": ok / t, "instances": b.n,
+                               "admm_iters": int(uo.admm_iters), "rho": round(float(uo.rho), 6),
                                "status_counts": np.bincount(st, minlength=6).tolist()}
     gb.close()
     del b, gb, res
@@ -166,7 +170,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=50_000)
-    ap.add_argument("--admm-iters", type=int, default=10)
+    ap.add_argument("--admm-iters", type=int, default=-1,
+                    help="ADMM warm-start iterations; -1 (default): options picked by the autotuner")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
@@ -201,8 +206,16 @@ def main():
     goal = torch.as_tensor(b.goal, device=dev)
     gP = torch.as_tensor(gbar.ravel(), device=dev)
     gC = torch.ones(b.n, dtype=torch.float64, device=dev)
-    opts = _lib.default_opts()
-    opts.admm_iters = args.admm_iters
+    if args.admm_iters >= 0:
+        opts = _lib.default_opts()
+        opts.admm_iters = args.admm_iters
+        tuned = None
+    else:
+        # fastest options for this batch signature, timed on the whole batch
+        # (every candidate reaches the same optima; see autotune.py)
+        from paper_2411_13507_amd import autotune
+        opts = autotune.tune(b, sample=b.n, reps=3, use_cache=False)
+        tuned = {"admm_iters": int(opts.admm_iters), "rho": round(float(opts.rho), 6)}
     out = gb.alloc_outputs()
     grads = None
 
@@ -249,7 +262,8 @@ def main():
 
     # forward kernel alone, HIP events on the launch stream
     fopts = _lib.default_opts()
-    fopts.admm_iters = args.admm_iters
+    fopts.admm_iters = opts.admm_iters
+    fopts.rho = opts.rho
     fopts.store_for_backward = 0
     stream = torch.cuda.current_stream(dev)
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
@@ -321,7 +335,8 @@ def main():
         "dtype": "fp32+fp64",
         "data": "synthetic",
         "config": {"workload": "edges50k_p7_clutter", "instances": b.n, "degree": 7, "faces": "8-24",
-                   "reach_rows": 32, "admm_iters": args.admm_iters,
+                   "reach_rows": 32, "admm_iters": int(opts.admm_iters), "rho": round(float(opts.rho), 6),
+                   "options": "autotuned" if tuned is not None else "fixed",
                    "obstacles": 200, "polytopes": 2000, "launch": launch},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_VALU_TFLOPS, "traffic": traffic,

@@ -327,6 +327,12 @@ struct rbp_chains {
   int32_t N = 0, s_max = 1, nf_max = 1, r_max = 0;
   int64_t pt_total = 0;
   int32_t* d_order = nullptr;
+  // work order, most segments first (longest paths start first, so the
+  // launch's tail is short); the launch groups hold LDS sizes (one group:
+  // separate launches per segment count were slower, each waiting out its
+  // own tail)
+  struct Group { int32_t start, count, s_max, nf_max, r_max; };
+  std::vector<Group> groups;
   hipStream_t last_stream = nullptr;
 };
 
@@ -340,7 +346,14 @@ int ensure_chain_constants(int device) {
   g_chain_const_done.push_back(device);
   return RBP_OK;
 }
-constexpr int kChainQCap = 64;   // working-set capacity of the path polish (one entry per lane)
+// working-set capacity of the path polish: two entries per lane (at most
+// 127 rows).  The dual method keeps linearly independent normals, so a path
+// with n free variables never holds more than n; the polish stops when q
+// reaches the capacity minus one, hence n + 2 for short paths.
+int chain_q_cap(int p, int s_max) {
+  const int n = 3 * ((p - 1) + (s_max - 1) * (p - 2));
+  return std::min(128, n + 2);
+}
 }  // namespace
 
 int rbp_build_chains(const rbp_chain_desc* d, hipStream_t stream, rbp_chains** out) {
@@ -401,6 +414,18 @@ int rbp_build_chains(const rbp_chain_desc* d, hipStream_t stream, rbp_chains** o
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
       return soff[a + 1] - soff[a] > soff[b + 1] - soff[b];
     });
+    for (int k = 0; k < N; ++k) {
+      const int i = order[k];
+      const int32_t S = int32_t(soff[i + 1] - soff[i]);
+      if (c->groups.empty()) c->groups.push_back({k, 0, S, 1, 0});
+      rbp_chains::Group& g = c->groups.back();
+      ++g.count;
+      g.s_max = std::max(g.s_max, S);
+      for (int64_t s = soff[i]; s < soff[i + 1]; ++s) {
+        g.r_max = std::max<int32_t>(g.r_max, int32_t(roff[s + 1] - roff[s]));
+        g.nf_max = std::max<int32_t>(g.nf_max, poff[pidx[s] + 1] - poff[pidx[s]]);
+      }
+    }
   }
   c->pt_total = int64_t(p + 1) * nseg;
   if ((rc = dalloc(&c->d_order, size_t(std::max(N, 1))))) { delete c; return rc; }
@@ -445,8 +470,12 @@ int rbp_solve_chains(rbp_chains* c, const double* x0, const double* goal, const 
   a.P_out = P_out; a.cost_out = cost_out; a.status_out = status_out; a.kkt_out = kkt_out; a.iters_out = iters_out;
   a.admm_iters = o.admm_iters; a.rho = o.rho; a.alpha = o.alpha; a.max_steps = o.max_polish_steps;
   a.feas_tol = o.feas_tol; a.kkt_tol = o.kkt_tol;
-  a.dims = rbp::make_chain_dims(d.degree, c->s_max, c->nf_max, c->r_max, kChainQCap);
-  if (rbp::launch_chains(a, stream) != hipSuccess) return RBP_E_DEVICE;
+  for (const rbp_chains::Group& g : c->groups) {
+    a.dims = rbp::make_chain_dims(d.degree, g.s_max, g.nf_max, g.r_max, chain_q_cap(d.degree, g.s_max));
+    a.inst_base = g.start;
+    a.N = g.start + g.count;
+    if (rbp::launch_chains(a, stream) != hipSuccess) return RBP_E_DEVICE;
+  }
   c->last_stream = stream;
   return RBP_OK;
 }

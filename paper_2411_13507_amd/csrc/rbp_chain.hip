@@ -58,7 +58,7 @@ struct CLds {
   float *Kb, *zr, *yr, *accp, *Pf, *xt, *Cs;
   double* Wm;
   // polish region
-  double *LS, *beta, *acte, *u, *w, *zv, *np, *cvec;
+  double *LS, *LSd, *beta, *acte, *u, *w, *zv, *np, *cvec;
   int *actid, *actside, *actseg;
 };
 
@@ -96,6 +96,7 @@ __device__ CLds<P> ccarve(char* s, const ChainDims& D) {
   L.Cs = (float*)(s + D.o_Cs);
   L.Wm = (double*)(s + D.o_Wm);
   L.LS = (double*)(s + D.o_LS);
+  L.LSd = (double*)(s + D.o_LSd);
   L.beta = (double*)(s + D.o_beta);
   L.acte = (double*)(s + D.o_acte);
   L.u = (double*)(s + D.o_u);
@@ -701,7 +702,17 @@ __device__ void chain_instance(const ChainArgs& A, const int ch, char* smem) {
   for (int e = lane; e < n; e += kWave) L.x[e] = L.xu[e];
   __syncthreads();
   int q = 0, steps = 0, status = kPolishFailed;
-  double lamr = 0.0;    // lane k < q: multiplier of active constraint k
+  // Working set of up to QC - 1 <= 127 rows: lane l holds entries l and l + 64
+  // of every working-set vector (multipliers, right-hand sides of the Schur
+  // solves).  L_S is stored packed by rows, row k in k + 2 slots (the spare
+  // slot past the diagonal takes the Givens downdate), with its reciprocal
+  // diagonal in LSd.
+  double lam0 = 0.0, lam1 = 0.0;   // multipliers of entries lane and lane + 64
+  const int e0 = lane, e1 = lane + kWave;
+  auto lso = [](int k) -> int { return (k * (k + 3)) >> 1; };
+  auto pick = [&](double v0, double v1, int k) -> double {
+    return wave::bcast(k < kWave ? v0 : v1, k & (kWave - 1));
+  };
   const double ftol = A.feas_tol;
   const int max_steps = A.max_steps > 0 ? A.max_steps : 8 * n + 64;
 
@@ -741,30 +752,36 @@ __device__ void chain_instance(const ChainArgs& A, const int ch, char* smem) {
     }
     return acc;
   };
-  // c = N^T u for the working set (lane k), u in L.u
-  auto nt_u = [&]() -> double { return lane < q ? ndot(lane, L.u) : 0.0; };
-  // forward / backward solves with L_S (lane k holds entry k)
-  auto ls_forward = [&](double v, int qq) {
+  // c = N^T u for the working set, u in L.u
+  auto nt_u = [&](double& c0, double& c1) {
+    c0 = e0 < q ? ndot(e0, L.u) : 0.0;
+    c1 = e1 < q ? ndot(e1, L.u) : 0.0;
+  };
+  // forward / backward solves with L_S on the first qq entries
+  auto ls_forward = [&](double& v0, double& v1, int qq) {
     for (int k = 0; k < qq; ++k) {
-      const double vk = wave::bcast(v, k) / L.LS[k * QC + k];
-      if (lane == k) v = vk;
-      else if (lane > k && lane < qq) v -= L.LS[lane * QC + k] * vk;
+      const double vk = pick(v0, v1, k) * L.LSd[k];
+      if (e0 == k) v0 = vk;
+      else if (e0 > k && e0 < qq) v0 -= L.LS[lso(e0) + k] * vk;
+      if (e1 == k) v1 = vk;
+      else if (e1 > k && e1 < qq) v1 -= L.LS[lso(e1) + k] * vk;
     }
-    return v;
   };
-  auto ls_backward = [&](double v, int qq) {
+  auto ls_backward = [&](double& v0, double& v1, int qq) {
     for (int k = qq - 1; k >= 0; --k) {
-      const double vk = wave::bcast(v, k) / L.LS[k * QC + k];
-      if (lane == k) v = vk;
-      else if (lane < k) v -= L.LS[k * QC + lane] * vk;
+      const double vk = pick(v0, v1, k) * L.LSd[k];
+      if (e0 == k) v0 = vk;
+      else if (e0 < k) v0 -= L.LS[lso(k) + e0] * vk;
+      if (e1 == k) v1 = vk;
+      else if (e1 < k) v1 -= L.LS[lso(k) + e1] * vk;
     }
-    return v;
   };
-  // w = N r (global), r held by lane k < q
-  auto n_times = [&](double rv, double* out) {
+  // w = N r (global), r given by entries (r0, r1)
+  auto n_times = [&](double r0, double r1, double* out) {
     for (int e = lane; e < n; e += kWave) out[e] = 0.0;
     __syncthreads();
-    if (lane < q) L.cvec[lane] = rv;
+    if (e0 < q) L.cvec[e0] = r0;
+    if (e1 < q) L.cvec[e1] = r1;
     __syncthreads();
     for (int k = 0; k < q; ++k) {
       const int ws = (P - 2) * L.actseg[k];
@@ -797,12 +814,17 @@ __device__ void chain_instance(const ChainArgs& A, const int ch, char* smem) {
     return side > 0 ? hi : -lo;
   };
   // append constraint (id, side) whose normal sits in beta slot q and np;
-  // u = G^-1 np must be in L.u, c = N^T u in cv (lane k); zz = np^T u - |l|^2
-  auto append_factor = [&](int id, int side, double cv, double zz) {
-    const double l = ls_forward(cv, q);
-    if (lane < q) L.LS[q * QC + lane] = l;
+  // u = G^-1 np must be in L.u, c = N^T u in (c0, c1); zz = np^T u - |l|^2
+  auto append_factor = [&](int id, int side, double c0, double c1, double zz) {
+    double l0 = c0, l1 = c1;
+    ls_forward(l0, l1, q);
+    const int ro = lso(q);
+    if (e0 < q) L.LS[ro + e0] = l0;
+    if (e1 < q) L.LS[ro + e1] = l1;
     if (lane == 0) {
-      L.LS[q * QC + q] = sqrt(zz);
+      const double dq = sqrt(zz);
+      L.LS[ro + q] = dq;
+      L.LSd[q] = 1.0 / dq;
       L.actid[q] = id; L.actside[q] = side;
       L.acte[q] = row_e(id, side) - double(side) * row_const(id);
     }
@@ -814,41 +836,67 @@ __device__ void chain_instance(const ChainArgs& A, const int ch, char* smem) {
   auto drop = [&](int kd) {
     set_bit(L.actid[kd], false);
     __syncthreads();
-    // shift rows kd+1.. up by one (row-major L_S, beta slots, ids)
+    // shift rows kd+1.. up by one (packed L_S, beta slots, ids): row k + 1
+    // (columns 0..k+1) becomes row k, whose spare slot takes column k + 1
     for (int k = kd; k < q - 1; ++k) {
-      double rowv = 0.0, bv = 0.0;
-      if (lane < q) rowv = L.LS[(k + 1) * QC + lane];
+      const int rs = lso(k + 1), rd = lso(k);
+      double a0 = 0.0, a1 = 0.0, bv = 0.0;
+      if (e0 <= k + 1) a0 = L.LS[rs + e0];
+      if (e1 <= k + 1) a1 = L.LS[rs + e1];
       if (lane < NC) bv = L.beta[(k + 1) * NC + lane];
       int id = 0, sd = 0, sg = 0;
       double ev = 0.0;
       if (lane == 0) { id = L.actid[k + 1]; sd = L.actside[k + 1]; sg = L.actseg[k + 1]; ev = L.acte[k + 1]; }
       __syncthreads();
-      if (lane < q) L.LS[k * QC + lane] = rowv;
+      if (e0 <= k + 1) L.LS[rd + e0] = a0;
+      if (e1 <= k + 1) L.LS[rd + e1] = a1;
       if (lane < NC) L.beta[k * NC + lane] = bv;
       if (lane == 0) { L.actid[k] = id; L.actside[k] = sd; L.actseg[k] = sg; L.acte[k] = ev; }
       __syncthreads();
     }
     {
-      const double nl = __shfl(lamr, (lane + 1) & 63, kWave);
-      if (lane >= kd && lane < q - 1) lamr = nl;
+      // entry j takes entry j + 1 (entry 64 comes from lane 0's second slot)
+      const double up0 = __shfl(lam0, (lane + 1) & (kWave - 1), kWave);
+      const double up1 = __shfl(lam1, (lane + 1) & (kWave - 1), kWave);
+      const double first1 = wave::bcast(lam1, 0);
+      const double n0 = (lane == kWave - 1) ? first1 : up0;
+      if (e0 >= kd && e0 < q - 1) lam0 = n0;
+      if (e1 >= kd && e1 < q - 1) lam1 = up1;
     }
     // rows kd..q-2 now have an entry one past the diagonal: rotate columns (j, j+1)
     for (int j = kd; j < q - 1; ++j) {
-      const double a = L.LS[j * QC + j], b = L.LS[j * QC + j + 1];
+      const int rj = lso(j);
+      const double a = L.LS[rj + j], b = L.LS[rj + j + 1];
       const double rr = hypot(a, b);
       const double cg = rr > 0.0 ? a / rr : 1.0, sg = rr > 0.0 ? b / rr : 0.0;
-      double x1 = 0, x2 = 0;
-      if (lane >= j && lane < q - 1) { x1 = L.LS[lane * QC + j]; x2 = L.LS[lane * QC + j + 1]; }
+      const bool w0 = e0 >= j && e0 < q - 1, w1 = e1 >= j && e1 < q - 1;
+      double x10 = 0, x20 = 0, x11 = 0, x21 = 0;
+      if (w0) { x10 = L.LS[lso(e0) + j]; x20 = L.LS[lso(e0) + j + 1]; }
+      if (w1) { x11 = L.LS[lso(e1) + j]; x21 = L.LS[lso(e1) + j + 1]; }
       __syncthreads();
-      if (lane >= j && lane < q - 1) {
-        L.LS[lane * QC + j] = cg * x1 + sg * x2;
-        L.LS[lane * QC + j + 1] = -sg * x1 + cg * x2;
+      if (w0) {
+        L.LS[lso(e0) + j] = cg * x10 + sg * x20;
+        L.LS[lso(e0) + j + 1] = -sg * x10 + cg * x20;
+      }
+      if (w1) {
+        L.LS[lso(e1) + j] = cg * x11 + sg * x21;
+        L.LS[lso(e1) + j + 1] = -sg * x11 + cg * x21;
       }
       __syncthreads();
     }
     --q;
-    if (lane >= q) lamr = 0.0;
+    if (e0 >= q) lam0 = 0.0;
+    if (e1 >= q) lam1 = 0.0;
+    if (e0 < q) L.LSd[e0] = 1.0 / L.LS[lso(e0) + e0];
+    if (e1 < q) L.LSd[e1] = 1.0 / L.LS[lso(e1) + e1];
     __syncthreads();
+  };
+  // smallest of the entries < q, lowest index on ties
+  auto min_entry = [&](double v0, double v1, double& mn, int& kd) {
+    mn = e0 < q ? v0 : 1.0;
+    kd = e0;
+    if (e1 < q && v1 < mn) { mn = v1; kd = e1; }
+    wave::argmin(mn, kd);
   };
   auto nplus_dot = [&](int slot, const double* v) -> double { return ndot(slot, v); };
 
@@ -859,28 +907,32 @@ __device__ void chain_instance(const ChainArgs& A, const int ch, char* smem) {
     if ((L.actbits[id >> 5] >> (id & 31)) & 1u) continue;
     load_normal(id, side, q);
     gsolve(L.np, L.u);
-    const double cv = nt_u();
+    double c0, c1;
+    nt_u(c0, c1);
     const double nu = nplus_dot(q, L.u);
-    const double l = ls_forward(cv, q);
-    const double ll = wave::sum(lane < q ? l * l : 0.0);
+    double l0 = c0, l1 = c1;
+    ls_forward(l0, l1, q);
+    const double ll = wave::sum((e0 < q ? l0 * l0 : 0.0) + (e1 < q ? l1 * l1 : 0.0));
     const double zz = nu - ll;
-    if (zz > 1e-10 * nu) append_factor(id, side, cv, zz);
+    if (zz > 1e-10 * nu) append_factor(id, side, c0, c1, zz);
   }
   // dual feasibility of the working set: S lam = N^T x_u - e
   for (int guard = 0; guard <= QC; ++guard) {
     if (q == 0) break;
-    double rhs = 0.0;
-    if (lane < q) rhs = ndot(lane, L.xu) - L.acte[lane];
-    double lm = ls_backward(ls_forward(rhs, q), q);
-    lamr = lane < q ? lm : 0.0;
-    double mn = lane < q ? lamr : 1.0;
-    int kd = lane;
-    wave::argmin(mn, kd);
+    double r0 = e0 < q ? ndot(e0, L.xu) - L.acte[e0] : 0.0;
+    double r1 = e1 < q ? ndot(e1, L.xu) - L.acte[e1] : 0.0;
+    ls_forward(r0, r1, q);
+    ls_backward(r0, r1, q);
+    lam0 = e0 < q ? r0 : 0.0;
+    lam1 = e1 < q ? r1 : 0.0;
+    double mn;
+    int kd;
+    min_entry(lam0, lam1, mn, kd);
     if (mn >= 0.0) break;
     drop(kd);
   }
   if (q > 0) {
-    n_times(lamr, L.w);
+    n_times(lam0, lam1, L.w);
     gsolve(L.w, L.zv);
     for (int e = lane; e < n; e += kWave) L.x[e] = L.xu[e] - L.zv[e];
     __syncthreads();
@@ -921,10 +973,14 @@ __device__ void chain_instance(const ChainArgs& A, const int ch, char* smem) {
     while (!added) {
       ++steps;
       gsolve(L.np, L.u);                      // u = G^-1 n+
-      const double cv = nt_u();               // c = N^T u
-      double rv = ls_backward(ls_forward(cv, q), q);   // r = S^-1 c
-      if (lane >= q) rv = 0.0;
-      n_times(rv, L.w);                       // w = N r
+      double c0, c1;
+      nt_u(c0, c1);                           // c = N^T u
+      double r0 = c0, r1 = c1;                // r = S^-1 c
+      ls_forward(r0, r1, q);
+      ls_backward(r0, r1, q);
+      if (e0 >= q) r0 = 0.0;
+      if (e1 >= q) r1 = 0.0;
+      n_times(r0, r1, L.w);                   // w = N r
       // d = n+ - N r; z = G^-1 d and zz = d^T G^-1 d = |L^-1 d|^2, a sum of
       // squares that is small exactly when n+ lies in the span of N
       for (int e = lane; e < n; e += kWave) L.zv[e] = L.np[e] - L.w[e];
@@ -934,10 +990,11 @@ __device__ void chain_instance(const ChainArgs& A, const int ch, char* smem) {
       const double zz = wave::sum(lane < NF ? f0 * f0 + f1 * f1 + f2 * f2 : 0.0);
       gbwd(f0, f1, f2, L.zv);
       const double nu = nplus_dot(q, L.u);
-      const double rmax = wave::max(lane < q ? fabs(rv) : 0.0);
+      const double rmax = wave::max(fmax(fabs(r0), fabs(r1)));
       double t1 = __builtin_huge_val();
-      int kd = lane;
-      if (lane < q && rv > 1e-13 * rmax) t1 = lamr / rv;
+      int kd = e0;
+      if (e0 < q && r0 > 1e-13 * rmax) t1 = lam0 / r0;
+      if (e1 < q && r1 > 1e-13 * rmax && lam1 / r1 < t1) { t1 = lam1 / r1; kd = e1; }
       wave::argmin(t1, kd);
       // below this ratio the entering normal counts as dependent: the Schur
       // solve for r carries a relative error of about cond(S) * 1e-16
@@ -945,12 +1002,12 @@ __device__ void chain_instance(const ChainArgs& A, const int ch, char* smem) {
       const double t2 = zfull ? splus / zz : __builtin_huge_val();
       if (!(t1 < 1e300) && !(t2 < 1e300)) {
         // Farkas vector: 1 on the entering constraint, -r_k >= 0 on the working set
-        const double wk = lane < q ? fmax(-rv, 0.0) : 0.0;
-        n_times(wk, L.w);
+        const double wk0 = e0 < q ? fmax(-r0, 0.0) : 0.0, wk1 = e1 < q ? fmax(-r1, 0.0) : 0.0;
+        n_times(wk0, wk1, L.w);
         double beta_v = e_free;
         double wabs = fabs(e_free);
         for (int k = 0; k < q; ++k) {
-          const double wkk = wave::bcast(wk, k);
+          const double wkk = pick(wk0, wk1, k);
           beta_v += wkk * L.acte[k];
           wabs += fabs(wkk * L.acte[k]);
         }
@@ -979,13 +1036,15 @@ __device__ void chain_instance(const ChainArgs& A, const int ch, char* smem) {
       if (zfull) {
         for (int e = lane; e < n; e += kWave) L.x[e] -= t * L.zv[e];
       }
-      if (lane < q) lamr -= t * rv;
+      if (e0 < q) lam0 -= t * r0;
+      if (e1 < q) lam1 -= t * r1;
       lamp += t;
       if (zfull) splus -= t * zz;
       __syncthreads();
       if (t2 <= t1) {
-        append_factor(id, side, cv, zz);
-        if (lane == q - 1) lamr = lamp;
+        append_factor(id, side, c0, c1, zz);
+        if (e0 == q - 1) lam0 = lamp;
+        if (e1 == q - 1) lam1 = lamp;
         added = true;
       } else {
         drop(kd);
@@ -1017,7 +1076,7 @@ __device__ void chain_instance(const ChainArgs& A, const int ch, char* smem) {
   pres = wave::max(pres);
   pscale = wave::max(pscale);
   // stationarity on the free variables: G x + q + N lam
-  n_times(fmax(lamr, 0.0), L.w);
+  n_times(fmax(lam0, 0.0), fmax(lam1, 0.0), L.w);
   double st = 0.0, sg = 0.0, sn = 0.0;
   for (int e = lane; e < n; e += kWave) {
     const int i = e / 3, c = e - 3 * (e / 3);
@@ -1036,7 +1095,7 @@ __device__ void chain_instance(const ChainArgs& A, const int ch, char* smem) {
   const double dres = wave::max(st) / (1.0 + fmax(wave::max(sg), wave::max(sn)));
   double cres = 0.0, lmax = 0.0;
   for (int k = 0; k < q; ++k) {
-    const double lk = fmax(wave::bcast(lamr, k), 0.0);
+    const double lk = fmax(pick(lam0, lam1, k), 0.0);
     const int id = L.actid[k];
     const int s = seg_of(id);
     const double v = row_value(s, id - L.rowoff[s], L.Pseg + s * NC);
@@ -1067,7 +1126,7 @@ __device__ void chain_instance(const ChainArgs& A, const int ch, char* smem) {
 template <int P>
 __global__ __launch_bounds__(64) void chain_kernel(ChainArgs A) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
-  const int b = blockIdx.x;
+  const int b = blockIdx.x + A.inst_base;
   if (b >= A.N) return;
   const int ch = A.order ? A.order[b] : b;
   chain_instance<P>(A, ch, smem);
@@ -1118,7 +1177,8 @@ ChainDims make_chain_dims(int p, int s_cap, int nf_cap, int r_cap, int q_cap) {
   d.o_Wm = take_a(2 * NP * NP * 8);
   int b = region;
   auto take_b = [&](int bytes) { const int at = b; b += (bytes + 15) & ~15; return at; };
-  d.o_LS = take_b(d.q_cap * d.q_cap * 8);
+  d.o_LS = take_b(((d.q_cap * (d.q_cap + 3)) >> 1) * 8);   // packed rows, k + 2 slots each
+  d.o_LSd = take_b(d.q_cap * 8);
   d.o_beta = take_b(d.q_cap * NC * 8);
   d.o_acte = take_b(d.q_cap * 8);
   d.o_u = take_b(4 * d.n_cap * 8);
@@ -1138,9 +1198,9 @@ hipError_t upload_chain_constants(int device) {
 }
 
 hipError_t launch_chains(const ChainArgs& a, hipStream_t s) {
-  if (a.N <= 0) return hipSuccess;
+  if (a.N - a.inst_base <= 0) return hipSuccess;
   if (a.P != 7) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((chain_kernel<7>), dim3(a.N), dim3(kWave), a.dims.bytes, s, a);
+  hipLaunchKernelGGL((chain_kernel<7>), dim3(a.N - a.inst_base), dim3(kWave), a.dims.bytes, s, a);
   return hipGetLastError();
 }
 

@@ -113,7 +113,7 @@ struct ChainDims {
   int o_segi, o_seg64, o_Af, o_bfs, o_fan, o_rb, o_rn, o_Pseg, o_gfull, o_G1b, o_L1b, o_L1r, o_qv, o_x, o_scal,
       o_cand, o_bits;
   int o_Kb, o_zr, o_yr, o_accp, o_Pf, o_xt, o_Cs, o_Wm;          // ADMM part of the region
-  int o_LS, o_beta, o_acte, o_u, o_cvec, o_actid;                 // polish part of the region
+  int o_LS, o_LSd, o_beta, o_acte, o_u, o_cvec, o_actid;          // polish part of the region
   int bytes;
 };
 
@@ -133,7 +133,8 @@ struct ChainArgs {
   const double* G;
   const double* x0;
   const double* goal;
-  const int32_t* order;
+  const int32_t* order;      // work order: block b solves order[inst_base + b]
+  int inst_base;             // N is the end of the launch's range
   double* P_out;
   double* cost_out;
   int32_t* status_out;

