@@ -168,10 +168,36 @@ __device__ __forceinline__ double unwhiten_at(const double* Li, double T15, cons
   return T15 * acc;
 }
 
+// Copy n doubles (rows of RL values) from global memory into LDS rows of
+// stride LD, with eight loads in flight per lane before the first store (the
+// instance's rows arrive in one or two HBM round trips instead of one per
+// element).  Returns true if a value is not finite.
+template <int RL, int LD>
+__device__ __forceinline__ bool stage_rows(double* dst, const double* __restrict__ src, int n, int lane) {
+  bool bad = false;
+  for (int base = 0; base < n; base += 8 * kWave) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = base + u * kWave + lane;
+      v[u] = e < n ? src[e] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = base + u * kWave + lane;
+      if (e < n) {
+        dst[e + (e / RL) * (LD - RL)] = v[u];
+        bad |= !isfinite(v[u]);
+      }
+    }
+  }
+  return bad;
+}
+
 // ==========================================================================
 // Forward pass
 // ==========================================================================
-template <int P, typename Real>
+template <int P, typename Real, bool kAdmm>
 __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
   using I = Inst<P>;
   constexpr int NFP = I::NFP, N = I::N, NC = I::NC, ND = I::ND, NS = I::NS, HDS = I::HDS;
@@ -218,12 +244,7 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
   };
 
   // ---- stage instance data in LDS
-  for (int e = lane; e < r * NC; e += kWave) {
-    const double h = A.H[in.hb + e];
-    const int l = e / NC;
-    L.Hd[e + l * (HDS - NC)] = h;
-    bad |= !isfinite(h);
-  }
+  bad |= stage_rows<NC, HDS>(L.Hd, A.H + in.hb, r * NC, lane);
   for (int e = lane; e < nf * 3; e += kWave) L.Af[e] = A.A_face[3 * (int64_t)in.f0 + e];
   if (lane < NC) {
     const int pt = lane / 3, c = lane - 3 * (lane / 3);
@@ -305,223 +326,231 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
   // ======================================================================
   // ADMM in precision Real
   // ======================================================================
-  const Real rho = Real(A.rho), alpha = Real(A.alpha), irho = Real(1) / Real(A.rho);
-  const int K_admm = A.admm_iters;
-  // var lane i < N: row i of M = K^{-1} (K = P + rho A^T D^2 A on the free
-  // variables), linear term q_i
-  Real Mrow[N];
+  const int K_admm = kAdmm ? A.admm_iters : 0;
   const bool vl = lane < N;
   const int vs = lane / 3, vc = lane - 3 * (lane / 3);
-  double qd = 0.0;
+  // rows proposed by the ADMM (z, y) for the polish's warm start: score |y|
+  // per owned row, -1 when not proposed (packed key = 2*id + (side > 0))
+  float sc_f[NFP], sc_d = -1.0f, sc_r[2] = {-1.0f, -1.0f};
+  int side_d = 0;
 #pragma unroll
-  for (int j = 0; j < N; ++j) Mrow[j] = 0;
-  if (K_admm > 0) {
-    // face Gram (3x3 symmetric) of unit face normals
-    double g00, g01, g02, g11, g12, g22;
-    {
-      const double w = fl ? 1.0 / (fan * fan) : 0.0;
-      g00 = wsum(w * fa0 * fa0); g01 = wsum(w * fa0 * fa1); g02 = wsum(w * fa0 * fa2);
-      g11 = wsum(w * fa1 * fa1); g12 = wsum(w * fa1 * fa2); g22 = wsum(w * fa2 * fa2);
-    }
-    // stage FP-Real copies of the rows used by the iteration
-    for (int e = lane; e < r * N; e += kWave) {
-      const int l = e / N, i = e - N * (e / N);
-      L.HfT[i * HS + l] = Real(L.Hd[l * HDS + 3 + i]);
-    }
-    if (fl) { L.Aff[4 * lane] = Real(fa0); L.Aff[4 * lane + 1] = Real(fa1); L.Aff[4 * lane + 2] = Real(fa2); }
-    {
-      // Gram sum_l d_l^2 h_l h_l^T over reachable rows with v_mfma_f32_32x32x2f32:
-      // A = B^T = scaled rows, two rows per instruction (lanes 0-31: row 2t,
-      // lanes 32-63: row 2t+1; column = lane % 32).
-      floatx16 acc;
+  for (int s = 0; s < NFP; ++s) sc_f[s] = -1.0f;
+  // the polish-only variant is compiled without the ADMM (its registers would
+  // otherwise bound the occupancy of the whole kernel)
+  if constexpr (kAdmm) {
+    const Real rho = Real(A.rho), alpha = Real(A.alpha), irho = Real(1) / Real(A.rho);
+    // var lane i < N: row i of M = K^{-1} (K = P + rho A^T D^2 A on the free
+    // variables), linear term q_i
+    Real Mrow[N];
+    double qd = 0.0;
 #pragma unroll
-      for (int g = 0; g < 16; ++g) acc[g] = 0.0f;
-      const int col = lane & 31, half = lane >> 5;
-      for (int t = 0; 2 * t < r; ++t) {
-        const int l = 2 * t + half;
-        float av = 0.0f;
-        if (l < r && col < N) av = float(L.rowval[RB + l] * L.Hd[l * HDS + 3 + col]);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, av, acc, 0, 0, 0);
+    for (int j = 0; j < N; ++j) Mrow[j] = 0;
+    if (K_admm > 0) {
+      // face Gram (3x3 symmetric) of unit face normals
+      double g00, g01, g02, g11, g12, g22;
+      {
+        const double w = fl ? 1.0 / (fan * fan) : 0.0;
+        g00 = wsum(w * fa0 * fa0); g01 = wsum(w * fa0 * fa1); g02 = wsum(w * fa0 * fa2);
+        g11 = wsum(w * fa1 * fa1); g12 = wsum(w * fa1 * fa2); g22 = wsum(w * fa2 * fa2);
+      }
+      // stage FP-Real copies of the rows used by the iteration
+      for (int e = lane; e < r * N; e += kWave) {
+        const int l = e / N, i = e - N * (e / N);
+        L.HfT[i * HS + l] = Real(L.Hd[l * HDS + 3 + i]);
+      }
+      if (fl) { L.Aff[4 * lane] = Real(fa0); L.Aff[4 * lane + 1] = Real(fa1); L.Aff[4 * lane + 2] = Real(fa2); }
+      {
+        // Gram sum_l d_l^2 h_l h_l^T over reachable rows with v_mfma_f32_32x32x2f32:
+        // A = B^T = scaled rows, two rows per instruction (lanes 0-31: row 2t,
+        // lanes 32-63: row 2t+1; column = lane % 32).
+        floatx16 acc;
+#pragma unroll
+        for (int g = 0; g < 16; ++g) acc[g] = 0.0f;
+        const int col = lane & 31, half = lane >> 5;
+        for (int t = 0; 2 * t < r; ++t) {
+          const int l = 2 * t + half;
+          float av = 0.0f;
+          if (l < r && col < N) av = float(L.rowval[RB + l] * L.Hd[l * HDS + 3 + col]);
+          acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, av, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int g = 0; g < 16; ++g) {
+          const int i = 8 * (g >> 2) + 4 * half + (g & 3);
+          if (i < N && col < N) L.Kx[i * N + col] = Real(A.rho * acc[g]);
+        }
+      }
+      __syncthreads();
+      // lane j < N assembles column j of K: Hessian and difference rows in
+      // closed form, face blocks from the face Gram, reachable rows from above
+      Real kc[N];
+      {
+        const double gfa = sel3(vc, g00, g01, g02), gfb = sel3(vc, g01, g11, g12), gfc = sel3(vc, g02, g12, g22);
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+          const int si = i / 3, ci = i - 3 * (i / 3);
+          kc[i] = 0;
+          if (vl) {
+            double v = 0.0;
+            if (ci == vc)
+              v = in.iT3 * (2.0 * L.cQ1[kMaxPts * (si + 1) + vs + 1] + double(A.rho) * L.cGd[kMaxFree * si + vs]);
+            if (si == vs) v += double(A.rho) * in.iT3 / K.kappa[si] * (ci == 0 ? gfa : (ci == 1 ? gfb : gfc));
+            kc[i] = Real(v) + L.Kx[i * N + lane];
+          }
+        }
+      }
+      // Gauss-Jordan sweep on the register columns (K is symmetric positive
+      // definite: no pivoting); afterwards kc = column ``lane`` of -K^{-1}
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        Real pk[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i) pk[i] = wave::bcast(kc[i], k);
+        const Real invd = Real(1) / pk[k];
+        const Real f = kc[k] * invd;
+        const bool isk = lane == k;
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+          if (i == k) kc[i] = isk ? -invd : f;
+          else kc[i] = isk ? pk[i] * invd : kc[i] - pk[i] * f;
+        }
+      }
+      if (vl) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) Mrow[j] = -kc[j];
+        qd = 2.0 * in.iT3 * L.cQ1[kMaxPts * (vs + 1) + P] * sel3(vc, in.dg[0], in.dg[1], in.dg[2]);
+      }
+    }
+    const Real qr = Real(qd);
+    // scaled row data in Real
+    Real ff[NFP], fhi[NFP], zf[NFP], yf[NFP];
+    const Real fa0r = Real(fa0), fa1r = Real(fa1), fa2r = Real(fa2);
+#pragma unroll
+    for (int s = 0; s < NFP; ++s) {
+      ff[s] = Real(fdn[s]); fhi[s] = fl ? Real(fdn[s] * fu) : Real(kBigF);
+      zf[s] = 0; yf[s] = 0;
+    }
+    const Real dd = Real(ddn);
+    const Real dlo = dl ? Real(ddn * (-dbd - dcst)) : Real(-kBigF);
+    const Real dhi = dl ? Real(ddn * (dbd - dcst)) : Real(kBigF);
+    Real zd = 0, yd = 0;
+    // stencil on the free vars (index -1: pinned point)
+    int di0 = -1, di1 = -1, di2 = -1;
+    Real dw0 = 0, dw1 = 0, dw2 = 0;
+    if (dl) {
+      if (dvel) {
+        if (dk + 1 <= NFP) { di0 = 3 * dk + dc; dw0 = Real(dsc); }          // P_{k+1}
+        if (dk >= 1) { di1 = 3 * (dk - 1) + dc; dw1 = Real(-dsc); }          // P_k
+      } else {
+        if (dk + 2 <= NFP) { di0 = 3 * (dk + 1) + dc; dw0 = Real(dsc); }    // P_{k+2}
+        if (dk + 1 >= 1 && dk + 1 <= NFP) { di1 = 3 * dk + dc; dw1 = Real(-2.0 * dsc); }
+        if (dk >= 1) { di2 = 3 * (dk - 1) + dc; dw2 = Real(dsc); }           // P_k
+      }
+    }
+    Real rr[2], rhi[2], zr[2], yr[2];
+#pragma unroll
+    for (int sl = 0; sl < 2; ++sl) {
+      const int l = lane + kWave * sl;
+      rr[sl] = Real(rdn[sl]);
+      rhi[sl] = (l < r) ? Real(rdn[sl] * (ru[sl] - rcst[sl])) : Real(kBigF);
+      zr[sl] = 0; yr[sl] = 0;
+    }
+    auto upd = [&](Real& z, Real& y, Real zh, Real lo, Real hi) {
+      const Real zrl = alpha * zh + (Real(1) - alpha) * z;
+      Real zn = zrl + y * irho;
+      zn = zn < lo ? lo : (zn > hi ? hi : zn);
+      y += rho * (zrl - zn);
+      z = zn;
+    };
+    for (int it = 0; it < K_admm; ++it) {
+      // v = D (rho z - y), in row order
+      if (fl) {
+#pragma unroll
+        for (int s = 0; s < NFP; ++s) L.vbuf[s * nf + lane] = ff[s] * (rho * zf[s] - yf[s]);
+      }
+      if (dl) L.vbuf[F + lane] = dd * (rho * zd - yd);
+#pragma unroll
+      for (int sl = 0; sl < 2; ++sl) {
+        const int l = lane + kWave * sl;
+        if (l < r) L.vbuf[RB + l] = rr[sl] * (rho * zr[sl] - yr[sl]);
+      }
+      __syncthreads();
+      if (vl) {
+        // A^T v with four partial sums so that the LDS loads overlap
+        Real t0 = 0, t1 = 0, t2 = 0, t3 = 0;
+        const int k = vs + 1;
+        const Real* vf = L.vbuf + vs * nf;
+        int j = 0;
+        for (; j + 4 <= nf; j += 4) {
+          t0 += L.Aff[4 * j + vc] * vf[j];
+          t1 += L.Aff[4 * j + 4 + vc] * vf[j + 1];
+          t2 += L.Aff[4 * j + 8 + vc] * vf[j + 2];
+          t3 += L.Aff[4 * j + 12 + vc] * vf[j + 3];
+        }
+        for (; j < nf; ++j) t0 += L.Aff[4 * j + vc] * vf[j];
+        const Real* hrow = L.HfT + lane * HS;
+        const Real* vr = L.vbuf + RB;
+        int l = 0;
+#pragma unroll 2
+        for (; l + 4 <= r; l += 4) {
+          t0 += hrow[l] * vr[l];
+          t1 += hrow[l + 1] * vr[l + 1];
+          t2 += hrow[l + 2] * vr[l + 2];
+          t3 += hrow[l + 3] * vr[l + 3];
+        }
+        for (; l < r; ++l) t0 += hrow[l] * vr[l];
+        Real t = (t0 + t1) + (t2 + t3);
+        t += Real(in.sv) * (L.vbuf[F + 3 * (k - 1) + vc] - L.vbuf[F + 3 * k + vc]);
+        const int AB = F + 3 * P;
+        if (k >= 2) t += Real(in.sa) * L.vbuf[AB + 3 * (k - 2) + vc];
+        t -= Real(2.0 * in.sa) * L.vbuf[AB + 3 * (k - 1) + vc];
+        if (k <= P - 2) t += Real(in.sa) * L.vbuf[AB + 3 * k + vc];
+        L.xb1[lane] = t - qr;
+      }
+      __syncthreads();
+      if (vl) {
+        Real x = 0;
+#pragma unroll
+        for (int j = 0; j < N; ++j) x += Mrow[j] * L.xb1[j];
+        L.xb2[lane] = x;
+      }
+      __syncthreads();
+      if (fl) {
+#pragma unroll
+        for (int s = 0; s < NFP; ++s) {
+          const Real zh = ff[s] * (fa0r * L.xb2[3 * s] + fa1r * L.xb2[3 * s + 1] + fa2r * L.xb2[3 * s + 2]);
+          upd(zf[s], yf[s], zh, Real(-kBigF), fhi[s]);
+        }
+      }
+      if (dl) {
+        Real v = 0;
+        if (di0 >= 0) v += dw0 * L.xb2[di0];
+        if (di1 >= 0) v += dw1 * L.xb2[di1];
+        if (di2 >= 0) v += dw2 * L.xb2[di2];
+        upd(zd, yd, dd * v, dlo, dhi);
       }
 #pragma unroll
-      for (int g = 0; g < 16; ++g) {
-        const int i = 8 * (g >> 2) + 4 * half + (g & 3);
-        if (i < N && col < N) L.Kx[i * N + col] = Real(A.rho * acc[g]);
-      }
-    }
-    __syncthreads();
-    // lane j < N assembles column j of K: Hessian and difference rows in
-    // closed form, face blocks from the face Gram, reachable rows from above
-    Real kc[N];
-    {
-      const double gfa = sel3(vc, g00, g01, g02), gfb = sel3(vc, g01, g11, g12), gfc = sel3(vc, g02, g12, g22);
-#pragma unroll
-      for (int i = 0; i < N; ++i) {
-        const int si = i / 3, ci = i - 3 * (i / 3);
-        kc[i] = 0;
-        if (vl) {
-          double v = 0.0;
-          if (ci == vc)
-            v = in.iT3 * (2.0 * L.cQ1[kMaxPts * (si + 1) + vs + 1] + double(A.rho) * L.cGd[kMaxFree * si + vs]);
-          if (si == vs) v += double(A.rho) * in.iT3 / K.kappa[si] * (ci == 0 ? gfa : (ci == 1 ? gfb : gfc));
-          kc[i] = Real(v) + L.Kx[i * N + lane];
+      for (int sl = 0; sl < 2; ++sl) {
+        const int l = lane + kWave * sl;
+        if (l < r) {
+          Real v = 0;
+          for (int i = 0; i < N; ++i) v += L.HfT[i * HS + l] * L.xb2[i];
+          upd(zr[sl], yr[sl], rr[sl] * v, Real(-kBigF), rhi[sl]);
         }
       }
     }
-    // Gauss-Jordan sweep on the register columns (K is symmetric positive
-    // definite: no pivoting); afterwards kc = column ``lane`` of -K^{-1}
+    // proposed active set from (z, y)
 #pragma unroll
-    for (int k = 0; k < N; ++k) {
-      Real pk[N];
-#pragma unroll
-      for (int i = 0; i < N; ++i) pk[i] = wave::bcast(kc[i], k);
-      const Real invd = Real(1) / pk[k];
-      const Real f = kc[k] * invd;
-      const bool isk = lane == k;
-#pragma unroll
-      for (int i = 0; i < N; ++i) {
-        if (i == k) kc[i] = isk ? -invd : f;
-        else kc[i] = isk ? pk[i] * invd : kc[i] - pk[i] * f;
-      }
-    }
-    if (vl) {
-#pragma unroll
-      for (int j = 0; j < N; ++j) Mrow[j] = -kc[j];
-      qd = 2.0 * in.iT3 * L.cQ1[kMaxPts * (vs + 1) + P] * sel3(vc, in.dg[0], in.dg[1], in.dg[2]);
-    }
-  }
-  const Real qr = Real(qd);
-  // scaled row data in Real
-  Real ff[NFP], fhi[NFP], zf[NFP], yf[NFP];
-  const Real fa0r = Real(fa0), fa1r = Real(fa1), fa2r = Real(fa2);
-#pragma unroll
-  for (int s = 0; s < NFP; ++s) {
-    ff[s] = Real(fdn[s]); fhi[s] = fl ? Real(fdn[s] * fu) : Real(kBigF);
-    zf[s] = 0; yf[s] = 0;
-  }
-  const Real dd = Real(ddn);
-  const Real dlo = dl ? Real(ddn * (-dbd - dcst)) : Real(-kBigF);
-  const Real dhi = dl ? Real(ddn * (dbd - dcst)) : Real(kBigF);
-  Real zd = 0, yd = 0;
-  // stencil on the free vars (index -1: pinned point)
-  int di0 = -1, di1 = -1, di2 = -1;
-  Real dw0 = 0, dw1 = 0, dw2 = 0;
-  if (dl) {
-    if (dvel) {
-      if (dk + 1 <= NFP) { di0 = 3 * dk + dc; dw0 = Real(dsc); }          // P_{k+1}
-      if (dk >= 1) { di1 = 3 * (dk - 1) + dc; dw1 = Real(-dsc); }          // P_k
-    } else {
-      if (dk + 2 <= NFP) { di0 = 3 * (dk + 1) + dc; dw0 = Real(dsc); }    // P_{k+2}
-      if (dk + 1 >= 1 && dk + 1 <= NFP) { di1 = 3 * dk + dc; dw1 = Real(-2.0 * dsc); }
-      if (dk >= 1) { di2 = 3 * (dk - 1) + dc; dw2 = Real(dsc); }           // P_k
-    }
-  }
-  Real rr[2], rhi[2], zr[2], yr[2];
-#pragma unroll
-  for (int sl = 0; sl < 2; ++sl) {
-    const int l = lane + kWave * sl;
-    rr[sl] = Real(rdn[sl]);
-    rhi[sl] = (l < r) ? Real(rdn[sl] * (ru[sl] - rcst[sl])) : Real(kBigF);
-    zr[sl] = 0; yr[sl] = 0;
-  }
-  auto upd = [&](Real& z, Real& y, Real zh, Real lo, Real hi) {
-    const Real zrl = alpha * zh + (Real(1) - alpha) * z;
-    Real zn = zrl + y * irho;
-    zn = zn < lo ? lo : (zn > hi ? hi : zn);
-    y += rho * (zrl - zn);
-    z = zn;
-  };
-  for (int it = 0; it < K_admm; ++it) {
-    // v = D (rho z - y), in row order
-    if (fl) {
-#pragma unroll
-      for (int s = 0; s < NFP; ++s) L.vbuf[s * nf + lane] = ff[s] * (rho * zf[s] - yf[s]);
-    }
-    if (dl) L.vbuf[F + lane] = dd * (rho * zd - yd);
-#pragma unroll
-    for (int sl = 0; sl < 2; ++sl) {
-      const int l = lane + kWave * sl;
-      if (l < r) L.vbuf[RB + l] = rr[sl] * (rho * zr[sl] - yr[sl]);
-    }
-    __syncthreads();
-    if (vl) {
-      // A^T v with four partial sums so that the LDS loads overlap
-      Real t0 = 0, t1 = 0, t2 = 0, t3 = 0;
-      const int k = vs + 1;
-      const Real* vf = L.vbuf + vs * nf;
-      int j = 0;
-      for (; j + 4 <= nf; j += 4) {
-        t0 += L.Aff[4 * j + vc] * vf[j];
-        t1 += L.Aff[4 * j + 4 + vc] * vf[j + 1];
-        t2 += L.Aff[4 * j + 8 + vc] * vf[j + 2];
-        t3 += L.Aff[4 * j + 12 + vc] * vf[j + 3];
-      }
-      for (; j < nf; ++j) t0 += L.Aff[4 * j + vc] * vf[j];
-      const Real* hrow = L.HfT + lane * HS;
-      const Real* vr = L.vbuf + RB;
-      int l = 0;
-#pragma unroll 2
-      for (; l + 4 <= r; l += 4) {
-        t0 += hrow[l] * vr[l];
-        t1 += hrow[l + 1] * vr[l + 1];
-        t2 += hrow[l + 2] * vr[l + 2];
-        t3 += hrow[l + 3] * vr[l + 3];
-      }
-      for (; l < r; ++l) t0 += hrow[l] * vr[l];
-      Real t = (t0 + t1) + (t2 + t3);
-      t += Real(in.sv) * (L.vbuf[F + 3 * (k - 1) + vc] - L.vbuf[F + 3 * k + vc]);
-      const int AB = F + 3 * P;
-      if (k >= 2) t += Real(in.sa) * L.vbuf[AB + 3 * (k - 2) + vc];
-      t -= Real(2.0 * in.sa) * L.vbuf[AB + 3 * (k - 1) + vc];
-      if (k <= P - 2) t += Real(in.sa) * L.vbuf[AB + 3 * k + vc];
-      L.xb1[lane] = t - qr;
-    }
-    __syncthreads();
-    if (vl) {
-      Real x = 0;
-#pragma unroll
-      for (int j = 0; j < N; ++j) x += Mrow[j] * L.xb1[j];
-      L.xb2[lane] = x;
-    }
-    __syncthreads();
-    if (fl) {
-#pragma unroll
-      for (int s = 0; s < NFP; ++s) {
-        const Real zh = ff[s] * (fa0r * L.xb2[3 * s] + fa1r * L.xb2[3 * s + 1] + fa2r * L.xb2[3 * s + 2]);
-        upd(zf[s], yf[s], zh, Real(-kBigF), fhi[s]);
-      }
-    }
+    for (int s = 0; s < NFP; ++s)
+      sc_f[s] = (fl && (fhi[s] - zf[s] < yf[s])) ? float(fabs(double(yf[s]))) : -1.0f;
     if (dl) {
-      Real v = 0;
-      if (di0 >= 0) v += dw0 * L.xb2[di0];
-      if (di1 >= 0) v += dw1 * L.xb2[di1];
-      if (di2 >= 0) v += dw2 * L.xb2[di2];
-      upd(zd, yd, dd * v, dlo, dhi);
+      if (dhi - zd < yd) { sc_d = float(fabs(double(yd))); side_d = 1; }
+      else if (zd - dlo < -yd) { sc_d = float(fabs(double(yd))); side_d = -1; }
     }
 #pragma unroll
     for (int sl = 0; sl < 2; ++sl) {
       const int l = lane + kWave * sl;
-      if (l < r) {
-        Real v = 0;
-        for (int i = 0; i < N; ++i) v += L.HfT[i * HS + l] * L.xb2[i];
-        upd(zr[sl], yr[sl], rr[sl] * v, Real(-kBigF), rhi[sl]);
-      }
+      sc_r[sl] = (l < r && (rhi[sl] - zr[sl] < yr[sl])) ? float(fabs(double(yr[sl]))) : -1.0f;
     }
-  }
-  // proposed active set from (z, y): packed key = 2*id + (side > 0)
-  float sc_f[NFP], sc_d = -1.0f, sc_r[2];
-#pragma unroll
-  for (int s = 0; s < NFP; ++s)
-    sc_f[s] = (fl && (fhi[s] - zf[s] < yf[s])) ? float(fabs(double(yf[s]))) : -1.0f;
-  int side_d = 0;
-  if (dl) {
-    if (dhi - zd < yd) { sc_d = float(fabs(double(yd))); side_d = 1; }
-    else if (zd - dlo < -yd) { sc_d = float(fabs(double(yd))); side_d = -1; }
-  }
-#pragma unroll
-  for (int sl = 0; sl < 2; ++sl) {
-    const int l = lane + kWave * sl;
-    sc_r[sl] = (l < r && (rhi[sl] - zr[sl] < yr[sl])) ? float(fabs(double(yr[sl]))) : -1.0f;
   }
   __syncthreads();   // ADMM scratch is reused by the polish from here on
 
@@ -707,7 +736,7 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
 
   // ---- warm start from the ADMM proposal
   const int max_steps = A.max_steps > 0 ? A.max_steps : 8 * N + 64;
-  for (int add = 0; add < N; ++add) {
+  for (int add = 0; kAdmm && add < N; ++add) {
     double best = -1.0;
     int key = 0x7fffffff;
 #pragma unroll
@@ -749,38 +778,43 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
     const double aa = wsum(vl ? L.vA[lane] * L.vA[lane] : 0.0);
     if (zz > 1e-16 * aa && q < N) append(sqrt(zz), id, side, e_full, c_full);
   }
-  // make the working set dual feasible
-  for (int guard = 0; guard <= N; ++guard) {
-    solve_lambda();
-    double mn = (lane < q) ? lamr : 1.0;
-    int kd = lane;
-    wargmin(mn, kd);
-    if (q == 0 || mn >= 0.0) break;
-    drop(kd);
-  }
-  // v = v0 - Q1 R lam
-  if (lane < q) L.vD[lane] = lamr;
-  __syncthreads();
-  if (lane < q) {
-    double acc = 0.0;
-#pragma unroll
-    for (int k = 0; k < N; ++k) {
-      const double rk = L.Rm[lane * NS + k], dk = L.vD[k];
-      acc += (k >= lane && k < q) ? rk * dk : 0.0;
+  if (q == 0) {
+    // no warm start: the unconstrained minimiser
+    vw = vl ? v0 : 0.0;
+  } else {
+    // make the working set dual feasible
+    for (int guard = 0; guard <= N; ++guard) {
+      solve_lambda();
+      double mn = (lane < q) ? lamr : 1.0;
+      int kd = lane;
+      wargmin(mn, kd);
+      if (q == 0 || mn >= 0.0) break;
+      drop(kd);
     }
-    L.vE[lane] = acc;
-  }
-  __syncthreads();
-  if (vl) {
-    double acc = v0;
+    // v = v0 - Q1 R lam
+    if (lane < q) L.vD[lane] = lamr;
+    __syncthreads();
+    if (lane < q) {
+      double acc = 0.0;
 #pragma unroll
-    for (int k = 0; k < N; ++k) {
-      const double qk = L.Q1[k * NS + lane], ek = L.vE[k];
-      acc -= (k < q) ? qk * ek : 0.0;
+      for (int k = 0; k < N; ++k) {
+        const double rk = L.Rm[lane * NS + k], dk = L.vD[k];
+        acc += (k >= lane && k < q) ? rk * dk : 0.0;
+      }
+      L.vE[lane] = acc;
     }
-    vw = acc;
+    __syncthreads();
+    if (vl) {
+      double acc = v0;
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        const double qk = L.Q1[k * NS + lane], ek = L.vE[k];
+        acc -= (k < q) ? qk * ek : 0.0;
+      }
+      vw = acc;
+    }
+    __syncthreads();
   }
-  __syncthreads();
 
   // ---- main loop
   // evaluate all rows on ybuf, return most violated inactive row
@@ -842,7 +876,7 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
     double best;
     int key;
     double dummy;
-    eval_rows(best, key, dummy, false);
+    eval_rows(best, key, dummy, true);   // the last pass leaves the solution's row values
     if (!(best > 0.0)) { status = kSolved; break; }
     if (steps >= max_steps || key < 0 || (key >> 1) >= m) { status = kPolishFailed; break; }
     const int id = key >> 1, side = (key & 1) ? 1 : -1;
@@ -958,11 +992,8 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
   }
 
   // ---- solution, KKT residuals, cost
-  refresh_y();
-  double best;
-  int key;
-  double dummy;
-  eval_rows(best, key, dummy, true);   // row values into rowval
+  // ybuf and rowval hold the solution and its row values from the main
+  // loop's last pass (no row was violated there)
   __syncthreads();
   // primal residual and scale over all rows (owners)
   double pres = 0.0, pscale = 0.0;
@@ -1041,13 +1072,13 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
 
 // One launch per degree P: block b solves order[inst_base + b]; instances
 // are grouped by degree in the work order.
-template <typename Real, int P>
+template <typename Real, int P, bool kAdmm>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void solve_kernel(SolveArgs A) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
   const int b = blockIdx.x + A.inst_base;
   if (b >= A.N) return;
   const int inst = A.order ? A.order[b] : b;
-  if (A.degree[inst] == P) solve_instance<P, Real>(A, inst, smem);
+  if (A.degree[inst] == P) solve_instance<P, Real, kAdmm>(A, inst, smem);
   else if (threadIdx.x == 0) A.status_out[inst] = kInvalid;
 }
 
@@ -1095,7 +1126,7 @@ __device__ void backward_instance(const BackArgs& A, const int inst, char* smem)
     if (A.flags && lane == 0) A.flags[inst] = 0;
     return;
   }
-  for (int e = lane; e < r * NC; e += kWave) L.Hd[e + (e / NC) * (HDS - NC)] = A.H[in.hb + e];
+  (void)stage_rows<NC, HDS>(L.Hd, A.H + in.hb, r * NC, lane);
   for (int e = lane; e < nf * 3; e += kWave) L.Af[e] = A.A_face[3 * (int64_t)in.f0 + e];
   const int64_t sb = (int64_t)inst * A.st_stride;
   if (lane < q) {
@@ -1281,26 +1312,29 @@ hipError_t upload_constants(int device) {
   return hipMemcpyToSymbol(HIP_SYMBOL(c_deg), host, sizeof(host), 0, hipMemcpyHostToDevice);
 }
 
-template <typename Real>
+template <typename Real, bool kAdmm>
 static void launch_solve_t(const SolveArgs& a, int n_blocks, hipStream_t s, int pfix) {
   const dim3 g(n_blocks), blk(kWave);
   const size_t sh = a.dims.bytes;
   switch (pfix) {
-    case 3: hipLaunchKernelGGL((solve_kernel<Real, 3>), g, blk, sh, s, a); break;
-    case 4: hipLaunchKernelGGL((solve_kernel<Real, 4>), g, blk, sh, s, a); break;
-    case 5: hipLaunchKernelGGL((solve_kernel<Real, 5>), g, blk, sh, s, a); break;
-    case 6: hipLaunchKernelGGL((solve_kernel<Real, 6>), g, blk, sh, s, a); break;
-    case 7: hipLaunchKernelGGL((solve_kernel<Real, 7>), g, blk, sh, s, a); break;
-    case 8: hipLaunchKernelGGL((solve_kernel<Real, 8>), g, blk, sh, s, a); break;
-    case 9: hipLaunchKernelGGL((solve_kernel<Real, 9>), g, blk, sh, s, a); break;
+    case 3: hipLaunchKernelGGL((solve_kernel<Real, 3, kAdmm>), g, blk, sh, s, a); break;
+    case 4: hipLaunchKernelGGL((solve_kernel<Real, 4, kAdmm>), g, blk, sh, s, a); break;
+    case 5: hipLaunchKernelGGL((solve_kernel<Real, 5, kAdmm>), g, blk, sh, s, a); break;
+    case 6: hipLaunchKernelGGL((solve_kernel<Real, 6, kAdmm>), g, blk, sh, s, a); break;
+    case 7: hipLaunchKernelGGL((solve_kernel<Real, 7, kAdmm>), g, blk, sh, s, a); break;
+    case 8: hipLaunchKernelGGL((solve_kernel<Real, 8, kAdmm>), g, blk, sh, s, a); break;
+    case 9: hipLaunchKernelGGL((solve_kernel<Real, 9, kAdmm>), g, blk, sh, s, a); break;
     default: break;
   }
 }
 
+// polish only (no ADMM iterations): one variant, its iteration precision is
+// irrelevant; otherwise FP32 or FP64 iterations
 hipError_t launch_solve(const SolveArgs& a, int n_blocks, hipStream_t s, bool fp64_iters, int pfix) {
   if (n_blocks <= 0) return hipSuccess;
-  if (fp64_iters) launch_solve_t<double>(a, n_blocks, s, pfix);
-  else launch_solve_t<float>(a, n_blocks, s, pfix);
+  if (a.admm_iters == 0) launch_solve_t<float, false>(a, n_blocks, s, pfix);
+  else if (fp64_iters) launch_solve_t<double, true>(a, n_blocks, s, pfix);
+  else launch_solve_t<float, true>(a, n_blocks, s, pfix);
   return hipGetLastError();
 }
 
