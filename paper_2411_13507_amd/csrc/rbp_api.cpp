@@ -260,7 +260,7 @@ int rbp_solve_batch(rbp_batch* b, const double* x0, const double* goal, const do
   hipError_t e = hipSuccess;
   if (o.plain) {
     a.order = nullptr;
-    a.dims = rbp::make_dims(b->pmax, b->rmax, b->nfmax, 8);
+    a.dims = rbp::make_dims(b->pmax, b->rmax, b->nfmax, 8, o.admm_iters > 0);
     for (int i = 0; i < b->N && e == hipSuccess; ++i) {
       a.inst_base = i;
       e = rbp::launch_solve(a, 1, stream, true, b->degree_host[i]);
@@ -269,7 +269,7 @@ int rbp_solve_batch(rbp_batch* b, const double* x0, const double* goal, const do
     a.order = b->d_order;
     for (size_t k = 0; k < b->groups.size() && e == hipSuccess; ++k) {
       const rbp_batch::Group& g = b->groups[k];
-      a.dims = rbp::make_dims(g.p, g.rmax, g.nfmax, 4);
+      a.dims = rbp::make_dims(g.p, g.rmax, g.nfmax, 4, o.admm_iters > 0);
       a.inst_base = g.start;
       a.N = g.start + g.count;
       e = rbp::launch_solve(a, g.count, stream, false, g.p);
@@ -312,7 +312,7 @@ int rbp_backward(rbp_batch* b, const double* grad_P, const double* grad_cost, do
   a.st_stride = b->nmax;
   for (size_t k = 0; k < b->groups.size(); ++k) {
     const rbp_batch::Group& g = b->groups[k];
-    a.dims = rbp::make_dims(g.p, g.rmax, g.nfmax, 8);
+    a.dims = rbp::make_dims(g.p, g.rmax, g.nfmax, 8, false);
     a.inst_base = g.start;
     a.N = g.start + g.count;
     if (rbp::launch_backward(a, g.count, stream, g.p) != hipSuccess) return RBP_E_DEVICE;

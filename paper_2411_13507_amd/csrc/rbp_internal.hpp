@@ -28,7 +28,7 @@ struct LdsDims {
   // byte offsets
   int o_Hd, o_Af, o_rowval, o_ybuf, o_vec, o_scal, o_acte, o_lam, o_actid, o_actside, o_cst, o_Rd, o_region;
   int o_Hf, o_Aff, o_vbuf, o_xb1, o_xb2, o_Kx;   // ADMM part of region
-  int o_Q1, o_R;                                  // polish part of region
+  int o_Q1, o_R, o_Ri;                            // polish part of region
   int bytes;
 };
 
@@ -147,7 +147,8 @@ struct ChainArgs {
   ChainDims dims;
 };
 
-LdsDims make_dims(int pmax, int r_cap, int nf_cap, int real_bytes);
+// admm = false: no room for the ADMM iteration (polish only)
+LdsDims make_dims(int pmax, int r_cap, int nf_cap, int real_bytes, bool admm);
 ChainDims make_chain_dims(int p, int s_cap, int nf_cap, int r_cap, int q_cap);
 hipError_t upload_chain_constants(int device);
 hipError_t launch_chains(const ChainArgs& a, hipStream_t s);

@@ -62,6 +62,7 @@ struct Lds {
   Real *HfT, *Aff, *vbuf, *xb1, *xb2, *Kx;
   double *Q1, *Rm;
   double *cL1i, *cQ1, *cGd, *Rd;   // staged degree tables; reciprocal diagonal of R
+  double *Ri;                      // R^-1 (upper triangular, same stride as R)
 };
 
 template <typename Real>
@@ -95,6 +96,7 @@ __device__ Lds<Real> carve(char* s, const LdsDims& D) {
   L.cQ1 = L.cL1i + kMaxFree * kMaxFree;
   L.cGd = L.cQ1 + kMaxPts * kMaxPts;
   L.Rd = (double*)(s + D.o_Rd);
+  L.Ri = (double*)(s + D.o_Ri);
   return L;
 }
 
@@ -250,12 +252,13 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
     const int pt = lane / 3, c = lane - 3 * (lane / 3);
     L.ybuf[lane] = (pt == P) ? sel3(c, in.dg[0], in.dg[1], in.dg[2]) : 0.0;
   }
-  // degree tables read with lane-dependent indices
-  for (int e = lane; e < kMaxFree * kMaxFree; e += kWave) {
-    L.cL1i[e] = (&K.L1inv[0][0])[e];
-    L.cGd[e] = (&K.Gdiff[0][0])[e];
+  // degree tables read with lane-dependent indices (the Hessian and the
+  // difference-row Gram only for the ADMM matrix)
+  for (int e = lane; e < kMaxFree * kMaxFree; e += kWave) L.cL1i[e] = (&K.L1inv[0][0])[e];
+  if constexpr (kAdmm) {
+    for (int e = lane; e < kMaxFree * kMaxFree; e += kWave) L.cGd[e] = (&K.Gdiff[0][0])[e];
+    for (int e = lane; e < kMaxPts * kMaxPts; e += kWave) L.cQ1[e] = (&K.Q1[0][0])[e];
   }
-  for (int e = lane; e < kMaxPts * kMaxPts; e += kWave) L.cQ1[e] = (&K.Q1[0][0])[e];
   __syncthreads();
 
   // ---- face rows: lane j < nf owns face j on every interior point
@@ -573,7 +576,7 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
     double acc = 0.0;
 #pragma unroll
     for (int t = 0; t < NFP; ++t) {
-      const double w = L.cL1i[kMaxFree * vs + t] * L.cQ1[kMaxPts * (t + 1) + P];
+      const double w = L.cL1i[kMaxFree * vs + t] * K.Q1[t + 1][P];
       acc += (t <= vs) ? w : 0.0;
     }
     v0 = -in.T15 * 2.0 * in.iT3 * sel3(vc, in.dg[0], in.dg[1], in.dg[2]) * acc;
@@ -597,24 +600,32 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
     __syncthreads();
   };
 
-  // c = Q1^T a, z = a - Q1 c (twice, classical Gram-Schmidt with one
-  // re-orthogonalisation); a in vA, z -> vB, c -> vC (first q entries)
-  auto project = [&]() {
+  // c = Q1^T a, z = a - Q1 c by classical Gram-Schmidt; a in vA, z -> vB,
+  // c -> vC (first q entries), zz = |z|^2, aa = |a|^2.  A second pass
+  // re-orthogonalises only when the first lost more than half of |a|^2
+  // (the Kahan-Parlett "twice is enough" test).
+  auto project = [&](double& zz, double& aa) {
     if (lane < q) {
       double acc = 0.0;
       for (int i = 0; i < N; ++i) acc += L.Q1[lane * NS + i] * L.vA[i];
       L.vC[lane] = acc;
     }
     __syncthreads();
+    double za = 0.0, zb = 0.0;
     if (vl) {
-      double acc = L.vA[lane];
+      za = L.vA[lane];
+      double acc = za;
 #pragma unroll
       for (int k = 0; k < N; ++k) {
         const double qk = L.Q1[k * NS + lane], ck = L.vC[k];
         acc -= (k < q) ? qk * ck : 0.0;
       }
       L.vB[lane] = acc;
+      zb = acc;
     }
+    aa = wsum(za * za);
+    zz = wsum(zb * zb);
+    if (!(zz < 0.5 * aa) || q == 0) return;
     __syncthreads();
     if (lane < q) {
       double acc = 0.0;
@@ -622,6 +633,7 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
       L.vE[lane] = acc;
     }
     __syncthreads();
+    double zc = 0.0;
     if (vl) {
       double acc = L.vB[lane];
 #pragma unroll
@@ -630,18 +642,53 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
         acc -= (k < q) ? qk * ek : 0.0;
       }
       L.vB[lane] = acc;
+      zc = acc;
     }
     if (lane < q) L.vC[lane] += L.vE[lane];
+    zz = wsum(zc * zc);
     __syncthreads();
   };
 
-  // append the projected direction as a new basis column (R gets c and |z|)
-  auto append = [&](double nz, int id, int side, double e_full, double c_full) {
-    if (vl) L.Q1[q * NS + lane] = L.vB[lane] / nz;
-    if (lane < q) L.Rm[lane * NS + q] = L.vC[lane];
+  // r = R^-1 c, c in vC (lane i < q gets r_i)
+  auto ri_times_c = [&]() -> double {
+    double acc = 0.0;
+    if (lane < q) {
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        const double xk = L.Ri[lane * NS + k], ck = L.vC[k];
+        acc += (k >= lane && k < q) ? xk * ck : 0.0;
+      }
+    }
+    return acc;
+  };
+  // R^-1 rebuilt by back substitution after a downdate: lane j builds column
+  // j (entries i <= j); each lane reads back only its own column
+  auto ri_rebuild = [&]() {
+    for (int i = q - 1; i >= 0; --i) {
+      double acc = (i == lane) ? 1.0 : 0.0;
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        const double rik = L.Rm[i * NS + k], xk = L.Ri[k * NS + lane];
+        acc -= (k > i && k <= lane && k < q) ? rik * xk : 0.0;
+      }
+      if (lane < q && i <= lane) L.Ri[i * NS + lane] = acc * L.Rd[i];
+    }
+    __syncthreads();
+  };
+
+  // append the projected direction as a new basis column (R gets c and |z|;
+  // R^-1 gets -R^-1 c / |z| and 1/|z|, with rv = R^-1 c on lanes < q)
+  auto append = [&](double nz, int id, int side, double e_full, double c_full, double rv) {
+    const double inz = 1.0 / nz;
+    if (vl) L.Q1[q * NS + lane] = L.vB[lane] * inz;
+    if (lane < q) {
+      L.Rm[lane * NS + q] = L.vC[lane];
+      L.Ri[lane * NS + q] = -rv * inz;
+    }
     if (lane == 0) {
       L.Rm[q * NS + q] = nz;
-      L.Rd[q] = 1.0 / nz;
+      L.Rd[q] = inz;
+      L.Ri[q * NS + q] = inz;
       L.actid[q] = id; L.actside[q] = side; L.acte[q] = e_full; L.actc[q] = c_full;
     }
     int ol, bit;
@@ -707,6 +754,7 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
     if (lane >= q) lamr = 0.0;
     if (lane < q) L.Rd[lane] = 1.0 / L.Rm[lane * NS + lane];
     __syncthreads();
+    ri_rebuild();
   };
 
   // multipliers of the current working set at the minimiser on its face:
@@ -773,10 +821,9 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
     __syncthreads();
     const double e_full = L.scal[0], c_full = L.scal[1];
     build_normal(id, side);
-    project();
-    const double zz = wsum(vl ? L.vB[lane] * L.vB[lane] : 0.0);
-    const double aa = wsum(vl ? L.vA[lane] * L.vA[lane] : 0.0);
-    if (zz > 1e-16 * aa && q < N) append(sqrt(zz), id, side, e_full, c_full);
+    double zz, aa;
+    project(zz, aa);
+    if (zz > 1e-16 * aa && q < N) append(sqrt(zz), id, side, e_full, c_full, ri_times_c());
   }
   if (q == 0) {
     // no warm start: the unconstrained minimiser
@@ -915,16 +962,9 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
     bool added = false;
     while (!added) {
       ++steps;
-      project();
-      const double zz = wsum(vl ? L.vB[lane] * L.vB[lane] : 0.0);
-      const double aa = wsum(vl ? L.vA[lane] * L.vA[lane] : 0.0);
-      // r = R^-1 c
-      double rv = (lane < q) ? L.vC[lane] : 0.0;
-      for (int k = q - 1; k >= 0; --k) {
-        const double rk = wave::bcast(rv, k) * L.Rd[k];
-        if (lane == k) rv = rk;
-        else if (lane < k) rv -= L.Rm[lane * NS + k] * rk;
-      }
+      double zz, aa;
+      project(zz, aa);
+      const double rv = ri_times_c();   // r = R^-1 c
       const double rmax = wmax((lane < q) ? fabs(rv) : 0.0);
       double t1 = __builtin_huge_val();
       int kd = lane;
@@ -973,7 +1013,7 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
       lamp += t;
       if (zfull) splus -= t * zz;
       if (t2 <= t1) {
-        append(sqrt(zz), id, side, e_full, c_full);
+        append(sqrt(zz), id, side, e_full, c_full, rv);
         if (lane == q - 1) lamr = lamp;
         added = true;
       } else {
@@ -1026,7 +1066,7 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
   if (lane < NC) {
     const int pt = lane / 3, c = lane - 3 * (lane / 3);
 #pragma unroll
-    for (int b = 0; b <= P; ++b) qy += L.cQ1[kMaxPts * pt + b] * L.ybuf[3 * b + c];
+    for (int b = 0; b <= P; ++b) qy += K.Q1[pt][b] * L.ybuf[3 * b + c];
     qy *= in.iT3;
     L.qbuf[lane] = qy;
   }
@@ -1262,7 +1302,7 @@ __global__ __launch_bounds__(64) void backward_kernel(BackArgs A) {
 
 }  // namespace
 
-LdsDims make_dims(int pmax, int r_cap, int nf_cap, int real_bytes) {
+LdsDims make_dims(int pmax, int r_cap, int nf_cap, int real_bytes, bool admm) {
   LdsDims d{};
   d.nmax = 3 * (pmax - 1);
   d.ncol = 3 * (pmax + 1);
@@ -1281,7 +1321,7 @@ LdsDims make_dims(int pmax, int r_cap, int nf_cap, int real_bytes) {
   d.o_lam = take(d.nmax * 8);
   d.o_actid = take(d.nmax * 4);
   d.o_actside = take(d.nmax * 4);
-  d.o_cst = take((2 * kMaxFree * kMaxFree + kMaxPts * kMaxPts) * 8);
+  d.o_cst = take((admm ? 2 * kMaxFree * kMaxFree + kMaxPts * kMaxPts : kMaxFree * kMaxFree) * 8);
   d.o_Rd = take(d.nmax * 8);
   d.o_region = o;
   // iteration scratch in the precision of the iterations
@@ -1289,16 +1329,21 @@ LdsDims make_dims(int pmax, int r_cap, int nf_cap, int real_bytes) {
   const int rb = real_bytes;
   int a = d.o_region;
   auto take_r = [&](int bytes) { const int at = a; a += (bytes + 15) & ~15; return at; };
-  d.o_Hf = take_r(d.nmax * hs * rb);
-  d.o_Aff = take_r(d.nf_cap * 4 * rb);
-  d.o_vbuf = take_r(d.m_cap * rb);
-  d.o_xb1 = take_r(d.nmax * rb);
-  d.o_xb2 = take_r(d.nmax * rb);
-  d.o_Kx = take_r(d.nmax * d.nmax * rb);
+  if (admm) {
+    d.o_Hf = take_r(d.nmax * hs * rb);
+    d.o_Aff = take_r(d.nf_cap * 4 * rb);
+    d.o_vbuf = take_r(d.m_cap * rb);
+    d.o_xb1 = take_r(d.nmax * rb);
+    d.o_xb2 = take_r(d.nmax * rb);
+    d.o_Kx = take_r(d.nmax * d.nmax * rb);
+  } else {
+    d.o_Hf = d.o_Aff = d.o_vbuf = d.o_xb1 = d.o_xb2 = d.o_Kx = d.o_region;   // unused
+  }
   int b = d.o_region;
   auto take_p = [&](int bytes) { const int at = b; b += (bytes + 15) & ~15; return at; };
   d.o_Q1 = take_p(d.nmax * (d.nmax | 1) * 8);
   d.o_R = take_p(d.nmax * (d.nmax | 1) * 8);
+  d.o_Ri = take_p(d.nmax * (d.nmax | 1) * 8);
   d.bytes = a > b ? a : b;
   return d;
 }
