@@ -543,3 +543,59 @@ def generate_chains(n: int = 8192, workers: Optional[int] = None) -> ChainBatch:
     with mp.get_context("fork").Pool(workers) as pool:
         parts = pool.map(_gen_chain_chunk, chunks)
     return concat_chains(parts)
+
+
+# ---------------------------------------------------------------------------
+# Cutting graph edges against obstacles (Sec. III-B, Alg. 2, eq. Cut-QP)
+# ---------------------------------------------------------------------------
+@dataclass
+class CutBatch:
+    """Edges (degree-p Bezier control points) and axis-aligned box obstacles.
+
+    P[e, k, c]: coordinate c of control point k of edge e; box_lo/box_hi:
+    [n_obstacles, 3]."""
+    name: str
+    degree: int
+    P: np.ndarray
+    box_lo: np.ndarray
+    box_hi: np.ndarray
+
+    @property
+    def n_edges(self) -> int:
+        return self.P.shape[0]
+
+    @property
+    def n_obstacles(self) -> int:
+        return self.box_lo.shape[0]
+
+
+def gen_cut(n_nodes: int = 5000, k_nn: int = 10, n_obst: int = 200, p: int = 7, cfg: int = 5,
+            bend: float = 0.15) -> CutBatch:
+    """Graph edges over the obstacle field of the cluttered environment: nodes
+    uniform in [0, 10]^3 outside every obstacle, each joined to its k nearest
+    neighbours (about n_nodes * k_nn edges; 5,000 nodes and 10 neighbours give
+    the 50,000 edges of Sec. IV-A), the curve of an edge being the straight
+    degree-p segment between its nodes with the interior control points moved
+    by N(0, bend * length) per coordinate (curved edges).  Obstacles: the
+    first n_obst boxes of the environment."""
+    env = environment(1)
+    lo, hi = env.obs_lo[:n_obst], env.obs_hi[:n_obst]
+    rng = np.random.default_rng(np.random.SeedSequence(1000 + cfg, spawn_key=(3,)))
+    nodes = []
+    while len(nodes) < n_nodes:
+        c = rng.uniform(0.0, 10.0, size=(2 * n_nodes, 3))
+        ok = ~np.any(np.all((c[:, None, :] >= lo[None]) & (c[:, None, :] <= hi[None]), axis=2), axis=1)
+        nodes.extend(c[ok][: n_nodes - len(nodes)])
+    V = np.asarray(nodes)
+    d2 = ((V[:, None, :] - V[None, :, :]) ** 2).sum(-1)
+    np.fill_diagonal(d2, np.inf)
+    nbr = np.argsort(d2, axis=1)[:, :k_nn]
+    src = np.repeat(np.arange(n_nodes), k_nn)
+    dst = nbr.reshape(-1)
+    a, b = V[src], V[dst]
+    t = np.arange(p + 1) / p
+    P = a[:, None, :] + t[None, :, None] * (b - a)[:, None, :]
+    length = np.linalg.norm(b - a, axis=1)
+    P[:, 1:p, :] += rng.standard_normal((len(src), p - 1, 3)) * (bend * length)[:, None, None]
+    return CutBatch(name=f"cut{len(src)}_o{n_obst}", degree=p, P=np.ascontiguousarray(P),
+                    box_lo=np.ascontiguousarray(lo), box_hi=np.ascontiguousarray(hi))
