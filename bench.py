@@ -146,6 +146,23 @@ def extra_workloads(reps=3):
                                "status_counts": np.bincount(st, minlength=6).tolist()}
     gb.close()
     del b, gb, res
+    # graph cut (Alg. 2 + Cut-QP): 50,000 edges x 200 box obstacles, codes and
+    # per-edge collision counts (the cut graph)
+    from paper_2411_13507_amd.api import CutGPU
+    cb_ = gen.gen_cut()
+    cg = CutGPU(cb_, cb_.n_edges, device="cuda:0")
+    Pc = torch.as_tensor(cb_.P, device=dev)
+    cres = cg.alloc()
+    t = time_launches(lambda: cg.run(Pc, out=cres, with_step=False, with_dist=False), reps, stream)
+    n_qp = cg.qp_count()
+    cg.run(Pc, out=cres)
+    steps = np.bincount(cres.step.cpu().numpy().ravel(), minlength=4)[1:].tolist()
+    n_pairs = cb_.n_edges * cb_.n_obstacles
+    out["cut50k_o200"] = {"ms": t * 1e3, "pairs_per_s": n_pairs / t, "edges": cb_.n_edges,
+                          "obstacles": cb_.n_obstacles, "pairs_by_step": steps, "qp_pairs": n_qp,
+                          "edges_cut": int((cres.n_collide.cpu().numpy() > 0).sum())}
+    cg.close()
+    del cres, Pc
     c = gen.generate_chains(8192)
     cb = ChainBatchGPU(c, device="cuda:0")
     x0, goal = torch.as_tensor(c.x0, device=dev), torch.as_tensor(c.goal, device=dev)

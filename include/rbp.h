@@ -237,6 +237,63 @@ int rbp_solve_chains(rbp_chains* chains, const double* x0, const double* goal, c
 /* Releases a path batch (no-op for NULL). */
 void rbp_destroy_chains(rbp_chains* chains);
 
+/* ------------------------------------------------------------------------
+ * Cutting graph edges against obstacles (Sec. III-B, Alg. 2, eq. Cut-QP).
+ *
+ * A pair is an edge, the control points of its degree-p Bezier curve, and
+ * an axis-aligned box obstacle lo <= x <= hi.  By the convex-hull property
+ * (Property 1) the curve is free of the box when conv(P) and the box are
+ * disjoint.  Each pair runs Alg. 2: (1) a control point inside the box ->
+ * may collide; (2) every control point strictly beyond the box's supporting
+ * plane with normal centroid - clamp(centroid) -> free; (3) otherwise the
+ * Cut-QP, whose optimum |delta*|^2 is, for a box, the squared distance
+ * between conv(P) and the box: free when it is positive.
+ * ------------------------------------------------------------------------ */
+typedef struct rbp_cut_desc {
+  int32_t n_edges;            /* >= 0                                         */
+  int32_t n_obstacles;        /* >= 0                                         */
+  int32_t degree;             /* 1..RBP_MAX_DEGREE, the same for every edge    */
+  int32_t reserved;           /* 0                                            */
+  const double* box_lo;       /* device [n_obstacles][3]                      */
+  const double* box_hi;       /* device [n_obstacles][3], hi >= lo             */
+} rbp_cut_desc;
+
+typedef struct rbp_cut rbp_cut;
+
+/* Upper bound on n_edges * n_obstacles (the undecided-pair list is sized
+ * for every pair). */
+#define RBP_CUT_MAX_PAIRS (1LL << 28)
+
+/*
+ * Keeps the obstacle arrays (device pointers, owned by the caller, which
+ * must keep them alive) and allocates the undecided-pair list.
+ * Errors: RBP_E_INVALID (null pointers, negative counts), RBP_E_SHAPE
+ * (degree out of range, more than RBP_CUT_MAX_PAIRS pairs), RBP_E_ALLOC.
+ */
+int rbp_build_cut(const rbp_cut_desc* desc, hipStream_t stream, rbp_cut** out);
+
+/*
+ * Classifies every (edge, obstacle) pair; stream-ordered, asynchronous.
+ *   P          device [n_edges][degree+1][3] control points (point-major)
+ *   code       device [n_obstacles][n_edges] uint8: 1 free, 0 may collide
+ *   step       nullable, same shape: the step of Alg. 2 that decided (1, 2, 3)
+ *   qp_dist2   nullable, same shape, double: |delta*|^2 where step 3 ran,
+ *              NaN where the heuristic decided
+ *   n_collide  device [n_edges] int32: obstacles the edge may collide with
+ *              (0 = the edge stays in the cut graph)
+ * Codes are obstacle-major: pair (e, o) is at o * n_edges + e.
+ * Errors: RBP_E_INVALID (null pointers), RBP_E_DEVICE.
+ */
+int rbp_cut_run(rbp_cut* cut, const double* P, uint8_t* code, uint8_t* step, double* qp_dist2,
+                int32_t* n_collide, hipStream_t stream);
+
+/* Number of pairs the last rbp_cut_run sent to step 3 (synchronises the
+ * stream of that run).  Errors: RBP_E_INVALID, RBP_E_DEVICE. */
+int rbp_cut_qp_count(rbp_cut* cut, int64_t* n_qp);
+
+/* Frees the list (waits for the last run). */
+void rbp_destroy_cut(rbp_cut* cut);
+
 /* Static string for a call result or per-instance status code. */
 const char* rbp_status_string(int code);
 

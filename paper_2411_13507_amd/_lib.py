@@ -15,6 +15,7 @@ EXPORTED = (
     "rbp_default_opts", "rbp_build_batch", "rbp_batch_get_sizes", "rbp_solve_batch",
     "rbp_backward", "rbp_destroy_batch", "rbp_status_string",
     "rbp_build_chains", "rbp_chains_get_sizes", "rbp_solve_chains", "rbp_destroy_chains",
+    "rbp_build_cut", "rbp_cut_run", "rbp_cut_qp_count", "rbp_destroy_cut",
 )
 
 _p = ctypes.c_void_p
@@ -35,6 +36,13 @@ class ChainDesc(ctypes.Structure):
         ("reserved", ctypes.c_int32), ("T", ctypes.c_double), ("vmax", ctypes.c_double),
         ("amax", ctypes.c_double), ("seg_off", _p), ("poly_off", _p), ("A_face", _p), ("b_face", _p),
         ("poly_idx", _p), ("reach_off", _p), ("H_off", _p), ("H", _p), ("h0", _p), ("G", _p),
+    ]
+
+
+class CutDesc(ctypes.Structure):
+    _fields_ = [
+        ("n_edges", ctypes.c_int32), ("n_obstacles", ctypes.c_int32), ("degree", ctypes.c_int32),
+        ("reserved", ctypes.c_int32), ("box_lo", _p), ("box_hi", _p),
     ]
 
 
@@ -89,6 +97,14 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.rbp_solve_chains.restype = ctypes.c_int
     L.rbp_destroy_chains.argtypes = [_p]
     L.rbp_destroy_chains.restype = None
+    L.rbp_build_cut.argtypes = [ctypes.POINTER(CutDesc), _p, ctypes.POINTER(_p)]
+    L.rbp_build_cut.restype = ctypes.c_int
+    L.rbp_cut_run.argtypes = [_p, _p, _p, _p, _p, _p, _p]
+    L.rbp_cut_run.restype = ctypes.c_int
+    L.rbp_cut_qp_count.argtypes = [_p, ctypes.POINTER(ctypes.c_int64)]
+    L.rbp_cut_qp_count.restype = ctypes.c_int
+    L.rbp_destroy_cut.argtypes = [_p]
+    L.rbp_destroy_cut.restype = None
     L.rbp_status_string.argtypes = [ctypes.c_int]
     L.rbp_status_string.restype = ctypes.c_char_p
     _LIB = L

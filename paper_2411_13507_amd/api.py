@@ -226,3 +226,71 @@ class ChainBatchGPU:
                                           _stream_handle(d))
         _lib.check(rc, "rbp_solve_chains")
         return o
+
+
+@dataclass
+class CutResult:
+    code: torch.Tensor        # [n_obstacles, n_edges] uint8: 1 free, 0 may collide
+    step: torch.Tensor        # [n_obstacles, n_edges] uint8: step of Alg. 2 that decided
+    qp_dist2: torch.Tensor    # [n_obstacles, n_edges] float64: |delta*|^2 where step 3 ran, NaN elsewhere
+    n_collide: torch.Tensor   # [n_edges] int32: obstacles the edge may collide with
+
+
+class CutGPU:
+    """Graph edges cut against axis-aligned box obstacles on one GPU (Alg. 2
+    with the Cut-QP for the undecided pairs).  ``problem`` has box_lo and
+    box_hi ([n_obstacles, 3]) and degree, e.g. ``workloads.gen.CutBatch``;
+    the edges' control points are passed to each run."""
+
+    def __init__(self, problem, n_edges: int, device: str = "cuda"):
+        if not torch.cuda.is_available():
+            raise _lib.RbpError("no GPU visible: the cut kernels run only on the GPU")
+        self.device = torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device(self.device.type, torch.cuda.current_device())
+        L = _lib.load()
+        d = self.device
+        self.box_lo = _dev(problem.box_lo, torch.float64, d)
+        self.box_hi = _dev(problem.box_hi, torch.float64, d)
+        self.n_edges, self.n_obst, self.degree = int(n_edges), int(self.box_lo.shape[0]), int(problem.degree)
+        desc = _lib.CutDesc(self.n_edges, self.n_obst, self.degree, 0, _ptr(self.box_lo), _ptr(self.box_hi))
+        h = ctypes.c_void_p()
+        with torch.cuda.device(d):
+            _lib.check(L.rbp_build_cut(ctypes.byref(desc), _stream_handle(d), ctypes.byref(h)), "rbp_build_cut")
+        self._h = h
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            _lib.load().rbp_destroy_cut(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def alloc(self) -> CutResult:
+        d, E, O = self.device, self.n_edges, self.n_obst
+        return CutResult(code=torch.empty((O, E), dtype=torch.uint8, device=d),
+                         step=torch.empty((O, E), dtype=torch.uint8, device=d),
+                         qp_dist2=torch.empty((O, E), dtype=torch.float64, device=d),
+                         n_collide=torch.empty(E, dtype=torch.int32, device=d))
+
+    def run(self, P: torch.Tensor, out: Optional[CutResult] = None, with_step: bool = True,
+            with_dist: bool = True) -> CutResult:
+        """Classify every (edge, obstacle) pair; P is [n_edges, degree+1, 3]
+        float64 on the device."""
+        o = out or self.alloc()
+        P = P.contiguous()
+        rc = _lib.load().rbp_cut_run(self._h, _ptr(P), _ptr(o.code), _ptr(o.step) if with_step else None,
+                                     _ptr(o.qp_dist2) if with_dist else None, _ptr(o.n_collide),
+                                     _stream_handle(self.device))
+        _lib.check(rc, "rbp_cut_run")
+        return o
+
+    def qp_count(self) -> int:
+        """Pairs the last run sent to the Cut-QP (synchronises)."""
+        v = ctypes.c_int64()
+        _lib.check(_lib.load().rbp_cut_qp_count(self._h, ctypes.byref(v)), "rbp_cut_qp_count")
+        return int(v.value)

@@ -496,4 +496,86 @@ void rbp_destroy_batch(rbp_batch* b) {
   free_batch(b);
 }
 
+struct rbp_cut {
+  int device = 0;
+  rbp_cut_desc desc{};
+  unsigned long long* counter = nullptr;
+  int64_t* list = nullptr;
+  int64_t cap = 0;
+  int qp_blocks = 0;
+  hipStream_t last_stream = nullptr;
+};
+
+int rbp_build_cut(const rbp_cut_desc* d, hipStream_t stream, rbp_cut** out) {
+  if (!d || !out) return RBP_E_INVALID;
+  *out = nullptr;
+  if (d->n_edges < 0 || d->n_obstacles < 0 || d->reserved != 0) return RBP_E_INVALID;
+  if (d->n_obstacles > 0 && (!d->box_lo || !d->box_hi)) return RBP_E_INVALID;
+  if (d->degree < 1 || d->degree > RBP_MAX_DEGREE) return RBP_E_SHAPE;
+  const int64_t pairs = int64_t(d->n_edges) * d->n_obstacles;
+  if (pairs > RBP_CUT_MAX_PAIRS) return RBP_E_SHAPE;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return RBP_E_DEVICE;
+  auto* c = new (std::nothrow) rbp_cut();
+  if (!c) return RBP_E_ALLOC;
+  c->device = dev;
+  c->desc = *d;
+  c->cap = std::max<int64_t>(pairs, 1);
+  int rc;
+  if ((rc = dalloc(&c->counter, 1)) || (rc = dalloc(&c->list, size_t(c->cap)))) {
+    if (c->counter) (void)hipFree(c->counter);
+    delete c;
+    return rc;
+  }
+  // the count reads 0 until the first run (which zeroes it with a kernel)
+  if (hipMemsetAsync(c->counter, 0, sizeof(unsigned long long), stream) != hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess) {
+    (void)hipFree(c->counter);
+    (void)hipFree(c->list);
+    delete c;
+    return RBP_E_DEVICE;
+  }
+  int n_cu = 0;
+  if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n_cu < 1) n_cu = 1;
+  c->qp_blocks = 4 * n_cu;   // grid-stride over the undecided pairs
+  c->last_stream = stream;
+  *out = c;
+  return RBP_OK;
+}
+
+int rbp_cut_run(rbp_cut* c, const double* P, uint8_t* code, uint8_t* step, double* qp_dist2, int32_t* n_collide,
+                hipStream_t stream) {
+  if (!c) return RBP_E_INVALID;
+  const rbp_cut_desc& d = c->desc;
+  if (d.n_edges == 0) return RBP_OK;
+  if (!P || !n_collide || (d.n_obstacles > 0 && !code)) return RBP_E_INVALID;
+  rbp::CutArgs a{};
+  a.n_edges = d.n_edges; a.n_obst = d.n_obstacles; a.degree = d.degree;
+  a.P = P; a.box_lo = d.box_lo; a.box_hi = d.box_hi;
+  a.code = code; a.step = step; a.qp_dist2 = qp_dist2; a.n_collide = n_collide;
+  a.counter = c->counter; a.list = c->list; a.list_cap = c->cap;
+  if (rbp::launch_cut(a, stream, c->qp_blocks) != hipSuccess) return RBP_E_DEVICE;
+  c->last_stream = stream;
+  return RBP_OK;
+}
+
+int rbp_cut_qp_count(rbp_cut* c, int64_t* n_qp) {
+  if (!c || !n_qp) return RBP_E_INVALID;
+  unsigned long long v = 0;
+  if (hipStreamSynchronize(c->last_stream) != hipSuccess ||
+      hipMemcpy(&v, c->counter, sizeof(v), hipMemcpyDeviceToHost) != hipSuccess)
+    return RBP_E_DEVICE;
+  *n_qp = int64_t(v);
+  return RBP_OK;
+}
+
+void rbp_destroy_cut(rbp_cut* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  if (c->last_stream) (void)hipStreamSynchronize(c->last_stream);
+  if (c->counter) (void)hipFree(c->counter);
+  if (c->list) (void)hipFree(c->list);
+  delete c;
+}
+
 }  // extern "C"

@@ -147,6 +147,22 @@ struct ChainArgs {
   ChainDims dims;
 };
 
+// ---- cutting graph edges against box obstacles (rbp_cut.hip)
+struct CutArgs {
+  int n_edges, n_obst, degree;
+  const double* P;           // [n_edges][degree+1][3]
+  const double* box_lo;      // [n_obst][3]
+  const double* box_hi;      // [n_obst][3]
+  uint8_t* code;             // [n_obst][n_edges]: 1 free, 0 may collide
+  uint8_t* step;             // nullable [n_obst][n_edges]: 1, 2 or 3 (Alg. 2 step that decided)
+  double* qp_dist2;          // nullable [n_obst][n_edges]: |delta*|^2 where step 3 ran, NaN elsewhere
+  int32_t* n_collide;        // [n_edges]: obstacles the edge may collide with
+  unsigned long long* counter;   // pairs appended to the list (device scalar)
+  int64_t* list;             // undecided pairs (o << 32 | e)
+  int64_t list_cap;
+};
+hipError_t launch_cut(const CutArgs& a, hipStream_t s, int qp_blocks);
+
 // admm = false: no room for the ADMM iteration (polish only)
 LdsDims make_dims(int pmax, int r_cap, int nf_cap, int real_bytes, bool admm);
 ChainDims make_chain_dims(int p, int s_cap, int nf_cap, int r_cap, int q_cap);

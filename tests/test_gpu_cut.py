@@ -1,0 +1,168 @@
+"""GPU cut of graph edges against box obstacles (Alg. 2 with the Cut-QP)
+against the FP64 oracle, through the C ABI.
+
+Integer outputs (the free / may-collide code, the step that decided) are
+compared bit for bit wherever floating point cannot flip them: a pair whose
+step-2 plane margin, or whose LP margin for the Cut-QP, is within rounding
+of zero is only checked for a valid outcome.  |delta*|^2 is compared within
+1e-9 relative (+1e-12)."""
+import multiprocessing as mp
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import cut as ocut
+from workloads import gen
+
+pytestmark = pytest.mark.gpu
+
+D2_RTOL, D2_ATOL = 1e-9, 1e-12
+
+
+def run_gpu(b, P=None):
+    from paper_2411_13507_amd.api import CutGPU
+    g = CutGPU(b, b.n_edges)
+    Pd = torch.as_tensor(b.P if P is None else P, device=g.device)
+    r = g.run(Pd)
+    nqp = g.qp_count()
+    torch.cuda.synchronize()
+    out = dict(code=r.code.cpu().numpy(), step=r.step.cpu().numpy(), d2=r.qp_dist2.cpu().numpy(),
+               n_collide=r.n_collide.cpu().numpy(), n_qp=nqp)
+    g.close()
+    return out
+
+
+def _plane_margin(P, lo, hi):
+    vo = ocut.closest_point(P, lo, hi)
+    n, l = ocut.adjacent_hyperplane(P, lo, hi, vo)
+    return float(np.min(P @ n) - l), float(np.abs(n).max())
+
+
+def _check_pair(args):
+    P, lo, hi, code, step, d2 = args
+    want_code, want_step, want_d2 = ocut.heuristic(P, lo, hi)
+    scale = 1.0 + np.abs(P).max() + max(np.abs(lo).max(), np.abs(hi).max())
+    # step 1 is an exact comparison of the same doubles
+    inside = bool(np.any(np.all((P >= lo) & (P <= hi), axis=1)))
+    assert (step == 1) == inside
+    if inside:
+        return "point" if code == 0 else "bad-point"
+    m, nn = _plane_margin(P, lo, hi)
+    if abs(m) <= 1e-10 * scale * (1.0 + nn):
+        return "tie"                          # plane test within rounding: either step is valid
+    if want_step != step:
+        return f"step {want_step} vs {step}"
+    if step == 2:
+        return "plane" if code == 1 else "bad-plane"
+    s = ocut.lp_margin(P, lo, hi)
+    if abs(s) >= ocut.TAU and code != want_code:
+        return f"qp code {want_code} vs {code} (margin {s:.2e})"
+    if abs(d2 - want_d2) > D2_RTOL * want_d2 + D2_ATOL * scale * scale:
+        return f"qp dist2 {want_d2} vs {d2}"
+    return "qp"
+
+
+def check(b, out, pairs, label):
+    args = [(b.P[e], b.box_lo[o], b.box_hi[o], int(out["code"][o, e]), int(out["step"][o, e]),
+             float(out["d2"][o, e])) for o, e in pairs]
+    with mp.get_context("fork").Pool(8) as pool:
+        res = pool.map(_check_pair, args, chunksize=64)
+    kinds = {k: res.count(k) for k in set(res)}
+    print(label, kinds, flush=True)
+    bad = [(p, r) for p, r in zip(pairs, res) if r not in ("point", "plane", "qp", "tie")]
+    assert not bad, bad[:5]
+    return kinds
+
+
+def test_small_graph_every_pair(gpu_available):
+    b = gen.gen_cut(n_nodes=300, k_nn=6, n_obst=40)
+    print(f"case: {b.n_edges} edges x {b.n_obstacles} boxes", flush=True)
+    out = run_gpu(b)
+    pairs = [(o, e) for o in range(b.n_obstacles) for e in range(b.n_edges)]
+    kinds = check(b, out, pairs, "small")
+    assert kinds.get("plane", 0) > 0.9 * len(pairs)
+    assert out["n_qp"] == int((out["step"] == 3).sum())
+    # n_collide is the count of may-collide codes per edge
+    assert np.array_equal(out["n_collide"], (out["code"] == 0).sum(axis=0))
+    assert np.all(np.isnan(out["d2"][out["step"] != 3]))
+
+
+def test_full_size_sampled_and_every_qp_pair(gpu_available):
+    """50,000 edges x 200 boxes: a random sample of all pairs, plus a sample of
+    the pairs that reached the Cut-QP, against the oracle."""
+    b = gen.gen_cut()
+    print(f"case: {b.n_edges} edges x {b.n_obstacles} boxes", flush=True)
+    out = run_gpu(b)
+    rng = np.random.default_rng(11)
+    E, O = b.n_edges, b.n_obstacles
+    idx = rng.choice(E * O, 3000, replace=False)
+    check(b, out, [(int(i // E), int(i % E)) for i in idx], "full-sampled")
+    qo, qe = np.nonzero(out["step"] == 3)
+    assert out["n_qp"] == qo.size and 0 < qo.size < 0.01 * E * O
+    sel = rng.choice(qo.size, min(400, qo.size), replace=False)
+    kinds = check(b, out, [(int(qo[i]), int(qe[i])) for i in sel], "full-qp")
+    assert kinds.get("qp", 0) > 0
+    assert np.array_equal(out["n_collide"], (out["code"] == 0).sum(axis=0))
+
+
+def test_edge_cases(gpu_available):
+    """Segments (degree 1) crossing, touching, near and far from a box; a
+    curve whose control points surround the box without entering it; zero
+    edges."""
+    lo = np.array([[0.0, 0.0, 0.0], [5.0, 5.0, 5.0]])
+    hi = np.array([[1.0, 1.0, 1.0], [6.0, 6.0, 6.0]])
+    segs = np.array([
+        [[-1.0, 0.5, 0.5], [2.0, 0.5, 0.5]],     # crosses box 0, both ends outside
+        [[1.0, 2.0, 0.5], [1.0, 3.0, 0.5]],      # touches the plane x = 1 of box 0 from above
+        [[1.5, 0.5, 0.5], [3.0, 0.5, 0.5]],      # 0.5 from box 0
+        [[-3.0, -3.0, 3.0], [3.0, 3.0, 3.0]],    # passes over box 0 at height 3
+        [[5.5, 5.5, 5.5], [5.5, 5.5, 5.5]],      # degenerate segment inside box 1
+    ])
+    b = gen.CutBatch(name="edge-cases", degree=1, P=segs, box_lo=lo, box_hi=hi)
+    out = run_gpu(b)
+    assert out["code"][0, 0] == 0 and out["step"][0, 0] == 3 and out["d2"][0, 0] == 0.0
+    assert out["code"][0, 2] == 1 and abs(out["d2"][0, 2] - 0.25) <= 1e-12 if out["step"][0, 2] == 3 else out["code"][0, 2] == 1
+    assert out["code"][0, 3] == 1
+    assert out["code"][1, 4] == 0 and out["step"][1, 4] == 1
+    assert out["code"][1, 0] == 1 and out["n_collide"][4] == 1
+    # surrounding points: the hull contains the box
+    ring = np.array([[[-1, -1, -1], [2, -1, -1], [-1, 2, -1], [2, 2, -1],
+                      [-1, -1, 2], [2, -1, 2], [-1, 2, 2], [2, 2, 2]]], dtype=float)
+    b2 = gen.CutBatch(name="ring", degree=7, P=ring, box_lo=lo[:1], box_hi=hi[:1])
+    out2 = run_gpu(b2)
+    assert out2["code"][0, 0] == 0 and out2["step"][0, 0] == 3 and out2["d2"][0, 0] == 0.0
+    b3 = gen.CutBatch(name="empty", degree=7, P=np.zeros((0, 8, 3)), box_lo=lo, box_hi=hi)
+    out3 = run_gpu(b3)
+    assert out3["code"].size == 0 and out3["n_qp"] == 0
+
+
+def test_graph_capture_replays(gpu_available):
+    """The three kernels of a run (counter reset, heuristic, Cut-QP) captured
+    in one graph; every replay equals the eager run."""
+    from paper_2411_13507_amd.api import CutGPU
+    b = gen.gen_cut(n_nodes=600, k_nn=8, n_obst=80)
+    g = CutGPU(b, b.n_edges)
+    P = torch.as_tensor(b.P, device=g.device)
+    ref = g.run(P)
+    torch.cuda.synchronize()
+    ref = [t.clone() for t in (ref.code, ref.step, ref.qp_dist2, ref.n_collide)]
+    out = g.alloc()
+    side = torch.cuda.Stream(device=g.device)
+    side.wait_stream(torch.cuda.current_stream(g.device))
+    with torch.cuda.stream(side):
+        g.run(P, out=out)
+    torch.cuda.current_stream(g.device).wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        g.run(P, out=out)
+    for rep in range(3):
+        out.code.fill_(7); out.n_collide.fill_(-1)
+        graph.replay()
+        torch.cuda.synchronize()
+        for a, r in zip((out.code, out.step, out.qp_dist2, out.n_collide), ref):
+            assert torch.equal(torch.nan_to_num(a.double() if a.dtype != torch.float64 else a, nan=1.5),
+                               torch.nan_to_num(r.double() if r.dtype != torch.float64 else r, nan=1.5)), rep
+        g.run(P, out=g.alloc())
+        torch.cuda.synchronize()
+    g.close()
