@@ -120,11 +120,12 @@ def time_launches(fn, reps, stream):
     return float(np.median([e0.elapsed_time(e1) for e0, e1 in evs])) / 1e3
 
 
-def extra_workloads(reps=3):
+def extra_workloads(reps=3, admm_iters=-1):
     """Forward throughput of the uneven batch (200,000 segments, degree 3-9,
     6-40 faces, 16-128 reachable rows; autotuned options) and of the
     path batch (8,192 paths of 4-12 joined degree-7 segments)."""
     import torch
+    from paper_2411_13507_amd import _lib
     from paper_2411_13507_amd.api import ChainBatchGPU, SegmentBatchGPU
     from workloads import gen
     dev = torch.device("cuda", 0)
@@ -135,7 +136,11 @@ def extra_workloads(reps=3):
     x0, goal = torch.as_tensor(b.x0, device=dev), torch.as_tensor(b.goal, device=dev)
     res = gb.alloc_outputs()
     from paper_2411_13507_amd import autotune
-    uo = autotune.tune(b, sample=b.n, reps=2, use_cache=False)
+    if admm_iters >= 0:
+        uo = _lib.default_opts()
+        uo.admm_iters = admm_iters
+    else:
+        uo = autotune.tune(b, sample=b.n, reps=2, use_cache=False)
     uo.store_for_backward = 0
     t = time_launches(lambda: gb.solve(x0, goal, opts=uo, out=res), reps, stream)
     st = res.status.cpu().numpy()
@@ -332,7 +337,7 @@ def main():
 
     extras = None
     if not args.no_extras:
-        extras = extra_workloads()
+        extras = extra_workloads(admm_iters=args.admm_iters)
 
     cpu = None
     if not args.no_cpu_baseline:
