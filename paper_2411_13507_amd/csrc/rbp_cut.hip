@@ -109,89 +109,119 @@ __global__ __launch_bounds__(kCutBlock) void cut_prefilter_kernel(CutArgs A) {
   if (live && collide) atomicAdd(&A.n_collide[e], collide);
 }
 
-// Closest point to the origin of conv(W[0..k)), k <= 4, by checking every
-// face of the simplex: the affine projection onto a face whose barycentric
-// weights are all positive is a candidate, and the nearest candidate is the
-// answer.  On return W holds the vertices of that face (k updated).
-// Returns false when no face qualified (degenerate input).
-__device__ bool closest_face(V3* W, int& k, V3& v) {
-  double best = __builtin_huge_val();
-  int best_mask = 0;
-  V3 best_v{0, 0, 0};
-  const int full = (1 << k) - 1;
-  for (int mask = 1; mask <= full; ++mask) {
-    int idx[4], s = 0;
-    for (int i = 0; i < k; ++i)
-      if (mask & (1 << i)) idx[s++] = i;
-    V3 x;
-    bool ok = true;
-    if (s == 1) {
-      x = W[idx[0]];
+// Closest point to the origin of the face of the simplex {w0..w3} selected
+// by MASK (bits = vertices): the affine projection, accepted when its
+// barycentric weights are all positive.  Every index is a compile-time
+// constant, so the simplex stays in registers.
+template <int MASK>
+__device__ __forceinline__ bool face_point(const V3 (&w)[4], V3& x) {
+  constexpr int S = __builtin_popcount(MASK);
+  constexpr int I0 = (MASK & 1) ? 0 : (MASK & 2) ? 1 : (MASK & 4) ? 2 : 3;
+  const V3 w0 = w[I0];
+  if constexpr (S == 1) {
+    x = w0;
+    return true;
+  } else {
+    // the other vertices of the face, in increasing order
+    V3 d[3];
+    int m = 0;
+#pragma unroll
+    for (int i = I0 + 1; i < 4; ++i)
+      if (MASK & (1 << i)) d[m++] = sub(w[i], w0);
+    // minimise |w0 + sum_j t_j d_j|^2: Gram system G t = -D^T w0
+    double G[3][3], rhs[3], t[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int a = 0; a < S - 1; ++a) {
+      rhs[a] = -dot(d[a], w0);
+#pragma unroll
+      for (int c = 0; c < S - 1; ++c) G[a][c] = dot(d[a], d[c]);
+    }
+    double scale = 0.0;
+#pragma unroll
+    for (int a = 0; a < S - 1; ++a) scale = fmax(scale, G[a][a]);
+    if constexpr (S == 2) {
+      if (!(G[0][0] > 1e-30 * fmax(scale, 1e-300))) return false;
+      t[0] = rhs[0] / G[0][0];
+    } else if constexpr (S == 3) {
+      const double det = G[0][0] * G[1][1] - G[0][1] * G[1][0];
+      if (!(fabs(det) > 1e-24 * scale * scale)) return false;
+      t[0] = (rhs[0] * G[1][1] - G[0][1] * rhs[1]) / det;
+      t[1] = (G[0][0] * rhs[1] - rhs[0] * G[1][0]) / det;
     } else {
-      // minimise |w0 + sum_j t_j d_j|^2: Gram system G t = -D^T w0
-      const V3 w0 = W[idx[0]];
-      V3 d[3];
-      for (int j = 1; j < s; ++j) d[j - 1] = sub(W[idx[j]], w0);
-      const int m = s - 1;
-      double G[3][3], rhs[3], t[3] = {0, 0, 0};
-      for (int a = 0; a < m; ++a) {
-        rhs[a] = -dot(d[a], w0);
-        for (int c = 0; c < m; ++c) G[a][c] = dot(d[a], d[c]);
-      }
-      double scale = 0.0;
-      for (int a = 0; a < m; ++a) scale = fmax(scale, G[a][a]);
-      if (m == 1) {
-        if (!(G[0][0] > 1e-30 * fmax(scale, 1e-300))) ok = false;
-        else t[0] = rhs[0] / G[0][0];
-      } else if (m == 2) {
-        const double det = G[0][0] * G[1][1] - G[0][1] * G[1][0];
-        if (!(fabs(det) > 1e-24 * scale * scale)) ok = false;
-        else {
-          t[0] = (rhs[0] * G[1][1] - G[0][1] * rhs[1]) / det;
-          t[1] = (G[0][0] * rhs[1] - rhs[0] * G[1][0]) / det;
-        }
-      } else {
-        const double c00 = G[1][1] * G[2][2] - G[1][2] * G[2][1];
-        const double c01 = G[1][2] * G[2][0] - G[1][0] * G[2][2];
-        const double c02 = G[1][0] * G[2][1] - G[1][1] * G[2][0];
-        const double det = G[0][0] * c00 + G[0][1] * c01 + G[0][2] * c02;
-        if (!(fabs(det) > 1e-24 * scale * scale * scale)) ok = false;
-        else {
-          // Cramer's rule
-          for (int col = 0; col < 3; ++col) {
-            double M[3][3];
-            for (int a = 0; a < 3; ++a)
-              for (int c = 0; c < 3; ++c) M[a][c] = (c == col) ? rhs[a] : G[a][c];
-            const double dm = M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1]) -
-                              M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0]) +
-                              M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0]);
-            t[col] = dm / det;
-          }
-        }
-      }
-      if (ok) {
-        double t0 = 1.0;
-        for (int j = 0; j < m; ++j) {
-          t0 -= t[j];
-          ok &= t[j] > -1e-14;
-        }
-        ok &= t0 > -1e-14;
-        x = w0;
-        for (int j = 0; j < m; ++j) x = axpy(t[j], d[j], x);
+      const double det = G[0][0] * (G[1][1] * G[2][2] - G[1][2] * G[2][1]) -
+                         G[0][1] * (G[1][0] * G[2][2] - G[1][2] * G[2][0]) +
+                         G[0][2] * (G[1][0] * G[2][1] - G[1][1] * G[2][0]);
+      if (!(fabs(det) > 1e-24 * scale * scale * scale)) return false;
+      // Cramer's rule, column c of G replaced by rhs
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        double M[3][3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int b = 0; b < 3; ++b) M[a][b] = (b == c) ? rhs[a] : G[a][b];
+        t[c] = (M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1]) - M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0]) +
+                M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0])) / det;
       }
     }
-    if (!ok) continue;
-    const double xx = dot(x, x);
-    if (xx < best) { best = xx; best_mask = mask; best_v = x; }
+    double t0 = 1.0;
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < S - 1; ++j) {
+      t0 -= t[j];
+      ok &= t[j] > -1e-14;
+    }
+    if (!(ok && t0 > -1e-14)) return false;
+    x = w0;
+#pragma unroll
+    for (int j = 0; j < S - 1; ++j) x = axpy(t[j], d[j], x);
+    return true;
   }
-  if (best_mask == 0) return false;
+}
+
+template <int MASK>
+__device__ __forceinline__ void try_face(const V3 (&w)[4], int k, double& best, int& best_mask, V3& best_v) {
+  if (MASK >= (1 << k)) return;
+  V3 x;
+  if (!face_point<MASK>(w, x)) return;
+  const double xx = dot(x, x);
+  if (xx < best) { best = xx; best_mask = MASK; best_v = x; }
+}
+
+// keep the vertices of face MASK, in order, as the new simplex
+template <int MASK>
+__device__ __forceinline__ void keep_face(V3 (&w)[4], int& k) {
+  V3 nw[4] = {w[0], w[0], w[0], w[0]};
   int s = 0;
-  V3 keep[4];
-  for (int i = 0; i < k; ++i)
-    if (best_mask & (1 << i)) keep[s++] = W[i];
-  for (int i = 0; i < s; ++i) W[i] = keep[i];
-  k = s;
-  v = best_v;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    if (MASK & (1 << i)) nw[s++] = w[i];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) w[i] = nw[i];
+  k = __builtin_popcount(MASK);
+}
+
+// Closest point to the origin of conv(w[0..k)), k <= 4: the nearest accepted
+// face projection over every face.  On return w[0..k) holds that face.
+// Returns false when no face qualified (degenerate input).
+__device__ bool closest_face(V3 (&w)[4], int& k, V3& v) {
+  double best = __builtin_huge_val();
+  int bm = 0;
+  V3 bv{0.0, 0.0, 0.0};
+  try_face<1>(w, k, best, bm, bv);  try_face<2>(w, k, best, bm, bv);  try_face<3>(w, k, best, bm, bv);
+  try_face<4>(w, k, best, bm, bv);  try_face<5>(w, k, best, bm, bv);  try_face<6>(w, k, best, bm, bv);
+  try_face<7>(w, k, best, bm, bv);  try_face<8>(w, k, best, bm, bv);  try_face<9>(w, k, best, bm, bv);
+  try_face<10>(w, k, best, bm, bv); try_face<11>(w, k, best, bm, bv); try_face<12>(w, k, best, bm, bv);
+  try_face<13>(w, k, best, bm, bv); try_face<14>(w, k, best, bm, bv); try_face<15>(w, k, best, bm, bv);
+  switch (bm) {
+    case 1: keep_face<1>(w, k); break;   case 2: keep_face<2>(w, k); break;   case 3: keep_face<3>(w, k); break;
+    case 4: keep_face<4>(w, k); break;   case 5: keep_face<5>(w, k); break;   case 6: keep_face<6>(w, k); break;
+    case 7: keep_face<7>(w, k); break;   case 8: keep_face<8>(w, k); break;   case 9: keep_face<9>(w, k); break;
+    case 10: keep_face<10>(w, k); break; case 11: keep_face<11>(w, k); break; case 12: keep_face<12>(w, k); break;
+    case 13: keep_face<13>(w, k); break; case 14: keep_face<14>(w, k); break; case 15: keep_face<15>(w, k); break;
+    default: return false;
+  }
+  v = bv;
   return true;
 }
 
@@ -206,6 +236,7 @@ __global__ __launch_bounds__(kCutBlock) void cut_qp_kernel(CutArgs A) {
     const int o = (int)(ent >> 32), e = (int)(ent & 0xffffffffll);
     V3 pts[NP];
     double scale = 1.0;
+#pragma unroll
     for (int k = 0; k < NP; ++k) {
       const int64_t b = (int64_t)e * (3 * NP) + 3 * k;
       pts[k] = {A.P[b], A.P[b + 1], A.P[b + 2]};
@@ -213,34 +244,41 @@ __global__ __launch_bounds__(kCutBlock) void cut_qp_kernel(CutArgs A) {
     }
     const V3 lo{A.box_lo[3 * o], A.box_lo[3 * o + 1], A.box_lo[3 * o + 2]};
     const V3 hi{A.box_hi[3 * o], A.box_hi[3 * o + 1], A.box_hi[3 * o + 2]};
-    // support point of conv(P) - box minimising u . w
+    // support point of conv(P) - box minimising u . w (kept by selection)
     auto support = [&](V3 u) -> V3 {
-      int best = 0;
-      double bv = dot(u, pts[0]);
+      V3 bp = pts[0];
+      double bd = dot(u, pts[0]);
+#pragma unroll
       for (int k = 1; k < NP; ++k) {
         const double d = dot(u, pts[k]);
-        if (d < bv) { bv = d; best = k; }
+        if (d < bd) { bd = d; bp = pts[k]; }
       }
       const V3 bx{u.x > 0.0 ? hi.x : lo.x, u.y > 0.0 ? hi.y : lo.y, u.z > 0.0 ? hi.z : lo.z};
-      return sub(pts[best], bx);
+      return sub(bp, bx);
     };
-    V3 W[4];
+    V3 w[4];
     int k = 1;
     const V3 c0{fmin(fmax(pts[0].x, lo.x), hi.x), fmin(fmax(pts[0].y, lo.y), hi.y), fmin(fmax(pts[0].z, lo.z), hi.z)};
-    W[0] = sub(pts[0], c0);
-    V3 v = W[0];
+    w[0] = sub(pts[0], c0);
+    w[1] = w[0]; w[2] = w[0]; w[3] = w[0];
+    V3 v = w[0];
     const double zero2 = 1e-24 * scale * scale;
     double vv = dot(v, v);
     for (int it = 0; it < 64 && vv > zero2; ++it) {
-      const V3 w = support(v);
+      const V3 wn = support(v);
       // |v|^2 - v.w bounds the gap between |v|^2 and the squared distance
-      if (vv - dot(v, w) <= 1e-13 * vv) break;
+      if (vv - dot(v, wn) <= 1e-13 * vv) break;
       bool dup = false;
-      for (int i = 0; i < k; ++i) dup |= (W[i].x == w.x) & (W[i].y == w.y) & (W[i].z == w.z);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) dup |= (i < k) & (w[i].x == wn.x) & (w[i].y == wn.y) & (w[i].z == wn.z);
       if (dup) break;
-      W[k++] = w;
+      // append at slot k (fixed slots keep the simplex in registers)
+      if (k == 1) w[1] = wn;
+      else if (k == 2) w[2] = wn;
+      else w[3] = wn;
+      ++k;
       V3 nv;
-      if (!closest_face(W, k, nv)) break;
+      if (!closest_face(w, k, nv)) break;
       const double nvv = dot(nv, nv);
       if (!(nvv < vv)) break;   // no progress: v is optimal to rounding
       v = nv;
