@@ -599,3 +599,51 @@ def gen_cut(n_nodes: int = 5000, k_nn: int = 10, n_obst: int = 200, p: int = 7, 
     P[:, 1:p, :] += rng.standard_normal((len(src), p - 1, 3)) * (bend * length)[:, None, None]
     return CutBatch(name=f"cut{len(src)}_o{n_obst}", degree=p, P=np.ascontiguousarray(P),
                     box_lo=np.ascontiguousarray(lo), box_hi=np.ascontiguousarray(hi))
+
+
+# ---------------------------------------------------------------------------
+# Building the graph (Sec. III-A, Thm. 2) and adjacent hyperplanes (Alg. 2)
+# ---------------------------------------------------------------------------
+@dataclass
+class GraphBatch:
+    """Nodes V [n, d] and the reachable-polytope pair of Theorem 2 split into
+    the columns on the start node (F1 [m, d]) and on the end node (F2 [m, d]),
+    with G [m]: edge i -> j when F1 v_i + F2 v_j <= G."""
+    name: str
+    V: np.ndarray
+    F1: np.ndarray
+    F2: np.ndarray
+    G: np.ndarray
+    box_lo: np.ndarray
+    box_hi: np.ndarray
+
+
+def morton_order(P: np.ndarray, bits: int = 10) -> np.ndarray:
+    """Indices sorting points of [0, 10]^3 along the Z-order curve."""
+    q = np.clip((P / 10.0 * (1 << bits)).astype(np.int64), 0, (1 << bits) - 1)
+    code = np.zeros(len(P), dtype=np.int64)
+    for b in range(bits):
+        for c in range(3):
+            code |= ((q[:, c] >> b) & 1) << (3 * b + c)
+    return np.argsort(code, kind="stable")
+
+
+def gen_graph(n_nodes: int = 5000, m: int = 64, cfg: int = 6, n_obst: int = 200) -> GraphBatch:
+    """Nodes uniform in [0, 10]^3 (the state space of interest), numbered
+    along the Z-order curve; the reachable polytope has m rows on the
+    displacement, a_k . (v_j - v_i) <= g_k with unit a_k uniform on the
+    sphere and g_k ~ U[0.85, 1.1] (about 10 edges per node, the paper's
+    5,000 nodes and 50,000 edges of Sec. IV-A), with F2 = A + N(0, 0.02^2) so
+    the test is not purely translation invariant.  Obstacles: the first
+    n_obst boxes of the environment (for the adjacent hyperplanes)."""
+    rng = np.random.default_rng(np.random.SeedSequence(1000 + cfg, spawn_key=(4,)))
+    V = rng.uniform(0.0, 10.0, size=(n_nodes, 3))
+    V = np.ascontiguousarray(V[morton_order(V)])
+    A = rng.standard_normal((m, 3))
+    A /= np.linalg.norm(A, axis=1, keepdims=True)
+    g = rng.uniform(0.85, 1.1, size=m)
+    F2 = A + 0.02 * rng.standard_normal((m, 3))
+    env = environment(1)
+    return GraphBatch(name=f"graph{n_nodes}_m{m}", V=V, F1=np.ascontiguousarray(-A), F2=np.ascontiguousarray(F2),
+                      G=g, box_lo=np.ascontiguousarray(env.obs_lo[:n_obst]),
+                      box_hi=np.ascontiguousarray(env.obs_hi[:n_obst]))
