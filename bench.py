@@ -168,6 +168,26 @@ def extra_workloads(reps=3, admm_iters=-1):
                           "edges_cut": int((cres.n_collide.cpu().numpy() > 0).sum())}
     cg.close()
     del cres, Pc
+    # graph building (F1 v_i + F2 v_j <= G over all 25M ordered pairs of 5,000
+    # nodes) in Z-order and in a random numbering (no tile skipping), and the
+    # adjacent hyperplanes of the nodes against 200 boxes
+    from paper_2411_13507_amd.api import GraphGPU, adjacent_hyperplanes
+    gb_ = gen.gen_graph()
+    gg = GraphGPU(gb_, gb_.V.shape[0], device="cuda:0")
+    Vz = torch.as_tensor(gb_.V, device=dev)
+    Vr = torch.as_tensor(gb_.V[np.random.default_rng(5).permutation(len(gb_.V))], device=dev)
+    adj, deg = gg.run(Vz)
+    t_z = time_launches(lambda: gg.run(Vz, adj, deg), reps, stream)
+    n_edges = int(deg.sum().item())
+    t_r = time_launches(lambda: gg.run(Vr, adj, deg), reps, stream)
+    lo_, hi_ = torch.as_tensor(gb_.box_lo, device=dev), torch.as_tensor(gb_.box_hi, device=dev)
+    t_h = time_launches(lambda: adjacent_hyperplanes(Vz, lo_, hi_), reps, stream)
+    n_pairs = gb_.V.shape[0] ** 2
+    out["graph5000_m64"] = {"ms_zorder": t_z * 1e3, "ms_random_order": t_r * 1e3, "edges": n_edges,
+                            "pairs_per_s_zorder": n_pairs / t_z, "rows": int(gb_.F1.shape[0])}
+    out["adjacent_hyperplanes_5000x200"] = {"ms": t_h * 1e3, "nodes": int(gb_.V.shape[0]),
+                                            "obstacles": int(gb_.box_lo.shape[0])}
+    gg.close()
     c = gen.generate_chains(8192)
     cb = ChainBatchGPU(c, device="cuda:0")
     x0, goal = torch.as_tensor(c.x0, device=dev), torch.as_tensor(c.goal, device=dev)

@@ -294,6 +294,62 @@ int rbp_cut_qp_count(rbp_cut* cut, int64_t* n_qp);
 /* Frees the list (waits for the last run). */
 void rbp_destroy_cut(rbp_cut* cut);
 
+/* ------------------------------------------------------------------------
+ * Building the graph (Sec. III-A, Thm. 2) and adjacent hyperplanes
+ * (Alg. 2, Sec. III-D).
+ *
+ * With the reachable-polytope pair (F, G) of Theorem 2 split into the
+ * columns acting on the start node (F1) and on the end node (F2), nodes v_i
+ * and v_j are joined by the edge i -> j when F1 v_i + F2 v_j <= G (every
+ * row); a node is not joined to itself.  Numbering the nodes along a
+ * space-filling curve lets the kernel skip whole tiles of far-apart pairs
+ * (an exact bound); the result does not depend on the numbering.
+ * ------------------------------------------------------------------------ */
+#define RBP_GRAPH_MAX_DIM 12
+#define RBP_GRAPH_MAX_ROWS 1024
+#define RBP_GRAPH_MAX_NODES (1 << 20)
+
+typedef struct rbp_graph_desc {
+  int32_t n_nodes;            /* 0..RBP_GRAPH_MAX_NODES                        */
+  int32_t dim;                /* node state dimension, 1..RBP_GRAPH_MAX_DIM     */
+  int32_t n_rows;             /* rows m of F, 1..RBP_GRAPH_MAX_ROWS             */
+  int32_t reserved;           /* 0                                             */
+  const double* F1;           /* device [m][dim], kept by pointer              */
+  const double* F2;           /* device [m][dim]                               */
+  const double* G;            /* device [m]                                    */
+} rbp_graph_desc;
+
+typedef struct rbp_graph rbp_graph;
+
+/* Keeps (F1, F2, G) by pointer (the caller keeps them alive) and allocates
+ * the per-node workspace (2 n m doubles plus tile bounds).  Errors:
+ * RBP_E_INVALID, RBP_E_SHAPE (sizes out of range), RBP_E_ALLOC. */
+int rbp_build_graph(const rbp_graph_desc* desc, hipStream_t stream, rbp_graph** out);
+
+/*
+ * Adjacency of the nodes V (device [n_nodes][dim]); stream-ordered.
+ *   adj     device [n_nodes][ceil(n_nodes / 32)] uint32: bit (j % 32) of word
+ *           (j / 32) in row i is the edge i -> j
+ *   degree  device [n_nodes] int32: out-degree
+ * Errors: RBP_E_INVALID (null pointers), RBP_E_DEVICE.
+ */
+int rbp_graph_run(rbp_graph* graph, const double* V, uint32_t* adj, int32_t* degree, hipStream_t stream);
+
+void rbp_destroy_graph(rbp_graph* graph);
+
+/*
+ * adjacentHyperplane for n nodes X (device [n][3]) against axis-aligned
+ * boxes (device [n_obstacles][3] each): the nearest box (Euclidean distance,
+ * lowest index on ties; -1 when there is none), the closest point on it,
+ * and the plane through that point with unit normal toward the node:
+ *   box_index [n] int32, point [n][3], plane [n][4] = (n_x, n_y, n_z, l):
+ *   the box lies in n.y <= l and the node in n.x > l (n = 0, l = 0 for a
+ *   node inside a box).  Stream-ordered.  Errors: RBP_E_INVALID, RBP_E_DEVICE.
+ */
+int rbp_adjacent_hyperplanes(int32_t n_nodes, const double* X, int32_t n_obstacles, const double* box_lo,
+                             const double* box_hi, int32_t* box_index, double* point, double* plane,
+                             hipStream_t stream);
+
 /* Static string for a call result or per-instance status code. */
 const char* rbp_status_string(int code);
 

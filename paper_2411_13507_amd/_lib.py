@@ -16,6 +16,7 @@ EXPORTED = (
     "rbp_backward", "rbp_destroy_batch", "rbp_status_string",
     "rbp_build_chains", "rbp_chains_get_sizes", "rbp_solve_chains", "rbp_destroy_chains",
     "rbp_build_cut", "rbp_cut_run", "rbp_cut_qp_count", "rbp_destroy_cut",
+    "rbp_build_graph", "rbp_graph_run", "rbp_destroy_graph", "rbp_adjacent_hyperplanes",
 )
 
 _p = ctypes.c_void_p
@@ -43,6 +44,13 @@ class CutDesc(ctypes.Structure):
     _fields_ = [
         ("n_edges", ctypes.c_int32), ("n_obstacles", ctypes.c_int32), ("degree", ctypes.c_int32),
         ("reserved", ctypes.c_int32), ("box_lo", _p), ("box_hi", _p),
+    ]
+
+
+class GraphDesc(ctypes.Structure):
+    _fields_ = [
+        ("n_nodes", ctypes.c_int32), ("dim", ctypes.c_int32), ("n_rows", ctypes.c_int32),
+        ("reserved", ctypes.c_int32), ("F1", _p), ("F2", _p), ("G", _p),
     ]
 
 
@@ -105,6 +113,14 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.rbp_cut_qp_count.restype = ctypes.c_int
     L.rbp_destroy_cut.argtypes = [_p]
     L.rbp_destroy_cut.restype = None
+    L.rbp_build_graph.argtypes = [ctypes.POINTER(GraphDesc), _p, ctypes.POINTER(_p)]
+    L.rbp_build_graph.restype = ctypes.c_int
+    L.rbp_graph_run.argtypes = [_p, _p, _p, _p, _p]
+    L.rbp_graph_run.restype = ctypes.c_int
+    L.rbp_destroy_graph.argtypes = [_p]
+    L.rbp_destroy_graph.restype = None
+    L.rbp_adjacent_hyperplanes.argtypes = [ctypes.c_int32, _p, ctypes.c_int32, _p, _p, _p, _p, _p, _p]
+    L.rbp_adjacent_hyperplanes.restype = ctypes.c_int
     L.rbp_status_string.argtypes = [ctypes.c_int]
     L.rbp_status_string.restype = ctypes.c_char_p
     _LIB = L

@@ -294,3 +294,63 @@ class CutGPU:
         v = ctypes.c_int64()
         _lib.check(_lib.load().rbp_cut_qp_count(self._h, ctypes.byref(v)), "rbp_cut_qp_count")
         return int(v.value)
+
+
+class GraphGPU:
+    """Edges of the graph of Bezier curves on one GPU (F1 v_i + F2 v_j <= G).
+    ``problem`` has F1 [m, d], F2 [m, d] and G [m], e.g.
+    ``workloads.gen.GraphBatch``; nodes are passed to each run."""
+
+    def __init__(self, problem, n_nodes: int, device: str = "cuda"):
+        if not torch.cuda.is_available():
+            raise _lib.RbpError("no GPU visible: the graph kernels run only on the GPU")
+        self.device = torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device(self.device.type, torch.cuda.current_device())
+        d = self.device
+        self.F1 = _dev(problem.F1, torch.float64, d)
+        self.F2 = _dev(problem.F2, torch.float64, d)
+        self.G = _dev(problem.G, torch.float64, d)
+        self.n_nodes, self.m, self.dim = int(n_nodes), int(self.F1.shape[0]), int(self.F1.shape[1])
+        desc = _lib.GraphDesc(self.n_nodes, self.dim, self.m, 0, _ptr(self.F1), _ptr(self.F2), _ptr(self.G))
+        h = ctypes.c_void_p()
+        with torch.cuda.device(d):
+            _lib.check(_lib.load().rbp_build_graph(ctypes.byref(desc), _stream_handle(d), ctypes.byref(h)),
+                       "rbp_build_graph")
+        self._h = h
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            _lib.load().rbp_destroy_graph(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, V: torch.Tensor, adj: Optional[torch.Tensor] = None, degree: Optional[torch.Tensor] = None):
+        """Adjacency bitmask [n, ceil(n/32)] (int32 tensor holding uint32 words)
+        and out-degrees [n] of the nodes V [n, d] (float64, on the device)."""
+        n, d = self.n_nodes, self.device
+        adj = adj if adj is not None else torch.empty((n, (n + 31) // 32), dtype=torch.int32, device=d)
+        degree = degree if degree is not None else torch.empty(n, dtype=torch.int32, device=d)
+        V = V.contiguous()
+        _lib.check(_lib.load().rbp_graph_run(self._h, _ptr(V), _ptr(adj), _ptr(degree), _stream_handle(d)),
+                   "rbp_graph_run")
+        return adj, degree
+
+
+def adjacent_hyperplanes(X: torch.Tensor, box_lo: torch.Tensor, box_hi: torch.Tensor):
+    """Nearest box, closest point and separating plane (n, l) per node;
+    tensors on the device (float64)."""
+    n, d = int(X.shape[0]), X.device
+    idx = torch.empty(n, dtype=torch.int32, device=d)
+    point = torch.empty((n, 3), dtype=torch.float64, device=d)
+    plane = torch.empty((n, 4), dtype=torch.float64, device=d)
+    X, box_lo, box_hi = X.contiguous(), box_lo.contiguous(), box_hi.contiguous()
+    _lib.check(_lib.load().rbp_adjacent_hyperplanes(n, _ptr(X), int(box_lo.shape[0]), _ptr(box_lo), _ptr(box_hi),
+                                                    _ptr(idx), _ptr(point), _ptr(plane), _stream_handle(d)),
+               "rbp_adjacent_hyperplanes")
+    return idx, point, plane

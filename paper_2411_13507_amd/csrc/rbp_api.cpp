@@ -578,4 +578,80 @@ void rbp_destroy_cut(rbp_cut* c) {
   delete c;
 }
 
+struct rbp_graph {
+  int device = 0;
+  rbp_graph_desc desc{};
+  double* A = nullptr;
+  double* B = nullptr;
+  double* Amin = nullptr;
+  double* Bmin = nullptr;
+  hipStream_t last_stream = nullptr;
+};
+
+namespace {
+void free_graph(rbp_graph* g) {
+  for (void* p : {static_cast<void*>(g->A), static_cast<void*>(g->B), static_cast<void*>(g->Amin),
+                  static_cast<void*>(g->Bmin)})
+    if (p) (void)hipFree(p);
+  delete g;
+}
+}  // namespace
+
+int rbp_build_graph(const rbp_graph_desc* d, hipStream_t stream, rbp_graph** out) {
+  if (!d || !out) return RBP_E_INVALID;
+  *out = nullptr;
+  if (d->reserved != 0 || !d->F1 || !d->F2 || !d->G) return RBP_E_INVALID;
+  if (d->n_nodes < 0 || d->n_nodes > RBP_GRAPH_MAX_NODES || d->dim < 1 || d->dim > RBP_GRAPH_MAX_DIM ||
+      d->n_rows < 1 || d->n_rows > RBP_GRAPH_MAX_ROWS)
+    return RBP_E_SHAPE;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return RBP_E_DEVICE;
+  auto* g = new (std::nothrow) rbp_graph();
+  if (!g) return RBP_E_ALLOC;
+  g->device = dev;
+  g->desc = *d;
+  const size_t nm = size_t(d->n_nodes) * size_t(d->n_rows);
+  const size_t tm = size_t((d->n_nodes + 63) / 64) * size_t(d->n_rows);
+  int rc;
+  if ((rc = dalloc(&g->A, nm)) || (rc = dalloc(&g->B, nm)) || (rc = dalloc(&g->Amin, tm)) ||
+      (rc = dalloc(&g->Bmin, tm))) {
+    free_graph(g);
+    return rc;
+  }
+  g->last_stream = stream;
+  *out = g;
+  return RBP_OK;
+}
+
+int rbp_graph_run(rbp_graph* g, const double* V, uint32_t* adj, int32_t* degree, hipStream_t stream) {
+  if (!g) return RBP_E_INVALID;
+  const rbp_graph_desc& d = g->desc;
+  if (d.n_nodes == 0) return RBP_OK;
+  if (!V || !adj || !degree) return RBP_E_INVALID;
+  rbp::GraphArgs a{};
+  a.n_nodes = d.n_nodes; a.dim = d.dim; a.m = d.n_rows;
+  a.V = V; a.F1 = d.F1; a.F2 = d.F2; a.G = d.G;
+  a.A = g->A; a.B = g->B; a.Amin = g->Amin; a.Bmin = g->Bmin;
+  a.adj = adj; a.degree = degree;
+  if (rbp::launch_graph(a, stream) != hipSuccess) return RBP_E_DEVICE;
+  g->last_stream = stream;
+  return RBP_OK;
+}
+
+void rbp_destroy_graph(rbp_graph* g) {
+  if (!g) return;
+  (void)hipSetDevice(g->device);
+  if (g->last_stream) (void)hipStreamSynchronize(g->last_stream);
+  free_graph(g);
+}
+
+int rbp_adjacent_hyperplanes(int32_t n, const double* X, int32_t n_obst, const double* lo, const double* hi,
+                             int32_t* idx, double* point, double* plane, hipStream_t stream) {
+  if (n < 0 || n_obst < 0) return RBP_E_INVALID;
+  if (n == 0) return RBP_OK;
+  if (!X || !idx || !point || !plane || (n_obst > 0 && (!lo || !hi))) return RBP_E_INVALID;
+  return rbp::launch_hyperplanes(n, X, n_obst, lo, hi, idx, point, plane, stream) == hipSuccess ? RBP_OK
+                                                                                                 : RBP_E_DEVICE;
+}
+
 }  // extern "C"

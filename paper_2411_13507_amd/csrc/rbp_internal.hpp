@@ -163,6 +163,24 @@ struct CutArgs {
 };
 hipError_t launch_cut(const CutArgs& a, hipStream_t s, int qp_blocks);
 
+// ---- building the graph and adjacent hyperplanes (rbp_graph.hip)
+struct GraphArgs {
+  int n_nodes, dim, m;
+  const double* V;           // [n_nodes][dim]
+  const double* F1;          // [m][dim] columns of F on the start node
+  const double* F2;          // [m][dim] columns of F on the end node
+  const double* G;           // [m]
+  double* A;                 // [n_nodes][m] F1 v (workspace)
+  double* B;                 // [n_nodes][m] F2 v - G (workspace)
+  double* Amin;              // [n_tiles][m] tile minima (workspace)
+  double* Bmin;
+  uint32_t* adj;             // [n_nodes][ceil(n_nodes / 32)] bitmask
+  int32_t* degree;           // [n_nodes]
+};
+hipError_t launch_graph(const GraphArgs& a, hipStream_t s);
+hipError_t launch_hyperplanes(int n, const double* X, int n_obst, const double* lo, const double* hi, int32_t* idx,
+                              double* point, double* plane, hipStream_t s);
+
 // admm = false: no room for the ADMM iteration (polish only)
 LdsDims make_dims(int pmax, int r_cap, int nf_cap, int real_bytes, bool admm);
 ChainDims make_chain_dims(int p, int s_cap, int nf_cap, int r_cap, int q_cap);
