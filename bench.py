@@ -31,6 +31,8 @@ def instance_sizes(b):
     p = b.degree.astype(np.int64)
     nf = np.diff(b.poly_off.astype(np.int64))[b.poly_idx]
     r = np.diff(b.reach_off)
+    if getattr(b, "reach_idx", None) is not None:
+        r = r[b.reach_idx]
     return p, nf, r
 
 
@@ -57,7 +59,10 @@ def algorithmic_bytes(b, q_mean=8):
     """HBM bytes per instance of the forward kernel: problem data read once,
     outputs and stored active set written once."""
     p, nf, r = instance_sizes(b)
-    reads = 8 * r * 3 * (p + 1) + 48 * r + 8 * r + 72 + 8 + 44 + 32 * nf
+    if getattr(b, "reach_idx", None) is None:
+        reads = 8 * r * 3 * (p + 1) + 48 * r + 8 * r + 72 + 8 + 44 + 32 * nf
+    else:                                    # shared blocks: read once per launch, not per instance
+        reads = 72 + 8 + 44 + 32 * nf + 4 + (8 * b.H.size + 56 * b.h0.size) / max(b.n, 1)
     writes = 24 * (p + 1) + 16 + 4 + 8 + 4 + 16 * q_mean
     return reads + writes
 
@@ -120,10 +125,12 @@ def time_launches(fn, reps, stream):
     return float(np.median([e0.elapsed_time(e1) for e0, e1 in evs])) / 1e3
 
 
-def extra_workloads(reps=3, admm_iters=-1):
-    """Forward throughput of the uneven batch (200,000 segments, degree 3-9,
-    6-40 faces, 16-128 reachable rows; autotuned options) and of the
-    path batch (8,192 paths of 4-12 joined degree-7 segments)."""
+def extra_workloads(reps=3, admm_iters=-1, edges=None, main_opts=None):
+    """Throughput of the other workloads: the 50,000 edges with one shared
+    reachable block, the uneven batch (200,000 segments, degree 3-9, 6-40
+    faces, 16-128 reachable rows; autotuned options), the graph cut, graph
+    building and adjacent hyperplanes, and the path batch (8,192 paths of
+    4-12 joined degree-7 segments)."""
     import torch
     from paper_2411_13507_amd import _lib
     from paper_2411_13507_amd.api import ChainBatchGPU, SegmentBatchGPU
@@ -131,6 +138,33 @@ def extra_workloads(reps=3, admm_iters=-1):
     dev = torch.device("cuda", 0)
     stream = torch.cuda.current_stream(dev)
     out = {}
+    if edges is not None:
+        # the same 50,000 edges, one reachable block shared by all (fwd + bwd
+        # with the headline options)
+        sb = gen.with_shared_reach(edges)
+        sg = SegmentBatchGPU(sb, device="cuda:0")
+        sx0, sgoal = torch.as_tensor(sb.x0, device=dev), torch.as_tensor(sb.goal, device=dev)
+        sres = sg.alloc_outputs()
+        sgP = torch.as_tensor(np.random.default_rng(5).standard_normal(3 * sg.points_total), device=dev)
+        sgC = torch.ones(sb.n, dtype=torch.float64, device=dev)
+        holder = {}
+
+        def fb():
+            sg.solve(sx0, sgoal, opts=main_opts, out=sres)
+            holder["g"] = sg.backward(sgP, sgC, out=holder.get("g"))
+        t = time_launches(fb, reps, stream)
+        fo = _lib.default_opts()
+        fo.admm_iters, fo.rho, fo.store_for_backward = main_opts.admm_iters, main_opts.rho, 0
+        t_f = time_launches(lambda: sg.solve(sx0, sgoal, opts=fo, out=sres), reps, stream)
+        st = sres.status.cpu().numpy()
+        kk = sres.kkt.cpu().numpy()
+        ok = int(((st == 0) & (kk <= KKT_OK)).sum() + (st == 1).sum())
+        out["edges50k_p7_shared_reach"] = {
+            "fwd_bwd_ms": t * 1e3, "solves_per_s": ok / t, "fwd_ms": t_f * 1e3, "instances": sb.n,
+            "reach_blocks": int(len(sb.reach_off) - 1), "algorithmic_bytes_per_instance":
+            float(algorithmic_bytes(sb).mean()), "status_counts": np.bincount(st, minlength=6).tolist()}
+        sg.close()
+        del sb, sg, sres
     b = gen.generate(2, 200_000)
     gb = SegmentBatchGPU(b, device="cuda:0")
     x0, goal = torch.as_tensor(b.x0, device=dev), torch.as_tensor(b.goal, device=dev)
@@ -357,7 +391,7 @@ def main():
 
     extras = None
     if not args.no_extras:
-        extras = extra_workloads(admm_iters=args.admm_iters)
+        extras = extra_workloads(admm_iters=args.admm_iters, edges=b, main_opts=opts)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -93,6 +93,18 @@ typedef struct rbp_problem_desc {
   const double* G;            /* [R][6] dependence of the right-hand side on x0  */
   double vmax;                /* velocity bound, > 0                             */
   double amax;                /* acceleration bound, > 0                         */
+  /* Shared reachable polytopes (Sec. III-A: the reachable set of Theorem 2
+   * depends only on the dynamics, the bounds and the duration, so one table
+   * entry can serve every edge).  reach_idx == NULL: reach_off and H_off
+   * above have N+1 entries, one block per instance, and n_reach is ignored.
+   * reach_idx != NULL: reach_off and H_off have n_reach+1 entries indexing a
+   * table of n_reach >= 1 blocks, and instance i uses block reach_idx[i]
+   * (0 <= reach_idx[i] < n_reach), whose H part must have r x 3(p_i+1)
+   * elements for that instance's degree.  The right-hand side h0 + G x0 is
+   * still formed per instance from its own x0.  rbp_build_batch checks all
+   * of this (RBP_E_SHAPE otherwise). */
+  int32_t n_reach;
+  const int32_t* reach_idx;   /* [N] or NULL                                     */
 } rbp_problem_desc;
 
 typedef struct rbp_solve_opts {

@@ -46,7 +46,10 @@ class SegmentBatchGPU:
 
     ``problem`` is any object with the array attributes of the C description
     (degree, T, poly_off, A_face, b_face, poly_idx, reach_off, H_off, H, h0,
-    G, vmax, amax), for instance a ``workloads.gen.SegmentBatch``.
+    G, vmax, amax), for instance a ``workloads.gen.SegmentBatch``.  An
+    optional ``reach_idx`` attribute (not None) selects the shared-table form
+    of the reachable rows: reach_off / H_off then index a table of blocks and
+    instance i uses block reach_idx[i].
     """
 
     def __init__(self, problem, device: str = "cuda"):
@@ -70,11 +73,14 @@ class SegmentBatchGPU:
         self.h0 = _dev(problem.h0, f64, d)
         self.G = _dev(np.asarray(problem.G).reshape(-1), f64, d)
         self.N = int(self.degree.numel())
+        ridx = getattr(problem, "reach_idx", None)
+        self.reach_idx = None if ridx is None else _dev(ridx, i32, d)
         desc = _lib.ProblemDesc(
             self.N, int(self.poly_off.numel()) - 1,
             _ptr(self.degree), _ptr(self.T), _ptr(self.poly_off), _ptr(self.A_face), _ptr(self.b_face),
             _ptr(self.poly_idx), _ptr(self.reach_off), _ptr(self.H_off), _ptr(self.H), _ptr(self.h0),
             _ptr(self.G), float(problem.vmax), float(problem.amax),
+            0 if ridx is None else int(self.reach_off.numel()) - 1, _ptr(self.reach_idx),
         )
         h = ctypes.c_void_p()
         with torch.cuda.device(d):

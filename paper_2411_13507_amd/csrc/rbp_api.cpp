@@ -128,16 +128,22 @@ int rbp_build_batch(const rbp_problem_desc* d, hipStream_t stream, rbp_batch** o
   if (hipGetDevice(&dev) != hipSuccess) return RBP_E_DEVICE;
   if (int rc = ensure_constants(dev)) return rc;
 
-  std::vector<int32_t> deg, pidx, poff;
+  // reachable blocks: one per instance, or a shared table indexed by reach_idx
+  const bool shared_reach = d->reach_idx != nullptr;
+  if (N > 0 && shared_reach && d->n_reach < 1) return RBP_E_SHAPE;
+  const size_t n_blk = shared_reach ? size_t(d->n_reach) : size_t(N);
+  std::vector<int32_t> deg, pidx, poff, ridx;
   std::vector<int64_t> roff, hoff;
   int rc = RBP_OK;
   if (N > 0) {
     if ((rc = d2h(deg, d->degree, N, stream)) || (rc = d2h(pidx, d->poly_idx, N, stream)) ||
         (rc = d2h(poff, d->poly_off, size_t(d->n_poly) + 1, stream)) ||
-        (rc = d2h(roff, d->reach_off, size_t(N) + 1, stream)) || (rc = d2h(hoff, d->H_off, size_t(N) + 1, stream)))
+        (rc = d2h(roff, d->reach_off, n_blk + 1, stream)) || (rc = d2h(hoff, d->H_off, n_blk + 1, stream)) ||
+        (shared_reach && (rc = d2h(ridx, d->reach_idx, N, stream))))
       return rc;
     if (hipStreamSynchronize(stream) != hipSuccess) return RBP_E_DEVICE;
   }
+  auto blk = [&](int i) -> int { return shared_reach ? ridx[i] : i; };
   auto* b = new (std::nothrow) rbp_batch();
   if (!b) return RBP_E_ALLOC;
   b->device = dev;
@@ -157,9 +163,11 @@ int rbp_build_batch(const rbp_problem_desc* d, hipStream_t stream, rbp_batch** o
       const int p = deg[i];
       if (p < RBP_MIN_DEGREE || p > RBP_MAX_DEGREE) { free_batch(b); return RBP_E_SHAPE; }
       if (pidx[i] < 0 || pidx[i] >= d->n_poly) { free_batch(b); return RBP_E_SHAPE; }
-      const int64_t r = roff[i + 1] - roff[i];
+      const int k = blk(i);
+      if (k < 0 || size_t(k) >= n_blk) { free_batch(b); return RBP_E_SHAPE; }
+      const int64_t r = roff[k + 1] - roff[k];
       if (r < 0 || r > RBP_MAX_REACH) { free_batch(b); return RBP_E_SHAPE; }
-      if (hoff[i + 1] - hoff[i] != r * 3 * (p + 1)) { free_batch(b); return RBP_E_SHAPE; }
+      if (hoff[k + 1] - hoff[k] != r * 3 * (p + 1)) { free_batch(b); return RBP_E_SHAPE; }
       const int nf = poff[pidx[i] + 1] - poff[pidx[i]];
       b->pmax = std::max<int32_t>(b->pmax, p);
       b->rmax = std::max<int32_t>(b->rmax, int32_t(r));
@@ -173,7 +181,7 @@ int rbp_build_batch(const rbp_problem_desc* d, hipStream_t stream, rbp_batch** o
     // launch each, LDS sized per group), most expensive first within a group
     // so that the tail of each launch is short
     auto rclass = [&](int i) -> int {
-      const int64_t r = roff[i + 1] - roff[i];
+      const int64_t r = roff[blk(i) + 1] - roff[blk(i)];
       return r <= 32 ? 0 : (r <= 64 ? 1 : 2);
     };
     std::iota(order.begin(), order.end(), 0);
@@ -184,7 +192,7 @@ int rbp_build_batch(const rbp_problem_desc* d, hipStream_t stream, rbp_batch** o
     });
     for (int k = 0; k < N; ++k) {
       const int i = order[k];
-      const int32_t r = int32_t(roff[i + 1] - roff[i]);
+      const int32_t r = int32_t(roff[blk(i) + 1] - roff[blk(i)]);
       const int32_t nf = poff[pidx[i] + 1] - poff[pidx[i]];
       if (b->groups.empty() || b->groups.back().p != deg[i] || rclass(order[b->groups.back().start]) != rclass(i))
         b->groups.push_back({deg[i], k, 0, 0, 1});
@@ -249,6 +257,7 @@ int rbp_solve_batch(rbp_batch* b, const double* x0, const double* goal, const do
   a.N = b->N;
   a.degree = d.degree; a.T = d.T; a.poly_off = d.poly_off; a.A_face = d.A_face; a.b_face = bf;
   a.poly_idx = d.poly_idx; a.reach_off = d.reach_off; a.H_off = d.H_off; a.H = d.H; a.h0 = d.h0; a.G = d.G;
+  a.reach_idx = d.reach_idx;
   a.vmax = d.vmax; a.amax = d.amax;
   a.x0 = x0; a.goal = goal; a.pt_off = b->d_pt_off;
   a.P_out = P_out; a.cost_out = cost_out; a.status_out = status_out; a.kkt_out = kkt_out; a.iters_out = iters_out;
@@ -302,6 +311,7 @@ int rbp_backward(rbp_batch* b, const double* grad_P, const double* grad_cost, do
   a.N = b->N;
   a.degree = d.degree; a.T = d.T; a.poly_off = d.poly_off; a.A_face = d.A_face; a.b_face = b->fw_bface;
   a.poly_idx = d.poly_idx; a.reach_off = d.reach_off; a.H_off = d.H_off; a.H = d.H; a.G = d.G;
+  a.reach_idx = d.reach_idx;
   a.vmax = d.vmax; a.amax = d.amax;
   a.x0 = b->fw_x0; a.goal = b->fw_goal; a.pt_off = b->d_pt_off; a.face_off = b->d_face_off;
   a.P_sol = b->fw_P; a.status = b->fw_status;

@@ -42,6 +42,7 @@ struct SolveArgs {
   const int32_t* poly_idx;
   const int64_t* reach_off;
   const int64_t* H_off;
+  const int32_t* reach_idx;  // nullable: reachable block of each instance (else the instance's own)
   const double* H;
   const double* h0;
   const double* G;
@@ -85,6 +86,7 @@ struct BackArgs {
   const int32_t* poly_idx;
   const int64_t* reach_off;
   const int64_t* H_off;
+  const int32_t* reach_idx;  // nullable: reachable block of each instance (else the instance's own)
   const double* H;
   const double* G;
   double vmax, amax;

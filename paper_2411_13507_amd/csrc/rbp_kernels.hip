@@ -214,9 +214,10 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
   const int poly = A.poly_idx[inst];
   in.f0 = A.poly_off[poly];
   in.nf = A.poly_off[poly + 1] - in.f0;
-  in.r0 = A.reach_off[inst];
-  in.r = int(A.reach_off[inst + 1] - in.r0);
-  in.hb = A.H_off[inst];
+  const int rblk = A.reach_idx ? A.reach_idx[inst] : inst;
+  in.r0 = A.reach_off[rblk];
+  in.r = int(A.reach_off[rblk + 1] - in.r0);
+  in.hb = A.H_off[rblk];
   in.po = A.pt_off[inst];
   in.F = NFP * in.nf;
   in.RB = in.F + ND;
@@ -1145,9 +1146,10 @@ __device__ void backward_instance(const BackArgs& A, const int inst, char* smem)
   const int poly = A.poly_idx[inst];
   in.f0 = A.poly_off[poly];
   in.nf = A.poly_off[poly + 1] - in.f0;
-  in.r0 = A.reach_off[inst];
-  in.r = int(A.reach_off[inst + 1] - in.r0);
-  in.hb = A.H_off[inst];
+  const int rblk = A.reach_idx ? A.reach_idx[inst] : inst;
+  in.r0 = A.reach_off[rblk];
+  in.r = int(A.reach_off[rblk + 1] - in.r0);
+  in.hb = A.H_off[rblk];
   in.po = A.pt_off[inst];
   in.F = NFP * in.nf;
   in.RB = in.F + ND;

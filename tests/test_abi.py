@@ -87,3 +87,34 @@ def test_missing_library_is_an_error(tmp_path):
             _lib.load(str(tmp_path / "missing.so"))
     finally:
         _lib._LIB = saved
+
+
+def test_descriptor_layouts_match_header(tmp_path):
+    """The ctypes descriptors have the field offsets and sizes the C compiler
+    gives the structs of include/rbp.h."""
+    import shutil
+    import subprocess
+    if not shutil.which("gcc") or not os.path.exists("/opt/rocm/include/hip/hip_runtime_api.h"):
+        pytest.skip("no host C compiler or HIP headers")
+    structs = {"rbp_problem_desc": _lib.ProblemDesc, "rbp_chain_desc": _lib.ChainDesc,
+               "rbp_cut_desc": _lib.CutDesc, "rbp_graph_desc": _lib.GraphDesc,
+               "rbp_solve_opts": _lib.SolveOpts, "rbp_batch_sizes": _lib.BatchSizes}
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "rbp.h"', "int main(void) {"]
+    for cname, cls in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f in cls._fields_:
+            lines.append(f'  printf("{cname} {f[0]} %zu\\n", offsetof({cname}, {f[0]}));')
+    lines.append("  return 0;\n}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"), "-I", "/opt/rocm/include",
+                    str(src), "-o", str(exe)], check=True, capture_output=True)
+    got = {}
+    for ln in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        c, f, v = ln.split()
+        got[(c, f)] = int(v)
+    for cname, cls in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for f in cls._fields_:
+            assert got[(cname, f[0])] == getattr(cls, f[0]).offset, (cname, f[0])

@@ -26,6 +26,7 @@ Conventions shared with the consumers (documented in include/rbp.h):
 """
 from __future__ import annotations
 
+import dataclasses
 from dataclasses import dataclass, field
 import os
 from typing import Dict, Optional, Sequence
@@ -80,21 +81,29 @@ class SegmentBatch:
     x0: np.ndarray              # float64 [N, 6]
     goal: np.ndarray            # float64 [N, 3]
     meta: Dict[str, object] = field(default_factory=dict)
+    # shared reachable blocks: None, or int32 [N] indexing blocks of
+    # reach_off / H_off (which then have one entry per block, plus one)
+    reach_idx: Optional[np.ndarray] = None
 
     @property
     def n(self) -> int:
         return int(self.degree.shape[0])
 
+    def block(self, i: int) -> int:
+        return int(i) if self.reach_idx is None else int(self.reach_idx[i])
+
     def reach_rows(self, i: int) -> int:
-        return int(self.reach_off[i + 1] - self.reach_off[i])
+        k = self.block(i)
+        return int(self.reach_off[k + 1] - self.reach_off[k])
 
     def instance(self, i: int) -> dict:
         """Plain per-instance view (numpy arrays, FP64)."""
         p = int(self.degree[i])
         j = int(self.poly_idx[i])
         f0, f1 = int(self.poly_off[j]), int(self.poly_off[j + 1])
-        r0, r1 = int(self.reach_off[i]), int(self.reach_off[i + 1])
-        h0_, h1_ = int(self.H_off[i]), int(self.H_off[i + 1])
+        k = self.block(i)
+        r0, r1 = int(self.reach_off[k]), int(self.reach_off[k + 1])
+        h0_, h1_ = int(self.H_off[k]), int(self.H_off[k + 1])
         return dict(
             p=p, T=float(self.T[i]), vmax=float(self.vmax), amax=float(self.amax),
             A_face=self.A_face[f0:f1].copy(), b_face=self.b_face[f0:f1].copy(),
@@ -103,8 +112,30 @@ class SegmentBatch:
             x0=self.x0[i].copy(), goal=self.goal[i].copy(),
         )
 
+    def expanded(self) -> "SegmentBatch":
+        """The same problems with every instance holding its own copy of its
+        reachable block (the per-instance layout)."""
+        if self.reach_idx is None:
+            return self
+        k = np.asarray(self.reach_idx, np.int64)
+        r = (self.reach_off[k + 1] - self.reach_off[k])
+        hsz = (self.H_off[k + 1] - self.H_off[k])
+        reach_off = np.concatenate([[0], np.cumsum(r)]).astype(np.int64)
+        H_off = np.concatenate([[0], np.cumsum(hsz)]).astype(np.int64)
+        H = np.concatenate([self.H[self.H_off[b]:self.H_off[b + 1]] for b in k]) if len(k) else np.zeros(0)
+        h0 = np.concatenate([self.h0[self.reach_off[b]:self.reach_off[b + 1]] for b in k]) if len(k) else np.zeros(0)
+        G = np.concatenate([self.G[self.reach_off[b]:self.reach_off[b + 1]] for b in k]) if len(k) else np.zeros((0, 6))
+        return dataclasses.replace(self, name=f"{self.name}[expanded]", reach_off=reach_off, H_off=H_off, H=H,
+                                   h0=h0, G=G.reshape(-1, 6), reach_idx=None)
+
     def subset(self, idx: Sequence[int]) -> "SegmentBatch":
         idx = np.asarray(idx, dtype=np.int64)
+        if self.reach_idx is not None:
+            return dataclasses.replace(self, name=f"{self.name}[subset]", degree=self.degree[idx].copy(),
+                                       T=self.T[idx].copy(), poly_idx=self.poly_idx[idx].copy(),
+                                       x0=self.x0[idx].copy(), goal=self.goal[idx].copy(),
+                                       reach_idx=self.reach_idx[idx].copy(),
+                                       meta=dict(self.meta, subset=idx.tolist()[:16]))
         r = self.reach_off[idx + 1] - self.reach_off[idx]
         hsz = self.H_off[idx + 1] - self.H_off[idx]
         reach_off = np.zeros(len(idx) + 1, np.int64)
@@ -336,6 +367,7 @@ def concat(parts) -> SegmentBatch:
     """Join batches that share one polytope table (same workload)."""
     parts = [p for p in parts if p.n > 0] or list(parts)[:1]
     first = parts[0]
+    assert all(p.reach_idx is None for p in parts), "concat joins per-instance reachable blocks only"
     reach = np.concatenate([[0]] + [np.diff(p.reach_off) for p in parts]).cumsum()
     hsz = np.concatenate([[0]] + [np.diff(p.H_off) for p in parts]).cumsum()
     return SegmentBatch(
@@ -349,6 +381,27 @@ def concat(parts) -> SegmentBatch:
         x0=np.concatenate([p.x0 for p in parts]), goal=np.concatenate([p.goal for p in parts]),
         meta=dict(first.meta),
     )
+
+
+def with_shared_reach(b: SegmentBatch, r: int = 32, h0_range=H0_CLUTTER, seed: int = 7) -> SegmentBatch:
+    """The same edges with one reachable block per degree shared by every
+    instance of that degree (the paper computes the reachable polytope once
+    and uses it for all edges, Sec. III-A); block draws as for a single edge,
+    from their own seed."""
+    degrees = sorted(set(int(p) for p in b.degree))
+    rng = np.random.default_rng(np.random.SeedSequence(seed, spawn_key=(3,)))
+    Hs, h0s, Gs = [], [], []
+    for p in degrees:
+        H, h0, G = _reach_block(rng, r, p, *h0_range)
+        Hs.append(H); h0s.append(h0); Gs.append(G)
+    slot = {p: k for k, p in enumerate(degrees)}
+    reach_idx = np.asarray([slot[int(p)] for p in b.degree], np.int32)
+    reach_off = np.concatenate([[0], np.cumsum([h.shape[0] for h in Hs])]).astype(np.int64)
+    H_off = np.concatenate([[0], np.cumsum([h.size for h in Hs])]).astype(np.int64)
+    return dataclasses.replace(b, name=f"{b.name}_shared_reach", reach_off=reach_off, H_off=H_off,
+                               H=np.concatenate([h.ravel() for h in Hs]), h0=np.concatenate(h0s),
+                               G=np.concatenate(Gs).reshape(-1, 6), reach_idx=reach_idx,
+                               meta=dict(b.meta, shared_reach=dict(r=r, h0=list(h0_range), seed=seed)))
 
 
 def _gen_chunk(args):
