@@ -13,7 +13,10 @@ Variable: ``y = vec(P)``, point-major, ``(p+1)*3`` entries.
 * reachable Bezier polytope (Theorem 2, stored affine in the start state):
   ``H y <= h0 + G x0``;
 * equalities: ``P_0 = pos(x0)`` and ``P_p = goal`` (the edge joins the two
-  waypoints, Sec. II-B graph semantics).
+  waypoints, Sec. II-B graph semantics); with ``pin_v0`` also the start
+  velocity, ``b'(0) = (p/T)(P_1 - P_0) = vel(x0)`` (the full-state start of
+  Lemma 1: the derivative of a Bezier curve at t = 0 is p/T times its first
+  control-polygon edge).
 
 Inequalities are one-sided ``A y <= u``; each row carries a label
 ``(kind, k, j)`` used to map multipliers back to parameters.
@@ -104,12 +107,19 @@ def build(inst: dict) -> SegmentQP:
     A = np.concatenate(blocks)
     u = np.concatenate(rhs)
 
-    E = np.zeros((6, n))
+    pin_v0 = bool(inst.get("pin_v0", False))
+    ne = 9 if pin_v0 else 6
+    E = np.zeros((ne, n))
     E[0:3, 0:3] = I3
     E[3:6, 3 * p:3 * p + 3] = I3
     e = np.concatenate([x0[:3], g])
-    de_dx0 = np.zeros((6, 6)); de_dx0[0:3, 0:3] = I3
-    de_dg = np.zeros((6, 3)); de_dg[3:6, :] = I3
+    de_dx0 = np.zeros((ne, 6)); de_dx0[0:3, 0:3] = I3
+    de_dg = np.zeros((ne, 3)); de_dg[3:6, :] = I3
+    if pin_v0:
+        E[6:9, 3:6] = (p / T) * I3
+        E[6:9, 0:3] = -(p / T) * I3
+        e = np.concatenate([e, x0[3:6]])
+        de_dx0[6:9, 3:6] = I3
 
     return SegmentQP(p=p, T=T, Q=bezier.hessian(p, T), A=A, u=u, E=E, e=e,
                      kind=np.asarray(kinds), kidx=np.asarray(ks), jidx=np.asarray(js),

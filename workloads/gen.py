@@ -40,6 +40,10 @@ AMAX = 5.0
 # reachable-row offsets for the cluttered-environment batches: shifted from
 # U[1,3] so that about 30% of the edges come out infeasible
 H0_CLUTTER = (1.3, 3.3)
+# offsets of a reachable block shared by all edges: with one block the
+# feasible fraction follows the block, so it is shifted to leave about a
+# third of the 50,000 edges infeasible, as in the per-edge batch
+H0_SHARED = (1.6, 3.6)
 # reachable-row offsets of the chain segments
 H0_CHAIN = (2.0, 4.0)
 
@@ -84,6 +88,8 @@ class SegmentBatch:
     # shared reachable blocks: None, or int32 [N] indexing blocks of
     # reach_off / H_off (which then have one entry per block, plus one)
     reach_idx: Optional[np.ndarray] = None
+    # start velocity pinned as well as the start position (b'(0) = x0[3:6])
+    pin_v0: bool = False
 
     @property
     def n(self) -> int:
@@ -109,7 +115,7 @@ class SegmentBatch:
             A_face=self.A_face[f0:f1].copy(), b_face=self.b_face[f0:f1].copy(),
             H=self.H[h0_:h1_].reshape(r1 - r0, 3 * (p + 1)).copy(),
             h0=self.h0[r0:r1].copy(), G=self.G[r0:r1].copy(),
-            x0=self.x0[i].copy(), goal=self.goal[i].copy(),
+            x0=self.x0[i].copy(), goal=self.goal[i].copy(), pin_v0=bool(self.pin_v0),
         )
 
     def expanded(self) -> "SegmentBatch":
@@ -150,7 +156,7 @@ class SegmentBatch:
             vmax=self.vmax, amax=self.amax, poly_off=self.poly_off, A_face=self.A_face,
             b_face=self.b_face, poly_idx=self.poly_idx[idx].copy(), reach_off=reach_off,
             H_off=H_off, H=H, h0=h0, G=G.reshape(-1, 6), x0=self.x0[idx].copy(),
-            goal=self.goal[idx].copy(), meta=dict(self.meta, subset=idx.tolist()[:16]),
+            goal=self.goal[idx].copy(), meta=dict(self.meta, subset=idx.tolist()[:16]), pin_v0=self.pin_v0,
         )
 
 
@@ -383,7 +389,7 @@ def concat(parts) -> SegmentBatch:
     )
 
 
-def with_shared_reach(b: SegmentBatch, r: int = 32, h0_range=H0_CLUTTER, seed: int = 7) -> SegmentBatch:
+def with_shared_reach(b: SegmentBatch, r: int = 32, h0_range=H0_SHARED, seed: int = 7) -> SegmentBatch:
     """The same edges with one reachable block per degree shared by every
     instance of that degree (the paper computes the reachable polytope once
     and uses it for all edges, Sec. III-A); block draws as for a single edge,
@@ -402,6 +408,12 @@ def with_shared_reach(b: SegmentBatch, r: int = 32, h0_range=H0_CLUTTER, seed: i
                                H=np.concatenate([h.ravel() for h in Hs]), h0=np.concatenate(h0s),
                                G=np.concatenate(Gs).reshape(-1, 6), reach_idx=reach_idx,
                                meta=dict(b.meta, shared_reach=dict(r=r, h0=list(h0_range), seed=seed)))
+
+
+def with_pinned_velocity(b: SegmentBatch) -> SegmentBatch:
+    """The same edges with the start velocity pinned too (Lemma 1's
+    full-state start: P_1 = P_0 + (T/p) vel(x0))."""
+    return dataclasses.replace(b, name=f"{b.name}_pinned_v0", pin_v0=True, meta=dict(b.meta, pin_v0=True))
 
 
 def _gen_chunk(args):
@@ -431,6 +443,10 @@ def generate(cfg: int, n: int, workers: Optional[int] = None) -> SegmentBatch:
 def from_instances(insts, name: str = "custom") -> SegmentBatch:
     """Pack per-instance dicts (the layout of ``SegmentBatch.instance``) into
     a batch; each instance gets its own polytope."""
+    pins = {bool(d.get("pin_v0", False)) for d in insts}
+    assert len(pins) <= 1, "pin_v0 is a property of the whole batch"
+    if pins == {True}:
+        return dataclasses.replace(from_instances([dict(d, pin_v0=False) for d in insts], name), pin_v0=True)
     return _finalize(name, [d["p"] for d in insts], [d["T"] for d in insts],
                      [np.asarray(d["A_face"], float) for d in insts],
                      [np.asarray(d["b_face"], float) for d in insts], np.arange(len(insts)),
