@@ -125,9 +125,42 @@ def time_launches(fn, reps, stream):
     return float(np.median([e0.elapsed_time(e1) for e0, e1 in evs])) / 1e3
 
 
+def _variant(sb, main_opts, reps, stream):
+    """Forward + backward and forward-only times of a variant of the
+    50,000-edge batch."""
+    import torch
+    from paper_2411_13507_amd import _lib
+    from paper_2411_13507_amd.api import SegmentBatchGPU
+    dev = torch.device("cuda", 0)
+    sg = SegmentBatchGPU(sb, device="cuda:0")
+    sx0, sgoal = torch.as_tensor(sb.x0, device=dev), torch.as_tensor(sb.goal, device=dev)
+    sres = sg.alloc_outputs()
+    sgP = torch.as_tensor(np.random.default_rng(5).standard_normal(3 * sg.points_total), device=dev)
+    sgC = torch.ones(sb.n, dtype=torch.float64, device=dev)
+    holder = {}
+
+    def fb():
+        sg.solve(sx0, sgoal, opts=main_opts, out=sres)
+        holder["g"] = sg.backward(sgP, sgC, out=holder.get("g"))
+    t = time_launches(fb, reps, stream)
+    fo = _lib.default_opts()
+    fo.admm_iters, fo.rho, fo.store_for_backward = main_opts.admm_iters, main_opts.rho, 0
+    t_f = time_launches(lambda: sg.solve(sx0, sgoal, opts=fo, out=sres), reps, stream)
+    st = sres.status.cpu().numpy()
+    kk = sres.kkt.cpu().numpy()
+    ok = int(((st == 0) & (kk <= KKT_OK)).sum() + (st == 1).sum())
+    rec = {"fwd_bwd_ms": t * 1e3, "solves_per_s": ok / t, "fwd_ms": t_f * 1e3, "instances": sb.n,
+           "algorithmic_bytes_per_instance": float(algorithmic_bytes(sb).mean()),
+           "status_counts": np.bincount(st, minlength=6).tolist()}
+    if sb.reach_idx is not None:
+        rec["reach_blocks"] = int(len(sb.reach_off) - 1)
+    sg.close()
+    return rec
+
+
 def extra_workloads(reps=3, admm_iters=-1, edges=None, main_opts=None):
     """Throughput of the other workloads: the 50,000 edges with one shared
-    reachable block, the uneven batch (200,000 segments, degree 3-9, 6-40
+    reachable block and with a pinned start velocity, the uneven batch (200,000 segments, degree 3-9, 6-40
     faces, 16-128 reachable rows; autotuned options), the graph cut, graph
     building and adjacent hyperplanes, and the path batch (8,192 paths of
     4-12 joined degree-7 segments)."""
@@ -139,32 +172,10 @@ def extra_workloads(reps=3, admm_iters=-1, edges=None, main_opts=None):
     stream = torch.cuda.current_stream(dev)
     out = {}
     if edges is not None:
-        # the same 50,000 edges, one reachable block shared by all (fwd + bwd
-        # with the headline options)
-        sb = gen.with_shared_reach(edges)
-        sg = SegmentBatchGPU(sb, device="cuda:0")
-        sx0, sgoal = torch.as_tensor(sb.x0, device=dev), torch.as_tensor(sb.goal, device=dev)
-        sres = sg.alloc_outputs()
-        sgP = torch.as_tensor(np.random.default_rng(5).standard_normal(3 * sg.points_total), device=dev)
-        sgC = torch.ones(sb.n, dtype=torch.float64, device=dev)
-        holder = {}
-
-        def fb():
-            sg.solve(sx0, sgoal, opts=main_opts, out=sres)
-            holder["g"] = sg.backward(sgP, sgC, out=holder.get("g"))
-        t = time_launches(fb, reps, stream)
-        fo = _lib.default_opts()
-        fo.admm_iters, fo.rho, fo.store_for_backward = main_opts.admm_iters, main_opts.rho, 0
-        t_f = time_launches(lambda: sg.solve(sx0, sgoal, opts=fo, out=sres), reps, stream)
-        st = sres.status.cpu().numpy()
-        kk = sres.kkt.cpu().numpy()
-        ok = int(((st == 0) & (kk <= KKT_OK)).sum() + (st == 1).sum())
-        out["edges50k_p7_shared_reach"] = {
-            "fwd_bwd_ms": t * 1e3, "solves_per_s": ok / t, "fwd_ms": t_f * 1e3, "instances": sb.n,
-            "reach_blocks": int(len(sb.reach_off) - 1), "algorithmic_bytes_per_instance":
-            float(algorithmic_bytes(sb).mean()), "status_counts": np.bincount(st, minlength=6).tolist()}
-        sg.close()
-        del sb, sg, sres
+        # the same 50,000 edges with one reachable block shared by all, and
+        # with the start velocity pinned (fwd + bwd with the headline options)
+        out["edges50k_p7_shared_reach"] = _variant(gen.with_shared_reach(edges), main_opts, reps, stream)
+        out["edges50k_p7_pinned_v0"] = _variant(gen.with_pinned_velocity(edges), main_opts, reps, stream)
     b = gen.generate(2, 200_000)
     gb = SegmentBatchGPU(b, device="cuda:0")
     x0, goal = torch.as_tensor(b.x0, device=dev), torch.as_tensor(b.goal, device=dev)

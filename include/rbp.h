@@ -16,6 +16,7 @@
  *               H vec(P) <= h0 + G x0        (reachable Bezier polytope,
  *                                             Theorem 2, affine in x0)
  *               P_0 = x0[0:3],  P_p = goal   (the edge joins two waypoints)
+ *               [optional] (p/T)(P_1 - P_0) = x0[3:6]  (pinned start velocity)
  *
  * vec(P) is point-major: element 3k + c is coordinate c of control point k.
  *
@@ -105,6 +106,13 @@ typedef struct rbp_problem_desc {
    * of this (RBP_E_SHAPE otherwise). */
   int32_t n_reach;
   const int32_t* reach_idx;   /* [N] or NULL                                     */
+  /* 1: the start velocity is pinned as well as the start position (the
+   * full-state start of Lemma 1): every instance also satisfies
+   * (p/T)(P_1 - P_0) = x0[3:6], the derivative of the curve at t = 0.  Its
+   * k = 0 velocity rows then reduce to |x0[3+c]| <= vmax, a constant test
+   * (RBP_INFEASIBLE when it fails).  0: only P_0 is pinned.  Other values:
+   * RBP_E_INVALID. */
+  int32_t pin_start_velocity;
 } rbp_problem_desc;
 
 typedef struct rbp_solve_opts {

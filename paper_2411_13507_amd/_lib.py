@@ -28,7 +28,7 @@ class ProblemDesc(ctypes.Structure):
         ("degree", _p), ("T", _p), ("poly_off", _p), ("A_face", _p), ("b_face", _p),
         ("poly_idx", _p), ("reach_off", _p), ("H_off", _p), ("H", _p), ("h0", _p), ("G", _p),
         ("vmax", ctypes.c_double), ("amax", ctypes.c_double),
-        ("n_reach", ctypes.c_int32), ("reach_idx", _p),
+        ("n_reach", ctypes.c_int32), ("reach_idx", _p), ("pin_start_velocity", ctypes.c_int32),
     ]
 
 

@@ -49,7 +49,8 @@ class SegmentBatchGPU:
     G, vmax, amax), for instance a ``workloads.gen.SegmentBatch``.  An
     optional ``reach_idx`` attribute (not None) selects the shared-table form
     of the reachable rows: reach_off / H_off then index a table of blocks and
-    instance i uses block reach_idx[i].
+    instance i uses block reach_idx[i].  ``pin_v0`` (if true) pins the start
+    velocity as well: (p/T)(P_1 - P_0) = x0[3:6].
     """
 
     def __init__(self, problem, device: str = "cuda"):
@@ -81,6 +82,7 @@ class SegmentBatchGPU:
             _ptr(self.poly_idx), _ptr(self.reach_off), _ptr(self.H_off), _ptr(self.H), _ptr(self.h0),
             _ptr(self.G), float(problem.vmax), float(problem.amax),
             0 if ridx is None else int(self.reach_off.numel()) - 1, _ptr(self.reach_idx),
+            1 if getattr(problem, "pin_v0", False) else 0,
         )
         h = ctypes.c_void_p()
         with torch.cuda.device(d):

@@ -118,6 +118,7 @@ int rbp_build_batch(const rbp_problem_desc* d, hipStream_t stream, rbp_batch** o
   const int32_t N = d->n_instances;
   if (N < 0 || d->n_poly < 0) return RBP_E_INVALID;
   if (!(d->vmax > 0.0) || !(d->amax > 0.0)) return RBP_E_INVALID;
+  if (d->pin_start_velocity != 0 && d->pin_start_velocity != 1) return RBP_E_INVALID;
   if (N > 0) {
     if (d->n_poly < 1) return RBP_E_SHAPE;
     if (!d->degree || !d->T || !d->poly_off || !d->A_face || !d->b_face || !d->poly_idx ||
@@ -258,6 +259,7 @@ int rbp_solve_batch(rbp_batch* b, const double* x0, const double* goal, const do
   a.degree = d.degree; a.T = d.T; a.poly_off = d.poly_off; a.A_face = d.A_face; a.b_face = bf;
   a.poly_idx = d.poly_idx; a.reach_off = d.reach_off; a.H_off = d.H_off; a.H = d.H; a.h0 = d.h0; a.G = d.G;
   a.reach_idx = d.reach_idx;
+  a.pin_v0 = d.pin_start_velocity;
   a.vmax = d.vmax; a.amax = d.amax;
   a.x0 = x0; a.goal = goal; a.pt_off = b->d_pt_off;
   a.P_out = P_out; a.cost_out = cost_out; a.status_out = status_out; a.kkt_out = kkt_out; a.iters_out = iters_out;
@@ -312,6 +314,7 @@ int rbp_backward(rbp_batch* b, const double* grad_P, const double* grad_cost, do
   a.degree = d.degree; a.T = d.T; a.poly_off = d.poly_off; a.A_face = d.A_face; a.b_face = b->fw_bface;
   a.poly_idx = d.poly_idx; a.reach_off = d.reach_off; a.H_off = d.H_off; a.H = d.H; a.G = d.G;
   a.reach_idx = d.reach_idx;
+  a.pin_v0 = d.pin_start_velocity;
   a.vmax = d.vmax; a.amax = d.amax;
   a.x0 = b->fw_x0; a.goal = b->fw_goal; a.pt_off = b->d_pt_off; a.face_off = b->d_face_off;
   a.P_sol = b->fw_P; a.status = b->fw_status;

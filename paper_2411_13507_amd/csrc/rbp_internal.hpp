@@ -43,6 +43,7 @@ struct SolveArgs {
   const int64_t* reach_off;
   const int64_t* H_off;
   const int32_t* reach_idx;  // nullable: reachable block of each instance (else the instance's own)
+  int pin_v0;                // 1: (p/T)(P_1 - P_0) = x0[3:6] replaces the k = 0 velocity rows
   const double* H;
   const double* h0;
   const double* G;
@@ -87,6 +88,7 @@ struct BackArgs {
   const int64_t* reach_off;
   const int64_t* H_off;
   const int32_t* reach_idx;  // nullable: reachable block of each instance (else the instance's own)
+  int pin_v0;                // 1: (p/T)(P_1 - P_0) = x0[3:6] replaces the k = 0 velocity rows
   const double* H;
   const double* G;
   double vmax, amax;

@@ -284,12 +284,20 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
   const bool dl = lane < ND;
   int dk = 0, dc = 0;
   bool dvel = true;
-  double dsc = 0, dbd = 0, dcst = 0, ddn = 0;
+  // a difference row holds its value in [dctr - dbd, dctr + dbd]
+  double dsc = 0, dbd = 0, dctr = 0, dcst = 0, ddn = 0;
   if (dl) {
     if (lane < 3 * P) {
       dk = lane / 3; dc = lane - 3 * dk; dvel = true; dsc = in.sv; dbd = in.vmax;
       dcst = (dk == P - 1) ? in.sv * sel3(dc, in.dg[0], in.dg[1], in.dg[2]) : 0.0;
       ddn = 1.0 / (K.wn_vel[dk] * sqrt(in.T));
+      if (A.pin_v0 && dk == 0) {
+        // pinned start velocity: the first derivative point equals x0[3+c];
+        // its speed bound is then a constant test
+        dctr = in.x0[3 + dc];
+        dbd = 0.0;
+        fixed_viol |= fabs(dctr) > in.vmax;
+      }
     } else {
       const int l2 = lane - 3 * P;
       dk = l2 / 3; dc = l2 - 3 * dk; dvel = false; dsc = in.sa; dbd = in.amax;
@@ -434,8 +442,8 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
       zf[s] = 0; yf[s] = 0;
     }
     const Real dd = Real(ddn);
-    const Real dlo = dl ? Real(ddn * (-dbd - dcst)) : Real(-kBigF);
-    const Real dhi = dl ? Real(ddn * (dbd - dcst)) : Real(kBigF);
+    const Real dlo = dl ? Real(ddn * (dctr - dbd - dcst)) : Real(-kBigF);
+    const Real dhi = dl ? Real(ddn * (dctr + dbd - dcst)) : Real(kBigF);
     Real zd = 0, yd = 0;
     // stencil on the free vars (index -1: pinned point)
     int di0 = -1, di1 = -1, di2 = -1;
@@ -810,7 +818,7 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
           L.scal[0] = fu; L.scal[1] = 0.0;
         } else if (bit == NFP) {
           sc_d = -1.0f;
-          L.scal[0] = dbd;                        // side*bound: u = dbd and -l = dbd
+          L.scal[0] = dbd + double(side) * dctr;  // side*bound: u = dctr + dbd, -l = dbd - dctr
           L.scal[1] = double(side) * dcst;
         } else if (bit == NFP + 1) {
           sc_r[0] = -1.0f; L.scal[0] = ru[0]; L.scal[1] = rcst[0];
@@ -888,9 +896,9 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
       else v = dsc * (L.ybuf[3 * (dk + 2) + dc] - 2.0 * L.ybuf[3 * (dk + 1) + dc] + L.ybuf[3 * dk + dc]);
       if (write_vals) L.rowval[F + lane] = v;
       if (!((act_bits >> NFP) & 1u)) {
-        const double vu = v - dbd, vlo = -dbd - v;
-        if (vu > ftol * (1.0 + dbd) && vu * ddn > best) { best = vu * ddn; key = 2 * (F + lane) + 1; }
-        if (vlo > ftol * (1.0 + dbd) && vlo * ddn > best) { best = vlo * ddn; key = 2 * (F + lane); }
+        const double vu = v - dctr - dbd, vlo = dctr - dbd - v, dtol = ftol * (1.0 + dbd + fabs(dctr));
+        if (vu > dtol && vu * ddn > best) { best = vu * ddn; key = 2 * (F + lane) + 1; }
+        if (vlo > dtol && vlo * ddn > best) { best = vlo * ddn; key = 2 * (F + lane); }
       }
     }
 #pragma unroll
@@ -941,7 +949,7 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
         } else if (bit == NFP) {
           val = dvel ? dsc * (L.ybuf[3 * (dk + 1) + dc] - L.ybuf[3 * dk + dc])
                      : dsc * (L.ybuf[3 * (dk + 2) + dc] - 2.0 * L.ybuf[3 * (dk + 1) + dc] + L.ybuf[3 * dk + dc]);
-          e_full = dbd; c_full = double(side) * dcst;
+          e_full = dbd + double(side) * dctr; c_full = double(side) * dcst;
         } else {
           const int sl = bit - NFP - 1;
           const double* hr = L.Hd + (lane + kWave * sl) * HDS;
@@ -1048,8 +1056,8 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
   }
   if (dl) {
     const double v = L.rowval[F + lane];
-    pres = fmax(pres, fmax(v - dbd, -dbd - v));
-    pscale = fmax(pscale, fmax(fabs(v), dbd));
+    pres = fmax(pres, fmax(v - dctr - dbd, dctr - dbd - v));
+    pscale = fmax(pscale, fmax(fabs(v), fabs(dctr) + dbd));
   }
 #pragma unroll
   for (int sl = 0; sl < 2; ++sl) {
@@ -1276,6 +1284,9 @@ __device__ void backward_instance(const BackArgs& A, const int inst, char* smem)
     for (int k = 0; k < q; ++k) {
       const int id = L.actid[k];
       if (id >= in.RB) g += L.vD[k] * A.G[6 * (in.r0 + (id - in.RB)) + lane];
+      // pinned start velocity: row F + c bounds its value by x0[3+c] on the
+      // active side (right-hand side side * x0[3+c])
+      if (A.pin_v0 && lane >= 3 && id == in.F + lane - 3) g += L.vD[k] * double(L.actside[k]);
     }
     A.grad_x0[6 * (int64_t)inst + lane] = g;
   }
