@@ -31,10 +31,37 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found (ROCm is required to build librbp.so)")
 
 
+RESOURCES = os.path.join(HERE, "librbp.resources.tsv")
+
+
+def _resource_table(remarks: str) -> str:
+    """Kernel name, VGPRs, SGPRs, scratch bytes per lane, LDS bytes and
+    occupancy from the compiler's kernel-resource-usage remarks."""
+    keys = {"VGPRs": "vgpr", "TotalSGPRs": "sgpr", "ScratchSize [bytes/lane]": "scratch",
+            "LDS Size [bytes/block]": "lds", "Occupancy [waves/SIMD]": "occupancy"}
+    rows, cur = [], None
+    for line in remarks.splitlines():
+        if "remark:" not in line:
+            continue
+        body = line.split("remark:", 1)[1].split(" [-Rpass", 1)[0].strip()
+        if body.startswith("Function Name:"):
+            cur = {"kernel": body.split(":", 1)[1].strip()}
+            rows.append(cur)
+        elif cur is not None and ":" in body:
+            k, v = body.rsplit(":", 1)
+            if k.strip() in keys:
+                cur[keys[k.strip()]] = v.strip()
+    cols = ["kernel", "vgpr", "sgpr", "scratch", "lds", "occupancy"]
+    return "\n".join(["\t".join(cols)] + ["\t".join(r.get(c, "") for c in cols) for r in rows]) + "\n"
+
+
 def build(verbose: bool = False) -> str:
-    """Compile every source for gfx950 and link ``librbp.so``; returns its path."""
+    """Compile every source for gfx950 and link ``librbp.so``; returns its
+    path.  The compiler's per-kernel resource usage (registers, scratch,
+    occupancy) is written beside it."""
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIP_FLAGS, "-shared", "-o", tmp] + [os.path.join(CSRC, s) for s in SOURCES]
+    cmd = [hipcc(), *HIP_FLAGS, "-Rpass-analysis=kernel-resource-usage", "-shared", "-o", tmp] + \
+        [os.path.join(CSRC, s) for s in SOURCES]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -42,6 +69,8 @@ def build(verbose: bool = False) -> str:
         sys.stderr.write(res.stdout + res.stderr)
         raise RuntimeError(f"hipcc failed with exit code {res.returncode}")
     os.replace(tmp, LIB)
+    with open(RESOURCES, "w") as fh:
+        fh.write(_resource_table(res.stderr))
     return LIB
 
 

@@ -284,19 +284,21 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
   const bool dl = lane < ND;
   int dk = 0, dc = 0;
   bool dvel = true;
-  // a difference row holds its value in [dctr - dbd, dctr + dbd]
-  double dsc = 0, dbd = 0, dctr = 0, dcst = 0, ddn = 0;
+  // a difference row holds its value in [dlo_of(), dbd]: [-dbd, dbd], or the
+  // single value dbd on a pinned start-velocity lane (no extra register)
+  const bool pinl = A.pin_v0 && lane < 3;
+  auto dlo_of = [&](double bd) { return pinl ? bd : -bd; };
+  double dsc = 0, dbd = 0, dcst = 0, ddn = 0;
   if (dl) {
     if (lane < 3 * P) {
       dk = lane / 3; dc = lane - 3 * dk; dvel = true; dsc = in.sv; dbd = in.vmax;
       dcst = (dk == P - 1) ? in.sv * sel3(dc, in.dg[0], in.dg[1], in.dg[2]) : 0.0;
       ddn = 1.0 / (K.wn_vel[dk] * sqrt(in.T));
-      if (A.pin_v0 && dk == 0) {
+      if (pinl) {
         // pinned start velocity: the first derivative point equals x0[3+c];
         // its speed bound is then a constant test
-        dctr = in.x0[3 + dc];
-        dbd = 0.0;
-        fixed_viol |= fabs(dctr) > in.vmax;
+        dbd = sel3(dc, in.x0[3], in.x0[4], in.x0[5]);   // no dynamic index into a register array
+        fixed_viol |= fabs(dbd) > in.vmax;
       }
     } else {
       const int l2 = lane - 3 * P;
@@ -442,8 +444,8 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
       zf[s] = 0; yf[s] = 0;
     }
     const Real dd = Real(ddn);
-    const Real dlo = dl ? Real(ddn * (dctr - dbd - dcst)) : Real(-kBigF);
-    const Real dhi = dl ? Real(ddn * (dctr + dbd - dcst)) : Real(kBigF);
+    const Real dlo = dl ? Real(ddn * (dlo_of(dbd) - dcst)) : Real(-kBigF);
+    const Real dhi = dl ? Real(ddn * (dbd - dcst)) : Real(kBigF);
     Real zd = 0, yd = 0;
     // stencil on the free vars (index -1: pinned point)
     int di0 = -1, di1 = -1, di2 = -1;
@@ -818,7 +820,7 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
           L.scal[0] = fu; L.scal[1] = 0.0;
         } else if (bit == NFP) {
           sc_d = -1.0f;
-          L.scal[0] = dbd + double(side) * dctr;  // side*bound: u = dctr + dbd, -l = dbd - dctr
+          L.scal[0] = side > 0 ? dbd : -dlo_of(dbd);  // side*bound: u = dbd and -l
           L.scal[1] = double(side) * dcst;
         } else if (bit == NFP + 1) {
           sc_r[0] = -1.0f; L.scal[0] = ru[0]; L.scal[1] = rcst[0];
@@ -896,7 +898,7 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
       else v = dsc * (L.ybuf[3 * (dk + 2) + dc] - 2.0 * L.ybuf[3 * (dk + 1) + dc] + L.ybuf[3 * dk + dc]);
       if (write_vals) L.rowval[F + lane] = v;
       if (!((act_bits >> NFP) & 1u)) {
-        const double vu = v - dctr - dbd, vlo = dctr - dbd - v, dtol = ftol * (1.0 + dbd + fabs(dctr));
+        const double vu = v - dbd, vlo = dlo_of(dbd) - v, dtol = ftol * (1.0 + fabs(dbd));
         if (vu > dtol && vu * ddn > best) { best = vu * ddn; key = 2 * (F + lane) + 1; }
         if (vlo > dtol && vlo * ddn > best) { best = vlo * ddn; key = 2 * (F + lane); }
       }
@@ -949,7 +951,7 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
         } else if (bit == NFP) {
           val = dvel ? dsc * (L.ybuf[3 * (dk + 1) + dc] - L.ybuf[3 * dk + dc])
                      : dsc * (L.ybuf[3 * (dk + 2) + dc] - 2.0 * L.ybuf[3 * (dk + 1) + dc] + L.ybuf[3 * dk + dc]);
-          e_full = dbd + double(side) * dctr; c_full = double(side) * dcst;
+          e_full = side > 0 ? dbd : -dlo_of(dbd); c_full = double(side) * dcst;
         } else {
           const int sl = bit - NFP - 1;
           const double* hr = L.Hd + (lane + kWave * sl) * HDS;
@@ -1056,8 +1058,8 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
   }
   if (dl) {
     const double v = L.rowval[F + lane];
-    pres = fmax(pres, fmax(v - dctr - dbd, dctr - dbd - v));
-    pscale = fmax(pscale, fmax(fabs(v), fabs(dctr) + dbd));
+    pres = fmax(pres, fmax(v - dbd, dlo_of(dbd) - v));
+    pscale = fmax(pscale, fmax(fabs(v), fabs(dbd)));
   }
 #pragma unroll
   for (int sl = 0; sl < 2; ++sl) {

@@ -1,0 +1,39 @@
+"""Register and scratch budget of the built kernels, from the compiler's
+resource-usage remarks that the build writes beside librbp.so.
+
+Per-lane scratch (private memory) is spill or dynamically indexed register
+arrays: it turns LDS-speed data into memory traffic.  The segment kernels of
+degree 3-8, the backward, graph-cut and graph-building kernels must have
+none; the degree-9 segment kernels and the path kernel are at the 256-VGPR
+limit and are allowed their (stated) spill."""
+import csv
+import os
+import re
+
+import pytest
+
+from paper_2411_13507_amd import build
+
+ALLOWED = {r"solve_kernelI[fd]Li9E": 128, r"chain_kernelILi7E": 1024}
+
+
+@pytest.fixture(scope="module")
+def table():
+    if not os.path.exists(build.RESOURCES):
+        pytest.skip("library not built here")
+    with open(build.RESOURCES) as fh:
+        return list(csv.DictReader(fh, delimiter="\t"))
+
+
+def test_every_kernel_reported(table):
+    names = " ".join(r["kernel"] for r in table)
+    for k in ("solve_kernel", "backward_kernel", "chain_kernel", "cut_qp_kernel", "cut_prefilter_kernel",
+              "graph_pairs_kernel", "hyperplane_kernel"):
+        assert k in names, k
+
+
+def test_no_scratch_outside_the_stated_kernels(table):
+    for r in table:
+        limit = next((v for pat, v in ALLOWED.items() if re.search(pat, r["kernel"])), 0)
+        assert int(r["scratch"]) <= limit, (r["kernel"], r["scratch"])
+        assert int(r["vgpr"]) <= 256

@@ -716,3 +716,134 @@ def gen_graph(n_nodes: int = 5000, m: int = 64, cfg: int = 6, n_obst: int = 200)
     return GraphBatch(name=f"graph{n_nodes}_m{m}", V=V, F1=np.ascontiguousarray(-A), F2=np.ascontiguousarray(F2),
                       G=g, box_lo=np.ascontiguousarray(env.obs_lo[:n_obst]),
                       box_hi=np.ascontiguousarray(env.obs_hi[:n_obst]))
+
+
+# ---------------------------------------------------------------------------
+# MPC refinement batches (eq. MPC, Sec. III-D)
+# ---------------------------------------------------------------------------
+
+@dataclass
+class MpcBatch:
+    """Independent MPC refinement problems over one horizon of N steps.
+
+    Shared: step dt, tracking weight Q [6, 6], input weight R [3, 3],
+    path-length weight w, and the reachable-polytope rows between
+    consecutive nodes F1 x_k + F2 x_{k+1} <= G (F1, F2 [m, 6], G [m]).
+    Per instance: start state x0 [6], reference states ref [N+1, 6] (the
+    graph path sampled at dt), one separating plane per step
+    planes [N, 4] = (n, l) with unit n (the segment from x_k to x_{k+1} must
+    stay in n . y >= l), and the reference curve's acceleration at the nodes
+    ref_u [N, 3]."""
+    name: str
+    N: int
+    dt: float
+    Q: np.ndarray
+    R: np.ndarray
+    w: float
+    F1: np.ndarray
+    F2: np.ndarray
+    G: np.ndarray
+    x0: np.ndarray
+    ref: np.ndarray
+    planes: np.ndarray
+    ref_u: np.ndarray
+    meta: Dict[str, object] = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return int(self.x0.shape[0])
+
+    def instance(self, i: int) -> dict:
+        return dict(N=self.N, dt=self.dt, Q=self.Q, R=self.R, w=self.w, F1=self.F1, F2=self.F2, G=self.G,
+                    x0=self.x0[i].copy(), ref=self.ref[i].copy(), planes=self.planes[i].copy())
+
+    def subset(self, idx) -> "MpcBatch":
+        idx = np.asarray(idx, np.int64)
+        return dataclasses.replace(self, name=f"{self.name}[subset]", x0=self.x0[idx].copy(),
+                                   ref=self.ref[idx].copy(), planes=self.planes[idx].copy(),
+                                   ref_u=self.ref_u[idx].copy())
+
+
+MPC_VMAX = 2.0
+MPC_AMAX = 4.0
+
+
+def mpc_reach_rows(dt: float, m_extra: int = 4, rng=None):
+    """Rows on [x_k; x_{k+1}] (x = position, velocity): a velocity box on the
+    next node, an input box |v_{k+1} - v_k| <= amax dt, and m_extra rows
+    a . (v_{k+1} - v_k) <= g with unit a and g ~ U[0.05, 0.09] (acceleration
+    limits of 0.5-0.9 m/s^2 in a few directions, below what the reference
+    sometimes uses, so these rows become active; m = 12 + m_extra)."""
+    rng = rng or np.random.default_rng(np.random.SeedSequence(1000 + 7, spawn_key=(5,)))
+    rows1, rows2, rhs = [], [], []
+    for c in range(3):
+        for sgn in (1.0, -1.0):
+            a1 = np.zeros(6); a2 = np.zeros(6); a2[3 + c] = sgn
+            rows1.append(a1); rows2.append(a2); rhs.append(MPC_VMAX)
+    for c in range(3):
+        for sgn in (1.0, -1.0):
+            a1 = np.zeros(6); a2 = np.zeros(6); a1[3 + c] = -sgn; a2[3 + c] = sgn
+            rows1.append(a1); rows2.append(a2); rhs.append(MPC_AMAX * dt)
+    for _ in range(m_extra):
+        a = rng.standard_normal(3); a /= np.linalg.norm(a)
+        a1 = np.zeros(6); a2 = np.zeros(6); a1[3:] = -a; a2[3:] = a
+        rows1.append(a1); rows2.append(a2); rhs.append(rng.uniform(0.05, 0.09))
+    return np.array(rows1), np.array(rows2), np.array(rhs)
+
+
+def gen_mpc(n: int = 4096, N: int = 50, dt: float = 0.1, m_extra: int = 4, seed_cfg: int = 7,
+            indices: Optional[Sequence[int]] = None) -> MpcBatch:
+    """The paper's refinement setting (Sec. IV): a 50-node horizon at 0.1 s,
+    path-length weight well above the tracking weight.  The reference samples
+    a smooth curve whose acceleration is a(t) = sum of two sinusoids per axis
+    (amplitude <= 0.5 each, frequency 1.5-3 rad/s, so |v| < vmax and
+    |a| < amax), integrated in closed form; the start state is ref[0]
+    plus a tracking error (position +-0.05, velocity +-0.1).  Plane k lies on
+    the inner side of the reference's turn at node k (normal along minus the
+    reference acceleration's component across the velocity, plus noise), at
+    a distance U[0.05, 0.25] from the reference node (U[0.22, 0.5] for the
+    first step, whose start is fixed), so cutting the corner, which the
+    path-length weight (50, against 1 for position tracking) asks for, meets
+    some of the planes."""
+    idx = range(n) if indices is None else indices
+    F1, F2, G = mpc_reach_rows(dt, m_extra)
+    Q = np.diag([1.0, 1.0, 1.0, 0.1, 0.1, 0.1])
+    R = 0.01 * np.eye(3)
+    w = 50.0
+    x0s, refs, planes, us = [], [], [], []
+    t = dt * np.arange(N)
+    for i in idx:
+        rng = np.random.default_rng(np.random.SeedSequence(1000 + seed_cfg, spawn_key=(0, int(i))))
+        amp = rng.uniform(0.2, 0.5, size=(2, 3))
+        om = rng.uniform(1.5, 3.0, size=(2, 3))
+        ph = rng.uniform(0, 2 * np.pi, size=(2, 3))
+        p0 = rng.uniform(2.0, 8.0, 3)
+        v0 = rng.uniform(-0.5, 0.5, 3)
+        # the continuous curve with acceleration a(t), sampled at k dt
+        tt = dt * np.arange(N + 1)[:, None]
+        x = np.zeros((N + 1, 6))
+        x[:, :3] = p0 + v0 * tt
+        x[:, 3:] = v0
+        for j in range(2):
+            A_, w_, f_ = amp[j], om[j], ph[j]
+            x[:, 3:] += A_ / w_ * (np.cos(f_) - np.cos(w_ * tt + f_))
+            x[:, :3] += A_ / w_ * (tt * np.cos(f_) - (np.sin(w_ * tt + f_) - np.sin(f_)) / w_)
+        u = (amp[0] * np.sin(om[0] * t[:, None] + ph[0]) + amp[1] * np.sin(om[1] * t[:, None] + ph[1]))
+        pl = np.zeros((N, 4))
+        for k in range(N):
+            v = x[k, 3:]
+            a = u[k]
+            vv = v @ v
+            side = a - (a @ v) / vv * v if vv > 1e-12 else a
+            nrm = -side / max(np.linalg.norm(side), 1e-12) + 0.3 * rng.standard_normal(3)
+            nrm /= np.linalg.norm(nrm)
+            pl[k, :3] = nrm
+            pl[k, 3] = nrm @ x[k, :3] - (rng.uniform(0.22, 0.5) if k == 0 else rng.uniform(0.05, 0.25))
+        x0 = x[0].copy()
+        x0[:3] += rng.uniform(-0.05, 0.05, 3)
+        x0[3:] += rng.uniform(-0.1, 0.1, 3)
+        x0s.append(x0); refs.append(x); planes.append(pl); us.append(u)
+    return MpcBatch(name=f"mpc{len(x0s)}_n{N}", N=N, dt=dt, Q=Q, R=R, w=w, F1=F1, F2=F2, G=G,
+                    x0=np.asarray(x0s).reshape(-1, 6), ref=np.asarray(refs).reshape(-1, N + 1, 6),
+                    planes=np.asarray(planes).reshape(-1, N, 4), ref_u=np.asarray(us).reshape(-1, N, 3),
+                    meta=dict(seed_cfg=seed_cfg, m=12 + m_extra))
