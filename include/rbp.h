@@ -371,6 +371,88 @@ int rbp_adjacent_hyperplanes(int32_t n_nodes, const double* X, int32_t n_obstacl
                              hipStream_t stream);
 
 /* Static string for a call result or per-instance status code. */
+/*
+ * Batched MPC refinement (eq. MPC, Sec. III-D).  Each instance refines a
+ * path over a horizon of N steps of length dt for the double integrator in
+ * R^3 (state x = (position p, velocity v), input u = acceleration, exact
+ * zero-order-hold discretisation x_{k+1} = A x_k + B u_k):
+ *
+ *   minimise   sum_{k=1}^{N-1} (x_k - r_k)' Q (x_k - r_k)
+ *            + sum_{k=0}^{N-1} u_k' R u_k + w |p_{k+1} - p_k|^2
+ *   subject to x_0 = x0,  x_N = r_N,  dynamics,
+ *              F1 x_k + F2 x_{k+1} <= G          (reachable rows, Thm. 2)
+ *              n_k . P_j >= l_k,  j = 0..3        (keep-out plane of step k)
+ *
+ * where P_j are the control points of the cubic Bezier curve on [0, dt]
+ * joining the two states (Lemma 1): p_k, p_k + dt/3 v_k, p_{k+1} - dt/3
+ * v_{k+1}, p_{k+1}; by the convex-hull property the whole step stays on the
+ * free side of the plane.  The planes (one per step) come from the adjacent
+ * hyperplanes of the reference nodes (rbp_adjacent_hyperplanes): one SQP
+ * iteration, as in Sec. IV.
+ *
+ * Solver: one wavefront per instance, primal-dual interior point in FP64
+ * with Riccati-structured Newton systems.  Instances are independent.
+ */
+#define RBP_MPC_MAX_HORIZON 64
+#define RBP_MPC_MAX_REACH 32
+
+typedef struct rbp_mpc_desc {
+  int32_t n_instances;        /* >= 0                                            */
+  int32_t horizon;            /* N, 2..RBP_MPC_MAX_HORIZON                       */
+  int32_t n_reach;            /* m reachable rows per step, 0..RBP_MPC_MAX_REACH  */
+  int32_t reserved;           /* must be 0                                       */
+  double dt;                  /* step, > 0                                       */
+  double Q[36];               /* tracking weight (6 x 6, row-major, symmetric
+                                 positive semidefinite; host values)             */
+  double R[9];                /* input weight (3 x 3, symmetric positive
+                                 definite; host values)                          */
+  double w_length;            /* weight of |p_{k+1} - p_k|^2, >= 0                */
+  const double* F1;           /* [m][6] device: rows on x_k                      */
+  const double* F2;           /* [m][6] device: rows on x_{k+1}                  */
+  const double* G;            /* [m] device                                      */
+} rbp_mpc_desc;
+
+typedef struct rbp_mpc rbp_mpc;
+
+/* Validates the description, copies F1, F2, G to the host (the call
+ * synchronises `stream`), prepares the per-step constants and uploads them.
+ * Errors: RBP_E_INVALID (null pointers with m > 0, reserved != 0, dt <= 0,
+ * w < 0, Q not symmetric or with a negative diagonal, R not symmetric
+ * positive definite), RBP_E_SHAPE (horizon or m out of range, a reachable row
+ * that vanishes once x_{k+1} is written through the dynamics), RBP_E_ALLOC,
+ * RBP_E_DEVICE. */
+int rbp_build_mpc(const rbp_mpc_desc* desc, hipStream_t stream, rbp_mpc** out);
+
+/*
+ * Solves every instance.
+ *   x0      [n][6]        start states
+ *   ref     [n][N+1][6]   reference states r_0..r_N (r_N is the terminal state)
+ *   planes  [n][N][4]     (n_k, l_k) per step; n_k need not be unit length
+ *   max_iters             interior-point iteration cap (> 0; 40 is ample)
+ *   tol                   target of the average complementarity; the primal
+ *                         and dual residuals must reach 1e3 tol (> 0; 1e-13)
+ *   X       [n][N+1][6]   states (X_N from the dynamics of the last step)
+ *   U       [n][N][3]     inputs
+ *   cost    [n]           objective value
+ *   status  [n]           RBP_SOLVED (converged, scaled KKT residual
+ *                         <= 1e-6), RBP_MAXITER (not converged: includes
+ *                         infeasible instances, which are not certified),
+ *                         RBP_NUMERICAL (converged, residual above 1e-6),
+ *                         RBP_INVALID_INPUT (non-finite input or a zero
+ *                         plane normal); X, U, cost are NaN for the last.
+ *   kkt     [n]           max of the scaled primal, dual (least-squares
+ *                         costates) and complementarity residuals
+ *   iters   [n] or NULL   interior-point iterations
+ * Errors: RBP_E_INVALID (null pointer, max_iters <= 0, tol <= 0),
+ * RBP_E_DEVICE.
+ */
+int rbp_mpc_solve(rbp_mpc* mpc, const double* x0, const double* ref, const double* planes, int32_t max_iters,
+                  double tol, double* X, double* U, double* cost, int32_t* status, double* kkt, int32_t* iters,
+                  hipStream_t stream);
+
+/* Releases the solver (no-op for NULL); synchronises its last stream first. */
+void rbp_destroy_mpc(rbp_mpc* mpc);
+
 const char* rbp_status_string(int code);
 
 #ifdef __cplusplus

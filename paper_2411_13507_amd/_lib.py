@@ -17,6 +17,7 @@ EXPORTED = (
     "rbp_build_chains", "rbp_chains_get_sizes", "rbp_solve_chains", "rbp_destroy_chains",
     "rbp_build_cut", "rbp_cut_run", "rbp_cut_qp_count", "rbp_destroy_cut",
     "rbp_build_graph", "rbp_graph_run", "rbp_destroy_graph", "rbp_adjacent_hyperplanes",
+    "rbp_build_mpc", "rbp_mpc_solve", "rbp_destroy_mpc",
 )
 
 _p = ctypes.c_void_p
@@ -52,6 +53,14 @@ class GraphDesc(ctypes.Structure):
     _fields_ = [
         ("n_nodes", ctypes.c_int32), ("dim", ctypes.c_int32), ("n_rows", ctypes.c_int32),
         ("reserved", ctypes.c_int32), ("F1", _p), ("F2", _p), ("G", _p),
+    ]
+
+
+class MpcDesc(ctypes.Structure):
+    _fields_ = [
+        ("n_instances", ctypes.c_int32), ("horizon", ctypes.c_int32), ("n_reach", ctypes.c_int32),
+        ("reserved", ctypes.c_int32), ("dt", ctypes.c_double), ("Q", ctypes.c_double * 36),
+        ("R", ctypes.c_double * 9), ("w_length", ctypes.c_double), ("F1", _p), ("F2", _p), ("G", _p),
     ]
 
 
@@ -122,6 +131,12 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.rbp_destroy_graph.restype = None
     L.rbp_adjacent_hyperplanes.argtypes = [ctypes.c_int32, _p, ctypes.c_int32, _p, _p, _p, _p, _p, _p]
     L.rbp_adjacent_hyperplanes.restype = ctypes.c_int
+    L.rbp_build_mpc.argtypes = [ctypes.POINTER(MpcDesc), _p, ctypes.POINTER(_p)]
+    L.rbp_build_mpc.restype = ctypes.c_int
+    L.rbp_mpc_solve.argtypes = [_p, _p, _p, _p, ctypes.c_int32, ctypes.c_double, _p, _p, _p, _p, _p, _p, _p]
+    L.rbp_mpc_solve.restype = ctypes.c_int
+    L.rbp_destroy_mpc.argtypes = [_p]
+    L.rbp_destroy_mpc.restype = None
     L.rbp_status_string.argtypes = [ctypes.c_int]
     L.rbp_status_string.restype = ctypes.c_char_p
     _LIB = L

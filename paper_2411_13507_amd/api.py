@@ -362,3 +362,70 @@ def adjacent_hyperplanes(X: torch.Tensor, box_lo: torch.Tensor, box_hi: torch.Te
                                                     _ptr(idx), _ptr(point), _ptr(plane), _stream_handle(d)),
                "rbp_adjacent_hyperplanes")
     return idx, point, plane
+
+
+@dataclass
+class MpcResult:
+    X: torch.Tensor          # [n, N+1, 6] float64
+    U: torch.Tensor          # [n, N, 3]
+    cost: torch.Tensor       # [n]
+    status: torch.Tensor     # [n] int32
+    kkt: torch.Tensor        # [n]
+    iters: torch.Tensor      # [n] int32
+
+
+class MpcGPU:
+    """Batched MPC refinement (eq. MPC) resident on one GPU.  ``problem``
+    has the shared attributes of ``workloads.gen.MpcBatch`` (N, dt, Q, R, w,
+    F1, F2, G); ``n`` is the number of instances per call."""
+
+    def __init__(self, problem, n: int, device: str = "cuda"):
+        if not torch.cuda.is_available():
+            raise _lib.RbpError("no GPU visible: the MPC solver runs only on the GPU")
+        self.device = torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device(self.device.type, torch.cuda.current_device())
+        L = _lib.load()
+        d = self.device
+        self.n, self.N = int(n), int(problem.N)
+        self.F1 = _dev(np.asarray(problem.F1).reshape(-1), torch.float64, d)
+        self.F2 = _dev(np.asarray(problem.F2).reshape(-1), torch.float64, d)
+        self.G = _dev(problem.G, torch.float64, d)
+        desc = _lib.MpcDesc()
+        desc.n_instances, desc.horizon, desc.n_reach, desc.reserved = self.n, self.N, int(self.G.numel()), 0
+        desc.dt = float(problem.dt)
+        desc.Q[:] = [float(v) for v in np.asarray(problem.Q, float).ravel()]
+        desc.R[:] = [float(v) for v in np.asarray(problem.R, float).ravel()]
+        desc.w_length = float(problem.w)
+        desc.F1, desc.F2, desc.G = _ptr(self.F1), _ptr(self.F2), _ptr(self.G)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(d):
+            _lib.check(L.rbp_build_mpc(ctypes.byref(desc), _stream_handle(d), ctypes.byref(h)), "rbp_build_mpc")
+        self._h = h
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            _lib.load().rbp_destroy_mpc(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def alloc(self) -> MpcResult:
+        d, n, N = self.device, self.n, self.N
+        f = dict(dtype=torch.float64, device=d)
+        return MpcResult(X=torch.empty((n, N + 1, 6), **f), U=torch.empty((n, N, 3), **f),
+                         cost=torch.empty(n, **f), status=torch.empty(n, dtype=torch.int32, device=d),
+                         kkt=torch.empty(n, **f), iters=torch.empty(n, dtype=torch.int32, device=d))
+
+    def solve(self, x0: torch.Tensor, ref: torch.Tensor, planes: torch.Tensor, max_iters: int = 40,
+              tol: float = 1e-13, out: Optional[MpcResult] = None) -> MpcResult:
+        o = out or self.alloc()
+        rc = _lib.load().rbp_mpc_solve(self._h, _ptr(x0), _ptr(ref), _ptr(planes), int(max_iters), float(tol),
+                                       _ptr(o.X), _ptr(o.U), _ptr(o.cost), _ptr(o.status), _ptr(o.kkt),
+                                       _ptr(o.iters), _stream_handle(self.device))
+        _lib.check(rc, "rbp_mpc_solve")
+        return o

@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librbp.so")
-SOURCES = ["rbp_kernels.hip", "rbp_chain.hip", "rbp_cut.hip", "rbp_graph.hip", "rbp_api.cpp"]
+SOURCES = ["rbp_kernels.hip", "rbp_chain.hip", "rbp_cut.hip", "rbp_graph.hip", "rbp_mpc.hip", "rbp_api.cpp"]
 HEADERS = ["rbp_consts.hpp", "rbp_internal.hpp", "rbp_wave.hpp"]
 
 # device-code flags: gfx950 only; packed FP32 instructions disabled (the

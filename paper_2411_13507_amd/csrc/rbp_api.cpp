@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdint>
 #include <cstring>
 #include <mutex>
@@ -665,6 +666,194 @@ int rbp_adjacent_hyperplanes(int32_t n, const double* X, int32_t n_obst, const d
   if (!X || !idx || !point || !plane || (n_obst > 0 && (!lo || !hi))) return RBP_E_INVALID;
   return rbp::launch_hyperplanes(n, X, n_obst, lo, hi, idx, point, plane, stream) == hipSuccess ? RBP_OK
                                                                                                  : RBP_E_DEVICE;
+}
+
+struct rbp_mpc {
+  int device = 0;
+  rbp_mpc_desc desc{};
+  double* params = nullptr;
+  hipStream_t last_stream = nullptr;
+};
+
+namespace {
+// Host preparation of the MPC constants (layout of rbp::mpc_param_layout).
+// State x = (p, v), z = (x, u); A = [[I, dt I], [0, I]], B = [[dt^2/2 I], [dt I]].
+int mpc_params(const rbp_mpc_desc& d, const std::vector<double>& F1, const std::vector<double>& F2,
+               const std::vector<double>& G, std::vector<double>& out) {
+  const int m = d.n_reach;
+  const double dt = d.dt, h2 = 0.5 * dt * dt;
+  const rbp::MpcLayout L = rbp::mpc_param_layout(m);
+  out.assign(size_t(L.total), 0.0);
+  // A, B as dense 6 x 6 and 6 x 3
+  double A[36] = {0}, B[18] = {0};
+  for (int c = 0; c < 6; ++c) A[7 * c] = 1.0;
+  for (int c = 0; c < 3; ++c) { A[6 * c + 3 + c] = dt; B[3 * c + c] = h2; B[3 * (3 + c) + c] = dt; }
+  // stage Hessians: 2 blkdiag(Q, R) + 2 w J'J with J z = p_{k+1} - p_k = dt v + dt^2/2 u
+  double J[27] = {0};
+  for (int c = 0; c < 3; ++c) { J[9 * c + 3 + c] = dt; J[9 * c + 6 + c] = h2; }
+  for (int a = 0; a < 9; ++a)
+    for (int b = 0; b < 9; ++b) {
+      double jj = 0.0;
+      for (int c = 0; c < 3; ++c) jj += J[9 * c + a] * J[9 * c + b];
+      double h0 = 2.0 * d.w_length * jj;
+      if (a >= 6 && b >= 6) h0 += 2.0 * d.R[3 * (a - 6) + (b - 6)];
+      double h1 = h0;
+      if (a < 6 && b < 6) h1 += 2.0 * d.Q[6 * a + b];
+      out[size_t(L.H0 + 9 * a + b)] = h0;
+      out[size_t(L.H1 + 9 * a + b)] = h1;
+    }
+  for (int e = 0; e < 36; ++e) out[size_t(L.Qm + e)] = d.Q[e];
+  // reachable rows in stage form: [F1 + F2 A, F2 B], scaled to unit norm
+  for (int i = 0; i < m; ++i) {
+    double row[9];
+    for (int a = 0; a < 6; ++a) {
+      double v = F1[size_t(6 * i + a)];
+      for (int c = 0; c < 6; ++c) v += F2[size_t(6 * i + c)] * A[6 * c + a];
+      row[a] = v;
+    }
+    for (int a = 0; a < 3; ++a) {
+      double v = 0.0;
+      for (int c = 0; c < 6; ++c) v += F2[size_t(6 * i + c)] * B[3 * c + a];
+      row[6 + a] = v;
+    }
+    double nn = 0.0;
+    for (double v : row) nn += v * v;
+    nn = std::sqrt(nn);
+    if (!(nn > 0.0) || !std::isfinite(nn) || !std::isfinite(G[size_t(i)])) return RBP_E_SHAPE;
+    for (int a = 0; a < 9; ++a) out[size_t(L.Cr + 9 * i + a)] = row[a] / nn;
+    out[size_t(L.dr + i)] = G[size_t(i)] / nn;
+  }
+  // [AB B]^-1 per axis: (1/dt^3) [[dt, -dt^2/2], [-dt, 3 dt^2/2]];
+  // rows (u_{N-2}, u_{N-1}), columns (target position, target velocity)
+  double Mi[36] = {0};
+  for (int c = 0; c < 3; ++c) {
+    Mi[6 * c + c] = 1.0 / (dt * dt);
+    Mi[6 * c + 3 + c] = -0.5 / dt;
+    Mi[6 * (3 + c) + c] = -1.0 / (dt * dt);
+    Mi[6 * (3 + c) + 3 + c] = 1.5 / dt;
+  }
+  for (int e = 0; e < 36; ++e) out[size_t(L.Mi + e)] = Mi[e];
+  // A^2 and the eliminated last stages for a zero terminal target:
+  // u_{N-2} = -L1 A^2 x, u_{N-1} = -L2 A^2 x (L1, L2: rows of Mi)
+  double A2[36] = {0};
+  for (int a = 0; a < 6; ++a)
+    for (int b = 0; b < 6; ++b)
+      for (int c = 0; c < 6; ++c) A2[6 * a + b] += A[6 * a + c] * A[6 * c + b];
+  double U1[18], U2[18];   // u_{N-2} = U1 x, u_{N-1} = U2 x (3 x 6)
+  for (int i = 0; i < 3; ++i)
+    for (int b = 0; b < 6; ++b) {
+      double v1 = 0.0, v2 = 0.0;
+      for (int c = 0; c < 6; ++c) { v1 += Mi[6 * i + c] * A2[6 * c + b]; v2 += Mi[6 * (3 + i) + c] * A2[6 * c + b]; }
+      U1[6 * i + b] = -v1;
+      U2[6 * i + b] = -v2;
+    }
+  for (int a = 0; a < 6; ++a)
+    for (int b = 0; b < 6; ++b) {
+      out[size_t(L.T2 + 6 * a + b)] = a == b ? 1.0 : 0.0;
+      double v = A[6 * a + b];     // x_{N-1} = (A + B U1) x
+      for (int i = 0; i < 3; ++i) v += B[3 * a + i] * U1[6 * i + b];
+      out[size_t(L.T1 + 6 * a + b)] = v;
+    }
+  for (int i = 0; i < 3; ++i)
+    for (int b = 0; b < 6; ++b) {
+      out[size_t(L.T2 + 6 * (6 + i) + b)] = U1[6 * i + b];
+      out[size_t(L.T1 + 6 * (6 + i) + b)] = U2[6 * i + b];
+    }
+  // keep-out rows: P_j = p + a_j v + b_j u; factors (1, a_j, b_j) / |(1, a_j, b_j)|
+  const double ab[4][2] = {{0.0, 0.0}, {dt / 3.0, 0.0}, {2.0 * dt / 3.0, dt * dt / 6.0}, {dt, h2}};
+  for (int j = 0; j < 4; ++j) {
+    const double inv = 1.0 / std::sqrt(1.0 + ab[j][0] * ab[j][0] + ab[j][1] * ab[j][1]);
+    out[size_t(L.pf + 3 * j)] = inv;
+    out[size_t(L.pf + 3 * j + 1)] = ab[j][0] * inv;
+    out[size_t(L.pf + 3 * j + 2)] = ab[j][1] * inv;
+  }
+  return RBP_OK;
+}
+
+bool sym_psd_diag(const double* M, int n) {
+  for (int a = 0; a < n; ++a) {
+    if (!std::isfinite(M[n * a + a]) || M[n * a + a] < 0.0) return false;
+    for (int b = 0; b < n; ++b)
+      if (!std::isfinite(M[n * a + b]) || std::fabs(M[n * a + b] - M[n * b + a]) > 1e-12 * (1.0 + std::fabs(M[n * a + b])))
+        return false;
+  }
+  return true;
+}
+
+bool spd3(const double* R) {
+  if (!sym_psd_diag(R, 3)) return false;
+  const double l00 = R[0];
+  if (!(l00 > 0.0)) return false;
+  const double a = std::sqrt(l00), l10 = R[3] / a, l20 = R[6] / a;
+  const double d1 = R[4] - l10 * l10;
+  if (!(d1 > 0.0)) return false;
+  const double b = std::sqrt(d1), l21 = (R[7] - l20 * l10) / b;
+  return R[8] - l20 * l20 - l21 * l21 > 0.0;
+}
+}  // namespace
+
+int rbp_build_mpc(const rbp_mpc_desc* d, hipStream_t stream, rbp_mpc** out) {
+  if (!d || !out) return RBP_E_INVALID;
+  *out = nullptr;
+  if (d->reserved != 0 || !(d->dt > 0.0) || !std::isfinite(d->dt) || !(d->w_length >= 0.0) ||
+      !std::isfinite(d->w_length) || !sym_psd_diag(d->Q, 6) || !spd3(d->R))
+    return RBP_E_INVALID;
+  if (d->n_instances < 0 || d->horizon < 2 || d->horizon > RBP_MPC_MAX_HORIZON || d->n_reach < 0 ||
+      d->n_reach > RBP_MPC_MAX_REACH)
+    return RBP_E_SHAPE;
+  const int m = d->n_reach;
+  if (m > 0 && (!d->F1 || !d->F2 || !d->G)) return RBP_E_INVALID;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return RBP_E_DEVICE;
+  std::vector<double> F1, F2, G, prm;
+  int rc;
+  if (m > 0) {
+    if ((rc = d2h(F1, d->F1, size_t(6 * m), stream)) || (rc = d2h(F2, d->F2, size_t(6 * m), stream)) ||
+        (rc = d2h(G, d->G, size_t(m), stream)))
+      return rc;
+    if (hipStreamSynchronize(stream) != hipSuccess) return RBP_E_DEVICE;
+  }
+  if ((rc = mpc_params(*d, F1, F2, G, prm))) return rc;
+  auto* q = new (std::nothrow) rbp_mpc();
+  if (!q) return RBP_E_ALLOC;
+  q->device = dev;
+  q->desc = *d;
+  if ((rc = dalloc(&q->params, prm.size()))) { delete q; return rc; }
+  if (hipMemcpyAsync(q->params, prm.data(), prm.size() * sizeof(double), hipMemcpyHostToDevice, stream) ||
+      hipStreamSynchronize(stream)) {
+    (void)hipFree(q->params);
+    delete q;
+    return RBP_E_DEVICE;
+  }
+  q->last_stream = stream;
+  *out = q;
+  return RBP_OK;
+}
+
+int rbp_mpc_solve(rbp_mpc* q, const double* x0, const double* ref, const double* planes, int32_t max_iters,
+                  double tol, double* X, double* U, double* cost, int32_t* status, double* kkt, int32_t* iters,
+                  hipStream_t stream) {
+  if (!q || max_iters <= 0 || !(tol > 0.0)) return RBP_E_INVALID;
+  const rbp_mpc_desc& d = q->desc;
+  if (d.n_instances == 0) return RBP_OK;
+  if (!x0 || !ref || !planes || !X || !U || !cost || !status || !kkt) return RBP_E_INVALID;
+  rbp::MpcArgs a{};
+  a.n = d.n_instances; a.N = d.horizon; a.m = d.n_reach;
+  a.max_iters = max_iters; a.tol = tol; a.dt = d.dt;
+  a.params = q->params;
+  a.x0 = x0; a.ref = ref; a.planes = planes;
+  a.X = X; a.U = U; a.cost = cost; a.status = status; a.kkt = kkt; a.iters = iters;
+  if (rbp::launch_mpc(a, stream) != hipSuccess) return RBP_E_DEVICE;
+  q->last_stream = stream;
+  return RBP_OK;
+}
+
+void rbp_destroy_mpc(rbp_mpc* q) {
+  if (!q) return;
+  (void)hipSetDevice(q->device);
+  if (q->last_stream) (void)hipStreamSynchronize(q->last_stream);
+  if (q->params) (void)hipFree(q->params);
+  delete q;
 }
 
 }  // extern "C"

@@ -185,6 +185,46 @@ hipError_t launch_graph(const GraphArgs& a, hipStream_t s);
 hipError_t launch_hyperplanes(int n, const double* X, int n_obst, const double* lo, const double* hi, int32_t* idx,
                               double* point, double* plane, hipStream_t s);
 
+// Batched MPC refinement (one wave per instance).  params: constants built
+// on the host by the library (layout in mpc_param_layout).
+struct MpcLayout {
+  int H1, H0, Qm, Cr, dr, T2, T1, Mi, pf, total;   // offsets in doubles
+};
+__host__ __device__ inline MpcLayout mpc_param_layout(int m) {
+  MpcLayout L{};
+  int o = 0;
+  L.H1 = o; o += 81;      // stage Hessian, k >= 1 (9 x 9, z = [x; u])
+  L.H0 = o; o += 81;      // stage Hessian, k = 0 (no tracking)
+  L.Qm = o; o += 36;      // tracking weight Q
+  L.Cr = o; o += 9 * m;   // reachable rows in stage form, unit norm
+  L.dr = o; o += m;       // their right-hand sides
+  L.T2 = o; o += 54;      // z_{N-2} = T2 x_{N-2}   (last two stages eliminated)
+  L.T1 = o; o += 54;      // z_{N-1} = T1 x_{N-2}
+  L.Mi = o; o += 36;      // [AB B]^-1 (start point: terminal inputs)
+  L.pf = o; o += 12;      // plane-row factors (1, a_j, b_j) / |(1, a_j, b_j)|
+  L.total = o;
+  return L;
+}
+struct MpcArgs {
+  int n;                     // instances
+  int N, m;                  // horizon, reachable rows per step
+  int max_iters;
+  double tol;                // complementarity / residual target
+  double dt;
+  const double* params;      // [mpc_param_layout(m).total]
+  const double* x0;          // [n][6]
+  const double* ref;         // [n][N+1][6]
+  const double* planes;      // [n][N][4]
+  double* X;                 // [n][N+1][6]
+  double* U;                 // [n][N][3]
+  double* cost;              // [n]
+  int32_t* status;           // [n]
+  double* kkt;               // [n]
+  int32_t* iters;            // [n] or null
+};
+size_t mpc_lds_bytes(int N, int m);
+hipError_t launch_mpc(const MpcArgs& a, hipStream_t s);
+
 // admm = false: no room for the ADMM iteration (polish only)
 LdsDims make_dims(int pmax, int r_cap, int nf_cap, int real_bytes, bool admm);
 ChainDims make_chain_dims(int p, int s_cap, int nf_cap, int r_cap, int q_cap);

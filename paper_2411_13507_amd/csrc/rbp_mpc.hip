@@ -1,0 +1,605 @@
+// Batched MPC refinement QP (eq. MPC, Sec. III-D): one 64-lane wave per
+// instance, primal-dual interior point (Mehrotra predictor-corrector), FP64.
+//
+// Stage variables z_k = (x_k, u_k), k = 0..N-1, with x = (position, velocity)
+// and u = acceleration; x_{k+1} = A x_k + B u_k is the exact discretisation of
+// the double integrator over dt.  x_0 = x0 and x_N = r_N are fixed.  Stage
+// cost 1/2 z'H z + h'z with h_k = (-2 Q r_k, 0) (no tracking at k = 0), so
+// the cost of the problem is the sum plus the constants r_k'Q r_k.  Rows of
+// stage k, each scaled to unit norm, c_i'z_k <= d_i: the m reachable rows
+// F1 x_k + F2 x_{k+1} <= G (Thm. 2) with x_{k+1} substituted, then four
+// keep-out rows n_k . P_j >= l_k on the control points of the cubic that
+// joins the two states (Lemma 1), P_j = p + a_j v + b_j u.
+//
+// Every Newton system is an equality-constrained LQ problem:
+//   min sum_k 1/2 dz_k' Ht_k dz_k + g_k' dz_k,  dynamics, dx_0 = 0, dx_N = 0,
+// with Ht_k = H_k + sum_i (lam_i / s_i) c_i c_i'.  It is solved by a Riccati
+// recursion in Cholesky form (Quu = L L', Y = L^-1 Qux, P = Qxx - Y'Y) with
+// the cost-to-go symmetrised at every stage: the plain update
+// P = Qxx - Qxu Quu^-1 Qux drifts away from symmetry and loses all accuracy
+// once some barrier weights are large.  The terminal state is fixed by
+// eliminating the last two stages exactly: [u_{N-2}; u_{N-1}] =
+// [AB B]^-1 (-A^2 x_{N-2}), so z_{N-2} = T2 x_{N-2} and z_{N-1} = T1 x_{N-2}.
+//
+// The dual residual is not carried along: every iteration fits the costates
+// (x-stationarity fixes pi_k from pi_{k+1}; pi_N is chosen by least squares)
+// and feeds the remaining u-stationarity residual into the Newton system, so
+// errors of earlier directions do not accumulate.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "rbp_internal.hpp"
+#include "rbp_wave.hpp"
+
+namespace rbp {
+namespace {
+
+constexpr int kW = 64;
+constexpr int kSolved = 0, kMaxIter = 2, kNumerical = 4, kInvalid = 5;
+
+// LDS carve, in doubles
+struct MpcSm {
+  double *prm, *z, *dz, *ref, *pl, *s, *lam, *rp, *prod, *g, *Lc, *Y, *yv, *rho, *P, *Ht, *Qh, *tmp;
+};
+
+__host__ __device__ inline int mpc_lds_doubles(int N, int m) {
+  const MpcLayout L = mpc_param_layout(m);
+  const int RT = N * (m + 4);
+  return L.total + 9 * N /*z*/ + 9 * N /*dz*/ + 6 * (N + 1) /*ref*/ + 4 * N /*pl*/ + 4 * RT /*s lam rp prod*/ +
+         9 * N /*g*/ + 6 * N /*Lc*/ + 18 * N /*Y*/ + 3 * N /*yv*/ + 3 * N /*rho*/ + 36 /*P*/ + 81 /*Ht*/ +
+         81 /*Qh*/ + 64 /*tmp*/;
+}
+
+__device__ inline MpcSm carve_mpc(double* base, int N, int m) {
+  const MpcLayout L = mpc_param_layout(m);
+  const int RT = N * (m + 4);
+  MpcSm S;
+  double* p = base;
+  S.prm = p; p += L.total;
+  S.z = p; p += 9 * N;
+  S.dz = p; p += 9 * N;
+  S.ref = p; p += 6 * (N + 1);
+  S.pl = p; p += 4 * N;
+  S.s = p; p += RT;
+  S.lam = p; p += RT;
+  S.rp = p; p += RT;
+  S.prod = p; p += RT;
+  S.g = p; p += 9 * N;
+  S.Lc = p; p += 6 * N;
+  S.Y = p; p += 18 * N;
+  S.yv = p; p += 3 * N;
+  S.rho = p; p += 3 * N;
+  S.P = p; p += 36;
+  S.Ht = p; p += 81;
+  S.Qh = p; p += 81;
+  S.tmp = p;
+  return S;
+}
+
+// Column b of [A B] (6 x 9) has at most two non-zeros: row q0 with weight w0
+// and row q1 with weight w1 (q1 < 0: none).
+__device__ inline void ab_col(int b, double dt, int& q0, double& w0, int& q1, double& w1) {
+  if (b < 3) { q0 = b; w0 = 1.0; q1 = -1; w1 = 0.0; }
+  else if (b < 6) { q0 = b; w0 = 1.0; q1 = b - 3; w1 = dt; }
+  else { q0 = b - 3; w0 = dt; q1 = b - 6; w1 = 0.5 * dt * dt; }
+}
+
+struct MpcCtx {
+  const MpcArgs& A;
+  MpcSm S;
+  MpcLayout Ly;
+  int N, m, mr, RT, lane;
+  double dt;
+
+  // coefficient a (0..8) of row i of stage k, and its right-hand side
+  __device__ double coef(int k, int i, int a) const {
+    if (i < m) return S.prm[Ly.Cr + 9 * i + a];
+    const int j = i - m;
+    return -S.pl[4 * k + (a % 3)] * S.prm[Ly.pf + 3 * j + a / 3];
+  }
+  __device__ double rhs(int k, int i) const {
+    if (i < m) return S.prm[Ly.dr + i];
+    return -S.pl[4 * k + 3] * S.prm[Ly.pf + 3 * (i - m)];
+  }
+  __device__ double row_value(int k, int i, const double* zk) const {
+    double v = 0.0;
+    for (int a = 0; a < 9; ++a) v += coef(k, i, a) * zk[a];
+    return v;
+  }
+  __device__ const double* Hk(int k) const { return S.prm + (k == 0 ? Ly.H0 : Ly.H1); }
+  // x-part of h_k: -2 Q r_k (k >= 1)
+  __device__ double hk(int k, int a) const {
+    if (k == 0 || a >= 6) return 0.0;
+    double v = 0.0;
+    for (int b = 0; b < 6; ++b) v += S.prm[Ly.Qm + 6 * a + b] * S.ref[6 * k + b];
+    return -2.0 * v;
+  }
+
+  // Riccati factorisation of the Newton LQ; with_rows = false uses H_k alone
+  __device__ void factor(bool with_rows) {
+    // Ht of stage k into S.Ht (full 9 x 9)
+    auto stage_ht = [&](int k) {
+      const double* H = Hk(k);
+      for (int e = lane; e < 81; e += kW) {
+        const int a = e / 9, b = e - 9 * (e / 9);
+        double v = H[e];
+        if (with_rows)
+          for (int i = 0; i < mr; ++i) {
+            const int r = k * mr + i;
+            v += S.lam[r] / S.s[r] * coef(k, i, a) * coef(k, i, b);
+          }
+        S.Ht[e] = v;
+      }
+      __syncthreads();
+    };
+    // terminal block: P = T2' Ht_{N-2} T2 + T1' Ht_{N-1} T1
+    for (int e = lane; e < 36; e += kW) S.P[e] = 0.0;
+    for (int t = 0; t < 2; ++t) {
+      const int k = N - 2 + t;
+      const double* T = S.prm + (t == 0 ? Ly.T2 : Ly.T1);
+      stage_ht(k);
+      // tmp2 = Ht T (9 x 6) in S.Qh
+      for (int e = lane; e < 54; e += kW) {
+        const int a = e / 6, c = e - 6 * (e / 6);
+        double v = 0.0;
+        for (int b = 0; b < 9; ++b) v += S.Ht[9 * a + b] * T[6 * b + c];
+        S.Qh[e] = v;
+      }
+      __syncthreads();
+      for (int e = lane; e < 36; e += kW) {
+        const int c = e / 6, d = e - 6 * (e / 6);
+        double v = 0.0;
+        for (int a = 0; a < 9; ++a) v += T[6 * a + c] * S.Qh[6 * a + d];
+        S.P[e] += v;
+      }
+      __syncthreads();
+    }
+    symmetrise_P();
+    for (int k = N - 3; k >= 0; --k) {
+      stage_ht(k);
+      // Qh = Ht + [A B]' P [A B]
+      for (int e = lane; e < 81; e += kW) {
+        const int a = e / 9, b = e - 9 * (e / 9);
+        int qa0, qa1, qb0, qb1;
+        double wa0, wa1, wb0, wb1;
+        ab_col(a, dt, qa0, wa0, qa1, wa1);
+        ab_col(b, dt, qb0, wb0, qb1, wb1);
+        double v = wa0 * wb0 * S.P[6 * qa0 + qb0];
+        if (qb1 >= 0) v += wa0 * wb1 * S.P[6 * qa0 + qb1];
+        if (qa1 >= 0) {
+          v += wa1 * wb0 * S.P[6 * qa1 + qb0];
+          if (qb1 >= 0) v += wa1 * wb1 * S.P[6 * qa1 + qb1];
+        }
+        S.Qh[e] = S.Ht[e] + v;
+      }
+      __syncthreads();
+      double* L = S.Lc + 6 * k;     // Quu = L L', packed (00, 10, 11, 20, 21, 22)
+      double* Y = S.Y + 18 * k;     // Y = L^-1 Qux (3 x 6)
+      if (lane == 0) {
+        const double q00 = S.Qh[60], q10 = 0.5 * (S.Qh[69] + S.Qh[61]), q11 = S.Qh[70];
+        const double q20 = 0.5 * (S.Qh[78] + S.Qh[62]), q21 = 0.5 * (S.Qh[79] + S.Qh[71]), q22 = S.Qh[80];
+        const double l00 = sqrt(q00);
+        const double l10 = q10 / l00, l20 = q20 / l00;
+        const double l11 = sqrt(q11 - l10 * l10);
+        const double l21 = (q21 - l20 * l10) / l11;
+        const double l22 = sqrt(q22 - l20 * l20 - l21 * l21);
+        L[0] = l00; L[1] = l10; L[2] = l11; L[3] = l20; L[4] = l21; L[5] = l22;
+      }
+      __syncthreads();
+      if (lane < 6) {
+        const int c = lane;
+        // Qux[i][c] = 1/2 (Qh[6+i][c] + Qh[c][6+i])
+        const double b0 = 0.5 * (S.Qh[9 * 6 + c] + S.Qh[9 * c + 6]);
+        const double b1 = 0.5 * (S.Qh[9 * 7 + c] + S.Qh[9 * c + 7]);
+        const double b2 = 0.5 * (S.Qh[9 * 8 + c] + S.Qh[9 * c + 8]);
+        const double y0 = b0 / L[0];
+        const double y1 = (b1 - L[1] * y0) / L[2];
+        const double y2 = (b2 - L[3] * y0 - L[4] * y1) / L[5];
+        Y[c] = y0; Y[6 + c] = y1; Y[12 + c] = y2;
+      }
+      __syncthreads();
+      if (k > 0) {
+        for (int e = lane; e < 36; e += kW) {
+          const int a = e / 6, b = e - 6 * (e / 6);
+          const double qxx = 0.5 * (S.Qh[9 * a + b] + S.Qh[9 * b + a]);
+          S.P[e] = qxx - (Y[a] * Y[b] + Y[6 + a] * Y[6 + b] + Y[12 + a] * Y[12 + b]);
+        }
+        __syncthreads();
+      }
+    }
+  }
+
+  __device__ void symmetrise_P() {
+    for (int e = lane; e < 36; e += kW) {
+      const int a = e / 6, b = e - 6 * (e / 6);
+      if (a < b) {
+        const double v = 0.5 * (S.P[e] + S.P[6 * b + a]);
+        S.P[e] = v; S.P[6 * b + a] = v;
+      }
+    }
+    __syncthreads();
+  }
+
+  // Solve the factorised LQ for the gradients in S.g; result into S.dz.
+  // Sequential over stages in lane 0 (a few dozen flops per stage).
+  __device__ void lq_solve() {
+    if (lane == 0) {
+      const double* T2 = S.prm + Ly.T2;
+      const double* T1 = S.prm + Ly.T1;
+      double p[6];
+      for (int c = 0; c < 6; ++c) {
+        double v = 0.0;
+        for (int a = 0; a < 9; ++a) v += T2[6 * a + c] * S.g[9 * (N - 2) + a] + T1[6 * a + c] * S.g[9 * (N - 1) + a];
+        p[c] = v;
+      }
+      const double h2 = 0.5 * dt * dt;
+      for (int k = N - 3; k >= 0; --k) {
+        const double* gk = S.g + 9 * k;
+        const double* L = S.Lc + 6 * k;
+        const double* Y = S.Y + 18 * k;
+        // qh = g + [A B]' p
+        double qx[6], qu[3];
+        for (int c = 0; c < 3; ++c) {
+          qx[c] = gk[c] + p[c];
+          qx[3 + c] = gk[3 + c] + dt * p[c] + p[3 + c];
+          qu[c] = gk[6 + c] + h2 * p[c] + dt * p[3 + c];
+        }
+        const double y0 = qu[0] / L[0];
+        const double y1 = (qu[1] - L[1] * y0) / L[2];
+        const double y2 = (qu[2] - L[3] * y0 - L[4] * y1) / L[5];
+        S.yv[3 * k] = y0; S.yv[3 * k + 1] = y1; S.yv[3 * k + 2] = y2;
+        for (int c = 0; c < 6; ++c) p[c] = qx[c] - (Y[c] * y0 + Y[6 + c] * y1 + Y[12 + c] * y2);
+      }
+      // forward from dx_0 = 0: du = -L^-T (Y dx + y)
+      double dx[6] = {0, 0, 0, 0, 0, 0};
+      for (int k = 0; k <= N - 3; ++k) {
+        const double* L = S.Lc + 6 * k;
+        const double* Y = S.Y + 18 * k;
+        double r[3];
+        for (int i = 0; i < 3; ++i) {
+          double v = S.yv[3 * k + i];
+          for (int c = 0; c < 6; ++c) v += Y[6 * i + c] * dx[c];
+          r[i] = v;
+        }
+        const double u2 = -r[2] / L[5];
+        const double u1 = -(r[1] + L[4] * u2) / L[2];
+        const double u0 = -(r[0] + L[1] * u1 + L[3] * u2) / L[0];
+        double* d = S.dz + 9 * k;
+        for (int c = 0; c < 6; ++c) d[c] = dx[c];
+        d[6] = u0; d[7] = u1; d[8] = u2;
+        const double uu[3] = {u0, u1, u2};
+        for (int c = 0; c < 3; ++c) {
+          const double pn = dx[c] + dt * dx[3 + c] + h2 * uu[c];
+          dx[3 + c] = dx[3 + c] + dt * uu[c];
+          dx[c] = pn;
+        }
+      }
+      for (int a = 0; a < 9; ++a) {
+        double v2 = 0.0, v1 = 0.0;
+        for (int c = 0; c < 6; ++c) { v2 += T2[6 * a + c] * dx[c]; v1 += T1[6 * a + c] * dx[c]; }
+        S.dz[9 * (N - 2) + a] = v2;
+        S.dz[9 * (N - 1) + a] = v1;
+      }
+    }
+    __syncthreads();
+  }
+
+  // g_k = [0; rho_k] + C_k' w, with w_r from the per-row rule
+  template <typename W>
+  __device__ void build_g(W wfun, bool with_rho) {
+    for (int e = lane; e < 9 * N; e += kW) {
+      const int k = e / 9, a = e - 9 * (e / 9);
+      double v = (with_rho && a >= 6) ? S.rho[3 * k + a - 6] : 0.0;
+      for (int i = 0; i < mr; ++i) v += coef(k, i, a) * wfun(k * mr + i);
+      S.g[e] = v;
+    }
+    __syncthreads();
+  }
+
+  // least-squares costates and the u-stationarity residual rho_k (into
+  // S.rho); returns max |rho| and the scale of the gradient terms
+  __device__ void dual_residual(double& rmax, double& gscale) {
+    double gs = 0.0;
+    for (int e = lane; e < 9 * N; e += kW) {
+      const int k = e / 9, a = e - 9 * (e / 9);
+      const double* H = Hk(k);
+      double hz = hk(k, a);
+      for (int b = 0; b < 9; ++b) hz += H[9 * a + b] * S.z[9 * k + b];
+      double ct = 0.0;
+      for (int i = 0; i < mr; ++i) ct += coef(k, i, a) * S.lam[k * mr + i];
+      S.g[e] = hz + ct;
+      gs = fmax(gs, fmax(fabs(hz), fabs(ct)));
+    }
+    gscale = wave::max(gs);
+    __syncthreads();
+    // backward: f_k = e_k + B' sig_{k+1};  sig_k = c_k + A' sig_{k+1} (k >= 1)
+    if (lane == 0) {
+      double sg[6] = {0, 0, 0, 0, 0, 0};
+      const double h2 = 0.5 * dt * dt;
+      for (int k = N - 1; k >= 0; --k) {
+        const double* gk = S.g + 9 * k;
+        for (int c = 0; c < 3; ++c) S.rho[3 * k + c] = gk[6 + c] + h2 * sg[c] + dt * sg[3 + c];
+        if (k >= 1)
+          for (int c = 0; c < 3; ++c) {
+            const double sp = gk[c] + sg[c];
+            sg[3 + c] = gk[3 + c] + dt * sg[c] + sg[3 + c];
+            sg[c] = sp;
+          }
+      }
+    }
+    __syncthreads();
+    // rho_k,c = f_k,c + al_k pi_p,c + dt pi_v,c, al_k = dt^2 (N - k - 1/2);
+    // pi_N minimises sum_k |rho_k|^2 (per coordinate, 2 x 2 normal equations)
+    double s_af = 0.0, s_f = 0.0;
+    const int c = lane % 3;
+    for (int k = lane / 3; k < N && lane < 63; k += 21) {
+      const double al = dt * dt * (N - k - 0.5);
+      s_af += al * S.rho[3 * k + c];
+      s_f += S.rho[3 * k + c];
+    }
+    // per-coordinate sums: lanes with the same lane % 3
+    double t_af[3], t_f[3];
+    for (int cc = 0; cc < 3; ++cc) {
+      t_af[cc] = wave::sum((c == cc && lane < 63) ? s_af : 0.0);
+      t_f[cc] = wave::sum((c == cc && lane < 63) ? s_f : 0.0);
+    }
+    double a11 = 0.0, a12 = 0.0;
+    for (int k = 0; k < N; ++k) {
+      const double al = dt * dt * (N - k - 0.5);
+      a11 += al * al;
+      a12 += dt * al;
+    }
+    const double a22 = N * dt * dt;
+    const double det = a11 * a22 - a12 * a12;
+    double pp[3], pv[3];
+    for (int cc = 0; cc < 3; ++cc) {
+      const double b1 = -t_af[cc], b2 = -dt * t_f[cc];
+      pp[cc] = (a22 * b1 - a12 * b2) / det;
+      pv[cc] = (a11 * b2 - a12 * b1) / det;
+    }
+    __syncthreads();
+    double rm = 0.0;
+    for (int e = lane; e < 3 * N; e += kW) {
+      const int k = e / 3, cc = e - 3 * (e / 3);
+      const double al = dt * dt * (N - k - 0.5);
+      const double ppc = cc == 0 ? pp[0] : (cc == 1 ? pp[1] : pp[2]);
+      const double pvc = cc == 0 ? pv[0] : (cc == 1 ? pv[1] : pv[2]);
+      const double v = S.rho[e] + al * ppc + dt * pvc;
+      S.rho[e] = v;
+      rm = fmax(rm, fabs(v));
+    }
+    rmax = wave::max(rm);
+    __syncthreads();
+  }
+};
+
+__global__ __launch_bounds__(kW) void mpc_kernel(MpcArgs A) {
+  extern __shared__ __attribute__((aligned(16))) char smem_raw[];
+  const int inst = blockIdx.x;
+  if (inst >= A.n) return;
+  const int N = A.N, m = A.m, mr = m + 4, RT = N * mr, lane = threadIdx.x;
+  MpcCtx C{A, carve_mpc(reinterpret_cast<double*>(smem_raw), N, m), mpc_param_layout(m), N, m, mr, RT, lane, A.dt};
+  MpcSm& S = C.S;
+  const MpcLayout& Ly = C.Ly;
+  const double dt = A.dt;
+
+  // ---- load
+  for (int e = lane; e < Ly.total; e += kW) S.prm[e] = A.params[e];
+  bool bad = false;
+  for (int e = lane; e < 6 * (N + 1); e += kW) {
+    const double v = A.ref[(int64_t)inst * 6 * (N + 1) + e];
+    S.ref[e] = v;
+    bad |= !isfinite(v);
+  }
+  for (int k = lane; k < N; k += kW) {
+    const double* q = A.planes + ((int64_t)inst * N + k) * 4;
+    const double nn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
+    bad |= !(nn > 0.0) || !isfinite(nn) || !isfinite(q[3]);
+    const double in = nn > 0.0 ? 1.0 / nn : 0.0;
+    S.pl[4 * k] = q[0] * in; S.pl[4 * k + 1] = q[1] * in; S.pl[4 * k + 2] = q[2] * in; S.pl[4 * k + 3] = q[3] * in;
+  }
+  double* x0 = S.tmp;          // start state, read with lane-dependent indices
+  if (lane < 6) S.tmp[lane] = A.x0[6 * (int64_t)inst + lane];
+  __syncthreads();
+  for (int c = 0; c < 6; ++c) bad |= !isfinite(x0[c]);
+  auto finish_nan = [&](int status, int its) {
+    for (int e = lane; e < 6 * (N + 1); e += kW) A.X[(int64_t)inst * 6 * (N + 1) + e] = __builtin_nan("");
+    for (int e = lane; e < 3 * N; e += kW) A.U[(int64_t)inst * 3 * N + e] = __builtin_nan("");
+    if (lane == 0) {
+      A.cost[inst] = __builtin_nan("");
+      A.status[inst] = status;
+      A.kkt[inst] = __builtin_nan("");
+      if (A.iters) A.iters[inst] = its;
+    }
+  };
+  if (__ballot(bad) != 0ull) { finish_nan(kInvalid, 0); return; }
+  __syncthreads();
+
+  // ---- start point: zero input up to x_{N-2}, then the two inputs that
+  // reach r_N; then the Newton step of the LQ without rows (its optimum)
+  for (int e = lane; e < 9 * (N - 2); e += kW) {
+    const int k = e / 9, a = e - 9 * (e / 9);
+    double v;
+    if (a < 3) v = x0[a] + k * dt * x0[3 + a];
+    else if (a < 6) v = x0[a];
+    else v = 0.0;
+    S.z[e] = v;
+  }
+  if (lane == 0) {
+    double xa[6];
+    for (int c = 0; c < 3; ++c) { xa[c] = x0[c] + (N - 2) * dt * x0[3 + c]; xa[3 + c] = x0[3 + c]; }
+    // rhs = r_N - A^2 x_{N-2}
+    double rr[6];
+    for (int c = 0; c < 3; ++c) {
+      rr[c] = S.ref[6 * N + c] - (xa[c] + 2.0 * dt * xa[3 + c]);
+      rr[3 + c] = S.ref[6 * N + 3 + c] - xa[3 + c];
+    }
+    double uu[6];
+    for (int i = 0; i < 6; ++i) {
+      double v = 0.0;
+      for (int c = 0; c < 6; ++c) v += S.prm[Ly.Mi + 6 * i + c] * rr[c];
+      uu[i] = v;
+    }
+    double* z2 = S.z + 9 * (N - 2);
+    double* z1 = S.z + 9 * (N - 1);
+    for (int c = 0; c < 6; ++c) z2[c] = xa[c];
+    for (int c = 0; c < 3; ++c) {
+      z2[6 + c] = uu[c];
+      z1[c] = xa[c] + dt * xa[3 + c] + 0.5 * dt * dt * uu[c];
+      z1[3 + c] = xa[3 + c] + dt * uu[c];
+      z1[6 + c] = uu[3 + c];
+    }
+  }
+  __syncthreads();
+  C.factor(false);
+  // g = H z + h
+  for (int e = lane; e < 9 * N; e += kW) {
+    const int k = e / 9, a = e - 9 * (e / 9);
+    const double* H = C.Hk(k);
+    double v = C.hk(k, a);
+    for (int b = 0; b < 9; ++b) v += H[9 * a + b] * S.z[9 * k + b];
+    S.g[e] = v;
+  }
+  __syncthreads();
+  C.lq_solve();
+  for (int e = lane; e < 9 * N; e += kW) S.z[e] += S.dz[e];
+  __syncthreads();
+  // slacks and multipliers
+  for (int r = lane; r < RT; r += kW) {
+    const int k = r / mr, i = r - mr * (r / mr);
+    const double sl = C.rhs(k, i) - C.row_value(k, i, S.z + 9 * k);
+    S.s[r] = fmax(sl, 1.0);
+    S.lam[r] = 1.0;
+  }
+  __syncthreads();
+
+  // ---- interior-point iterations
+  int it = 0;
+  bool converged = false;
+  double mu = 0.0, rpmax = 0.0, rdmax = 0.0, gscale = 0.0;
+  for (;; ++it) {
+    double smu = 0.0, rpm = 0.0;
+    for (int r = lane; r < RT; r += kW) {
+      const int k = r / mr, i = r - mr * (r / mr);
+      const double v = C.row_value(k, i, S.z + 9 * k) + S.s[r] - C.rhs(k, i);
+      S.rp[r] = v;
+      rpm = fmax(rpm, fabs(v));
+      smu += S.s[r] * S.lam[r];
+    }
+    mu = wave::sum(smu) / RT;
+    rpmax = wave::max(rpm);
+    __syncthreads();
+    C.dual_residual(rdmax, gscale);
+    if (mu <= A.tol && rpmax <= 1e3 * A.tol && rdmax <= 1e3 * A.tol * (1.0 + gscale)) { converged = true; break; }
+    if (it >= A.max_iters || !isfinite(mu)) break;
+    C.factor(true);
+    // predictor: w = sigma rp - lam
+    C.build_g([&](int r) { return S.lam[r] / S.s[r] * S.rp[r] - S.lam[r]; }, true);
+    C.lq_solve();
+    double amax_l = 1.0, mua = 0.0;
+    for (int r = lane; r < RT; r += kW) {
+      const int k = r / mr, i = r - mr * (r / mr);
+      const double ds = -S.rp[r] - C.row_value(k, i, S.dz + 9 * k);
+      const double dl = -S.lam[r] - S.lam[r] / S.s[r] * ds;
+      if (ds < 0.0) amax_l = fmin(amax_l, -S.s[r] / ds);
+      if (dl < 0.0) amax_l = fmin(amax_l, -S.lam[r] / dl);
+      S.prod[r] = ds * dl;
+    }
+    const double aa = wave::min(amax_l);
+    for (int r = lane; r < RT; r += kW) {
+      const int k = r / mr, i = r - mr * (r / mr);
+      const double ds = -S.rp[r] - C.row_value(k, i, S.dz + 9 * k);
+      const double dl = -S.lam[r] - S.lam[r] / S.s[r] * ds;
+      mua += (S.s[r] + aa * ds) * (S.lam[r] + aa * dl);
+    }
+    mua = wave::sum(mua) / RT;
+    const double sc = (mua / mu) * (mua / mu) * (mua / mu);
+    __syncthreads();
+    // corrector: rc = s lam + ds_aff dl_aff - sc mu, w = (lam rp - rc) / s
+    const double smu_t = sc * mu;
+    C.build_g([&](int r) {
+      const double rc = S.s[r] * S.lam[r] + S.prod[r] - smu_t;
+      return (S.lam[r] * S.rp[r] - rc) / S.s[r];
+    }, true);
+    C.lq_solve();
+    double am = 1.0;
+    for (int r = lane; r < RT; r += kW) {
+      const int k = r / mr, i = r - mr * (r / mr);
+      const double ds = -S.rp[r] - C.row_value(k, i, S.dz + 9 * k);
+      const double rc = S.s[r] * S.lam[r] + S.prod[r] - smu_t;
+      const double dl = (-rc - S.lam[r] * ds) / S.s[r];
+      if (ds < 0.0) am = fmin(am, -S.s[r] / ds);
+      if (dl < 0.0) am = fmin(am, -S.lam[r] / dl);
+      S.prod[r] = ds;            // keep ds and dl for the update
+      S.rp[r] = dl;
+    }
+    const double alpha = fmin(1.0, 0.995 * wave::min(am));
+    __syncthreads();
+    for (int r = lane; r < RT; r += kW) {
+      S.s[r] += alpha * S.prod[r];
+      S.lam[r] += alpha * S.rp[r];
+    }
+    for (int e = lane; e < 9 * N; e += kW) S.z[e] += alpha * S.dz[e];
+    __syncthreads();
+  }
+
+  // ---- outputs: states (x_N from the dynamics), inputs, cost, residuals
+  double cst = 0.0;
+  for (int e = lane; e < 9 * N; e += kW) {
+    const int k = e / 9, a = e - 9 * (e / 9);
+    const double* H = C.Hk(k);
+    double hz = 0.0;
+    for (int b = 0; b < 9; ++b) hz += H[9 * a + b] * S.z[9 * k + b];
+    cst += 0.5 * S.z[e] * hz + C.hk(k, a) * S.z[e];
+    if (a < 6 && k >= 1) {
+      double qr = 0.0;
+      for (int b = 0; b < 6; ++b) qr += S.prm[Ly.Qm + 6 * a + b] * S.ref[6 * k + b];
+      cst += S.ref[6 * k + a] * qr;
+    }
+  }
+  const double cost = wave::sum(cst);
+  double pres = 0.0, pscale = 0.0, cres = 0.0, lmax = 0.0;
+  for (int r = lane; r < RT; r += kW) {
+    const int k = r / mr, i = r - mr * (r / mr);
+    const double v = C.row_value(k, i, S.z + 9 * k), d = C.rhs(k, i);
+    pres = fmax(pres, v - d);
+    pscale = fmax(pscale, fmax(fabs(v), fabs(d)));
+    cres = fmax(cres, S.lam[r] * fabs(d - v));
+    lmax = fmax(lmax, S.lam[r]);
+  }
+  pres = wave::max(pres); pscale = wave::max(pscale); cres = wave::max(cres); lmax = wave::max(lmax);
+  const double kkt = fmax(fmax(fmax(pres, 0.0) / (1.0 + pscale), rdmax / (1.0 + gscale)), cres / (1.0 + lmax));
+  const int64_t xo = (int64_t)inst * 6 * (N + 1);
+  for (int e = lane; e < 6 * N; e += kW) {
+    const int k = e / 6, a = e - 6 * (e / 6);
+    A.X[xo + e] = (k == 0) ? x0[a] : S.z[9 * k + a];
+  }
+  if (lane < 6) {
+    const double* zl = S.z + 9 * (N - 1);
+    const int c = lane % 3;
+    const double v = lane < 3 ? zl[c] + dt * zl[3 + c] + 0.5 * dt * dt * zl[6 + c] : zl[3 + c] + dt * zl[6 + c];
+    A.X[xo + 6 * N + lane] = v;
+  }
+  for (int e = lane; e < 3 * N; e += kW) A.U[(int64_t)inst * 3 * N + e] = S.z[9 * (e / 3) + 6 + e % 3];
+  if (lane == 0) {
+    A.cost[inst] = cost;
+    A.kkt[inst] = kkt;
+    A.status[inst] = !converged ? kMaxIter : (kkt <= 1e-6 ? kSolved : kNumerical);
+    if (A.iters) A.iters[inst] = it;
+  }
+}
+
+}  // namespace
+
+size_t mpc_lds_bytes(int N, int m) { return sizeof(double) * size_t(mpc_lds_doubles(N, m)); }
+
+hipError_t launch_mpc(const MpcArgs& a, hipStream_t s) {
+  if (a.n <= 0) return hipSuccess;
+  const size_t lds = mpc_lds_bytes(a.N, a.m);
+  hipLaunchKernelGGL(mpc_kernel, dim3(a.n), dim3(kW), lds, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace rbp

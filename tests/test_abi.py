@@ -97,7 +97,7 @@ def test_descriptor_layouts_match_header(tmp_path):
     if not shutil.which("gcc") or not os.path.exists("/opt/rocm/include/hip/hip_runtime_api.h"):
         pytest.skip("no host C compiler or HIP headers")
     structs = {"rbp_problem_desc": _lib.ProblemDesc, "rbp_chain_desc": _lib.ChainDesc,
-               "rbp_cut_desc": _lib.CutDesc, "rbp_graph_desc": _lib.GraphDesc,
+               "rbp_cut_desc": _lib.CutDesc, "rbp_graph_desc": _lib.GraphDesc, "rbp_mpc_desc": _lib.MpcDesc,
                "rbp_solve_opts": _lib.SolveOpts, "rbp_batch_sizes": _lib.BatchSizes}
     lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "rbp.h"', "int main(void) {"]
     for cname, cls in structs.items():

@@ -3,8 +3,8 @@ resource-usage remarks that the build writes beside librbp.so.
 
 Per-lane scratch (private memory) is spill or dynamically indexed register
 arrays: it turns LDS-speed data into memory traffic.  The segment kernels of
-degree 3-8, the backward, graph-cut and graph-building kernels must have
-none; the degree-9 segment kernels and the path kernel are at the 256-VGPR
+degree 3-8, the backward, graph-cut and graph-building and MPC kernels must
+have none; the degree-9 segment kernels and the path kernel are at the 256-VGPR
 limit and are allowed their (stated) spill."""
 import csv
 import os
@@ -28,7 +28,7 @@ def table():
 def test_every_kernel_reported(table):
     names = " ".join(r["kernel"] for r in table)
     for k in ("solve_kernel", "backward_kernel", "chain_kernel", "cut_qp_kernel", "cut_prefilter_kernel",
-              "graph_pairs_kernel", "hyperplane_kernel"):
+              "graph_pairs_kernel", "hyperplane_kernel", "mpc_kernel"):
         assert k in names, k
 
 

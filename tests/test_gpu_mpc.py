@@ -1,0 +1,161 @@
+"""GPU MPC refinement (eq. MPC, Sec. III-D) against the FP64 oracle, through
+the C ABI.
+
+Tolerances: states and inputs within 1e-6 (1 + max |oracle value|), cost
+1e-6 relative (+1e-9), scaled KKT residual <= 1e-6, status SOLVED wherever
+the oracle certifies an optimum.  The full 4,096-instance batch is sampled
+against the oracle and checked by properties everywhere: x_0 = x0, the
+dynamics, the terminal state, the reachable rows and the keep-out planes on
+the control points of every step."""
+import multiprocessing as mp
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import mpc as ompc
+from oracle import qp
+from workloads import gen
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-6
+
+
+def run(b, max_iters=40, tol=1e-13, x0=None, ref=None, planes=None):
+    from paper_2411_13507_amd.api import MpcGPU
+    g = MpcGPU(b, b.n)
+    d = g.device
+    t = lambda a, v: torch.as_tensor(np.ascontiguousarray(a if v is None else v), device=d)
+    r = g.solve(t(b.x0, x0), t(b.ref, ref), t(b.planes, planes), max_iters=max_iters, tol=tol)
+    torch.cuda.synchronize()
+    out = {k: getattr(r, k).cpu().numpy() for k in ("X", "U", "cost", "status", "kkt", "iters")}
+    g.close()
+    return out
+
+
+def _oracle(inst):
+    r = ompc.solve(inst)
+    return r.status, r.X, r.U, r.cost
+
+
+def compare(b, out, idx, label):
+    with mp.get_context("fork").Pool(8) as pool:
+        orc = pool.map(_oracle, [b.instance(i) for i in idx], chunksize=2)
+    worst = 0.0
+    for i, (st, X, U, c) in zip(idx, orc):
+        assert st == qp.SOLVED, (label, i, st)
+        assert out["status"][i] == qp.SOLVED and out["kkt"][i] <= TOL, (label, i, out["status"][i], out["kkt"][i])
+        ex = np.abs(out["X"][i] - X).max() / (1.0 + np.abs(X).max())
+        eu = np.abs(out["U"][i] - U).max() / (1.0 + np.abs(U).max())
+        assert ex <= TOL and eu <= TOL, (label, i, ex, eu)
+        assert abs(out["cost"][i] - c) <= TOL * abs(c) + 1e-9, (label, i, out["cost"][i], c)
+        worst = max(worst, ex, eu)
+    print(f"{label}: {len(idx)} instances vs oracle, worst state/input error {worst:.2e}, "
+          f"iterations {out['iters'][list(idx)].min()}-{out['iters'][list(idx)].max()}", flush=True)
+
+
+def check_properties(b, out):
+    N, dt = b.N, b.dt
+    X, U = out["X"], out["U"]
+    assert np.array_equal(X[:, 0], b.x0)
+    assert np.abs(X[:, N] - b.ref[:, N]).max() <= 1e-9 * (1 + np.abs(b.ref[:, N]).max())
+    p, v = X[:, :-1, :3], X[:, :-1, 3:]
+    pn = p + dt * v + 0.5 * dt * dt * U
+    vn = v + dt * U
+    assert np.abs(X[:, 1:, :3] - pn).max() <= 1e-12 * (1 + np.abs(pn).max())
+    assert np.abs(X[:, 1:, 3:] - vn).max() <= 1e-12 * (1 + np.abs(vn).max())
+    reach = np.einsum("ij,nkj->nki", b.F1, X[:, :-1]) + np.einsum("ij,nkj->nki", b.F2, X[:, 1:])
+    assert np.all(reach <= b.G + 1e-9)
+    # keep-out planes on the four control points of every step
+    n, l = b.planes[:, :, :3], b.planes[:, :, 3]
+    nrm = np.linalg.norm(n, axis=2)
+    P = [p, p + dt / 3 * v, X[:, 1:, :3] - dt / 3 * X[:, 1:, 3:], X[:, 1:, :3]]
+    for Pj in P:
+        assert np.all(np.sum(n * Pj, axis=2) >= l - 1e-9 * (1 + nrm))
+
+
+def test_mpc_against_oracle(gpu_available):
+    b = gen.gen_mpc(48)
+    print(f"case: {b.n} instances, horizon {b.N}, {b.G.size} reachable rows", flush=True)
+    out = run(b)
+    compare(b, out, range(b.n), "mpc48")
+    check_properties(b, out)
+
+
+def test_mpc_full_batch(gpu_available):
+    b = gen.gen_mpc(4096)
+    print(f"case: {b.n} instances, horizon {b.N}", flush=True)
+    out = run(b)
+    assert np.all(out["status"] == qp.SOLVED), np.bincount(out["status"], minlength=6)
+    assert np.all(out["kkt"] <= TOL)
+    check_properties(b, out)
+    idx = np.random.default_rng(41).choice(b.n, 48, replace=False)
+    compare(b, out, [int(i) for i in idx], "mpc4096-sampled")
+
+
+@pytest.mark.parametrize("N,m_extra", [(2, 4), (3, 0), (17, 4), (64, 20)])
+def test_mpc_horizons_and_row_counts(gpu_available, N, m_extra):
+    """The shortest horizons (two steps: one feasible point), no extra rows,
+    a ragged horizon, and the maximum sizes (64 steps, 32 reachable rows)."""
+    b = gen.gen_mpc(12, N=N, m_extra=m_extra)
+    if N == 2:
+        # the two inputs are fixed by the end states: loose rows so that the
+        # single point is feasible
+        b.G = np.full_like(b.G, 1e3)
+        b.planes[:, :, 3] = -1e3
+    print(f"case: horizon {N}, {b.G.size} reachable rows", flush=True)
+    out = run(b)
+    idx = [i for i in range(b.n)]
+    with mp.get_context("fork").Pool(8) as pool:
+        orc = pool.map(_oracle, [b.instance(i) for i in idx])
+    ok = [i for i, o in zip(idx, orc) if o[0] == qp.SOLVED]
+    assert len(ok) >= b.n // 2
+    for i, o in zip(idx, orc):
+        if o[0] == qp.INFEASIBLE:
+            assert out["status"][i] != qp.SOLVED
+    compare(b, out, ok, f"mpc-N{N}-m{b.G.size}")
+
+
+def test_mpc_invalid_and_infeasible(gpu_available):
+    b = gen.gen_mpc(6)
+    x0 = b.x0.copy(); x0[1, 2] = np.nan
+    planes = b.planes.copy(); planes[2, 5, :3] = 0.0
+    # plane of the first step 0.05 beyond the fixed start: infeasible
+    n = planes[3, 0, :3]
+    planes[3, 0, 3] = n @ b.x0[3, :3] + 0.05 * np.linalg.norm(n)
+    out = run(b, x0=x0, planes=planes)
+    from paper_2411_13507_amd import _lib
+    assert out["status"][1] == _lib.INVALID_INPUT and out["status"][2] == _lib.INVALID_INPUT
+    assert np.isnan(out["X"][1]).all() and np.isnan(out["cost"][2])
+    assert out["status"][3] != qp.SOLVED
+    compare(b, out, [0, 4, 5], "mpc-rest")
+
+
+def test_mpc_graph_capture_replays(gpu_available):
+    from paper_2411_13507_amd.api import MpcGPU
+    b = gen.gen_mpc(64)
+    g = MpcGPU(b, b.n)
+    d = g.device
+    x0, ref, pl = (torch.as_tensor(a, device=d) for a in (b.x0, b.ref, b.planes))
+    ref_out = g.solve(x0, ref, pl)
+    torch.cuda.synchronize()
+    want = [t.clone() for t in (ref_out.X, ref_out.U, ref_out.cost, ref_out.status)]
+    o = g.alloc()
+    side = torch.cuda.Stream(device=d)
+    side.wait_stream(torch.cuda.current_stream(d))
+    with torch.cuda.stream(side):
+        g.solve(x0, ref, pl, out=o)
+    torch.cuda.current_stream(d).wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        g.solve(x0, ref, pl, out=o)
+    for rep in range(3):
+        o.X.fill_(7.0); o.status.fill_(-1)
+        graph.replay()
+        torch.cuda.synchronize()
+        for a, w in zip((o.X, o.U, o.cost, o.status), want):
+            assert torch.equal(a, w), rep
+        g.solve(x0, ref, pl)
+        torch.cuda.synchronize()
+    g.close()
