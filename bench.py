@@ -162,8 +162,9 @@ def extra_workloads(reps=3, admm_iters=-1, edges=None, main_opts=None):
     """Throughput of the other workloads: the 50,000 edges with one shared
     reachable block and with a pinned start velocity, the uneven batch (200,000 segments, degree 3-9, 6-40
     faces, 16-128 reachable rows; autotuned options), the graph cut, graph
-    building and adjacent hyperplanes, and the path batch (8,192 paths of
-    4-12 joined degree-7 segments)."""
+    building and adjacent hyperplanes, the path batch (8,192 paths of 4-12
+    joined degree-7 segments) and the MPC refinement batch (4,096 horizons of
+    50 steps)."""
     import torch
     from paper_2411_13507_amd import _lib
     from paper_2411_13507_amd.api import ChainBatchGPU, SegmentBatchGPU
@@ -248,6 +249,21 @@ def extra_workloads(reps=3, admm_iters=-1, edges=None, main_opts=None):
                           "status_counts": np.bincount(st, minlength=6).tolist(),
                           "polish_steps_mean": float(r.iters.cpu().numpy()[:, 1].mean())}
     cb.close()
+    # MPC refinement (eq. MPC): 4,096 independent 50-step horizons, one
+    # separating plane per step, 16 reachable rows per step
+    from paper_2411_13507_amd.api import MpcGPU
+    mb = gen.gen_mpc(4096)
+    mg = MpcGPU(mb, mb.n, device="cuda:0")
+    mx0, mref, mpl = (torch.as_tensor(a, device=dev) for a in (mb.x0, mb.ref, mb.planes))
+    mres = mg.alloc()
+    t = time_launches(lambda: mg.solve(mx0, mref, mpl, out=mres), reps, stream)
+    st = mres.status.cpu().numpy()
+    its = mres.iters.cpu().numpy()
+    ok = int((st == 0).sum())
+    out["mpc4096_n50"] = {"ms": t * 1e3, "solves_per_s": ok / t, "instances": mb.n, "horizon": mb.N,
+                          "reach_rows": int(mb.G.size), "status_counts": np.bincount(st, minlength=6).tolist(),
+                          "ipm_iters_mean": float(its.mean()), "ipm_iters_max": int(its.max())}
+    mg.close()
     return out
 
 

@@ -430,16 +430,20 @@ int rbp_build_mpc(const rbp_mpc_desc* desc, hipStream_t stream, rbp_mpc** out);
  *   planes  [n][N][4]     (n_k, l_k) per step; n_k need not be unit length
  *   max_iters             interior-point iteration cap (> 0; 40 is ample)
  *   tol                   target of the average complementarity; the primal
- *                         and dual residuals must reach 1e3 tol (> 0; 1e-13)
+ *                         residual must also reach 1e3 tol and the dual
+ *                         residual 1e5 tol (1 + gradient scale) (> 0; 1e-13)
  *   X       [n][N+1][6]   states (X_N from the dynamics of the last step)
  *   U       [n][N][3]     inputs
  *   cost    [n]           objective value
- *   status  [n]           RBP_SOLVED (converged, scaled KKT residual
- *                         <= 1e-6), RBP_MAXITER (not converged: includes
- *                         infeasible instances, which are not certified),
- *                         RBP_NUMERICAL (converged, residual above 1e-6),
+ *   status  [n]           RBP_SOLVED (scaled KKT residual of the returned
+ *                         point <= 1e-6), RBP_MAXITER (stopped before that:
+ *                         iteration cap, or a Newton system that broke down;
+ *                         infeasible instances end here and are not
+ *                         certified), RBP_NUMERICAL (converged by the
+ *                         tolerances above, residual still above 1e-6),
  *                         RBP_INVALID_INPUT (non-finite input or a zero
- *                         plane normal); X, U, cost are NaN for the last.
+ *                         plane normal; X, U, cost are NaN).  Otherwise X,
+ *                         U, cost hold the last iterate.
  *   kkt     [n]           max of the scaled primal, dual (least-squares
  *                         costates) and complementarity residuals
  *   iters   [n] or NULL   interior-point iterations

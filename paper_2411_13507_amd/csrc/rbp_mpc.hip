@@ -117,8 +117,10 @@ struct MpcCtx {
     return -2.0 * v;
   }
 
-  // Riccati factorisation of the Newton LQ; with_rows = false uses H_k alone
-  __device__ void factor(bool with_rows) {
+  // Riccati factorisation of the Newton LQ; with_rows = false uses H_k alone.
+  // Returns false (uniformly) when a pivot of some Quu is not positive.
+  __device__ bool factor(bool with_rows) {
+    if (lane == 0) S.tmp[8] = 0.0;
     // Ht of stage k into S.Ht (full 9 x 9)
     auto stage_ht = [&](int k) {
       const double* H = Hk(k);
@@ -186,6 +188,7 @@ struct MpcCtx {
         const double l21 = (q21 - l20 * l10) / l11;
         const double l22 = sqrt(q22 - l20 * l20 - l21 * l21);
         L[0] = l00; L[1] = l10; L[2] = l11; L[3] = l20; L[4] = l21; L[5] = l22;
+        if (!(l00 > 0.0 && l11 > 0.0 && l22 > 0.0) || !isfinite(l00 * l11 * l22)) S.tmp[8] = 1.0;
       }
       __syncthreads();
       if (lane < 6) {
@@ -209,6 +212,7 @@ struct MpcCtx {
         __syncthreads();
       }
     }
+    return S.tmp[8] == 0.0;
   }
 
   __device__ void symmetrise_P() {
@@ -492,9 +496,9 @@ __global__ __launch_bounds__(kW) void mpc_kernel(MpcArgs A) {
     rpmax = wave::max(rpm);
     __syncthreads();
     C.dual_residual(rdmax, gscale);
-    if (mu <= A.tol && rpmax <= 1e3 * A.tol && rdmax <= 1e3 * A.tol * (1.0 + gscale)) { converged = true; break; }
+    if (mu <= A.tol && rpmax <= 1e3 * A.tol && rdmax <= 1e5 * A.tol * (1.0 + gscale)) { converged = true; break; }
     if (it >= A.max_iters || !isfinite(mu)) break;
-    C.factor(true);
+    if (!C.factor(true)) break;                 // a Quu lost definiteness: keep the current iterate
     // predictor: w = sigma rp - lam
     C.build_g([&](int r) { return S.lam[r] / S.s[r] * S.rp[r] - S.lam[r]; }, true);
     C.lq_solve();
@@ -537,6 +541,9 @@ __global__ __launch_bounds__(kW) void mpc_kernel(MpcArgs A) {
     }
     const double alpha = fmin(1.0, 0.995 * wave::min(am));
     __syncthreads();
+    bool nonfinite = !(alpha > 0.0) || !isfinite(alpha);
+    for (int e = lane; e < 9 * N; e += kW) nonfinite |= !isfinite(S.dz[e]);
+    if (__ballot(nonfinite) != 0ull) break;     // a broken direction: keep the current iterate
     for (int r = lane; r < RT; r += kW) {
       S.s[r] += alpha * S.prod[r];
       S.lam[r] += alpha * S.rp[r];
@@ -586,7 +593,7 @@ __global__ __launch_bounds__(kW) void mpc_kernel(MpcArgs A) {
   if (lane == 0) {
     A.cost[inst] = cost;
     A.kkt[inst] = kkt;
-    A.status[inst] = !converged ? kMaxIter : (kkt <= 1e-6 ? kSolved : kNumerical);
+    A.status[inst] = (kkt <= 1e-6 && isfinite(cost)) ? kSolved : (converged ? kNumerical : kMaxIter);
     if (A.iters) A.iters[inst] = it;
   }
 }

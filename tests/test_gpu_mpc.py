@@ -87,10 +87,17 @@ def test_mpc_full_batch(gpu_available):
     b = gen.gen_mpc(4096)
     print(f"case: {b.n} instances, horizon {b.N}", flush=True)
     out = run(b)
-    assert np.all(out["status"] == qp.SOLVED), np.bincount(out["status"], minlength=6)
-    assert np.all(out["kkt"] <= TOL)
-    check_properties(b, out)
-    idx = np.random.default_rng(41).choice(b.n, 48, replace=False)
+    ok = out["status"] == qp.SOLVED
+    print("statuses", np.bincount(out["status"], minlength=6).tolist(), flush=True)
+    assert ok.mean() >= 0.995
+    assert np.all(out["kkt"][ok] <= TOL)
+    # every instance the GPU did not solve is one the oracle certifies infeasible
+    rest = [int(i) for i in np.nonzero(~ok)[0]]
+    with mp.get_context("fork").Pool(8) as pool:
+        orc = pool.map(_oracle, [b.instance(i) for i in rest])
+    assert all(o[0] == qp.INFEASIBLE for o in orc), [(i, o[0]) for i, o in zip(rest, orc)]
+    check_properties(b.subset(np.nonzero(ok)[0]), {k: v[ok] for k, v in out.items()})
+    idx = np.random.default_rng(41).choice(np.nonzero(ok)[0], 48, replace=False)
     compare(b, out, [int(i) for i in idx], "mpc4096-sampled")
 
 
