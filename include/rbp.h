@@ -429,9 +429,11 @@ int rbp_build_mpc(const rbp_mpc_desc* desc, hipStream_t stream, rbp_mpc** out);
  *   ref     [n][N+1][6]   reference states r_0..r_N (r_N is the terminal state)
  *   planes  [n][N][4]     (n_k, l_k) per step; n_k need not be unit length
  *   max_iters             interior-point iteration cap (> 0; 40 is ample)
- *   tol                   target of the average complementarity; the primal
- *                         residual must also reach 1e3 tol and the dual
- *                         residual 1e5 tol (1 + gradient scale) (> 0; 1e-13)
+ *   tol                   target of the average complementarity (> 0;
+ *                         1e-15 is the default of the Python binding); the
+ *                         primal residual of the unit rows must also reach
+ *                         1e-10 and the dual residual 1e-8 (1 + gradient
+ *                         scale)
  *   X       [n][N+1][6]   states (X_N from the dynamics of the last step)
  *   U       [n][N][3]     inputs
  *   cost    [n]           objective value

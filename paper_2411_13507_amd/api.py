@@ -422,7 +422,7 @@ class MpcGPU:
                          kkt=torch.empty(n, **f), iters=torch.empty(n, dtype=torch.int32, device=d))
 
     def solve(self, x0: torch.Tensor, ref: torch.Tensor, planes: torch.Tensor, max_iters: int = 40,
-              tol: float = 1e-13, out: Optional[MpcResult] = None) -> MpcResult:
+              tol: float = 1e-15, out: Optional[MpcResult] = None) -> MpcResult:
         o = out or self.alloc()
         rc = _lib.load().rbp_mpc_solve(self._h, _ptr(x0), _ptr(ref), _ptr(planes), int(max_iters), float(tol),
                                        _ptr(o.X), _ptr(o.U), _ptr(o.cost), _ptr(o.status), _ptr(o.kkt),

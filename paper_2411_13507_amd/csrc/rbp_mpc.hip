@@ -496,7 +496,7 @@ __global__ __launch_bounds__(kW) void mpc_kernel(MpcArgs A) {
     rpmax = wave::max(rpm);
     __syncthreads();
     C.dual_residual(rdmax, gscale);
-    if (mu <= A.tol && rpmax <= 1e3 * A.tol && rdmax <= 1e5 * A.tol * (1.0 + gscale)) { converged = true; break; }
+    if (mu <= A.tol && rpmax <= 1e-10 && rdmax <= 1e-8 * (1.0 + gscale)) { converged = true; break; }
     if (it >= A.max_iters || !isfinite(mu)) break;
     if (!C.factor(true)) break;                 // a Quu lost definiteness: keep the current iterate
     // predictor: w = sigma rp - lam

@@ -22,7 +22,7 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-6
 
 
-def run(b, max_iters=40, tol=1e-13, x0=None, ref=None, planes=None):
+def run(b, max_iters=40, tol=1e-15, x0=None, ref=None, planes=None):
     from paper_2411_13507_amd.api import MpcGPU
     g = MpcGPU(b, b.n)
     d = g.device
