@@ -125,6 +125,17 @@ def time_launches(fn, reps, stream):
     return float(np.median([e0.elapsed_time(e1) for e0, e1 in evs])) / 1e3
 
 
+def mpc_flops_per_iteration(N, m):
+    """Algorithmic FP64 flops of one interior-point iteration of the MPC
+    kernel (mr = m + 4 unit rows per step, RT = N mr rows): per step the
+    barrier Hessian (81 entries x mr rows x 3), the Riccati update (~1,000),
+    two gradient builds (2 x 9 x mr x 2) and Riccati solves (2 x 150), the
+    costate gradient (18 (15 + mr)) and scan (40); per row the residual,
+    the two direction recoveries, step lengths and the update (~93)."""
+    mr = m + 4
+    return N * (243 * mr + 1000 + 36 * mr + 300 + 18 * (15 + mr) + 40) + N * mr * 93
+
+
 def _variant(sb, main_opts, reps, stream):
     """Forward + backward and forward-only times of a variant of the
     50,000-edge batch."""
@@ -260,9 +271,11 @@ def extra_workloads(reps=3, admm_iters=-1, edges=None, main_opts=None):
     st = mres.status.cpu().numpy()
     its = mres.iters.cpu().numpy()
     ok = int((st == 0).sum())
+    flops = float(mpc_flops_per_iteration(mb.N, int(mb.G.size)) * (its.astype(np.float64) + 1.0).sum())
     out["mpc4096_n50"] = {"ms": t * 1e3, "solves_per_s": ok / t, "instances": mb.n, "horizon": mb.N,
                           "reach_rows": int(mb.G.size), "status_counts": np.bincount(st, minlength=6).tolist(),
-                          "ipm_iters_mean": float(its.mean()), "ipm_iters_max": int(its.max())}
+                          "ipm_iters_mean": float(its.mean()), "ipm_iters_max": int(its.max()),
+                          "alu_tflops": flops / t / 1e12, "alu_frac": flops / t / 1e12 / PEAK_VALU_TFLOPS}
     mg.close()
     return out
 
