@@ -39,17 +39,20 @@ namespace {
 constexpr int kW = 64;
 constexpr int kSolved = 0, kMaxIter = 2, kNumerical = 4, kInvalid = 5;
 
-// LDS carve, in doubles
+// LDS carve, in doubles.  Per row only the slack, the multiplier and one
+// working value (the Newton weight w, then the affine product ds*dl) are
+// kept; residuals are recomputed from z where needed, and the gradient of
+// the LQ solve shares its storage with the direction it produces.
 struct MpcSm {
-  double *prm, *z, *dz, *ref, *pl, *s, *lam, *rp, *prod, *g, *Lc, *Y, *yv, *rho, *P, *Ht, *Qh, *tmp;
+  double *prm, *z, *g, *dz, *ref, *pl, *s, *lam, *wv, *Lc, *Y, *yv, *rho, *P, *Ht, *Qh, *tmp;
 };
 
 __host__ __device__ inline int mpc_lds_doubles(int N, int m) {
   const MpcLayout L = mpc_param_layout(m);
   const int RT = N * (m + 4);
-  return L.total + 9 * N /*z*/ + 9 * N /*dz*/ + 6 * (N + 1) /*ref*/ + 4 * N /*pl*/ + 4 * RT /*s lam rp prod*/ +
-         9 * N /*g*/ + 6 * N /*Lc*/ + 18 * N /*Y*/ + 3 * N /*yv*/ + 3 * N /*rho*/ + 36 /*P*/ + 81 /*Ht*/ +
-         81 /*Qh*/ + 64 /*tmp*/;
+  return L.total + 9 * N /*z*/ + 9 * N /*g = dz*/ + 6 * (N + 1) /*ref*/ + 4 * N /*pl*/ + 3 * RT /*s lam wv*/ +
+         6 * N /*Lc*/ + 18 * N /*Y*/ + 3 * N /*yv*/ + 3 * N /*rho*/ + 36 /*P*/ + 81 /*Ht*/ + 81 /*Qh*/ +
+         64 /*tmp*/;
 }
 
 __device__ inline MpcSm carve_mpc(double* base, int N, int m) {
@@ -59,14 +62,12 @@ __device__ inline MpcSm carve_mpc(double* base, int N, int m) {
   double* p = base;
   S.prm = p; p += L.total;
   S.z = p; p += 9 * N;
-  S.dz = p; p += 9 * N;
+  S.g = p; S.dz = p; p += 9 * N;
   S.ref = p; p += 6 * (N + 1);
   S.pl = p; p += 4 * N;
   S.s = p; p += RT;
   S.lam = p; p += RT;
-  S.rp = p; p += RT;
-  S.prod = p; p += RT;
-  S.g = p; p += 9 * N;
+  S.wv = p; p += RT;
   S.Lc = p; p += 6 * N;
   S.Y = p; p += 18 * N;
   S.yv = p; p += 3 * N;
@@ -77,6 +78,10 @@ __device__ inline MpcSm carve_mpc(double* base, int N, int m) {
   S.tmp = p;
   return S;
 }
+
+// tmp layout: [0, 6) start state, [8] factorisation flag, [16, 16 + mr) the
+// barrier weights lam/s of the stage being factorised (mr <= 36)
+constexpr int kTmpFlag = 8, kTmpSig = 16;
 
 // Column b of [A B] (6 x 9) has at most two non-zeros: row q0 with weight w0
 // and row q1 with weight w1 (q1 < 0: none).
@@ -92,6 +97,7 @@ struct MpcCtx {
   MpcLayout Ly;
   int N, m, mr, RT, lane;
   double dt;
+  int ua, ub;          // upper-triangle entry (ua <= ub) of a 9 x 9 matrix owned by lanes < 45
 
   // coefficient a (0..8) of row i of stage k, and its right-hand side
   __device__ double coef(int k, int i, int a) const {
@@ -108,6 +114,18 @@ struct MpcCtx {
     for (int a = 0; a < 9; ++a) v += coef(k, i, a) * zk[a];
     return v;
   }
+  // c'z and c'dz of one row in one sweep of its coefficients
+  __device__ void row_values(int k, int i, double& cz, double& cd) const {
+    const double* zk = S.z + 9 * k;
+    const double* dk = S.dz + 9 * k;
+    double v = 0.0, w = 0.0;
+    for (int a = 0; a < 9; ++a) {
+      const double c = coef(k, i, a);
+      v += c * zk[a];
+      w += c * dk[a];
+    }
+    cz = v; cd = w;
+  }
   __device__ const double* Hk(int k) const { return S.prm + (k == 0 ? Ly.H0 : Ly.H1); }
   // x-part of h_k: -2 Q r_k (k >= 1)
   __device__ double hk(int k, int a) const {
@@ -117,32 +135,38 @@ struct MpcCtx {
     return -2.0 * v;
   }
 
+  // barrier weights lam/s of stage k's rows into tmp (or zero)
+  __device__ void stage_sigma(int k, bool with_rows) {
+    if (lane < mr) {
+      const int r = k * mr + lane;
+      S.tmp[kTmpSig + lane] = with_rows ? S.lam[r] / S.s[r] : 0.0;
+    }
+    __syncthreads();
+  }
+  // upper entry (ua, ub) of Ht_k = H_k + sum_i sigma_i c_i c_i'
+  __device__ double ht_entry(int k) const {
+    double v = Hk(k)[9 * ua + ub];
+    for (int i = 0; i < mr; ++i) v += S.tmp[kTmpSig + i] * coef(k, i, ua) * coef(k, i, ub);
+    return v;
+  }
+
   // Riccati factorisation of the Newton LQ; with_rows = false uses H_k alone.
   // Returns false (uniformly) when a pivot of some Quu is not positive.
   __device__ bool factor(bool with_rows) {
-    if (lane == 0) S.tmp[8] = 0.0;
-    // Ht of stage k into S.Ht (full 9 x 9)
-    auto stage_ht = [&](int k) {
-      const double* H = Hk(k);
-      for (int e = lane; e < 81; e += kW) {
-        const int a = e / 9, b = e - 9 * (e / 9);
-        double v = H[e];
-        if (with_rows)
-          for (int i = 0; i < mr; ++i) {
-            const int r = k * mr + i;
-            v += S.lam[r] / S.s[r] * coef(k, i, a) * coef(k, i, b);
-          }
-        S.Ht[e] = v;
-      }
-      __syncthreads();
-    };
+    if (lane == 0) S.tmp[kTmpFlag] = 0.0;
     // terminal block: P = T2' Ht_{N-2} T2 + T1' Ht_{N-1} T1
     for (int e = lane; e < 36; e += kW) S.P[e] = 0.0;
     for (int t = 0; t < 2; ++t) {
       const int k = N - 2 + t;
       const double* T = S.prm + (t == 0 ? Ly.T2 : Ly.T1);
-      stage_ht(k);
-      // tmp2 = Ht T (9 x 6) in S.Qh
+      stage_sigma(k, with_rows);
+      if (lane < 45) {
+        const double v = ht_entry(k);
+        S.Ht[9 * ua + ub] = v;
+        S.Ht[9 * ub + ua] = v;
+      }
+      __syncthreads();
+      // Ht T (9 x 6) into Qh
       for (int e = lane; e < 54; e += kW) {
         const int a = e / 6, c = e - 6 * (e / 6);
         double v = 0.0;
@@ -158,64 +182,6 @@ struct MpcCtx {
       }
       __syncthreads();
     }
-    symmetrise_P();
-    for (int k = N - 3; k >= 0; --k) {
-      stage_ht(k);
-      // Qh = Ht + [A B]' P [A B]
-      for (int e = lane; e < 81; e += kW) {
-        const int a = e / 9, b = e - 9 * (e / 9);
-        int qa0, qa1, qb0, qb1;
-        double wa0, wa1, wb0, wb1;
-        ab_col(a, dt, qa0, wa0, qa1, wa1);
-        ab_col(b, dt, qb0, wb0, qb1, wb1);
-        double v = wa0 * wb0 * S.P[6 * qa0 + qb0];
-        if (qb1 >= 0) v += wa0 * wb1 * S.P[6 * qa0 + qb1];
-        if (qa1 >= 0) {
-          v += wa1 * wb0 * S.P[6 * qa1 + qb0];
-          if (qb1 >= 0) v += wa1 * wb1 * S.P[6 * qa1 + qb1];
-        }
-        S.Qh[e] = S.Ht[e] + v;
-      }
-      __syncthreads();
-      double* L = S.Lc + 6 * k;     // Quu = L L', packed (00, 10, 11, 20, 21, 22)
-      double* Y = S.Y + 18 * k;     // Y = L^-1 Qux (3 x 6)
-      if (lane == 0) {
-        const double q00 = S.Qh[60], q10 = 0.5 * (S.Qh[69] + S.Qh[61]), q11 = S.Qh[70];
-        const double q20 = 0.5 * (S.Qh[78] + S.Qh[62]), q21 = 0.5 * (S.Qh[79] + S.Qh[71]), q22 = S.Qh[80];
-        const double l00 = sqrt(q00);
-        const double l10 = q10 / l00, l20 = q20 / l00;
-        const double l11 = sqrt(q11 - l10 * l10);
-        const double l21 = (q21 - l20 * l10) / l11;
-        const double l22 = sqrt(q22 - l20 * l20 - l21 * l21);
-        L[0] = l00; L[1] = l10; L[2] = l11; L[3] = l20; L[4] = l21; L[5] = l22;
-        if (!(l00 > 0.0 && l11 > 0.0 && l22 > 0.0) || !isfinite(l00 * l11 * l22)) S.tmp[8] = 1.0;
-      }
-      __syncthreads();
-      if (lane < 6) {
-        const int c = lane;
-        // Qux[i][c] = 1/2 (Qh[6+i][c] + Qh[c][6+i])
-        const double b0 = 0.5 * (S.Qh[9 * 6 + c] + S.Qh[9 * c + 6]);
-        const double b1 = 0.5 * (S.Qh[9 * 7 + c] + S.Qh[9 * c + 7]);
-        const double b2 = 0.5 * (S.Qh[9 * 8 + c] + S.Qh[9 * c + 8]);
-        const double y0 = b0 / L[0];
-        const double y1 = (b1 - L[1] * y0) / L[2];
-        const double y2 = (b2 - L[3] * y0 - L[4] * y1) / L[5];
-        Y[c] = y0; Y[6 + c] = y1; Y[12 + c] = y2;
-      }
-      __syncthreads();
-      if (k > 0) {
-        for (int e = lane; e < 36; e += kW) {
-          const int a = e / 6, b = e - 6 * (e / 6);
-          const double qxx = 0.5 * (S.Qh[9 * a + b] + S.Qh[9 * b + a]);
-          S.P[e] = qxx - (Y[a] * Y[b] + Y[6 + a] * Y[6 + b] + Y[12 + a] * Y[12 + b]);
-        }
-        __syncthreads();
-      }
-    }
-    return S.tmp[8] == 0.0;
-  }
-
-  __device__ void symmetrise_P() {
     for (int e = lane; e < 36; e += kW) {
       const int a = e / 6, b = e - 6 * (e / 6);
       if (a < b) {
@@ -224,10 +190,66 @@ struct MpcCtx {
       }
     }
     __syncthreads();
+    for (int k = N - 3; k >= 0; --k) {
+      stage_sigma(k, with_rows);
+      // Qh = Ht + [A B]' P [A B] (symmetric: lanes own the upper triangle)
+      if (lane < 45) {
+        int qa0, qa1, qb0, qb1;
+        double wa0, wa1, wb0, wb1;
+        ab_col(ua, dt, qa0, wa0, qa1, wa1);
+        ab_col(ub, dt, qb0, wb0, qb1, wb1);
+        double v = wa0 * wb0 * S.P[6 * qa0 + qb0];
+        if (qb1 >= 0) v += wa0 * wb1 * S.P[6 * qa0 + qb1];
+        if (qa1 >= 0) {
+          v += wa1 * wb0 * S.P[6 * qa1 + qb0];
+          if (qb1 >= 0) v += wa1 * wb1 * S.P[6 * qa1 + qb1];
+        }
+        v += ht_entry(k);
+        S.Qh[9 * ua + ub] = v;
+        S.Qh[9 * ub + ua] = v;
+      }
+      __syncthreads();
+      // Quu = L L' (every lane < 6 factors it, lane 0 stores it) and
+      // Y = L^-1 Qux, column c in lane c.  Lc holds (1/l00, l10, 1/l11, l20, l21, 1/l22).
+      double* L = S.Lc + 6 * k;
+      double* Y = S.Y + 18 * k;
+      if (lane < 6) {
+        const double l00 = sqrt(S.Qh[60]);
+        const double l10 = S.Qh[69] / l00, l20 = S.Qh[78] / l00;
+        const double l11 = sqrt(S.Qh[70] - l10 * l10);
+        const double l21 = (S.Qh[79] - l20 * l10) / l11;
+        const double l22 = sqrt(S.Qh[80] - l20 * l20 - l21 * l21);
+        const double i00 = 1.0 / l00, i11 = 1.0 / l11, i22 = 1.0 / l22;
+        if (lane == 0) {
+          L[0] = i00; L[1] = l10; L[2] = i11; L[3] = l20; L[4] = l21; L[5] = i22;
+          if (!(l00 > 0.0 && l11 > 0.0 && l22 > 0.0) || !isfinite(l00 * l11 * l22)) S.tmp[kTmpFlag] = 1.0;
+        }
+        const int c = lane;
+        const double y0 = S.Qh[9 * 6 + c] * i00;
+        const double y1 = (S.Qh[9 * 7 + c] - l10 * y0) * i11;
+        const double y2 = (S.Qh[9 * 8 + c] - l20 * y0 - l21 * y1) * i22;
+        Y[c] = y0; Y[6 + c] = y1; Y[12 + c] = y2;
+      }
+      __syncthreads();
+      if (k > 0) {
+        if (lane < 21) {
+          // upper entry of the 6 x 6 cost-to-go: lane -> (a, b), a <= b
+          int a = 0, t = lane;
+          while (t >= 6 - a) { t -= 6 - a; ++a; }
+          const int b = a + t;
+          const double v = S.Qh[9 * a + b] - (Y[a] * Y[b] + Y[6 + a] * Y[6 + b] + Y[12 + a] * Y[12 + b]);
+          S.P[6 * a + b] = v;
+          S.P[6 * b + a] = v;
+        }
+        __syncthreads();
+      }
+    }
+    return S.tmp[kTmpFlag] == 0.0;
   }
 
-  // Solve the factorised LQ for the gradients in S.g; result into S.dz.
-  // Sequential over stages in lane 0 (a few dozen flops per stage).
+  // Solve the factorised LQ for the gradients in S.g; the direction replaces
+  // them (S.dz aliases S.g: the backward sweep reads every g_k before the
+  // forward sweep writes dz_k).  Sequential over stages in lane 0.
   __device__ void lq_solve() {
     if (lane == 0) {
       const double* T2 = S.prm + Ly.T2;
@@ -250,9 +272,9 @@ struct MpcCtx {
           qx[3 + c] = gk[3 + c] + dt * p[c] + p[3 + c];
           qu[c] = gk[6 + c] + h2 * p[c] + dt * p[3 + c];
         }
-        const double y0 = qu[0] / L[0];
-        const double y1 = (qu[1] - L[1] * y0) / L[2];
-        const double y2 = (qu[2] - L[3] * y0 - L[4] * y1) / L[5];
+        const double y0 = qu[0] * L[0];
+        const double y1 = (qu[1] - L[1] * y0) * L[2];
+        const double y2 = (qu[2] - L[3] * y0 - L[4] * y1) * L[5];
         S.yv[3 * k] = y0; S.yv[3 * k + 1] = y1; S.yv[3 * k + 2] = y2;
         for (int c = 0; c < 6; ++c) p[c] = qx[c] - (Y[c] * y0 + Y[6 + c] * y1 + Y[12 + c] * y2);
       }
@@ -267,9 +289,9 @@ struct MpcCtx {
           for (int c = 0; c < 6; ++c) v += Y[6 * i + c] * dx[c];
           r[i] = v;
         }
-        const double u2 = -r[2] / L[5];
-        const double u1 = -(r[1] + L[4] * u2) / L[2];
-        const double u0 = -(r[0] + L[1] * u1 + L[3] * u2) / L[0];
+        const double u2 = -r[2] * L[5];
+        const double u1 = -(r[1] + L[4] * u2) * L[2];
+        const double u0 = -(r[0] + L[1] * u1 + L[3] * u2) * L[0];
         double* d = S.dz + 9 * k;
         for (int c = 0; c < 6; ++c) d[c] = dx[c];
         d[6] = u0; d[7] = u1; d[8] = u2;
@@ -290,13 +312,12 @@ struct MpcCtx {
     __syncthreads();
   }
 
-  // g_k = [0; rho_k] + C_k' w, with w_r from the per-row rule
-  template <typename W>
-  __device__ void build_g(W wfun, bool with_rho) {
+  // g_k = [0; rho_k] + C_k' w, with the per-row weights in S.wv
+  __device__ void build_g() {
     for (int e = lane; e < 9 * N; e += kW) {
       const int k = e / 9, a = e - 9 * (e / 9);
-      double v = (with_rho && a >= 6) ? S.rho[3 * k + a - 6] : 0.0;
-      for (int i = 0; i < mr; ++i) v += coef(k, i, a) * wfun(k * mr + i);
+      double v = a >= 6 ? S.rho[3 * k + a - 6] : 0.0;
+      for (int i = 0; i < mr; ++i) v += coef(k, i, a) * S.wv[k * mr + i];
       S.g[e] = v;
     }
     __syncthreads();
@@ -384,7 +405,14 @@ __global__ __launch_bounds__(kW) void mpc_kernel(MpcArgs A) {
   const int inst = blockIdx.x;
   if (inst >= A.n) return;
   const int N = A.N, m = A.m, mr = m + 4, RT = N * mr, lane = threadIdx.x;
-  MpcCtx C{A, carve_mpc(reinterpret_cast<double*>(smem_raw), N, m), mpc_param_layout(m), N, m, mr, RT, lane, A.dt};
+  int ua = 0, ub = 0;
+  {
+    int t = lane < 45 ? lane : 0;
+    while (t >= 9 - ua) { t -= 9 - ua; ++ua; }
+    ub = ua + t;
+  }
+  MpcCtx C{A, carve_mpc(reinterpret_cast<double*>(smem_raw), N, m), mpc_param_layout(m), N, m, mr, RT, lane, A.dt,
+           ua, ub};
   MpcSm& S = C.S;
   const MpcLayout& Ly = C.Ly;
   const double dt = A.dt;
@@ -488,66 +516,88 @@ __global__ __launch_bounds__(kW) void mpc_kernel(MpcArgs A) {
     for (int r = lane; r < RT; r += kW) {
       const int k = r / mr, i = r - mr * (r / mr);
       const double v = C.row_value(k, i, S.z + 9 * k) + S.s[r] - C.rhs(k, i);
-      S.rp[r] = v;
       rpm = fmax(rpm, fabs(v));
       smu += S.s[r] * S.lam[r];
     }
     mu = wave::sum(smu) / RT;
     rpmax = wave::max(rpm);
-    __syncthreads();
     C.dual_residual(rdmax, gscale);
     if (mu <= A.tol && rpmax <= 1e-10 && rdmax <= 1e-8 * (1.0 + gscale)) { converged = true; break; }
     if (it >= A.max_iters || !isfinite(mu)) break;
     if (!C.factor(true)) break;                 // a Quu lost definiteness: keep the current iterate
-    // predictor: w = sigma rp - lam
-    C.build_g([&](int r) { return S.lam[r] / S.s[r] * S.rp[r] - S.lam[r]; }, true);
-    C.lq_solve();
-    double amax_l = 1.0, mua = 0.0;
+    // predictor: w = (lam / s) rp - lam, rp = c'z + s - d
     for (int r = lane; r < RT; r += kW) {
       const int k = r / mr, i = r - mr * (r / mr);
-      const double ds = -S.rp[r] - C.row_value(k, i, S.dz + 9 * k);
+      const double rp = C.row_value(k, i, S.z + 9 * k) + S.s[r] - C.rhs(k, i);
+      S.wv[r] = S.lam[r] / S.s[r] * rp - S.lam[r];
+    }
+    __syncthreads();
+    C.build_g();
+    C.lq_solve();
+    double amax_l = 1.0;
+    for (int r = lane; r < RT; r += kW) {
+      const int k = r / mr, i = r - mr * (r / mr);
+      double cz, cd;
+      C.row_values(k, i, cz, cd);
+      const double ds = -(cz + S.s[r] - C.rhs(k, i)) - cd;
       const double dl = -S.lam[r] - S.lam[r] / S.s[r] * ds;
       if (ds < 0.0) amax_l = fmin(amax_l, -S.s[r] / ds);
       if (dl < 0.0) amax_l = fmin(amax_l, -S.lam[r] / dl);
-      S.prod[r] = ds * dl;
     }
     const double aa = wave::min(amax_l);
+    double mua = 0.0;
     for (int r = lane; r < RT; r += kW) {
       const int k = r / mr, i = r - mr * (r / mr);
-      const double ds = -S.rp[r] - C.row_value(k, i, S.dz + 9 * k);
+      double cz, cd;
+      C.row_values(k, i, cz, cd);
+      const double ds = -(cz + S.s[r] - C.rhs(k, i)) - cd;
       const double dl = -S.lam[r] - S.lam[r] / S.s[r] * ds;
       mua += (S.s[r] + aa * ds) * (S.lam[r] + aa * dl);
+      S.wv[r] = ds * dl;                          // affine product for the corrector
     }
     mua = wave::sum(mua) / RT;
     const double sc = (mua / mu) * (mua / mu) * (mua / mu);
+    const double smu_t = sc * mu;
     __syncthreads();
     // corrector: rc = s lam + ds_aff dl_aff - sc mu, w = (lam rp - rc) / s
-    const double smu_t = sc * mu;
-    C.build_g([&](int r) {
-      const double rc = S.s[r] * S.lam[r] + S.prod[r] - smu_t;
-      return (S.lam[r] * S.rp[r] - rc) / S.s[r];
-    }, true);
+    for (int r = lane; r < RT; r += kW) {
+      const int k = r / mr, i = r - mr * (r / mr);
+      const double rp = C.row_value(k, i, S.z + 9 * k) + S.s[r] - C.rhs(k, i);
+      const double rc = S.s[r] * S.lam[r] + S.wv[r] - smu_t;
+      S.wv[r] = (S.lam[r] * rp - rc) / S.s[r];
+    }
+    __syncthreads();
+    C.build_g();
     C.lq_solve();
+    // step: ds = -rp - c'dz, dl = (-rc - lam ds) / s with rc = lam rp - s w
     double am = 1.0;
     for (int r = lane; r < RT; r += kW) {
       const int k = r / mr, i = r - mr * (r / mr);
-      const double ds = -S.rp[r] - C.row_value(k, i, S.dz + 9 * k);
-      const double rc = S.s[r] * S.lam[r] + S.prod[r] - smu_t;
+      double cz, cd;
+      C.row_values(k, i, cz, cd);
+      const double rp = cz + S.s[r] - C.rhs(k, i);
+      const double ds = -rp - cd;
+      const double rc = S.lam[r] * rp - S.s[r] * S.wv[r];
       const double dl = (-rc - S.lam[r] * ds) / S.s[r];
       if (ds < 0.0) am = fmin(am, -S.s[r] / ds);
       if (dl < 0.0) am = fmin(am, -S.lam[r] / dl);
-      S.prod[r] = ds;            // keep ds and dl for the update
-      S.rp[r] = dl;
     }
     const double alpha = fmin(1.0, 0.995 * wave::min(am));
-    __syncthreads();
     bool nonfinite = !(alpha > 0.0) || !isfinite(alpha);
     for (int e = lane; e < 9 * N; e += kW) nonfinite |= !isfinite(S.dz[e]);
     if (__ballot(nonfinite) != 0ull) break;     // a broken direction: keep the current iterate
     for (int r = lane; r < RT; r += kW) {
-      S.s[r] += alpha * S.prod[r];
-      S.lam[r] += alpha * S.rp[r];
+      const int k = r / mr, i = r - mr * (r / mr);
+      double cz, cd;
+      C.row_values(k, i, cz, cd);
+      const double rp = cz + S.s[r] - C.rhs(k, i);
+      const double ds = -rp - cd;
+      const double rc = S.lam[r] * rp - S.s[r] * S.wv[r];
+      const double dl = (-rc - S.lam[r] * ds) / S.s[r];
+      S.s[r] += alpha * ds;
+      S.lam[r] += alpha * dl;
     }
+    __syncthreads();
     for (int e = lane; e < 9 * N; e += kW) S.z[e] += alpha * S.dz[e];
     __syncthreads();
   }
