@@ -720,7 +720,7 @@ int mpc_params(const rbp_mpc_desc& d, const std::vector<double>& F1, const std::
     for (double v : row) nn += v * v;
     nn = std::sqrt(nn);
     if (!(nn > 0.0) || !std::isfinite(nn) || !std::isfinite(G[size_t(i)])) return RBP_E_SHAPE;
-    for (int a = 0; a < 9; ++a) out[size_t(L.Cr + 9 * i + a)] = row[a] / nn;
+    for (int a = 0; a < 9; ++a) out[size_t(L.Cr + a * L.cs + i)] = row[a] / nn;
     out[size_t(L.dr + i)] = G[size_t(i)] / nn;
   }
   // [AB B]^-1 per axis: (1/dt^3) [[dt, -dt^2/2], [-dt, 3 dt^2/2]];

@@ -189,6 +189,7 @@ hipError_t launch_hyperplanes(int n, const double* X, int n_obst, const double* 
 // on the host by the library (layout in mpc_param_layout).
 struct MpcLayout {
   int H1, H0, Qm, Cr, dr, T2, T1, Mi, pf, total;   // offsets in doubles
+  int cs;                                          // column stride of Cr (odd)
 };
 __host__ __device__ inline MpcLayout mpc_param_layout(int m) {
   MpcLayout L{};
@@ -196,7 +197,9 @@ __host__ __device__ inline MpcLayout mpc_param_layout(int m) {
   L.H1 = o; o += 81;      // stage Hessian, k >= 1 (9 x 9, z = [x; u])
   L.H0 = o; o += 81;      // stage Hessian, k = 0 (no tracking)
   L.Qm = o; o += 36;      // tracking weight Q
-  L.Cr = o; o += 9 * m;   // reachable rows in stage form, unit norm
+  L.cs = m | 1;
+  L.Cr = o; o += 9 * L.cs;  // reachable rows in stage form, unit norm, stored by
+                            // column: entry (i, a) at a * cs + i (odd stride)
   L.dr = o; o += m;       // their right-hand sides
   L.T2 = o; o += 54;      // z_{N-2} = T2 x_{N-2}   (last two stages eliminated)
   L.T1 = o; o += 54;      // z_{N-1} = T1 x_{N-2}

@@ -52,7 +52,7 @@ __host__ __device__ inline int mpc_lds_doubles(int N, int m) {
   const int RT = N * (m + 4);
   return L.total + 9 * N /*z*/ + 9 * N /*g = dz*/ + 6 * (N + 1) /*ref*/ + 4 * N /*pl*/ + 3 * RT /*s lam wv*/ +
          6 * N /*Lc*/ + 18 * N /*Y*/ + 3 * N /*yv*/ + 3 * N /*rho*/ + 36 /*P*/ + 81 /*Ht*/ + 81 /*Qh*/ +
-         64 /*tmp*/;
+         96 /*tmp*/;
 }
 
 __device__ inline MpcSm carve_mpc(double* base, int N, int m) {
@@ -79,9 +79,11 @@ __device__ inline MpcSm carve_mpc(double* base, int N, int m) {
   return S;
 }
 
-// tmp layout: [0, 6) start state, [8] factorisation flag, [16, 16 + mr) the
-// barrier weights lam/s of the stage being factorised (mr <= 36)
-constexpr int kTmpFlag = 8, kTmpSig = 16;
+// tmp layout: [0, 6) start state, [8] factorisation flag, [16, 52) and
+// [52, 88) two buffers of the barrier weights lam/s of one stage's rows
+// (mr <= 36): the factorisation of stage k reads one while stage k-1's are
+// written into the other
+constexpr int kTmpFlag = 8, kTmpSig = 16, kSigBuf = 36;
 
 // Column b of [A B] (6 x 9) has at most two non-zeros: row q0 with weight w0
 // and row q1 with weight w1 (q1 < 0: none).
@@ -99,32 +101,43 @@ struct MpcCtx {
   double dt;
   int ua, ub;          // upper-triangle entry (ua <= ub) of a 9 x 9 matrix owned by lanes < 45
 
-  // coefficient a (0..8) of row i of stage k, and its right-hand side
-  __device__ double coef(int k, int i, int a) const {
-    if (i < m) return S.prm[Ly.Cr + 9 * i + a];
-    const int j = i - m;
-    return -S.pl[4 * k + (a % 3)] * S.prm[Ly.pf + 3 * j + a / 3];
-  }
+  // right-hand side of row i of stage k
   __device__ double rhs(int k, int i) const {
     if (i < m) return S.prm[Ly.dr + i];
     return -S.pl[4 * k + 3] * S.prm[Ly.pf + 3 * (i - m)];
   }
-  __device__ double row_value(int k, int i, const double* zk) const {
-    double v = 0.0;
-    for (int a = 0; a < 9; ++a) v += coef(k, i, a) * zk[a];
-    return v;
-  }
-  // c'z and c'dz of one row in one sweep of its coefficients
-  __device__ void row_values(int k, int i, double& cz, double& cd) const {
-    const double* zk = S.z + 9 * k;
-    const double* dk = S.dz + 9 * k;
-    double v = 0.0, w = 0.0;
-    for (int a = 0; a < 9; ++a) {
-      const double c = coef(k, i, a);
-      v += c * zk[a];
-      w += c * dk[a];
+  // c'v for row i of stage k and a 9-vector v (reachable rows: a shared
+  // table; plane rows: -n . (f0 p + f1 v + f2 u))
+  __device__ double row_dot(int k, int i, const double* v) const {
+    if (i < m) {
+      const double* c = S.prm + Ly.Cr + i;
+      double t = 0.0;
+#pragma unroll
+      for (int a = 0; a < 9; ++a) t += c[a * Ly.cs] * v[a];
+      return t;
     }
-    cz = v; cd = w;
+    const double* f = S.prm + Ly.pf + 3 * (i - m);
+    const double* n = S.pl + 4 * k;
+    double t = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) t += n[c] * (f[0] * v[c] + f[1] * v[3 + c] + f[2] * v[6 + c]);
+    return -t;
+  }
+  __device__ double row_value(int k, int i, const double* zk) const { return row_dot(k, i, zk); }
+  // c'z and c'dz of one row
+  __device__ void row_values(int k, int i, double& cz, double& cd) const {
+    cz = row_dot(k, i, S.z + 9 * k);
+    cd = row_dot(k, i, S.dz + 9 * k);
+  }
+  // component a of C_k' w for per-row weights w (rows of stage k at w[0..mr))
+  __device__ double ct_times(int k, int a, const double* w) const {
+    const double* c = S.prm + Ly.Cr + a * Ly.cs;
+    double t = 0.0;
+#pragma unroll 4
+    for (int i = 0; i < m; ++i) t += c[i] * w[i];
+    const double* f = S.prm + Ly.pf + a / 3;
+    const double tp = f[0] * w[m] + f[3] * w[m + 1] + f[6] * w[m + 2] + f[9] * w[m + 3];
+    return t - S.pl[4 * k + a % 3] * tp;
   }
   __device__ const double* Hk(int k) const { return S.prm + (k == 0 ? Ly.H0 : Ly.H1); }
   // x-part of h_k: -2 Q r_k (k >= 1)
@@ -135,19 +148,28 @@ struct MpcCtx {
     return -2.0 * v;
   }
 
-  // barrier weights lam/s of stage k's rows into tmp (or zero)
-  __device__ void stage_sigma(int k, bool with_rows) {
-    if (lane < mr) {
-      const int r = k * mr + lane;
-      S.tmp[kTmpSig + lane] = with_rows ? S.lam[r] / S.s[r] : 0.0;
+  // barrier weights lam/s of stage k's rows (or zero) into buffer b, by
+  // lanes first .. first + mr - 1
+  __device__ void put_sigma(int k, bool with_rows, int b, int first) {
+    const int i = lane - first;
+    if (i >= 0 && i < mr) {
+      const int r = k * mr + i;
+      S.tmp[kTmpSig + kSigBuf * b + i] = with_rows ? S.lam[r] / S.s[r] : 0.0;
     }
-    __syncthreads();
   }
-  // upper entry (ua, ub) of Ht_k = H_k + sum_i sigma_i c_i c_i'
-  __device__ double ht_entry(int k) const {
+  // upper entry (ua, ub) of Ht_k = H_k + sum_i sigma_i c_i c_i' (weights in buffer b)
+  __device__ double ht_entry(int k, int b) const {
+    const double* sg = S.tmp + kTmpSig + kSigBuf * b;
+    const double* ca = S.prm + Ly.Cr + ua * Ly.cs;
+    const double* cb = S.prm + Ly.Cr + ub * Ly.cs;
     double v = Hk(k)[9 * ua + ub];
-    for (int i = 0; i < mr; ++i) v += S.tmp[kTmpSig + i] * coef(k, i, ua) * coef(k, i, ub);
-    return v;
+#pragma unroll 4
+    for (int i = 0; i < m; ++i) v += sg[i] * ca[i] * cb[i];
+    const double* fa = S.prm + Ly.pf + ua / 3;
+    const double* fb = S.prm + Ly.pf + ub / 3;
+    const double tp = sg[m] * fa[0] * fb[0] + sg[m + 1] * fa[3] * fb[3] + sg[m + 2] * fa[6] * fb[6] +
+                      sg[m + 3] * fa[9] * fb[9];
+    return v + S.pl[4 * k + ua % 3] * S.pl[4 * k + ub % 3] * tp;
   }
 
   // Riccati factorisation of the Newton LQ; with_rows = false uses H_k alone.
@@ -159,9 +181,10 @@ struct MpcCtx {
     for (int t = 0; t < 2; ++t) {
       const int k = N - 2 + t;
       const double* T = S.prm + (t == 0 ? Ly.T2 : Ly.T1);
-      stage_sigma(k, with_rows);
+      put_sigma(k, with_rows, 0, 0);
+      __syncthreads();
       if (lane < 45) {
-        const double v = ht_entry(k);
+        const double v = ht_entry(k, 0);
         S.Ht[9 * ua + ub] = v;
         S.Ht[9 * ub + ua] = v;
       }
@@ -190,8 +213,10 @@ struct MpcCtx {
       }
     }
     __syncthreads();
+    int buf = 0;
+    if (N >= 3) put_sigma(N - 3, with_rows, 0, 0);
+    __syncthreads();
     for (int k = N - 3; k >= 0; --k) {
-      stage_sigma(k, with_rows);
       // Qh = Ht + [A B]' P [A B] (symmetric: lanes own the upper triangle)
       if (lane < 45) {
         int qa0, qa1, qb0, qb1;
@@ -204,45 +229,51 @@ struct MpcCtx {
           v += wa1 * wb0 * S.P[6 * qa1 + qb0];
           if (qb1 >= 0) v += wa1 * wb1 * S.P[6 * qa1 + qb1];
         }
-        v += ht_entry(k);
+        v += ht_entry(k, buf);
         S.Qh[9 * ua + ub] = v;
         S.Qh[9 * ub + ua] = v;
       }
       __syncthreads();
-      // Quu = L L' (every lane < 6 factors it, lane 0 stores it) and
-      // Y = L^-1 Qux, column c in lane c.  Lc holds (1/l00, l10, 1/l11, l20, l21, 1/l22).
-      double* L = S.Lc + 6 * k;
-      double* Y = S.Y + 18 * k;
-      if (lane < 6) {
+      // Quu = L L' and the columns of Y = L^-1 Qux that entry (a, b) of the
+      // next cost-to-go P = Qxx - Y'Y needs, all in the lane of that entry
+      // (lanes < 21); lanes 0..5 (entries (0, c)) store column c of Y, lane 0
+      // stores L as (1/l00, l10, 1/l11, l20, l21, 1/l22).  Lanes 21.. write
+      // the barrier weights of stage k-1 meanwhile.
+      if (lane < 21) {
+        int a = 0, t = lane;
+        while (t >= 6 - a) { t -= 6 - a; ++a; }
+        const int b = a + t;
         const double l00 = sqrt(S.Qh[60]);
         const double l10 = S.Qh[69] / l00, l20 = S.Qh[78] / l00;
         const double l11 = sqrt(S.Qh[70] - l10 * l10);
         const double l21 = (S.Qh[79] - l20 * l10) / l11;
         const double l22 = sqrt(S.Qh[80] - l20 * l20 - l21 * l21);
         const double i00 = 1.0 / l00, i11 = 1.0 / l11, i22 = 1.0 / l22;
+        const double ya0 = S.Qh[54 + a] * i00;
+        const double ya1 = (S.Qh[63 + a] - l10 * ya0) * i11;
+        const double ya2 = (S.Qh[72 + a] - l20 * ya0 - l21 * ya1) * i22;
+        const double yb0 = S.Qh[54 + b] * i00;
+        const double yb1 = (S.Qh[63 + b] - l10 * yb0) * i11;
+        const double yb2 = (S.Qh[72 + b] - l20 * yb0 - l21 * yb1) * i22;
+        if (lane < 6) {
+          double* Y = S.Y + 18 * k;
+          Y[b] = yb0; Y[6 + b] = yb1; Y[12 + b] = yb2;
+        }
         if (lane == 0) {
+          double* L = S.Lc + 6 * k;
           L[0] = i00; L[1] = l10; L[2] = i11; L[3] = l20; L[4] = l21; L[5] = i22;
           if (!(l00 > 0.0 && l11 > 0.0 && l22 > 0.0) || !isfinite(l00 * l11 * l22)) S.tmp[kTmpFlag] = 1.0;
         }
-        const int c = lane;
-        const double y0 = S.Qh[9 * 6 + c] * i00;
-        const double y1 = (S.Qh[9 * 7 + c] - l10 * y0) * i11;
-        const double y2 = (S.Qh[9 * 8 + c] - l20 * y0 - l21 * y1) * i22;
-        Y[c] = y0; Y[6 + c] = y1; Y[12 + c] = y2;
-      }
-      __syncthreads();
-      if (k > 0) {
-        if (lane < 21) {
-          // upper entry of the 6 x 6 cost-to-go: lane -> (a, b), a <= b
-          int a = 0, t = lane;
-          while (t >= 6 - a) { t -= 6 - a; ++a; }
-          const int b = a + t;
-          const double v = S.Qh[9 * a + b] - (Y[a] * Y[b] + Y[6 + a] * Y[6 + b] + Y[12 + a] * Y[12 + b]);
+        if (k > 0) {
+          const double v = S.Qh[9 * a + b] - (ya0 * yb0 + ya1 * yb1 + ya2 * yb2);
           S.P[6 * a + b] = v;
           S.P[6 * b + a] = v;
         }
-        __syncthreads();
+      } else if (k > 0) {
+        put_sigma(k - 1, with_rows, buf ^ 1, 21);
       }
+      __syncthreads();
+      buf ^= 1;
     }
     return S.tmp[kTmpFlag] == 0.0;
   }
@@ -316,9 +347,8 @@ struct MpcCtx {
   __device__ void build_g() {
     for (int e = lane; e < 9 * N; e += kW) {
       const int k = e / 9, a = e - 9 * (e / 9);
-      double v = a >= 6 ? S.rho[3 * k + a - 6] : 0.0;
-      for (int i = 0; i < mr; ++i) v += coef(k, i, a) * S.wv[k * mr + i];
-      S.g[e] = v;
+      const double v = a >= 6 ? S.rho[3 * k + a - 6] : 0.0;
+      S.g[e] = v + ct_times(k, a, S.wv + k * mr);
     }
     __syncthreads();
   }
@@ -332,8 +362,7 @@ struct MpcCtx {
       const double* H = Hk(k);
       double hz = hk(k, a);
       for (int b = 0; b < 9; ++b) hz += H[9 * a + b] * S.z[9 * k + b];
-      double ct = 0.0;
-      for (int i = 0; i < mr; ++i) ct += coef(k, i, a) * S.lam[k * mr + i];
+      const double ct = ct_times(k, a, S.lam + k * mr);
       S.g[e] = hz + ct;
       gs = fmax(gs, fmax(fabs(hz), fabs(ct)));
     }
@@ -416,6 +445,11 @@ __global__ __launch_bounds__(kW) void mpc_kernel(MpcArgs A) {
   MpcSm& S = C.S;
   const MpcLayout& Ly = C.Ly;
   const double dt = A.dt;
+  // rows r = lane + 64 t as (stage k, row i) without integer division in the loop
+  const int rq = kW / mr, rr = kW - rq * mr, k_l = lane / mr, i_l = lane - mr * (lane / mr);
+#define MPC_FOR_ROWS                                                        \
+  for (int r = lane, k = k_l, i = i_l; r < RT;                              \
+       r += kW, k += rq + (i + rr >= mr ? 1 : 0), i = (i + rr >= mr ? i + rr - mr : i + rr))
 
   // ---- load
   for (int e = lane; e < Ly.total; e += kW) S.prm[e] = A.params[e];
@@ -499,8 +533,7 @@ __global__ __launch_bounds__(kW) void mpc_kernel(MpcArgs A) {
   for (int e = lane; e < 9 * N; e += kW) S.z[e] += S.dz[e];
   __syncthreads();
   // slacks and multipliers
-  for (int r = lane; r < RT; r += kW) {
-    const int k = r / mr, i = r - mr * (r / mr);
+  MPC_FOR_ROWS {
     const double sl = C.rhs(k, i) - C.row_value(k, i, S.z + 9 * k);
     S.s[r] = fmax(sl, 1.0);
     S.lam[r] = 1.0;
@@ -513,8 +546,7 @@ __global__ __launch_bounds__(kW) void mpc_kernel(MpcArgs A) {
   double mu = 0.0, rpmax = 0.0, rdmax = 0.0, gscale = 0.0;
   for (;; ++it) {
     double smu = 0.0, rpm = 0.0;
-    for (int r = lane; r < RT; r += kW) {
-      const int k = r / mr, i = r - mr * (r / mr);
+    MPC_FOR_ROWS {
       const double v = C.row_value(k, i, S.z + 9 * k) + S.s[r] - C.rhs(k, i);
       rpm = fmax(rpm, fabs(v));
       smu += S.s[r] * S.lam[r];
@@ -526,8 +558,7 @@ __global__ __launch_bounds__(kW) void mpc_kernel(MpcArgs A) {
     if (it >= A.max_iters || !isfinite(mu)) break;
     if (!C.factor(true)) break;                 // a Quu lost definiteness: keep the current iterate
     // predictor: w = (lam / s) rp - lam, rp = c'z + s - d
-    for (int r = lane; r < RT; r += kW) {
-      const int k = r / mr, i = r - mr * (r / mr);
+    MPC_FOR_ROWS {
       const double rp = C.row_value(k, i, S.z + 9 * k) + S.s[r] - C.rhs(k, i);
       S.wv[r] = S.lam[r] / S.s[r] * rp - S.lam[r];
     }
@@ -535,8 +566,7 @@ __global__ __launch_bounds__(kW) void mpc_kernel(MpcArgs A) {
     C.build_g();
     C.lq_solve();
     double amax_l = 1.0;
-    for (int r = lane; r < RT; r += kW) {
-      const int k = r / mr, i = r - mr * (r / mr);
+    MPC_FOR_ROWS {
       double cz, cd;
       C.row_values(k, i, cz, cd);
       const double ds = -(cz + S.s[r] - C.rhs(k, i)) - cd;
@@ -546,8 +576,7 @@ __global__ __launch_bounds__(kW) void mpc_kernel(MpcArgs A) {
     }
     const double aa = wave::min(amax_l);
     double mua = 0.0;
-    for (int r = lane; r < RT; r += kW) {
-      const int k = r / mr, i = r - mr * (r / mr);
+    MPC_FOR_ROWS {
       double cz, cd;
       C.row_values(k, i, cz, cd);
       const double ds = -(cz + S.s[r] - C.rhs(k, i)) - cd;
@@ -560,8 +589,7 @@ __global__ __launch_bounds__(kW) void mpc_kernel(MpcArgs A) {
     const double smu_t = sc * mu;
     __syncthreads();
     // corrector: rc = s lam + ds_aff dl_aff - sc mu, w = (lam rp - rc) / s
-    for (int r = lane; r < RT; r += kW) {
-      const int k = r / mr, i = r - mr * (r / mr);
+    MPC_FOR_ROWS {
       const double rp = C.row_value(k, i, S.z + 9 * k) + S.s[r] - C.rhs(k, i);
       const double rc = S.s[r] * S.lam[r] + S.wv[r] - smu_t;
       S.wv[r] = (S.lam[r] * rp - rc) / S.s[r];
@@ -571,8 +599,7 @@ __global__ __launch_bounds__(kW) void mpc_kernel(MpcArgs A) {
     C.lq_solve();
     // step: ds = -rp - c'dz, dl = (-rc - lam ds) / s with rc = lam rp - s w
     double am = 1.0;
-    for (int r = lane; r < RT; r += kW) {
-      const int k = r / mr, i = r - mr * (r / mr);
+    MPC_FOR_ROWS {
       double cz, cd;
       C.row_values(k, i, cz, cd);
       const double rp = cz + S.s[r] - C.rhs(k, i);
@@ -586,8 +613,7 @@ __global__ __launch_bounds__(kW) void mpc_kernel(MpcArgs A) {
     bool nonfinite = !(alpha > 0.0) || !isfinite(alpha);
     for (int e = lane; e < 9 * N; e += kW) nonfinite |= !isfinite(S.dz[e]);
     if (__ballot(nonfinite) != 0ull) break;     // a broken direction: keep the current iterate
-    for (int r = lane; r < RT; r += kW) {
-      const int k = r / mr, i = r - mr * (r / mr);
+    MPC_FOR_ROWS {
       double cz, cd;
       C.row_values(k, i, cz, cd);
       const double rp = cz + S.s[r] - C.rhs(k, i);
@@ -618,8 +644,7 @@ __global__ __launch_bounds__(kW) void mpc_kernel(MpcArgs A) {
   }
   const double cost = wave::sum(cst);
   double pres = 0.0, pscale = 0.0, cres = 0.0, lmax = 0.0;
-  for (int r = lane; r < RT; r += kW) {
-    const int k = r / mr, i = r - mr * (r / mr);
+  MPC_FOR_ROWS {
     const double v = C.row_value(k, i, S.z + 9 * k), d = C.rhs(k, i);
     pres = fmax(pres, v - d);
     pscale = fmax(pscale, fmax(fabs(v), fabs(d)));
@@ -646,6 +671,7 @@ __global__ __launch_bounds__(kW) void mpc_kernel(MpcArgs A) {
     A.status[inst] = (kkt <= 1e-6 && isfinite(cost)) ? kSolved : (converged ? kNumerical : kMaxIter);
     if (A.iters) A.iters[inst] = it;
   }
+#undef MPC_FOR_ROWS
 }
 
 }  // namespace
