@@ -44,15 +44,20 @@ constexpr int kSolved = 0, kMaxIter = 2, kNumerical = 4, kInvalid = 5;
 // kept; residuals are recomputed from z where needed, and the gradient of
 // the LQ solve shares its storage with the direction it produces.
 struct MpcSm {
-  double *prm, *z, *g, *dz, *ref, *pl, *s, *lam, *wv, *Lc, *Y, *yv, *rho, *P, *Ht, *Qh, *tmp;
+  double *prm, *z, *g, *dz, *ref, *pl, *s, *lam, *wv, *Lc, *Y, *yv, *rho, *P, *tmp;
+  // scratch of the factorisation, inside the gradient buffer (free while it runs)
+  double *Ht, *Qh, *HtT, *sig;
 };
+
+// the gradient / direction buffer also holds the factorisation's scratch
+// (Ht 81, Qh 81, Ht T 54, two weight buffers 2 x 36)
+__host__ __device__ inline int mpc_g_doubles(int N) { return 9 * N > 288 ? 9 * N : 288; }
 
 __host__ __device__ inline int mpc_lds_doubles(int N, int m) {
   const MpcLayout L = mpc_param_layout(m);
   const int RT = N * (m + 4);
-  return L.total + 9 * N /*z*/ + 9 * N /*g = dz*/ + 6 * (N + 1) /*ref*/ + 4 * N /*pl*/ + 3 * RT /*s lam wv*/ +
-         6 * N /*Lc*/ + 18 * N /*Y*/ + 3 * N /*yv*/ + 3 * N /*rho*/ + 36 /*P*/ + 81 /*Ht*/ + 81 /*Qh*/ +
-         96 /*tmp*/;
+  return L.total + 9 * N /*z*/ + mpc_g_doubles(N) /*g = dz*/ + 6 * (N + 1) /*ref*/ + 4 * N /*pl*/ +
+         3 * RT /*s lam wv*/ + 6 * N /*Lc*/ + 18 * N /*Y*/ + 3 * N /*yv*/ + 3 * N /*rho*/ + 36 /*P*/ + 16 /*tmp*/;
 }
 
 __device__ inline MpcSm carve_mpc(double* base, int N, int m) {
@@ -62,7 +67,9 @@ __device__ inline MpcSm carve_mpc(double* base, int N, int m) {
   double* p = base;
   S.prm = p; p += L.total;
   S.z = p; p += 9 * N;
-  S.g = p; S.dz = p; p += 9 * N;
+  S.g = p; S.dz = p;
+  S.Ht = p; S.Qh = p + 81; S.HtT = p + 162; S.sig = p + 216;
+  p += mpc_g_doubles(N);
   S.ref = p; p += 6 * (N + 1);
   S.pl = p; p += 4 * N;
   S.s = p; p += RT;
@@ -73,17 +80,15 @@ __device__ inline MpcSm carve_mpc(double* base, int N, int m) {
   S.yv = p; p += 3 * N;
   S.rho = p; p += 3 * N;
   S.P = p; p += 36;
-  S.Ht = p; p += 81;
-  S.Qh = p; p += 81;
   S.tmp = p;
   return S;
 }
 
-// tmp layout: [0, 6) start state, [8] factorisation flag, [16, 52) and
-// [52, 88) two buffers of the barrier weights lam/s of one stage's rows
-// (mr <= 36): the factorisation of stage k reads one while stage k-1's are
-// written into the other
-constexpr int kTmpFlag = 8, kTmpSig = 16, kSigBuf = 36;
+// tmp layout: [0, 6) start state, [8] factorisation flag.  S.sig holds two
+// buffers of the barrier weights lam/s of one stage's rows (mr <= 36): the
+// factorisation of stage k reads one while stage k-1's are written into the
+// other
+constexpr int kTmpFlag = 8, kSigBuf = 36;
 
 // Column b of [A B] (6 x 9) has at most two non-zeros: row q0 with weight w0
 // and row q1 with weight w1 (q1 < 0: none).
@@ -154,12 +159,12 @@ struct MpcCtx {
     const int i = lane - first;
     if (i >= 0 && i < mr) {
       const int r = k * mr + i;
-      S.tmp[kTmpSig + kSigBuf * b + i] = with_rows ? S.lam[r] / S.s[r] : 0.0;
+      S.sig[kSigBuf * b + i] = with_rows ? S.lam[r] / S.s[r] : 0.0;
     }
   }
   // upper entry (ua, ub) of Ht_k = H_k + sum_i sigma_i c_i c_i' (weights in buffer b)
   __device__ double ht_entry(int k, int b) const {
-    const double* sg = S.tmp + kTmpSig + kSigBuf * b;
+    const double* sg = S.sig + kSigBuf * b;
     const double* ca = S.prm + Ly.Cr + ua * Ly.cs;
     const double* cb = S.prm + Ly.Cr + ub * Ly.cs;
     double v = Hk(k)[9 * ua + ub];
@@ -189,18 +194,18 @@ struct MpcCtx {
         S.Ht[9 * ub + ua] = v;
       }
       __syncthreads();
-      // Ht T (9 x 6) into Qh
+      // Ht T (9 x 6)
       for (int e = lane; e < 54; e += kW) {
         const int a = e / 6, c = e - 6 * (e / 6);
         double v = 0.0;
         for (int b = 0; b < 9; ++b) v += S.Ht[9 * a + b] * T[6 * b + c];
-        S.Qh[e] = v;
+        S.HtT[e] = v;
       }
       __syncthreads();
       for (int e = lane; e < 36; e += kW) {
         const int c = e / 6, d = e - 6 * (e / 6);
         double v = 0.0;
-        for (int a = 0; a < 9; ++a) v += T[6 * a + c] * S.Qh[6 * a + d];
+        for (int a = 0; a < 9; ++a) v += T[6 * a + c] * S.HtT[6 * a + d];
         S.P[e] += v;
       }
       __syncthreads();
