@@ -98,6 +98,25 @@ __device__ inline void ab_col(int b, double dt, int& q0, double& w0, int& q1, do
   else { q0 = b - 3; w0 = dt; q1 = b - 6; w1 = 0.5 * dt * dt; }
 }
 
+// 1/sqrt(x) and a / b from the hardware approximations (v_rsq_f64, v_rcp_f64)
+// refined by Newton steps to full double precision: the chains of a
+// factorisation stage and the per-row weights stay short.  x, b > 0 here
+// (a non-positive pivot is caught by the caller).
+__device__ inline double rsqrt_nr(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+  const double hx = 0.5 * x;
+  r = r * fma(-hx * r, r, 1.5);
+  r = r * fma(-hx * r, r, 1.5);
+  return r;
+}
+__device__ inline double div_nr(double a, double b) {
+  double r = __builtin_amdgcn_rcp(b);
+  r = fma(fma(-b, r, 1.0), r, r);
+  r = fma(fma(-b, r, 1.0), r, r);
+  const double q = a * r;
+  return fma(fma(-b, q, a), r, q);
+}
+
 struct MpcCtx {
   const MpcArgs& A;
   MpcSm S;
@@ -106,34 +125,6 @@ struct MpcCtx {
   double dt;
   int ua, ub;          // upper-triangle entry (ua <= ub) of a 9 x 9 matrix owned by lanes < 45
 
-  // right-hand side of row i of stage k
-  __device__ double rhs(int k, int i) const {
-    if (i < m) return S.prm[Ly.dr + i];
-    return -S.pl[4 * k + 3] * S.prm[Ly.pf + 3 * (i - m)];
-  }
-  // c'v for row i of stage k and a 9-vector v (reachable rows: a shared
-  // table; plane rows: -n . (f0 p + f1 v + f2 u))
-  __device__ double row_dot(int k, int i, const double* v) const {
-    if (i < m) {
-      const double* c = S.prm + Ly.Cr + i;
-      double t = 0.0;
-#pragma unroll
-      for (int a = 0; a < 9; ++a) t += c[a * Ly.cs] * v[a];
-      return t;
-    }
-    const double* f = S.prm + Ly.pf + 3 * (i - m);
-    const double* n = S.pl + 4 * k;
-    double t = 0.0;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) t += n[c] * (f[0] * v[c] + f[1] * v[3 + c] + f[2] * v[6 + c]);
-    return -t;
-  }
-  __device__ double row_value(int k, int i, const double* zk) const { return row_dot(k, i, zk); }
-  // c'z and c'dz of one row
-  __device__ void row_values(int k, int i, double& cz, double& cd) const {
-    cz = row_dot(k, i, S.z + 9 * k);
-    cd = row_dot(k, i, S.dz + 9 * k);
-  }
   // component a of C_k' w for per-row weights w (rows of stage k at w[0..mr))
   __device__ double ct_times(int k, int a, const double* w) const {
     const double* c = S.prm + Ly.Cr + a * Ly.cs;
@@ -159,7 +150,7 @@ struct MpcCtx {
     const int i = lane - first;
     if (i >= 0 && i < mr) {
       const int r = k * mr + i;
-      S.sig[kSigBuf * b + i] = with_rows ? S.lam[r] / S.s[r] : 0.0;
+      S.sig[kSigBuf * b + i] = with_rows ? div_nr(S.lam[r], S.s[r]) : 0.0;
     }
   }
   // upper entry (ua, ub) of Ht_k = H_k + sum_i sigma_i c_i c_i' (weights in buffer b)
@@ -248,12 +239,14 @@ struct MpcCtx {
         int a = 0, t = lane;
         while (t >= 6 - a) { t -= 6 - a; ++a; }
         const int b = a + t;
-        const double l00 = sqrt(S.Qh[60]);
-        const double l10 = S.Qh[69] / l00, l20 = S.Qh[78] / l00;
-        const double l11 = sqrt(S.Qh[70] - l10 * l10);
-        const double l21 = (S.Qh[79] - l20 * l10) / l11;
-        const double l22 = sqrt(S.Qh[80] - l20 * l20 - l21 * l21);
-        const double i00 = 1.0 / l00, i11 = 1.0 / l11, i22 = 1.0 / l22;
+        const double d0 = S.Qh[60];
+        const double i00 = rsqrt_nr(d0);
+        const double l10 = S.Qh[69] * i00, l20 = S.Qh[78] * i00;
+        const double d1 = S.Qh[70] - l10 * l10;
+        const double i11 = rsqrt_nr(d1);
+        const double l21 = (S.Qh[79] - l20 * l10) * i11;
+        const double d2 = S.Qh[80] - l20 * l20 - l21 * l21;
+        const double i22 = rsqrt_nr(d2);
         const double ya0 = S.Qh[54 + a] * i00;
         const double ya1 = (S.Qh[63 + a] - l10 * ya0) * i11;
         const double ya2 = (S.Qh[72 + a] - l20 * ya0 - l21 * ya1) * i22;
@@ -267,7 +260,7 @@ struct MpcCtx {
         if (lane == 0) {
           double* L = S.Lc + 6 * k;
           L[0] = i00; L[1] = l10; L[2] = i11; L[3] = l20; L[4] = l21; L[5] = i22;
-          if (!(l00 > 0.0 && l11 > 0.0 && l22 > 0.0) || !isfinite(l00 * l11 * l22)) S.tmp[kTmpFlag] = 1.0;
+          if (!(d0 > 0.0 && d1 > 0.0 && d2 > 0.0) || !isfinite(i00 * i11 * i22)) S.tmp[kTmpFlag] = 1.0;
         }
         if (k > 0) {
           const double v = S.Qh[9 * a + b] - (ya0 * yb0 + ya1 * yb1 + ya2 * yb2);
@@ -346,6 +339,47 @@ struct MpcCtx {
       }
     }
     __syncthreads();
+  }
+
+  // visit every row: f(r, c'z_k, c'dz_k, d_r) -- the reachable rows (shared
+  // coefficient table), then the plane rows, so a wavefront never mixes the
+  // two kinds
+  template <typename F>
+  __device__ void for_rows(F&& f) const {
+    if (m > 0) {
+      const int rq = kW / m, rr = kW - rq * m;
+      int k = lane / m, i = lane - m * (lane / m);
+      for (int t = lane; t < N * m; t += kW) {
+        const double* c = S.prm + Ly.Cr + i;
+        const double* zk = S.z + 9 * k;
+        const double* dk = S.dz + 9 * k;
+        double cz = 0.0, cd = 0.0;
+#pragma unroll
+        for (int a = 0; a < 9; ++a) {
+          const double ca = c[a * Ly.cs];
+          cz += ca * zk[a];
+          cd += ca * dk[a];
+        }
+        f(k * mr + i, cz, cd, S.prm[Ly.dr + i]);
+        k += rq;
+        i += rr;
+        if (i >= m) { i -= m; ++k; }
+      }
+    }
+    for (int t = lane; t < 4 * N; t += kW) {
+      const int k = t >> 2, j = t & 3;
+      const double* f3 = S.prm + Ly.pf + 3 * j;
+      const double* n = S.pl + 4 * k;
+      const double* zk = S.z + 9 * k;
+      const double* dk = S.dz + 9 * k;
+      double cz = 0.0, cd = 0.0;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        cz += n[c] * (f3[0] * zk[c] + f3[1] * zk[3 + c] + f3[2] * zk[6 + c]);
+        cd += n[c] * (f3[0] * dk[c] + f3[1] * dk[3 + c] + f3[2] * dk[6 + c]);
+      }
+      f(k * mr + m + j, -cz, -cd, -n[3] * f3[0]);
+    }
   }
 
   // g_k = [0; rho_k] + C_k' w, with the per-row weights in S.wv
@@ -450,11 +484,6 @@ __global__ __launch_bounds__(kW) void mpc_kernel(MpcArgs A) {
   MpcSm& S = C.S;
   const MpcLayout& Ly = C.Ly;
   const double dt = A.dt;
-  // rows r = lane + 64 t as (stage k, row i) without integer division in the loop
-  const int rq = kW / mr, rr = kW - rq * mr, k_l = lane / mr, i_l = lane - mr * (lane / mr);
-#define MPC_FOR_ROWS                                                        \
-  for (int r = lane, k = k_l, i = i_l; r < RT;                              \
-       r += kW, k += rq + (i + rr >= mr ? 1 : 0), i = (i + rr >= mr ? i + rr - mr : i + rr))
 
   // ---- load
   for (int e = lane; e < Ly.total; e += kW) S.prm[e] = A.params[e];
@@ -538,11 +567,10 @@ __global__ __launch_bounds__(kW) void mpc_kernel(MpcArgs A) {
   for (int e = lane; e < 9 * N; e += kW) S.z[e] += S.dz[e];
   __syncthreads();
   // slacks and multipliers
-  MPC_FOR_ROWS {
-    const double sl = C.rhs(k, i) - C.row_value(k, i, S.z + 9 * k);
-    S.s[r] = fmax(sl, 1.0);
+  C.for_rows([&](int r, double cz, double, double d) {
+    S.s[r] = fmax(d - cz, 1.0);
     S.lam[r] = 1.0;
-  }
+  });
   __syncthreads();
 
   // ---- interior-point iterations
@@ -551,11 +579,10 @@ __global__ __launch_bounds__(kW) void mpc_kernel(MpcArgs A) {
   double mu = 0.0, rpmax = 0.0, rdmax = 0.0, gscale = 0.0;
   for (;; ++it) {
     double smu = 0.0, rpm = 0.0;
-    MPC_FOR_ROWS {
-      const double v = C.row_value(k, i, S.z + 9 * k) + S.s[r] - C.rhs(k, i);
-      rpm = fmax(rpm, fabs(v));
+    C.for_rows([&](int r, double cz, double, double d) {
+      rpm = fmax(rpm, fabs(cz + S.s[r] - d));
       smu += S.s[r] * S.lam[r];
-    }
+    });
     mu = wave::sum(smu) / RT;
     rpmax = wave::max(rpm);
     C.dual_residual(rdmax, gscale);
@@ -563,71 +590,62 @@ __global__ __launch_bounds__(kW) void mpc_kernel(MpcArgs A) {
     if (it >= A.max_iters || !isfinite(mu)) break;
     if (!C.factor(true)) break;                 // a Quu lost definiteness: keep the current iterate
     // predictor: w = (lam / s) rp - lam, rp = c'z + s - d
-    MPC_FOR_ROWS {
-      const double rp = C.row_value(k, i, S.z + 9 * k) + S.s[r] - C.rhs(k, i);
-      S.wv[r] = S.lam[r] / S.s[r] * rp - S.lam[r];
-    }
+    C.for_rows([&](int r, double cz, double, double d) {
+      S.wv[r] = div_nr(S.lam[r], S.s[r]) * (cz + S.s[r] - d) - S.lam[r];
+    });
     __syncthreads();
     C.build_g();
     C.lq_solve();
+    // affine step: ds = -rp - c'dz, dl = -lam - (lam / s) ds
     double amax_l = 1.0;
-    MPC_FOR_ROWS {
-      double cz, cd;
-      C.row_values(k, i, cz, cd);
-      const double ds = -(cz + S.s[r] - C.rhs(k, i)) - cd;
-      const double dl = -S.lam[r] - S.lam[r] / S.s[r] * ds;
-      if (ds < 0.0) amax_l = fmin(amax_l, -S.s[r] / ds);
-      if (dl < 0.0) amax_l = fmin(amax_l, -S.lam[r] / dl);
-    }
+    C.for_rows([&](int r, double cz, double cd, double d) {
+      const double ds = -(cz + S.s[r] - d) - cd;
+      const double dl = -S.lam[r] - div_nr(S.lam[r], S.s[r]) * ds;
+      if (ds < 0.0) amax_l = fmin(amax_l, div_nr(S.s[r], -ds));
+      if (dl < 0.0) amax_l = fmin(amax_l, div_nr(S.lam[r], -dl));
+    });
     const double aa = wave::min(amax_l);
     double mua = 0.0;
-    MPC_FOR_ROWS {
-      double cz, cd;
-      C.row_values(k, i, cz, cd);
-      const double ds = -(cz + S.s[r] - C.rhs(k, i)) - cd;
-      const double dl = -S.lam[r] - S.lam[r] / S.s[r] * ds;
+    C.for_rows([&](int r, double cz, double cd, double d) {
+      const double ds = -(cz + S.s[r] - d) - cd;
+      const double dl = -S.lam[r] - div_nr(S.lam[r], S.s[r]) * ds;
       mua += (S.s[r] + aa * ds) * (S.lam[r] + aa * dl);
       S.wv[r] = ds * dl;                          // affine product for the corrector
-    }
+    });
     mua = wave::sum(mua) / RT;
     const double sc = (mua / mu) * (mua / mu) * (mua / mu);
     const double smu_t = sc * mu;
     __syncthreads();
     // corrector: rc = s lam + ds_aff dl_aff - sc mu, w = (lam rp - rc) / s
-    MPC_FOR_ROWS {
-      const double rp = C.row_value(k, i, S.z + 9 * k) + S.s[r] - C.rhs(k, i);
+    C.for_rows([&](int r, double cz, double, double d) {
       const double rc = S.s[r] * S.lam[r] + S.wv[r] - smu_t;
-      S.wv[r] = (S.lam[r] * rp - rc) / S.s[r];
-    }
+      S.wv[r] = div_nr(S.lam[r] * (cz + S.s[r] - d) - rc, S.s[r]);
+    });
     __syncthreads();
     C.build_g();
     C.lq_solve();
     // step: ds = -rp - c'dz, dl = (-rc - lam ds) / s with rc = lam rp - s w
     double am = 1.0;
-    MPC_FOR_ROWS {
-      double cz, cd;
-      C.row_values(k, i, cz, cd);
-      const double rp = cz + S.s[r] - C.rhs(k, i);
+    C.for_rows([&](int r, double cz, double cd, double d) {
+      const double rp = cz + S.s[r] - d;
       const double ds = -rp - cd;
       const double rc = S.lam[r] * rp - S.s[r] * S.wv[r];
-      const double dl = (-rc - S.lam[r] * ds) / S.s[r];
-      if (ds < 0.0) am = fmin(am, -S.s[r] / ds);
-      if (dl < 0.0) am = fmin(am, -S.lam[r] / dl);
-    }
+      const double dl = div_nr(-rc - S.lam[r] * ds, S.s[r]);
+      if (ds < 0.0) am = fmin(am, div_nr(S.s[r], -ds));
+      if (dl < 0.0) am = fmin(am, div_nr(S.lam[r], -dl));
+    });
     const double alpha = fmin(1.0, 0.995 * wave::min(am));
     bool nonfinite = !(alpha > 0.0) || !isfinite(alpha);
     for (int e = lane; e < 9 * N; e += kW) nonfinite |= !isfinite(S.dz[e]);
     if (__ballot(nonfinite) != 0ull) break;     // a broken direction: keep the current iterate
-    MPC_FOR_ROWS {
-      double cz, cd;
-      C.row_values(k, i, cz, cd);
-      const double rp = cz + S.s[r] - C.rhs(k, i);
+    C.for_rows([&](int r, double cz, double cd, double d) {
+      const double rp = cz + S.s[r] - d;
       const double ds = -rp - cd;
       const double rc = S.lam[r] * rp - S.s[r] * S.wv[r];
-      const double dl = (-rc - S.lam[r] * ds) / S.s[r];
+      const double dl = div_nr(-rc - S.lam[r] * ds, S.s[r]);
       S.s[r] += alpha * ds;
       S.lam[r] += alpha * dl;
-    }
+    });
     __syncthreads();
     for (int e = lane; e < 9 * N; e += kW) S.z[e] += alpha * S.dz[e];
     __syncthreads();
@@ -649,13 +667,12 @@ __global__ __launch_bounds__(kW) void mpc_kernel(MpcArgs A) {
   }
   const double cost = wave::sum(cst);
   double pres = 0.0, pscale = 0.0, cres = 0.0, lmax = 0.0;
-  MPC_FOR_ROWS {
-    const double v = C.row_value(k, i, S.z + 9 * k), d = C.rhs(k, i);
+  C.for_rows([&](int r, double v, double, double d) {
     pres = fmax(pres, v - d);
     pscale = fmax(pscale, fmax(fabs(v), fabs(d)));
     cres = fmax(cres, S.lam[r] * fabs(d - v));
     lmax = fmax(lmax, S.lam[r]);
-  }
+  });
   pres = wave::max(pres); pscale = wave::max(pscale); cres = wave::max(cres); lmax = wave::max(lmax);
   const double kkt = fmax(fmax(fmax(pres, 0.0) / (1.0 + pscale), rdmax / (1.0 + gscale)), cres / (1.0 + lmax));
   const int64_t xo = (int64_t)inst * 6 * (N + 1);
@@ -676,7 +693,6 @@ __global__ __launch_bounds__(kW) void mpc_kernel(MpcArgs A) {
     A.status[inst] = (kkt <= 1e-6 && isfinite(cost)) ? kSolved : (converged ? kNumerical : kMaxIter);
     if (A.iters) A.iters[inst] = it;
   }
-#undef MPC_FOR_ROWS
 }
 
 }  // namespace
