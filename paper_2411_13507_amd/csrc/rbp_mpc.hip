@@ -127,9 +127,19 @@ struct MpcCtx {
   // component a of C_k' w for per-row weights w (rows of stage k at w[0..mr))
   __device__ double ct_times(int k, int a, const double* w) const {
     const double* c = S.prm + Ly.Cr + a * Ly.cs;
-    double t = 0.0;
-#pragma unroll 4
-    for (int i = 0; i < m; ++i) t += c[i] * w[i];
+    double t = 0.0, t1 = 0.0;
+    int i = 0;
+    for (; i + 4 <= m; i += 4) {         // loads of four rows issued together
+      double x[4], y[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) { x[q] = c[i + q]; y[q] = w[i + q]; }
+      t += x[0] * y[0];
+      t1 += x[1] * y[1];
+      t += x[2] * y[2];
+      t1 += x[3] * y[3];
+    }
+    for (; i < m; ++i) t += c[i] * w[i];
+    t += t1;
     const double* f = S.prm + Ly.pf + a / 3;
     const double tp = f[0] * w[m] + f[3] * w[m + 1] + f[6] * w[m + 2] + f[9] * w[m + 3];
     return t - S.pl[4 * k + a % 3] * tp;
@@ -150,11 +160,16 @@ struct MpcCtx {
     const double* cb = S.prm + Ly.Cr + b * Ly.cs;
     double v0 = Hk(k)[9 * a + b], v1 = 0.0;
     int i = 0;
-    for (; i + 1 < m; i += 2) {          // two independent chains
-      v0 += sg[i] * ca[i] * cb[i];
-      v1 += sg[i + 1] * ca[i + 1] * cb[i + 1];
+    for (; i + 4 <= m; i += 4) {         // loads of four rows issued together
+      double w[4], x[4], y[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) { w[q] = sg[i + q]; x[q] = ca[i + q]; y[q] = cb[i + q]; }
+      v0 += w[0] * x[0] * y[0];
+      v1 += w[1] * x[1] * y[1];
+      v0 += w[2] * x[2] * y[2];
+      v1 += w[3] * x[3] * y[3];
     }
-    if (i < m) v0 += sg[i] * ca[i] * cb[i];
+    for (; i < m; ++i) v0 += sg[i] * ca[i] * cb[i];
     const double* fa = S.prm + Ly.pf + a / 3;
     const double* fb = S.prm + Ly.pf + b / 3;
     const double tp = sg[m] * fa[0] * fb[0] + sg[m + 1] * fa[3] * fb[3] + sg[m + 2] * fa[6] * fb[6] +
