@@ -45,15 +45,13 @@ constexpr int kSolved = 0, kMaxIter = 2, kNumerical = 4, kInvalid = 5;
 // the LQ solve shares its storage with the direction it produces.
 struct MpcSm {
   double *prm, *z, *g, *dz, *ref, *pl, *s, *lam, *wv, *Lc, *Y, *yv, *rho, *P, *tmp;
+  // scratch of the factorisation, inside the gradient buffer (free while it runs)
+  double *Ht, *Qh, *HtT, *sig;
 };
 
-// stages whose barrier Hessians are formed in one parallel pass
-constexpr int kChunk = 4;
-// the gradient / direction buffer also holds the factorisation's scratch:
-// Qh (81), the weights of kChunk stages (36 each) and their Ht (45 each)
-__host__ __device__ inline int mpc_g_doubles(int N) {
-  return 9 * N > 81 + kChunk * (36 + 45) ? 9 * N : 81 + kChunk * (36 + 45);
-}
+// the gradient / direction buffer also holds the factorisation's scratch
+// (Ht 81, Qh 81, Ht T 54, two weight buffers 2 x 36)
+__host__ __device__ inline int mpc_g_doubles(int N) { return 9 * N > 288 ? 9 * N : 288; }
 
 __host__ __device__ inline int mpc_lds_doubles(int N, int m) {
   const MpcLayout L = mpc_param_layout(m);
@@ -70,6 +68,7 @@ __device__ inline MpcSm carve_mpc(double* base, int N, int m) {
   S.prm = p; p += L.total;
   S.z = p; p += 9 * N;
   S.g = p; S.dz = p;
+  S.Ht = p; S.Qh = p + 81; S.HtT = p + 162; S.sig = p + 216;
   p += mpc_g_doubles(N);
   S.ref = p; p += 6 * (N + 1);
   S.pl = p; p += 4 * N;
@@ -85,8 +84,10 @@ __device__ inline MpcSm carve_mpc(double* base, int N, int m) {
   return S;
 }
 
-// tmp layout: [0, 6) start state, [8] factorisation flag.  Barrier weights
-// of one stage's rows take kSigBuf >= mr doubles.
+// tmp layout: [0, 6) start state, [8] factorisation flag.  S.sig holds two
+// buffers of the barrier weights lam/s of one stage's rows (mr <= 36): the
+// factorisation of stage k reads one while stage k-1's are written into the
+// other
 constexpr int kTmpFlag = 8, kSigBuf = 36;
 
 // Column b of [A B] (6 x 9) has at most two non-zeros: row q0 with weight w0
@@ -153,74 +154,69 @@ struct MpcCtx {
     return -2.0 * v;
   }
 
-  // entry (a, b) of Ht_k = H_k + sum_i sigma_i c_i c_i', sigma of stage k's
-  // rows at sg[0..mr)
-  __device__ double ht_upper(int k, int a, int b, const double* sg) const {
-    const double* ca = S.prm + Ly.Cr + a * Ly.cs;
-    const double* cb = S.prm + Ly.Cr + b * Ly.cs;
-    double v0 = Hk(k)[9 * a + b], v1 = 0.0;
+  // barrier weights lam/s of stage k's rows (or zero) into buffer b, by
+  // lanes first .. first + mr - 1
+  __device__ void put_sigma(int k, bool with_rows, int b, int first) {
+    const int i = lane - first;
+    if (i >= 0 && i < mr) {
+      const int r = k * mr + i;
+      S.sig[kSigBuf * b + i] = with_rows ? div_nr(S.lam[r], S.s[r]) : 0.0;
+    }
+  }
+  // upper entry (ua, ub) of Ht_k = H_k + sum_i sigma_i c_i c_i' (weights in buffer b)
+  __device__ double ht_entry(int k, int b) const {
+    const double* sg = S.sig + kSigBuf * b;
+    const double* ca = S.prm + Ly.Cr + ua * Ly.cs;
+    const double* cb = S.prm + Ly.Cr + ub * Ly.cs;
+    double v = Hk(k)[9 * ua + ub], v1 = 0.0;
     int i = 0;
     for (; i + 4 <= m; i += 4) {         // loads of four rows issued together
       double w[4], x[4], y[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) { w[q] = sg[i + q]; x[q] = ca[i + q]; y[q] = cb[i + q]; }
-      v0 += w[0] * x[0] * y[0];
+      v += w[0] * x[0] * y[0];
       v1 += w[1] * x[1] * y[1];
-      v0 += w[2] * x[2] * y[2];
+      v += w[2] * x[2] * y[2];
       v1 += w[3] * x[3] * y[3];
     }
-    for (; i < m; ++i) v0 += sg[i] * ca[i] * cb[i];
-    const double* fa = S.prm + Ly.pf + a / 3;
-    const double* fb = S.prm + Ly.pf + b / 3;
+    for (; i < m; ++i) v += sg[i] * ca[i] * cb[i];
+    v += v1;
+    const double* fa = S.prm + Ly.pf + ua / 3;
+    const double* fb = S.prm + Ly.pf + ub / 3;
     const double tp = sg[m] * fa[0] * fb[0] + sg[m + 1] * fa[3] * fb[3] + sg[m + 2] * fa[6] * fb[6] +
                       sg[m + 3] * fa[9] * fb[9];
-    return v0 + v1 + S.pl[4 * k + a % 3] * S.pl[4 * k + b % 3] * tp;
-  }
-  // barrier weights lam/s (or zero) of the rows of stages k, k-1, ..., k-n+1
-  // into sg[36 j + i] (stage k - j, row i), all lanes
-  __device__ void put_sigmas(int k, int n, bool with_rows, double* sg) {
-    for (int e = lane; e < n * mr; e += kW) {
-      const int j = e / mr, i = e - mr * (e / mr);
-      const int r = (k - j) * mr + i;
-      sg[kSigBuf * j + i] = with_rows ? div_nr(S.lam[r], S.s[r]) : 0.0;
-    }
+    return v + S.pl[4 * k + ua % 3] * S.pl[4 * k + ub % 3] * tp;
   }
 
   // Riccati factorisation of the Newton LQ; with_rows = false uses H_k alone.
   // Returns false (uniformly) when a pivot of some Quu is not positive.
-  // Scratch (in the gradient buffer): Qh / Ht at +0, the barrier weights of
-  // up to kChunk stages at +81, their Ht upper triangles at +225.
   __device__ bool factor(bool with_rows) {
-    double* Qh = S.g;
-    double* sgc = S.g + 81;
-    double* htc = S.g + 81 + kChunk * kSigBuf;
     if (lane == 0) S.tmp[kTmpFlag] = 0.0;
     // terminal block: P = T2' Ht_{N-2} T2 + T1' Ht_{N-1} T1
-    double* Ht = S.g;
-    double* HtT = S.g + 81;
     for (int e = lane; e < 36; e += kW) S.P[e] = 0.0;
     for (int t = 0; t < 2; ++t) {
       const int k = N - 2 + t;
       const double* T = S.prm + (t == 0 ? Ly.T2 : Ly.T1);
-      put_sigmas(k, 1, with_rows, htc);
+      put_sigma(k, with_rows, 0, 0);
       __syncthreads();
       if (lane < 45) {
-        const double v = ht_upper(k, ua, ub, htc);
-        Ht[9 * ua + ub] = v;
-        Ht[9 * ub + ua] = v;
+        const double v = ht_entry(k, 0);
+        S.Ht[9 * ua + ub] = v;
+        S.Ht[9 * ub + ua] = v;
       }
       __syncthreads();
-      for (int e = lane; e < 54; e += kW) {      // Ht T (9 x 6)
+      // Ht T (9 x 6)
+      for (int e = lane; e < 54; e += kW) {
         const int a = e / 6, c = e - 6 * (e / 6);
         double v = 0.0;
-        for (int b = 0; b < 9; ++b) v += Ht[9 * a + b] * T[6 * b + c];
-        HtT[e] = v;
+        for (int b = 0; b < 9; ++b) v += S.Ht[9 * a + b] * T[6 * b + c];
+        S.HtT[e] = v;
       }
       __syncthreads();
       for (int e = lane; e < 36; e += kW) {
         const int c = e / 6, d = e - 6 * (e / 6);
         double v = 0.0;
-        for (int a = 0; a < 9; ++a) v += T[6 * a + c] * HtT[6 * a + d];
+        for (int a = 0; a < 9; ++a) v += T[6 * a + c] * S.HtT[6 * a + d];
         S.P[e] += v;
       }
       __syncthreads();
@@ -233,76 +229,69 @@ struct MpcCtx {
       }
     }
     __syncthreads();
-    for (int kc = N - 3; kc >= 0; kc -= kChunk) {
-      // barrier Hessians of a chunk of stages at once (they do not depend on P)
-      const int nk = kc + 1 < kChunk ? kc + 1 : kChunk;
-      put_sigmas(kc, nk, with_rows, sgc);
-      __syncthreads();
-      for (int e = lane; e < 45 * nk; e += kW) {
-        const int j = e / 45, q = e - 45 * (e / 45);
-        int a = 0, t = q;
-        while (t >= 9 - a) { t -= 9 - a; ++a; }
-        htc[e] = ht_upper(kc - j, a, a + t, sgc + kSigBuf * j);
+    int buf = 0;
+    if (N >= 3) put_sigma(N - 3, with_rows, 0, 0);
+    __syncthreads();
+    for (int k = N - 3; k >= 0; --k) {
+      // Qh = Ht + [A B]' P [A B] (symmetric: lanes own the upper triangle)
+      if (lane < 45) {
+        int qa0, qa1, qb0, qb1;
+        double wa0, wa1, wb0, wb1;
+        ab_col(ua, dt, qa0, wa0, qa1, wa1);
+        ab_col(ub, dt, qb0, wb0, qb1, wb1);
+        double v = wa0 * wb0 * S.P[6 * qa0 + qb0];
+        if (qb1 >= 0) v += wa0 * wb1 * S.P[6 * qa0 + qb1];
+        if (qa1 >= 0) {
+          v += wa1 * wb0 * S.P[6 * qa1 + qb0];
+          if (qb1 >= 0) v += wa1 * wb1 * S.P[6 * qa1 + qb1];
+        }
+        v += ht_entry(k, buf);
+        S.Qh[9 * ua + ub] = v;
+        S.Qh[9 * ub + ua] = v;
       }
       __syncthreads();
-      for (int j = 0; j < nk; ++j) {
-        const int k = kc - j;
-        // Qh = Ht + [A B]' P [A B] (symmetric: lanes own the upper triangle)
-        if (lane < 45) {
-          int qa0, qa1, qb0, qb1;
-          double wa0, wa1, wb0, wb1;
-          ab_col(ua, dt, qa0, wa0, qa1, wa1);
-          ab_col(ub, dt, qb0, wb0, qb1, wb1);
-          double v = wa0 * wb0 * S.P[6 * qa0 + qb0];
-          if (qb1 >= 0) v += wa0 * wb1 * S.P[6 * qa0 + qb1];
-          if (qa1 >= 0) {
-            v += wa1 * wb0 * S.P[6 * qa1 + qb0];
-            if (qb1 >= 0) v += wa1 * wb1 * S.P[6 * qa1 + qb1];
-          }
-          v += htc[45 * j + lane];
-          Qh[9 * ua + ub] = v;
-          Qh[9 * ub + ua] = v;
+      // Quu = L L' and the columns of Y = L^-1 Qux that entry (a, b) of the
+      // next cost-to-go P = Qxx - Y'Y needs, all in the lane of that entry
+      // (lanes < 21); lanes 0..5 (entries (0, c)) store column c of Y, lane 0
+      // stores L as (1/l00, l10, 1/l11, l20, l21, 1/l22).  Lanes 21.. write
+      // the barrier weights of stage k-1 meanwhile.
+      if (lane < 21) {
+        int a = 0, t = lane;
+        while (t >= 6 - a) { t -= 6 - a; ++a; }
+        const int b = a + t;
+        const double d0 = S.Qh[60];
+        const double i00 = rsqrt_nr(d0);
+        const double l10 = S.Qh[69] * i00, l20 = S.Qh[78] * i00;
+        const double d1 = S.Qh[70] - l10 * l10;
+        const double i11 = rsqrt_nr(d1);
+        const double l21 = (S.Qh[79] - l20 * l10) * i11;
+        const double d2 = S.Qh[80] - l20 * l20 - l21 * l21;
+        const double i22 = rsqrt_nr(d2);
+        const double ya0 = S.Qh[54 + a] * i00;
+        const double ya1 = (S.Qh[63 + a] - l10 * ya0) * i11;
+        const double ya2 = (S.Qh[72 + a] - l20 * ya0 - l21 * ya1) * i22;
+        const double yb0 = S.Qh[54 + b] * i00;
+        const double yb1 = (S.Qh[63 + b] - l10 * yb0) * i11;
+        const double yb2 = (S.Qh[72 + b] - l20 * yb0 - l21 * yb1) * i22;
+        if (lane < 6) {
+          double* Y = S.Y + 18 * k;
+          Y[b] = yb0; Y[6 + b] = yb1; Y[12 + b] = yb2;
         }
-        __syncthreads();
-        // Quu = L L' and the columns of Y = L^-1 Qux that entry (a, b) of the
-        // next cost-to-go P = Qxx - Y'Y needs, all in the lane of that entry
-        // (lanes < 21); lanes 0..5 (entries (0, c)) store column c of Y, lane 0
-        // stores L as (1/l00, l10, 1/l11, l20, l21, 1/l22).
-        if (lane < 21) {
-          int a = 0, t = lane;
-          while (t >= 6 - a) { t -= 6 - a; ++a; }
-          const int b = a + t;
-          const double d0 = Qh[60];
-          const double i00 = rsqrt_nr(d0);
-          const double l10 = Qh[69] * i00, l20 = Qh[78] * i00;
-          const double d1 = Qh[70] - l10 * l10;
-          const double i11 = rsqrt_nr(d1);
-          const double l21 = (Qh[79] - l20 * l10) * i11;
-          const double d2 = Qh[80] - l20 * l20 - l21 * l21;
-          const double i22 = rsqrt_nr(d2);
-          const double ya0 = Qh[54 + a] * i00;
-          const double ya1 = (Qh[63 + a] - l10 * ya0) * i11;
-          const double ya2 = (Qh[72 + a] - l20 * ya0 - l21 * ya1) * i22;
-          const double yb0 = Qh[54 + b] * i00;
-          const double yb1 = (Qh[63 + b] - l10 * yb0) * i11;
-          const double yb2 = (Qh[72 + b] - l20 * yb0 - l21 * yb1) * i22;
-          if (lane < 6) {
-            double* Y = S.Y + 18 * k;
-            Y[b] = yb0; Y[6 + b] = yb1; Y[12 + b] = yb2;
-          }
-          if (lane == 0) {
-            double* L = S.Lc + 6 * k;
-            L[0] = i00; L[1] = l10; L[2] = i11; L[3] = l20; L[4] = l21; L[5] = i22;
-            if (!(d0 > 0.0 && d1 > 0.0 && d2 > 0.0) || !isfinite(i00 * i11 * i22)) S.tmp[kTmpFlag] = 1.0;
-          }
-          if (k > 0) {
-            const double v = Qh[9 * a + b] - (ya0 * yb0 + ya1 * yb1 + ya2 * yb2);
-            S.P[6 * a + b] = v;
-            S.P[6 * b + a] = v;
-          }
+        if (lane == 0) {
+          double* L = S.Lc + 6 * k;
+          L[0] = i00; L[1] = l10; L[2] = i11; L[3] = l20; L[4] = l21; L[5] = i22;
+          if (!(d0 > 0.0 && d1 > 0.0 && d2 > 0.0) || !isfinite(i00 * i11 * i22)) S.tmp[kTmpFlag] = 1.0;
         }
-        __syncthreads();
+        if (k > 0) {
+          const double v = S.Qh[9 * a + b] - (ya0 * yb0 + ya1 * yb1 + ya2 * yb2);
+          S.P[6 * a + b] = v;
+          S.P[6 * b + a] = v;
+        }
+      } else if (k > 0) {
+        put_sigma(k - 1, with_rows, buf ^ 1, 21);
       }
+      __syncthreads();
+      buf ^= 1;
     }
     return S.tmp[kTmpFlag] == 0.0;
   }
