@@ -120,7 +120,7 @@ __device__ __forceinline__ double mcoef(int s, int k, int j) {
 }
 
 template <int P>
-__device__ void chain_instance(const ChainArgs& A, const int ch, char* smem) {
+__device__ __forceinline__ void chain_instance(const ChainArgs& A, const int ch, char* smem) {
   using L_t = CLds<P>;
   constexpr int NP = L_t::NP, NC = L_t::NC, BW = L_t::BW;
   const int lane = threadIdx.x;
