@@ -1,8 +1,9 @@
 """Register and scratch budget of the built kernels, from the compiler's
 resource-usage remarks that the build writes beside librbp.so.
 
-Per-lane scratch (private memory) is spill or dynamically indexed register
-arrays: it turns LDS-speed data into memory traffic.  The segment kernels of
+Per-lane scratch (private memory) is spill, a dynamically indexed register
+array or the frame of an out-of-line call: it turns register or LDS data into
+memory traffic.  The segment kernels of
 degree 3-8, the backward, graph-cut and graph-building and MPC kernels must
 have none, nor the path kernel; the degree-9 segment kernels are at the 256-VGPR
 limit and are allowed their (stated) spill."""
