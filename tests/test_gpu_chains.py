@@ -59,25 +59,36 @@ def compare_chains(b, out, idx, label):
     assert not mism
 
 
-def test_chain_subset(gpu_available):
+def _opts(admm):
+    if admm is None:
+        return None
+    from paper_2411_13507_amd import _lib
+    o = _lib.default_opts()
+    o.admm_iters = admm
+    return o
+
+
+@pytest.mark.parametrize("admm", [None, 0], ids=["default", "polish-only"])
+def test_chain_subset(gpu_available, admm):
     b = gen.gen_cfg3(indices=range(48))
-    print("case: 48 paths of 4-12 segments", flush=True)
-    _, out = gpu_chains(b)
+    print(f"case: 48 paths of 4-12 segments, admm_iters {admm}", flush=True)
+    _, out = gpu_chains(b, _opts(admm))
     compare_chains(b, out, list(range(b.n)), "paths48")
 
 
 POLISH_FAILED = 3
 
 
-def test_chain_full_size_sampled(gpu_available):
+@pytest.mark.parametrize("admm", [None, 0], ids=["default", "polish-only"])
+def test_chain_full_size_sampled(gpu_available, admm):
     """Every path ends SOLVED, certified INFEASIBLE or POLISH_FAILED (no
     verified answer).  The last happens only when the working set would need
     more than 63 rows (one per lane) before the dual method proves
     infeasibility: at most 1 % of paths, and the oracle must find each of them
     infeasible or uncertified — never a path it solves."""
     b = gen.gen_cfg3(8192)
-    print("case: 8192 paths", flush=True)
-    _, out = gpu_chains(b)
+    print(f"case: 8192 paths, admm_iters {admm}", flush=True)
+    _, out = gpu_chains(b, _opts(admm))
     st = out["status"]
     assert set(np.unique(st).tolist()) <= {qp.SOLVED, qp.INFEASIBLE, POLISH_FAILED}, np.bincount(st)
     assert np.all(out["kkt"][st == qp.SOLVED] <= KKT_TOL)
