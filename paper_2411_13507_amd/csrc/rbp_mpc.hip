@@ -39,25 +39,28 @@ namespace {
 constexpr int kW = 64;
 constexpr int kSolved = 0, kMaxIter = 2, kNumerical = 4, kInvalid = 5;
 
-// LDS carve, in doubles.  Per row only the slack, the multiplier and one
-// working value (the Newton weight w, then the affine product ds*dl) are
-// kept; residuals are recomputed from z where needed, and the gradient of
-// the LQ solve shares its storage with the direction it produces.
+// LDS carve, in doubles.  The per-row state (slack, multiplier, primal
+// residual, Newton weight) lives in registers of the lane that owns the row;
+// LDS holds one value per row, X, for the reads that cross lanes: the
+// multipliers (dual residual), the barrier weights lam/s (factorisation), the
+// Newton weights (gradient build), and meanwhile each row's c'dz for its own
+// lane.  The gradient of the LQ solve shares its storage with the direction
+// it produces.
 struct MpcSm {
-  double *prm, *z, *g, *dz, *ref, *pl, *s, *lam, *wv, *Lc, *Y, *yv, *rho, *P, *tmp;
+  double *prm, *z, *g, *dz, *ref, *pl, *X, *Lc, *Y, *yv, *rho, *P, *tmp;
   // scratch of the factorisation, inside the gradient buffer (free while it runs)
-  double *Ht, *Qh, *HtT, *sig;
+  double *Ht, *Qh, *HtT;
 };
 
 // the gradient / direction buffer also holds the factorisation's scratch
-// (Ht 81, Qh 81, Ht T 54, two weight buffers 2 x 36)
+// (Ht 81, Qh 81, Ht T 54)
 __host__ __device__ inline int mpc_g_doubles(int N) { return 9 * N > 288 ? 9 * N : 288; }
 
 __host__ __device__ inline int mpc_lds_doubles(int N, int m) {
   const MpcLayout L = mpc_param_layout(m);
   const int RT = N * (m + 4);
   return L.total + 9 * N /*z*/ + mpc_g_doubles(N) /*g = dz*/ + 6 * (N + 1) /*ref*/ + 4 * N /*pl*/ +
-         3 * RT /*s lam wv*/ + 6 * N /*Lc*/ + 18 * N /*Y*/ + 3 * N /*yv*/ + 3 * N /*rho*/ + 36 /*P*/ + 16 /*tmp*/;
+         RT /*X*/ + 6 * N /*Lc*/ + 18 * N /*Y*/ + 3 * N /*yv*/ + 3 * N /*rho*/ + 36 /*P*/ + 16 /*tmp*/;
 }
 
 __device__ inline MpcSm carve_mpc(double* base, int N, int m) {
@@ -68,13 +71,11 @@ __device__ inline MpcSm carve_mpc(double* base, int N, int m) {
   S.prm = p; p += L.total;
   S.z = p; p += 9 * N;
   S.g = p; S.dz = p;
-  S.Ht = p; S.Qh = p + 81; S.HtT = p + 162; S.sig = p + 216;
+  S.Ht = p; S.Qh = p + 81; S.HtT = p + 162;
   p += mpc_g_doubles(N);
   S.ref = p; p += 6 * (N + 1);
   S.pl = p; p += 4 * N;
-  S.s = p; p += RT;
-  S.lam = p; p += RT;
-  S.wv = p; p += RT;
+  S.X = p; p += RT;
   S.Lc = p; p += 6 * N;
   S.Y = p; p += 18 * N;
   S.yv = p; p += 3 * N;
@@ -84,11 +85,8 @@ __device__ inline MpcSm carve_mpc(double* base, int N, int m) {
   return S;
 }
 
-// tmp layout: [0, 6) start state, [8] factorisation flag.  S.sig holds two
-// buffers of the barrier weights lam/s of one stage's rows (mr <= 36): the
-// factorisation of stage k reads one while stage k-1's are written into the
-// other
-constexpr int kTmpFlag = 8, kSigBuf = 36;
+// tmp layout: [0, 6) start state, [8] factorisation flag
+constexpr int kTmpFlag = 8;
 
 // Column b of [A B] (6 x 9) has at most two non-zeros: row q0 with weight w0
 // and row q1 with weight w1 (q1 < 0: none).
@@ -126,7 +124,7 @@ struct MpcCtx {
   int ua, ub;          // upper-triangle entry (ua <= ub) of a 9 x 9 matrix owned by lanes < 45
 
   // component a of C_k' w for per-row weights w (rows of stage k at w[0..mr))
-  __device__ double ct_times(int k, int a, const double* w) const {
+  __device__ __forceinline__ double ct_times(int k, int a, const double* w) const {
     const double* c = S.prm + Ly.Cr + a * Ly.cs;
     double t = 0.0, t1 = 0.0;
     int i = 0;
@@ -145,27 +143,19 @@ struct MpcCtx {
     const double tp = f[0] * w[m] + f[3] * w[m + 1] + f[6] * w[m + 2] + f[9] * w[m + 3];
     return t - S.pl[4 * k + a % 3] * tp;
   }
-  __device__ const double* Hk(int k) const { return S.prm + (k == 0 ? Ly.H0 : Ly.H1); }
+  __device__ __forceinline__ const double* Hk(int k) const { return S.prm + (k == 0 ? Ly.H0 : Ly.H1); }
   // x-part of h_k: -2 Q r_k (k >= 1)
-  __device__ double hk(int k, int a) const {
+  __device__ __forceinline__ double hk(int k, int a) const {
     if (k == 0 || a >= 6) return 0.0;
     double v = 0.0;
     for (int b = 0; b < 6; ++b) v += S.prm[Ly.Qm + 6 * a + b] * S.ref[6 * k + b];
     return -2.0 * v;
   }
 
-  // barrier weights lam/s of stage k's rows (or zero) into buffer b, by
-  // lanes first .. first + mr - 1
-  __device__ void put_sigma(int k, bool with_rows, int b, int first) {
-    const int i = lane - first;
-    if (i >= 0 && i < mr) {
-      const int r = k * mr + i;
-      S.sig[kSigBuf * b + i] = with_rows ? div_nr(S.lam[r], S.s[r]) : 0.0;
-    }
-  }
-  // upper entry (ua, ub) of Ht_k = H_k + sum_i sigma_i c_i c_i' (weights in buffer b)
-  __device__ double ht_entry(int k, int b) const {
-    const double* sg = S.sig + kSigBuf * b;
+  // upper entry (ua, ub) of Ht_k = H_k + sum_i sigma_i c_i c_i', with the
+  // barrier weights sigma of stage k's rows in S.X
+  __device__ __forceinline__ double ht_entry(int k) const {
+    const double* sg = S.X + k * mr;
     const double* ca = S.prm + Ly.Cr + ua * Ly.cs;
     const double* cb = S.prm + Ly.Cr + ub * Ly.cs;
     double v = Hk(k)[9 * ua + ub], v1 = 0.0;
@@ -188,19 +178,18 @@ struct MpcCtx {
     return v + S.pl[4 * k + ua % 3] * S.pl[4 * k + ub % 3] * tp;
   }
 
-  // Riccati factorisation of the Newton LQ; with_rows = false uses H_k alone.
-  // Returns false (uniformly) when a pivot of some Quu is not positive.
-  __device__ bool factor(bool with_rows) {
+  // Riccati factorisation of the Newton LQ with the barrier weights in S.X
+  // (zero weights: H_k alone).  Returns false (uniformly) when a pivot of
+  // some Quu is not positive.
+  __device__ __forceinline__ bool factor() {
     if (lane == 0) S.tmp[kTmpFlag] = 0.0;
     // terminal block: P = T2' Ht_{N-2} T2 + T1' Ht_{N-1} T1
     for (int e = lane; e < 36; e += kW) S.P[e] = 0.0;
     for (int t = 0; t < 2; ++t) {
       const int k = N - 2 + t;
       const double* T = S.prm + (t == 0 ? Ly.T2 : Ly.T1);
-      put_sigma(k, with_rows, 0, 0);
-      __syncthreads();
       if (lane < 45) {
-        const double v = ht_entry(k, 0);
+        const double v = ht_entry(k);
         S.Ht[9 * ua + ub] = v;
         S.Ht[9 * ub + ua] = v;
       }
@@ -229,9 +218,6 @@ struct MpcCtx {
       }
     }
     __syncthreads();
-    int buf = 0;
-    if (N >= 3) put_sigma(N - 3, with_rows, 0, 0);
-    __syncthreads();
     for (int k = N - 3; k >= 0; --k) {
       // Qh = Ht + [A B]' P [A B] (symmetric: lanes own the upper triangle)
       if (lane < 45) {
@@ -245,7 +231,7 @@ struct MpcCtx {
           v += wa1 * wb0 * S.P[6 * qa1 + qb0];
           if (qb1 >= 0) v += wa1 * wb1 * S.P[6 * qa1 + qb1];
         }
-        v += ht_entry(k, buf);
+        v += ht_entry(k);
         S.Qh[9 * ua + ub] = v;
         S.Qh[9 * ub + ua] = v;
       }
@@ -253,8 +239,7 @@ struct MpcCtx {
       // Quu = L L' and the columns of Y = L^-1 Qux that entry (a, b) of the
       // next cost-to-go P = Qxx - Y'Y needs, all in the lane of that entry
       // (lanes < 21); lanes 0..5 (entries (0, c)) store column c of Y, lane 0
-      // stores L as (1/l00, l10, 1/l11, l20, l21, 1/l22).  Lanes 21.. write
-      // the barrier weights of stage k-1 meanwhile.
+      // stores L as (1/l00, l10, 1/l11, l20, l21, 1/l22).
       if (lane < 21) {
         int a = 0, t = lane;
         while (t >= 6 - a) { t -= 6 - a; ++a; }
@@ -287,11 +272,8 @@ struct MpcCtx {
           S.P[6 * a + b] = v;
           S.P[6 * b + a] = v;
         }
-      } else if (k > 0) {
-        put_sigma(k - 1, with_rows, buf ^ 1, 21);
       }
       __syncthreads();
-      buf ^= 1;
     }
     return S.tmp[kTmpFlag] == 0.0;
   }
@@ -299,7 +281,7 @@ struct MpcCtx {
   // Solve the factorised LQ for the gradients in S.g; the direction replaces
   // them (S.dz aliases S.g: the backward sweep reads every g_k before the
   // forward sweep writes dz_k).  Sequential over stages in lane 0.
-  __device__ void lq_solve() {
+  __device__ __forceinline__ void lq_solve() {
     if (lane == 0) {
       const double* T2 = S.prm + Ly.T2;
       const double* T1 = S.prm + Ly.T1;
@@ -311,9 +293,15 @@ struct MpcCtx {
       }
       const double h2 = 0.5 * dt * dt;
       for (int k = N - 3; k >= 0; --k) {
-        const double* gk = S.g + 9 * k;
-        const double* L = S.Lc + 6 * k;
-        const double* Y = S.Y + 18 * k;
+        // the stage's data, loaded before any of it is used: one LDS round
+        // trip per stage on the sequential path
+        double gk[9], L[6], Y[18];
+#pragma unroll
+        for (int e = 0; e < 9; ++e) gk[e] = S.g[9 * k + e];
+#pragma unroll
+        for (int e = 0; e < 6; ++e) L[e] = S.Lc[6 * k + e];
+#pragma unroll
+        for (int e = 0; e < 18; ++e) Y[e] = S.Y[18 * k + e];
         // qh = g + [A B]' p
         double qx[6], qu[3];
         for (int c = 0; c < 3; ++c) {
@@ -330,11 +318,16 @@ struct MpcCtx {
       // forward from dx_0 = 0: du = -L^-T (Y dx + y)
       double dx[6] = {0, 0, 0, 0, 0, 0};
       for (int k = 0; k <= N - 3; ++k) {
-        const double* L = S.Lc + 6 * k;
-        const double* Y = S.Y + 18 * k;
+        double L[6], Y[18], yk[3];
+#pragma unroll
+        for (int e = 0; e < 6; ++e) L[e] = S.Lc[6 * k + e];
+#pragma unroll
+        for (int e = 0; e < 18; ++e) Y[e] = S.Y[18 * k + e];
+#pragma unroll
+        for (int e = 0; e < 3; ++e) yk[e] = S.yv[3 * k + e];
         double r[3];
         for (int i = 0; i < 3; ++i) {
-          double v = S.yv[3 * k + i];
+          double v = yk[i];
           for (int c = 0; c < 6; ++c) v += Y[6 * i + c] * dx[c];
           r[i] = v;
         }
@@ -361,67 +354,83 @@ struct MpcCtx {
     __syncthreads();
   }
 
-  // visit every row: f(r, c'z_k, c'dz_k, d_r) -- the reachable rows (shared
-  // coefficient table), then the plane rows, so a wavefront never mixes the
-  // two kinds
-  template <typename F>
-  __device__ void for_rows(F&& f) const {
+  // visit every row: f(slot, r, c'z_k, c'dz_k, d_r) -- the reachable rows
+  // (shared coefficient table), then the plane rows, so a wavefront never
+  // mixes the two kinds.  Lane l owns reachable row t = l + 64 j in register
+  // slot j < RS and plane row l + 64 j in slot RS + j (j < 4): the loops are
+  // unrolled, so slot is a constant wherever f indexes a register array with
+  // it.  c'z and c'dz are formed only when CZ / CD ask for them.
+  template <int RS, bool CZ, bool CD, typename F>
+  __device__ __forceinline__ void for_rows(F&& f) const {
+    // the lane index is made opaque here, so the per-slot row indices and
+    // addresses are recomputed in every pass instead of being hoisted out of
+    // the iteration loop (where they would hold registers throughout)
+    int ln = lane;
+    asm volatile("" : "+v"(ln));
     if (m > 0) {
       const int rq = kW / m, rr = kW - rq * m;
-      int k = lane / m, i = lane - m * (lane / m);
-      for (int t = lane; t < N * m; t += kW) {
-        const double* c = S.prm + Ly.Cr + i;
-        const double* zk = S.z + 9 * k;
-        const double* dk = S.dz + 9 * k;
-        double cz = 0.0, cd = 0.0;
+      int k = ln / m, i = ln - m * (ln / m);
 #pragma unroll
-        for (int a = 0; a < 9; ++a) {
-          const double ca = c[a * Ly.cs];
-          cz += ca * zk[a];
-          cd += ca * dk[a];
+      for (int j = 0; j < RS; ++j) {
+        if (ln + kW * j < N * m) {
+          const double* c = S.prm + Ly.Cr + i;
+          const double* zk = S.z + 9 * k;
+          const double* dk = S.dz + 9 * k;
+          double cz = 0.0, cd = 0.0;
+#pragma unroll
+          for (int a = 0; a < 9; ++a) {
+            const double ca = c[a * Ly.cs];
+            if (CZ) cz += ca * zk[a];
+            if (CD) cd += ca * dk[a];
+          }
+          f(j, k * mr + i, cz, cd, S.prm[Ly.dr + i]);
         }
-        f(k * mr + i, cz, cd, S.prm[Ly.dr + i]);
         k += rq;
         i += rr;
         if (i >= m) { i -= m; ++k; }
       }
     }
-    for (int t = lane; t < 4 * N; t += kW) {
-      const int k = t >> 2, j = t & 3;
-      const double* f3 = S.prm + Ly.pf + 3 * j;
-      const double* n = S.pl + 4 * k;
-      const double* zk = S.z + 9 * k;
-      const double* dk = S.dz + 9 * k;
-      double cz = 0.0, cd = 0.0;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        cz += n[c] * (f3[0] * zk[c] + f3[1] * zk[3 + c] + f3[2] * zk[6 + c]);
-        cd += n[c] * (f3[0] * dk[c] + f3[1] * dk[3 + c] + f3[2] * dk[6 + c]);
+    for (int j = 0; j < 4; ++j) {
+      const int t = ln + kW * j;
+      if (t < 4 * N) {
+        const int k = t >> 2, jj = t & 3;
+        const double* f3 = S.prm + Ly.pf + 3 * jj;
+        const double* n = S.pl + 4 * k;
+        const double* zk = S.z + 9 * k;
+        const double* dk = S.dz + 9 * k;
+        double cz = 0.0, cd = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          if (CZ) cz += n[c] * (f3[0] * zk[c] + f3[1] * zk[3 + c] + f3[2] * zk[6 + c]);
+          if (CD) cd += n[c] * (f3[0] * dk[c] + f3[1] * dk[3 + c] + f3[2] * dk[6 + c]);
+        }
+        f(RS + j, k * mr + m + jj, -cz, -cd, -n[3] * f3[0]);
       }
-      f(k * mr + m + j, -cz, -cd, -n[3] * f3[0]);
     }
   }
 
-  // g_k = [0; rho_k] + C_k' w, with the per-row weights in S.wv
-  __device__ void build_g() {
+  // g_k = [0; rho_k] + C_k' w, with the per-row weights in S.X
+  __device__ __forceinline__ void build_g() {
     for (int e = lane; e < 9 * N; e += kW) {
       const int k = e / 9, a = e - 9 * (e / 9);
       const double v = a >= 6 ? S.rho[3 * k + a - 6] : 0.0;
-      S.g[e] = v + ct_times(k, a, S.wv + k * mr);
+      S.g[e] = v + ct_times(k, a, S.X + k * mr);
     }
     __syncthreads();
   }
 
   // least-squares costates and the u-stationarity residual rho_k (into
-  // S.rho); returns max |rho| and the scale of the gradient terms
-  __device__ void dual_residual(double& rmax, double& gscale) {
+  // S.rho), with the multipliers in S.X; returns max |rho| and the scale of
+  // the gradient terms
+  __device__ __forceinline__ void dual_residual(double& rmax, double& gscale) {
     double gs = 0.0;
     for (int e = lane; e < 9 * N; e += kW) {
       const int k = e / 9, a = e - 9 * (e / 9);
       const double* H = Hk(k);
       double hz = hk(k, a);
       for (int b = 0; b < 9; ++b) hz += H[9 * a + b] * S.z[9 * k + b];
-      const double ct = ct_times(k, a, S.lam + k * mr);
+      const double ct = ct_times(k, a, S.X + k * mr);
       S.g[e] = hz + ct;
       gs = fmax(gs, fmax(fabs(hz), fabs(ct)));
     }
@@ -488,6 +497,8 @@ struct MpcCtx {
   }
 };
 
+// RS: register slots per lane for the reachable rows (N m <= 64 RS)
+template <int RS>
 __global__ __launch_bounds__(kW) void mpc_kernel(MpcArgs A) {
   extern __shared__ __attribute__((aligned(16))) char smem_raw[];
   const int inst = blockIdx.x;
@@ -572,8 +583,9 @@ __global__ __launch_bounds__(kW) void mpc_kernel(MpcArgs A) {
       z1[6 + c] = uu[3 + c];
     }
   }
+  for (int e = lane; e < RT; e += kW) S.X[e] = 0.0;     // no rows yet
   __syncthreads();
-  C.factor(false);
+  C.factor();
   // g = H z + h
   for (int e = lane; e < 9 * N; e += kW) {
     const int k = e / 9, a = e - 9 * (e / 9);
@@ -586,10 +598,15 @@ __global__ __launch_bounds__(kW) void mpc_kernel(MpcArgs A) {
   C.lq_solve();
   for (int e = lane; e < 9 * N; e += kW) S.z[e] += S.dz[e];
   __syncthreads();
-  // slacks and multipliers
-  C.for_rows([&](int r, double cz, double, double d) {
-    S.s[r] = fmax(d - cz, 1.0);
-    S.lam[r] = 1.0;
+  // slacks and multipliers; per row, in registers of the owning lane: slack
+  // s, multiplier l and primal residual rp = c'z + s - d
+  constexpr int NS = RS + 4;
+  double rs[NS], rl[NS], rp[NS];
+#pragma unroll
+  for (int j = 0; j < NS; ++j) { rs[j] = 1.0; rl[j] = 1.0; rp[j] = 0.0; }
+  C.template for_rows<RS, true, false>([&](int j, int r, double cz, double, double d) {
+    rs[j] = fmax(d - cz, 1.0);
+    S.X[r] = 1.0;
   });
   __syncthreads();
 
@@ -598,73 +615,76 @@ __global__ __launch_bounds__(kW) void mpc_kernel(MpcArgs A) {
   bool converged = false;
   double mu = 0.0, rpmax = 0.0, rdmax = 0.0, gscale = 0.0;
   for (;; ++it) {
+    C.dual_residual(rdmax, gscale);             // multipliers in S.X
     double smu = 0.0, rpm = 0.0;
-    C.for_rows([&](int r, double cz, double, double d) {
-      rpm = fmax(rpm, fabs(cz + S.s[r] - d));
-      smu += S.s[r] * S.lam[r];
+    C.template for_rows<RS, true, false>([&](int j, int r, double cz, double, double d) {
+      const double v = cz + rs[j] - d;
+      rp[j] = v;
+      rpm = fmax(rpm, fabs(v));
+      smu += rs[j] * rl[j];
+      S.X[r] = div_nr(rl[j], rs[j]);            // barrier weight for the factorisation
     });
+    __syncthreads();
     mu = wave::sum(smu) / RT;
     rpmax = wave::max(rpm);
-    C.dual_residual(rdmax, gscale);
     if (mu <= A.tol && rpmax <= 1e-10 && rdmax <= 1e-8 * (1.0 + gscale)) { converged = true; break; }
     if (it >= A.max_iters || !isfinite(mu)) break;
-    if (!C.factor(true)) break;                 // a Quu lost definiteness: keep the current iterate
-    // predictor: w = (lam / s) rp - lam, rp = c'z + s - d
-    C.for_rows([&](int r, double cz, double, double d) {
-      S.wv[r] = div_nr(S.lam[r], S.s[r]) * (cz + S.s[r] - d) - S.lam[r];
+    if (!C.factor()) break;                     // a Quu lost definiteness: keep the current iterate
+    // predictor: w = (l / s) rp - l
+    C.template for_rows<RS, false, false>([&](int j, int r, double, double, double) {
+      S.X[r] = div_nr(rl[j], rs[j]) * rp[j] - rl[j];
     });
     __syncthreads();
     C.build_g();
     C.lq_solve();
-    // affine step: ds = -rp - c'dz, dl = -lam - (lam / s) ds
+    // affine step: ds = -rp - c'dz, dl = -l - (l / s) ds; c'dz kept in S.X
     double amax_l = 1.0;
-    C.for_rows([&](int r, double cz, double cd, double d) {
-      const double ds = -(cz + S.s[r] - d) - cd;
-      const double dl = -S.lam[r] - div_nr(S.lam[r], S.s[r]) * ds;
-      if (ds < 0.0) amax_l = fmin(amax_l, div_nr(S.s[r], -ds));
-      if (dl < 0.0) amax_l = fmin(amax_l, div_nr(S.lam[r], -dl));
+    C.template for_rows<RS, false, true>([&](int j, int r, double, double cd, double) {
+      const double ds = -rp[j] - cd;
+      const double dl = -rl[j] - div_nr(rl[j], rs[j]) * ds;
+      if (ds < 0.0) amax_l = fmin(amax_l, div_nr(rs[j], -ds));
+      if (dl < 0.0) amax_l = fmin(amax_l, div_nr(rl[j], -dl));
+      S.X[r] = cd;
     });
     const double aa = wave::min(amax_l);
     double mua = 0.0;
-    C.for_rows([&](int r, double cz, double cd, double d) {
-      const double ds = -(cz + S.s[r] - d) - cd;
-      const double dl = -S.lam[r] - div_nr(S.lam[r], S.s[r]) * ds;
-      mua += (S.s[r] + aa * ds) * (S.lam[r] + aa * dl);
-      S.wv[r] = ds * dl;                          // affine product for the corrector
+    C.template for_rows<RS, false, false>([&](int j, int r, double, double, double) {
+      const double ds = -rp[j] - S.X[r];
+      const double dl = -rl[j] - div_nr(rl[j], rs[j]) * ds;
+      mua += (rs[j] + aa * ds) * (rl[j] + aa * dl);
+      S.X[r] = ds * dl;                         // affine product for the corrector
     });
     mua = wave::sum(mua) / RT;
     const double sc = (mua / mu) * (mua / mu) * (mua / mu);
     const double smu_t = sc * mu;
-    __syncthreads();
-    // corrector: rc = s lam + ds_aff dl_aff - sc mu, w = (lam rp - rc) / s
-    C.for_rows([&](int r, double cz, double, double d) {
-      const double rc = S.s[r] * S.lam[r] + S.wv[r] - smu_t;
-      S.wv[r] = div_nr(S.lam[r] * (cz + S.s[r] - d) - rc, S.s[r]);
+    // corrector: rc = s l + ds_aff dl_aff - sc mu, w = (l rp - rc) / s
+    C.template for_rows<RS, false, false>([&](int j, int r, double, double, double) {
+      const double rc = rs[j] * rl[j] + S.X[r] - smu_t;
+      S.X[r] = div_nr(rl[j] * rp[j] - rc, rs[j]);
     });
     __syncthreads();
     C.build_g();
     C.lq_solve();
-    // step: ds = -rp - c'dz, dl = (-rc - lam ds) / s with rc = lam rp - s w
+    // step: ds = -rp - c'dz, dl = (-rc - l ds) / s with rc = l rp - s w (w in S.X)
     double am = 1.0;
-    C.for_rows([&](int r, double cz, double cd, double d) {
-      const double rp = cz + S.s[r] - d;
-      const double ds = -rp - cd;
-      const double rc = S.lam[r] * rp - S.s[r] * S.wv[r];
-      const double dl = div_nr(-rc - S.lam[r] * ds, S.s[r]);
-      if (ds < 0.0) am = fmin(am, div_nr(S.s[r], -ds));
-      if (dl < 0.0) am = fmin(am, div_nr(S.lam[r], -dl));
+    C.template for_rows<RS, false, true>([&](int j, int r, double, double cd, double) {
+      const double ds = -rp[j] - cd;
+      const double rc = rl[j] * rp[j] - rs[j] * S.X[r];
+      const double dl = div_nr(-rc - rl[j] * ds, rs[j]);
+      if (ds < 0.0) am = fmin(am, div_nr(rs[j], -ds));
+      if (dl < 0.0) am = fmin(am, div_nr(rl[j], -dl));
     });
     const double alpha = fmin(1.0, 0.995 * wave::min(am));
     bool nonfinite = !(alpha > 0.0) || !isfinite(alpha);
     for (int e = lane; e < 9 * N; e += kW) nonfinite |= !isfinite(S.dz[e]);
     if (__ballot(nonfinite) != 0ull) break;     // a broken direction: keep the current iterate
-    C.for_rows([&](int r, double cz, double cd, double d) {
-      const double rp = cz + S.s[r] - d;
-      const double ds = -rp - cd;
-      const double rc = S.lam[r] * rp - S.s[r] * S.wv[r];
-      const double dl = div_nr(-rc - S.lam[r] * ds, S.s[r]);
-      S.s[r] += alpha * ds;
-      S.lam[r] += alpha * dl;
+    C.template for_rows<RS, false, true>([&](int j, int r, double, double cd, double) {
+      const double ds = -rp[j] - cd;
+      const double rc = rl[j] * rp[j] - rs[j] * S.X[r];
+      const double dl = div_nr(-rc - rl[j] * ds, rs[j]);
+      rs[j] += alpha * ds;
+      rl[j] += alpha * dl;
+      S.X[r] = rl[j];
     });
     __syncthreads();
     for (int e = lane; e < 9 * N; e += kW) S.z[e] += alpha * S.dz[e];
@@ -687,11 +707,11 @@ __global__ __launch_bounds__(kW) void mpc_kernel(MpcArgs A) {
   }
   const double cost = wave::sum(cst);
   double pres = 0.0, pscale = 0.0, cres = 0.0, lmax = 0.0;
-  C.for_rows([&](int r, double v, double, double d) {
+  C.template for_rows<RS, true, false>([&](int j, int, double v, double, double d) {
     pres = fmax(pres, v - d);
     pscale = fmax(pscale, fmax(fabs(v), fabs(d)));
-    cres = fmax(cres, S.lam[r] * fabs(d - v));
-    lmax = fmax(lmax, S.lam[r]);
+    cres = fmax(cres, rl[j] * fabs(d - v));
+    lmax = fmax(lmax, rl[j]);
   });
   pres = wave::max(pres); pscale = wave::max(pscale); cres = wave::max(cres); lmax = wave::max(lmax);
   const double kkt = fmax(fmax(fmax(pres, 0.0) / (1.0 + pscale), rdmax / (1.0 + gscale)), cres / (1.0 + lmax));
@@ -722,7 +742,16 @@ size_t mpc_lds_bytes(int N, int m) { return sizeof(double) * size_t(mpc_lds_doub
 hipError_t launch_mpc(const MpcArgs& a, hipStream_t s) {
   if (a.n <= 0) return hipSuccess;
   const size_t lds = mpc_lds_bytes(a.N, a.m);
-  hipLaunchKernelGGL(mpc_kernel, dim3(a.n), dim3(kW), lds, s, a);
+  // register slots for the reachable rows; the plane rows (4 N <= 256) take
+  // four more
+  const int rows = a.N * a.m;
+  if (a.N < 2 || a.N > 64 || a.m < 0 || rows > 32 * kW) return hipErrorInvalidValue;
+  if (rows <= 8 * kW)
+    hipLaunchKernelGGL(mpc_kernel<8>, dim3(a.n), dim3(kW), lds, s, a);
+  else if (rows <= 16 * kW)
+    hipLaunchKernelGGL(mpc_kernel<16>, dim3(a.n), dim3(kW), lds, s, a);
+  else
+    hipLaunchKernelGGL(mpc_kernel<32>, dim3(a.n), dim3(kW), lds, s, a);
   return hipGetLastError();
 }
 
