@@ -364,6 +364,10 @@ int ensure_chain_constants(int device) {
 // 127 rows).  The dual method keeps linearly independent normals, so a path
 // with n free variables never holds more than n; the polish stops when q
 // reaches the capacity minus one, hence n + 2 for short paths.
+// working-set rows of the first path pass: at 12 segments of degree 7 its LDS
+// (about 50 KB) leaves three paths resident per CU, against one at the full cap
+constexpr int kChainFirstPassRows = 32;
+
 int chain_q_cap(int p, int s_max) {
   const int n = 3 * ((p - 1) + (s_max - 1) * (p - 2));
   return std::min(128, n + 2);
@@ -485,10 +489,23 @@ int rbp_solve_chains(rbp_chains* c, const double* x0, const double* goal, const 
   a.admm_iters = o.admm_iters; a.rho = o.rho; a.alpha = o.alpha; a.max_steps = o.max_polish_steps;
   a.feas_tol = o.feas_tol; a.kkt_tol = o.kkt_tol;
   for (const rbp_chains::Group& g : c->groups) {
-    a.dims = rbp::make_chain_dims(d.degree, g.s_max, g.nf_max, g.r_max, chain_q_cap(d.degree, g.s_max));
+    // a first pass with a small working-set cap keeps LDS per path low (more
+    // paths resident per CU); the few paths whose working set outgrows it are
+    // solved again by a full-cap pass, which skips every other path
+    const int q_full = chain_q_cap(d.degree, g.s_max);
+    const int q_first = std::min(q_full, kChainFirstPassRows);
+    const bool admm = o.admm_iters > 0;
     a.inst_base = g.start;
     a.N = g.start + g.count;
+    a.q_full = q_full;
+    a.retry_only = 0;
+    a.dims = rbp::make_chain_dims(d.degree, g.s_max, g.nf_max, g.r_max, q_first, admm);
     if (rbp::launch_chains(a, stream) != hipSuccess) return RBP_E_DEVICE;
+    if (q_first < q_full) {
+      a.retry_only = 1;
+      a.dims = rbp::make_chain_dims(d.degree, g.s_max, g.nf_max, g.r_max, q_full, admm);
+      if (rbp::launch_chains(a, stream) != hipSuccess) return RBP_E_DEVICE;
+    }
   }
   c->last_stream = stream;
   return RBP_OK;

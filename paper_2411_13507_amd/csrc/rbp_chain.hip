@@ -38,6 +38,9 @@ namespace {
 
 constexpr int kWave = 64;
 constexpr int kSolved = 0, kInfeasible = 1, kPolishFailed = 3, kNumerical = 4, kInvalid = 5;
+// internal: the working set outgrew a reduced-cap pass; the full-cap pass
+// that follows solves the path again and overwrites every output
+constexpr int kRetry = 6;
 constexpr float kBigF = 1e30f;
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
@@ -364,28 +367,43 @@ __device__ __forceinline__ void chain_instance(const ChainArgs& A, const int ch,
   // backward half-solve writes L^-T y; reciprocal diagonal in L1r
   for (int i = lane; i < NF; i += kWave) L.L1r[i] = 1.0 / L.L1b[i * (P + 1)];
   __syncthreads();
+  // Banded forward / backward solves, one lane per free point.  The band
+  // coefficient a lane needs at the next point and that point's reciprocal
+  // pivot are loaded one point ahead (they do not depend on the solution),
+  // so each point costs the broadcast and one multiply-add on the sequential
+  // path; lanes outside the band use a zero coefficient.
   auto gfwd = [&](const double* rhs, double& y0, double& y1, double& y2) {
     y0 = 0; y1 = 0; y2 = 0;
     if (lane < NF) { y0 = rhs[3 * lane]; y1 = rhs[3 * lane + 1]; y2 = rhs[3 * lane + 2]; }
+    auto band = [&](int i) -> double {      // L[lane][i] below the diagonal, else 0
+      const int d = lane - i;
+      return (d > 0 && d <= P && lane < NF) ? L.L1b[lane * (P + 1) + d] : 0.0;
+    };
+    double dinv = NF > 0 ? L.L1r[0] : 0.0, l = band(0);
     for (int i = 0; i < NF; ++i) {
-      const double dinv = L.L1r[i];
+      const double dinv_n = i + 1 < NF ? L.L1r[i + 1] : 0.0;
+      const double l_n = band(i + 1);
       const double a0 = wave::bcast(y0, i) * dinv, a1 = wave::bcast(y1, i) * dinv, a2 = wave::bcast(y2, i) * dinv;
       if (lane == i) { y0 = a0; y1 = a1; y2 = a2; }
-      else if (lane > i && lane <= i + P && lane < NF) {
-        const double l = L.L1b[lane * (P + 1) + (lane - i)];
-        y0 -= l * a0; y1 -= l * a1; y2 -= l * a2;
-      }
+      else { y0 -= l * a0; y1 -= l * a1; y2 -= l * a2; }
+      dinv = dinv_n;
+      l = l_n;
     }
   };
   auto gbwd = [&](double y0, double y1, double y2, double* out) {
+    auto band = [&](int i) -> double {      // L[i][lane] for lanes in the band above i, else 0
+      const int d = i - lane;
+      return (d > 0 && d <= P && i >= 0) ? L.L1b[i * (P + 1) + d] : 0.0;
+    };
+    double dinv = NF > 0 ? L.L1r[NF - 1] : 0.0, l = band(NF - 1);
     for (int i = NF - 1; i >= 0; --i) {
-      const double dinv = L.L1r[i];
+      const double dinv_n = i > 0 ? L.L1r[i - 1] : 0.0;
+      const double l_n = band(i - 1);
       const double a0 = wave::bcast(y0, i) * dinv, a1 = wave::bcast(y1, i) * dinv, a2 = wave::bcast(y2, i) * dinv;
       if (lane == i) { y0 = a0; y1 = a1; y2 = a2; }
-      else if (lane < i && lane >= i - P) {
-        const double l = L.L1b[i * (P + 1) + (i - lane)];
-        y0 -= l * a0; y1 -= l * a1; y2 -= l * a2;
-      }
+      else { y0 -= l * a0; y1 -= l * a1; y2 -= l * a2; }
+      dinv = dinv_n;
+      l = l_n;
     }
     if (lane < NF) { out[3 * lane] = y0; out[3 * lane + 1] = y1; out[3 * lane + 2] = y2; }
     __syncthreads();
@@ -960,6 +978,7 @@ __device__ __forceinline__ void chain_instance(const ChainArgs& A, const int ch,
     }
     wave::argmax(best, key);
     if (!(best > 0.0)) { status = kSolved; break; }
+    if (q >= QC - 1 && QC < A.q_full) { status = kRetry; break; }
     if (steps >= max_steps || key < 0 || (key >> 1) >= m || q >= QC - 1) { status = kPolishFailed; break; }
     const int id = key >> 1, side = (key & 1) ? 1 : -1;
     const int sp = seg_of(id);
@@ -1129,12 +1148,13 @@ __global__ __launch_bounds__(64) void chain_kernel(ChainArgs A) {
   const int b = blockIdx.x + A.inst_base;
   if (b >= A.N) return;
   const int ch = A.order ? A.order[b] : b;
+  if (A.retry_only && A.status_out[ch] != kRetry) return;
   chain_instance<P>(A, ch, smem);
 }
 
 }  // namespace
 
-ChainDims make_chain_dims(int p, int s_cap, int nf_cap, int r_cap, int q_cap) {
+ChainDims make_chain_dims(int p, int s_cap, int nf_cap, int r_cap, int q_cap, bool admm) {
   ChainDims d{};
   d.s_cap = s_cap < 1 ? 1 : s_cap;
   d.nf_cap = nf_cap < 1 ? 1 : nf_cap;
@@ -1167,6 +1187,9 @@ ChainDims make_chain_dims(int p, int s_cap, int nf_cap, int r_cap, int q_cap) {
   const int region = o;
   int a = region;
   auto take_a = [&](int bytes) { const int at = a; a += (bytes + 15) & ~15; return at; };
+  // the window Hessians are built during set-up whether or not ADMM runs
+  d.o_Wm = take_a(2 * NP * NP * 8);
+  const int setup_end = a;
   d.o_Kb = take_a(d.n_cap * (BW + 1) * 4);
   d.o_zr = take_a(d.m_cap * 4);
   d.o_yr = take_a(d.m_cap * 4);
@@ -1174,7 +1197,6 @@ ChainDims make_chain_dims(int p, int s_cap, int nf_cap, int r_cap, int q_cap) {
   d.o_Pf = take_a(d.s_cap * NC * 4);
   d.o_xt = take_a(d.n_cap * 4);
   d.o_Cs = take_a(NC * NC * 4);
-  d.o_Wm = take_a(2 * NP * NP * 8);
   int b = region;
   auto take_b = [&](int bytes) { const int at = b; b += (bytes + 15) & ~15; return at; };
   d.o_LS = take_b(((d.q_cap * (d.q_cap + 3)) >> 1) * 8);   // packed rows, k + 2 slots each
@@ -1184,6 +1206,8 @@ ChainDims make_chain_dims(int p, int s_cap, int nf_cap, int r_cap, int q_cap) {
   d.o_u = take_b(4 * d.n_cap * 8);
   d.o_cvec = take_b(d.q_cap * 8);
   d.o_actid = take_b(3 * d.q_cap * 4);
+  // polish only: nothing of the ADMM part but the window Hessians is used
+  if (!admm) a = setup_end;
   d.bytes = a > b ? a : b;
   return d;
 }

@@ -149,6 +149,8 @@ struct ChainArgs {
   int max_steps;
   double feas_tol, kkt_tol;
   ChainDims dims;
+  int q_full;       // working-set cap of the full pass; a smaller dims.q_cap marks overflows for retry
+  int retry_only;   // solve only the paths a reduced-cap pass marked for retry
 };
 
 // ---- cutting graph edges against box obstacles (rbp_cut.hip)
@@ -230,7 +232,7 @@ hipError_t launch_mpc(const MpcArgs& a, hipStream_t s);
 
 // admm = false: no room for the ADMM iteration (polish only)
 LdsDims make_dims(int pmax, int r_cap, int nf_cap, int real_bytes, bool admm);
-ChainDims make_chain_dims(int p, int s_cap, int nf_cap, int r_cap, int q_cap);
+ChainDims make_chain_dims(int p, int s_cap, int nf_cap, int r_cap, int q_cap, bool admm);
 hipError_t upload_chain_constants(int device);
 hipError_t launch_chains(const ChainArgs& a, hipStream_t s);
 hipError_t upload_constants(int device);
