@@ -368,42 +368,71 @@ __device__ __forceinline__ void chain_instance(const ChainArgs& A, const int ch,
   for (int i = lane; i < NF; i += kWave) L.L1r[i] = 1.0 / L.L1b[i * (P + 1)];
   __syncthreads();
   // Banded forward / backward solves, one lane per free point.  The band
-  // coefficient a lane needs at the next point and that point's reciprocal
-  // pivot are loaded one point ahead (they do not depend on the solution),
-  // so each point costs the broadcast and one multiply-add on the sequential
-  // path; lanes outside the band use a zero coefficient.
+  // coefficient a lane needs at a point and that point's reciprocal pivot do
+  // not depend on the solution: they are loaded two points ahead (the loop
+  // handles two points per pass), from addresses clamped into the factor, and
+  // lanes outside the band multiply theirs by zero (the clamped entries are
+  // finite), so no load waits behind a branch.
   auto gfwd = [&](const double* rhs, double& y0, double& y1, double& y2) {
     y0 = 0; y1 = 0; y2 = 0;
     if (lane < NF) { y0 = rhs[3 * lane]; y1 = rhs[3 * lane + 1]; y2 = rhs[3 * lane + 2]; }
-    auto band = [&](int i) -> double {      // L[lane][i] below the diagonal, else 0
-      const int d = lane - i;
-      return (d > 0 && d <= P && lane < NF) ? L.L1b[lane * (P + 1) + d] : 0.0;
+    const int jj = lane < NF ? lane : NF - 1;
+    auto fetch = [&](int i, double& dinv, double& l) {      // L[lane][i] below the diagonal, else 0
+      const int ic = i < NF ? i : NF - 1;
+      const int d = lane - i, dc = d < 0 ? 0 : (d > P ? P : d);
+      dinv = L.L1r[ic];
+      l = L.L1b[jj * (P + 1) + dc] * ((d > 0 && d <= P && lane < NF) ? 1.0 : 0.0);
     };
-    double dinv = NF > 0 ? L.L1r[0] : 0.0, l = band(0);
-    for (int i = 0; i < NF; ++i) {
-      const double dinv_n = i + 1 < NF ? L.L1r[i + 1] : 0.0;
-      const double l_n = band(i + 1);
+    auto step = [&](int i, double dinv, double l) {
       const double a0 = wave::bcast(y0, i) * dinv, a1 = wave::bcast(y1, i) * dinv, a2 = wave::bcast(y2, i) * dinv;
-      if (lane == i) { y0 = a0; y1 = a1; y2 = a2; }
-      else { y0 -= l * a0; y1 -= l * a1; y2 -= l * a2; }
-      dinv = dinv_n;
-      l = l_n;
+      const bool piv = lane == i;
+      y0 = piv ? a0 : y0 - l * a0;
+      y1 = piv ? a1 : y1 - l * a1;
+      y2 = piv ? a2 : y2 - l * a2;
+    };
+    if (NF <= 0) return;
+    double dA, lA, dB, lB;
+    fetch(0, dA, lA);
+    fetch(1, dB, lB);
+    int i = 0;
+    for (; i + 1 < NF; i += 2) {
+      double dC, lC, dD, lD;
+      fetch(i + 2, dC, lC);
+      fetch(i + 3, dD, lD);
+      step(i, dA, lA);
+      step(i + 1, dB, lB);
+      dA = dC; lA = lC; dB = dD; lB = lD;
     }
+    if (i < NF) step(i, dA, lA);
   };
   auto gbwd = [&](double y0, double y1, double y2, double* out) {
-    auto band = [&](int i) -> double {      // L[i][lane] for lanes in the band above i, else 0
-      const int d = i - lane;
-      return (d > 0 && d <= P && i >= 0) ? L.L1b[i * (P + 1) + d] : 0.0;
+    auto fetch = [&](int i, double& dinv, double& l) {      // L[i][lane] above i in the band, else 0
+      const int ic = i < 0 ? 0 : i;
+      const int d = i - lane, dc = d < 0 ? 0 : (d > P ? P : d);
+      dinv = L.L1r[ic];
+      l = L.L1b[ic * (P + 1) + dc] * ((d > 0 && d <= P && i >= 0) ? 1.0 : 0.0);
     };
-    double dinv = NF > 0 ? L.L1r[NF - 1] : 0.0, l = band(NF - 1);
-    for (int i = NF - 1; i >= 0; --i) {
-      const double dinv_n = i > 0 ? L.L1r[i - 1] : 0.0;
-      const double l_n = band(i - 1);
+    auto step = [&](int i, double dinv, double l) {
       const double a0 = wave::bcast(y0, i) * dinv, a1 = wave::bcast(y1, i) * dinv, a2 = wave::bcast(y2, i) * dinv;
-      if (lane == i) { y0 = a0; y1 = a1; y2 = a2; }
-      else { y0 -= l * a0; y1 -= l * a1; y2 -= l * a2; }
-      dinv = dinv_n;
-      l = l_n;
+      const bool piv = lane == i;
+      y0 = piv ? a0 : y0 - l * a0;
+      y1 = piv ? a1 : y1 - l * a1;
+      y2 = piv ? a2 : y2 - l * a2;
+    };
+    if (NF > 0) {
+      double dA, lA, dB, lB;
+      fetch(NF - 1, dA, lA);
+      fetch(NF - 2, dB, lB);
+      int i = NF - 1;
+      for (; i - 1 >= 0; i -= 2) {
+        double dC, lC, dD, lD;
+        fetch(i - 2, dC, lC);
+        fetch(i - 3, dD, lD);
+        step(i, dA, lA);
+        step(i - 1, dB, lB);
+        dA = dC; lA = lC; dB = dD; lB = lD;
+      }
+      if (i >= 0) step(i, dA, lA);
     }
     if (lane < NF) { out[3 * lane] = y0; out[3 * lane + 1] = y1; out[3 * lane + 2] = y2; }
     __syncthreads();
