@@ -991,18 +991,32 @@ __device__ __forceinline__ void chain_instance(const ChainArgs& A, const int ch,
     build_points(L.x);
     double best = -1.0;
     int key = 0x7fffffff;
+    auto consider = [&](int s, int loc, int id) {
+      if ((L.actbits[id >> 5] >> (id & 31)) & 1u) return;
+      double lo, hi;
+      row_bounds(s, loc, lo, hi);
+      const double v = row_value(s, loc, L.Pseg + s * NC);
+      const double d = row_scale(s, loc);
+      const double vu = v - hi, vl = lo - v;
+      if (vu > ftol * (1.0 + fabs(hi)) && vu * d > best) { best = vu * d; key = 2 * id + 1; }
+      if (isfinite(lo) && vl > ftol * (1.0 + fabs(lo)) && vl * d > best) { best = vl * d; key = 2 * id; }
+    };
+    // the rows held in LDS (faces, velocity, acceleration) segment by
+    // segment, then the reachable rows, whose coefficients come from global
+    // memory, two segments per pass: the two kinds never share a pass, and
+    // two segments' reachable rows (<= 64 together) cost one global round trip
     for (int s = 0; s < S; ++s) {
-      const int ms = L.rowoff[s + 1] - L.rowoff[s], ro = L.rowoff[s];
-      for (int loc = lane; loc < ms; loc += kWave) {
-        const int id = ro + loc;
-        if ((L.actbits[id >> 5] >> (id & 31)) & 1u) continue;
-        double lo, hi;
-        row_bounds(s, loc, lo, hi);
-        const double v = row_value(s, loc, L.Pseg + s * NC);
-        const double d = row_scale(s, loc);
-        const double vu = v - hi, vl = lo - v;
-        if (vu > ftol * (1.0 + fabs(hi)) && vu * d > best) { best = vu * d; key = 2 * id + 1; }
-        if (isfinite(lo) && vl > ftol * (1.0 + fabs(lo)) && vl * d > best) { best = vl * d; key = 2 * id; }
+      const int nl = NP * L.nf[s] + 6 * P - 3;
+      for (int loc = lane; loc < nl; loc += kWave) consider(s, loc, L.rowoff[s] + loc);
+    }
+    for (int s = 0; s < S; s += 2) {
+      const int nl0 = NP * L.nf[s] + 6 * P - 3, r0n = L.rowoff[s + 1] - L.rowoff[s] - nl0;
+      int nl1 = 0, r1n = 0;
+      if (s + 1 < S) { nl1 = NP * L.nf[s + 1] + 6 * P - 3; r1n = L.rowoff[s + 2] - L.rowoff[s + 1] - nl1; }
+      for (int u = lane; u < r0n + r1n; u += kWave) {
+        const int sp = u < r0n ? s : s + 1;
+        const int loc = u < r0n ? nl0 + u : nl1 + (u - r0n);
+        consider(sp, loc, L.rowoff[sp] + loc);
       }
     }
     wave::argmax(best, key);
