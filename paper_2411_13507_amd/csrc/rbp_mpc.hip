@@ -282,39 +282,38 @@ struct MpcCtx {
   // them (S.dz aliases S.g: the backward sweep reads every g_k before the
   // forward sweep writes dz_k).  Sequential over stages in lane 0.
   __device__ __forceinline__ void lq_solve() {
-    if (lane == 0) {
-      const double* T2 = S.prm + Ly.T2;
-      const double* T1 = S.prm + Ly.T1;
-      double p[6];
-      for (int c = 0; c < 6; ++c) {
-        double v = 0.0;
-        for (int a = 0; a < 9; ++a) v += T2[6 * a + c] * S.g[9 * (N - 2) + a] + T1[6 * a + c] * S.g[9 * (N - 1) + a];
-        p[c] = v;
-      }
-      const double h2 = 0.5 * dt * dt;
+    const double* T2 = S.prm + Ly.T2;
+    const double* T1 = S.prm + Ly.T1;
+    const double h2 = 0.5 * dt * dt;
+    // backward sweep, one costate component per lane: lane c < 6 holds p_c;
+    // the u-part of [A B]'p needs p_{c+3} and the x-part p_{c-3}, both a DPP
+    // row shift by three lanes away, and y = L^-1 qu takes qu from lanes 0..2
+    {
+      const int c = lane < 6 ? lane : 5;
+      const int cu = lane < 3 ? lane : 2;
+      double pc = 0.0;
+      for (int a = 0; a < 9; ++a) pc += T2[6 * a + c] * S.g[9 * (N - 2) + a] + T1[6 * a + c] * S.g[9 * (N - 1) + a];
       for (int k = N - 3; k >= 0; --k) {
-        // the stage's data, loaded before any of it is used: one LDS round
-        // trip per stage on the sequential path
-        double gk[9], L[6], Y[18];
-#pragma unroll
-        for (int e = 0; e < 9; ++e) gk[e] = S.g[9 * k + e];
+        const double gx = S.g[9 * k + c], gu = S.g[9 * k + 6 + cu];
+        const double Y0 = S.Y[18 * k + c], Y1 = S.Y[18 * k + 6 + c], Y2 = S.Y[18 * k + 12 + c];
+        double L[6];
 #pragma unroll
         for (int e = 0; e < 6; ++e) L[e] = S.Lc[6 * k + e];
-#pragma unroll
-        for (int e = 0; e < 18; ++e) Y[e] = S.Y[18 * k + e];
+        const double p_up = wave::dpp_f64<0x103>(pc);     // p_{c+3}
+        const double p_dn = wave::dpp_f64<0x113>(pc);     // p_{c-3}
         // qh = g + [A B]' p
-        double qx[6], qu[3];
-        for (int c = 0; c < 3; ++c) {
-          qx[c] = gk[c] + p[c];
-          qx[3 + c] = gk[3 + c] + dt * p[c] + p[3 + c];
-          qu[c] = gk[6 + c] + h2 * p[c] + dt * p[3 + c];
-        }
-        const double y0 = qu[0] * L[0];
-        const double y1 = (qu[1] - L[1] * y0) * L[2];
-        const double y2 = (qu[2] - L[3] * y0 - L[4] * y1) * L[5];
-        S.yv[3 * k] = y0; S.yv[3 * k + 1] = y1; S.yv[3 * k + 2] = y2;
-        for (int c = 0; c < 6; ++c) p[c] = qx[c] - (Y[c] * y0 + Y[6 + c] * y1 + Y[12 + c] * y2);
+        const double qx = lane < 3 ? gx + pc : gx + dt * p_dn + pc;
+        const double qu = gu + h2 * pc + dt * p_up;
+        const double qu0 = wave::bcast(qu, 0), qu1 = wave::bcast(qu, 1), qu2 = wave::bcast(qu, 2);
+        const double y0 = qu0 * L[0];
+        const double y1 = (qu1 - L[1] * y0) * L[2];
+        const double y2 = (qu2 - L[3] * y0 - L[4] * y1) * L[5];
+        if (lane < 3) S.yv[3 * k + lane] = lane == 0 ? y0 : (lane == 1 ? y1 : y2);
+        pc = qx - (Y0 * y0 + Y1 * y1 + Y2 * y2);
       }
+    }
+    __syncthreads();
+    if (lane == 0) {
       // forward from dx_0 = 0: du = -L^-T (Y dx + y)
       double dx[6] = {0, 0, 0, 0, 0, 0};
       for (int k = 0; k <= N - 3; ++k) {
