@@ -160,14 +160,15 @@ struct MpcCtx {
     const double* cb = S.prm + Ly.Cr + ub * Ly.cs;
     double v = Hk(k)[9 * ua + ub], v1 = 0.0;
     int i = 0;
-    for (; i + 4 <= m; i += 4) {         // loads of four rows issued together
-      double w[4], x[4], y[4];
+    for (; i + 8 <= m; i += 8) {         // loads of eight rows issued together
+      double w[8], x[8], y[8];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) { w[q] = sg[i + q]; x[q] = ca[i + q]; y[q] = cb[i + q]; }
-      v += w[0] * x[0] * y[0];
-      v1 += w[1] * x[1] * y[1];
-      v += w[2] * x[2] * y[2];
-      v1 += w[3] * x[3] * y[3];
+      for (int q = 0; q < 8; ++q) { w[q] = sg[i + q]; x[q] = ca[i + q]; y[q] = cb[i + q]; }
+#pragma unroll
+      for (int q = 0; q < 8; q += 2) {
+        v += w[q] * x[q] * y[q];
+        v1 += w[q + 1] * x[q + 1] * y[q + 1];
+      }
     }
     for (; i < m; ++i) v += sg[i] * ca[i] * cb[i];
     v += v1;
