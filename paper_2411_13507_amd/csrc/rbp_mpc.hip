@@ -128,14 +128,15 @@ struct MpcCtx {
     const double* c = S.prm + Ly.Cr + a * Ly.cs;
     double t = 0.0, t1 = 0.0;
     int i = 0;
-    for (; i + 4 <= m; i += 4) {         // loads of four rows issued together
-      double x[4], y[4];
+    for (; i + 8 <= m; i += 8) {         // loads of eight rows issued together
+      double x[8], y[8];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) { x[q] = c[i + q]; y[q] = w[i + q]; }
-      t += x[0] * y[0];
-      t1 += x[1] * y[1];
-      t += x[2] * y[2];
-      t1 += x[3] * y[3];
+      for (int q = 0; q < 8; ++q) { x[q] = c[i + q]; y[q] = w[i + q]; }
+#pragma unroll
+      for (int q = 0; q < 8; q += 2) {
+        t += x[q] * y[q];
+        t1 += x[q + 1] * y[q + 1];
+      }
     }
     for (; i < m; ++i) t += c[i] * w[i];
     t += t1;
