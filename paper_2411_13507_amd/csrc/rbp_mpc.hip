@@ -437,20 +437,38 @@ struct MpcCtx {
     }
     gscale = wave::max(gs);
     __syncthreads();
-    // backward: f_k = e_k + B' sig_{k+1};  sig_k = c_k + A' sig_{k+1} (k >= 1)
-    if (lane == 0) {
-      double sg[6] = {0, 0, 0, 0, 0, 0};
+    // backward: f_k = e_k + B' sig_{k+1};  sig_k = c_k + A' sig_{k+1} (k >= 1).
+    // The axes do not mix: lane c < 3 carries (sig_p,c, sig_v,c), with each
+    // stage's three gradient entries loaded two stages ahead
+    if (lane < 3) {
+      const int c = lane;
       const double h2 = 0.5 * dt * dt;
-      for (int k = N - 1; k >= 0; --k) {
-        const double* gk = S.g + 9 * k;
-        for (int c = 0; c < 3; ++c) S.rho[3 * k + c] = gk[6 + c] + h2 * sg[c] + dt * sg[3 + c];
-        if (k >= 1)
-          for (int c = 0; c < 3; ++c) {
-            const double sp = gk[c] + sg[c];
-            sg[3 + c] = gk[3 + c] + dt * sg[c] + sg[3 + c];
-            sg[c] = sp;
-          }
+      double sp_ = 0.0, sv_ = 0.0;
+      auto fetch = [&](int k, double& gp, double& gv, double& gu) {
+        const int kc = k < 0 ? 0 : k;
+        gp = S.g[9 * kc + c]; gv = S.g[9 * kc + 3 + c]; gu = S.g[9 * kc + 6 + c];
+      };
+      auto stage = [&](int k, double gp, double gv, double gu) {
+        S.rho[3 * k + c] = gu + h2 * sp_ + dt * sv_;
+        if (k >= 1) {
+          const double sp = gp + sp_;
+          sv_ = gv + dt * sp_ + sv_;
+          sp_ = sp;
+        }
+      };
+      double pA, vA, uA, pB, vB, uB;
+      fetch(N - 1, pA, vA, uA);
+      fetch(N - 2, pB, vB, uB);
+      int k = N - 1;
+      for (; k - 1 >= 0; k -= 2) {
+        double pC, vC, uC, pD, vD, uD;
+        fetch(k - 2, pC, vC, uC);
+        fetch(k - 3, pD, vD, uD);
+        stage(k, pA, vA, uA);
+        stage(k - 1, pB, vB, uB);
+        pA = pC; vA = vC; uA = uC; pB = pD; vB = vD; uB = uD;
       }
+      if (k >= 0) stage(k, pA, vA, uA);
     }
     __syncthreads();
     // rho_k,c = f_k,c + al_k pi_p,c + dt pi_v,c, al_k = dt^2 (N - k - 1/2);
