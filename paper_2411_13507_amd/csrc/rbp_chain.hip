@@ -804,24 +804,65 @@ __device__ __forceinline__ void chain_instance(const ChainArgs& A, const int ch,
     c0 = e0 < q ? ndot(e0, L.u) : 0.0;
     c1 = e1 < q ? ndot(e1, L.u) : 0.0;
   };
-  // forward / backward solves with L_S on the first qq entries
+  // forward / backward solves with L_S on the first qq entries.  The factor
+  // entries a lane needs at step k and the reciprocal pivot do not depend on
+  // the solution: they are loaded two steps ahead, from addresses clamped to
+  // entries the factor holds (finite), and lanes that do not take part
+  // multiply theirs by zero, so no load waits behind a branch.
   auto ls_forward = [&](double& v0, double& v1, int qq) {
-    for (int k = 0; k < qq; ++k) {
-      const double vk = pick(v0, v1, k) * L.LSd[k];
-      if (e0 == k) v0 = vk;
-      else if (e0 > k && e0 < qq) v0 -= L.LS[lso(e0) + k] * vk;
-      if (e1 == k) v1 = vk;
-      else if (e1 > k && e1 < qq) v1 -= L.LS[lso(e1) + k] * vk;
+    if (qq <= 0) return;
+    const int a0 = e0 < qq ? e0 : qq - 1, a1 = e1 < qq ? e1 : qq - 1;
+    auto fetch = [&](int k, double& d, double& l0, double& l1) {   // L_S[e][k] below the diagonal
+      const int kc = k < qq ? k : qq - 1;
+      d = L.LSd[kc];
+      l0 = L.LS[lso(a0) + (kc < a0 ? kc : a0)] * ((e0 > k && e0 < qq) ? 1.0 : 0.0);
+      l1 = L.LS[lso(a1) + (kc < a1 ? kc : a1)] * ((e1 > k && e1 < qq) ? 1.0 : 0.0);
+    };
+    auto step = [&](int k, double d, double l0, double l1) {
+      const double vk = pick(v0, v1, k) * d;
+      v0 = e0 == k ? vk : v0 - l0 * vk;
+      v1 = e1 == k ? vk : v1 - l1 * vk;
+    };
+    double dA, xA, yA, dB, xB, yB;
+    fetch(0, dA, xA, yA);
+    fetch(1, dB, xB, yB);
+    int k = 0;
+    for (; k + 1 < qq; k += 2) {
+      double dC, xC, yC, dD, xD, yD;
+      fetch(k + 2, dC, xC, yC);
+      fetch(k + 3, dD, xD, yD);
+      step(k, dA, xA, yA);
+      step(k + 1, dB, xB, yB);
+      dA = dC; xA = xC; yA = yC; dB = dD; xB = xD; yB = yD;
     }
+    if (k < qq) step(k, dA, xA, yA);
   };
   auto ls_backward = [&](double& v0, double& v1, int qq) {
-    for (int k = qq - 1; k >= 0; --k) {
-      const double vk = pick(v0, v1, k) * L.LSd[k];
-      if (e0 == k) v0 = vk;
-      else if (e0 < k) v0 -= L.LS[lso(k) + e0] * vk;
-      if (e1 == k) v1 = vk;
-      else if (e1 < k) v1 -= L.LS[lso(k) + e1] * vk;
+    if (qq <= 0) return;
+    auto fetch = [&](int k, double& d, double& l0, double& l1) {   // L_S[k][e] left of the diagonal
+      const int kc = k < 0 ? 0 : k;
+      d = L.LSd[kc];
+      l0 = L.LS[lso(kc) + (e0 < kc ? e0 : kc)] * (e0 < k ? 1.0 : 0.0);
+      l1 = L.LS[lso(kc) + (e1 < kc ? e1 : kc)] * (e1 < k ? 1.0 : 0.0);
+    };
+    auto step = [&](int k, double d, double l0, double l1) {
+      const double vk = pick(v0, v1, k) * d;
+      v0 = e0 == k ? vk : v0 - l0 * vk;
+      v1 = e1 == k ? vk : v1 - l1 * vk;
+    };
+    double dA, xA, yA, dB, xB, yB;
+    fetch(qq - 1, dA, xA, yA);
+    fetch(qq - 2, dB, xB, yB);
+    int k = qq - 1;
+    for (; k - 1 >= 0; k -= 2) {
+      double dC, xC, yC, dD, xD, yD;
+      fetch(k - 2, dC, xC, yC);
+      fetch(k - 3, dD, xD, yD);
+      step(k, dA, xA, yA);
+      step(k - 1, dB, xB, yB);
+      dA = dC; xA = xC; yA = yC; dB = dD; xB = xD; yB = yD;
     }
+    if (k >= 0) step(k, dA, xA, yA);
   };
   // w = N r (global), r given by entries (r0, r1)
   auto n_times = [&](double r0, double r1, double* out) {
