@@ -139,3 +139,41 @@ def test_chain_admm_iteration_counts(gpu_available):
         assert np.nanmax(np.abs(outs[k]["P"] - outs[10]["P"])) <= 1e-8
     print("mean polish steps by ADMM iterations", {k: float(v["iters"][:, 1].mean()) for k, v in outs.items()})
     compare_chains(b, outs[0], list(range(b.n)), "paths-polish-only")
+
+
+def test_chain_graph_capture_replays(gpu_available):
+    """Both launches of the path solve -- the reduced-cap pass and the
+    full-cap pass that re-solves the paths marked for retry, reading the
+    statuses the first wrote -- replay from one captured graph with the eager
+    results, replay after replay."""
+    from paper_2411_13507_amd import _lib
+    from paper_2411_13507_amd.api import ChainBatchGPU
+    b = gen.gen_cfg3(indices=range(256))
+    print("case: 256 paths, graph capture of the polish-only solve", flush=True)
+    cb = ChainBatchGPU(b)
+    d = cb.device
+    x0, goal = torch.as_tensor(b.x0, device=d), torch.as_tensor(b.goal, device=d)
+    o = _lib.default_opts()
+    o.admm_iters = 0
+    ref = cb.solve(x0, goal, opts=o)
+    torch.cuda.synchronize()
+    want = [t.clone() for t in (ref.P, ref.cost, ref.status, ref.kkt)]
+    assert int((want[2] == 0).sum()) > 0
+    out = cb.solve(x0, goal, opts=o)
+    side = torch.cuda.Stream(device=d)
+    side.wait_stream(torch.cuda.current_stream(d))
+    with torch.cuda.stream(side):
+        cb.solve(x0, goal, opts=o, out=out)
+    torch.cuda.current_stream(d).wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        cb.solve(x0, goal, opts=o, out=out)
+    for rep in range(3):
+        out.P.fill_(7.0)
+        out.status.fill_(-1)
+        graph.replay()
+        torch.cuda.synchronize()
+        for a, w in zip((out.P, out.cost, out.status, out.kkt), want):
+            assert torch.equal(a, w) or torch.allclose(a, w, rtol=0.0, atol=0.0, equal_nan=True), rep
+        cb.solve(x0, goal, opts=o)
+        torch.cuda.synchronize()
