@@ -242,12 +242,17 @@ int rbp_build_chains(const rbp_chain_desc* desc, hipStream_t stream, rbp_chains*
 int rbp_chains_get_sizes(const rbp_chains* chains, rbp_batch_sizes* out);
 
 /*
- * Forward pass over all paths: FP32 ADMM warm start with a banded KKT matrix
- * in LDS, FP64 dual active-set polish with banded Cholesky solves.
+ * Forward pass over all paths: FP32 ADMM warm start (admm_iters > 0) with a
+ * banded KKT matrix in LDS, FP64 dual active-set polish with banded Cholesky
+ * solves.  Two launches on the stream: every path first runs with a small
+ * working set; the few whose working set outgrows it are solved again by a
+ * second launch at the full size, which also rewrites their outputs (until
+ * it has run, status_out may hold an internal value).
  *   x0 [N][6], goal [N][3]; opts as for rbp_solve_batch (plain and
  *   store_for_backward are ignored);
  *   P_out [3 points_total]: the control points of every segment (NaN unless
- *   SOLVED); cost_out, status_out, kkt_out [N]; iters_out [N][2] or NULL.
+ *   SOLVED); cost_out, status_out, kkt_out [N]; iters_out [N][2] or NULL
+ *   (ADMM iterations, polish steps).
  * Errors: RBP_E_INVALID, RBP_E_DEVICE.
  */
 int rbp_solve_chains(rbp_chains* chains, const double* x0, const double* goal, const rbp_solve_opts* opts,
