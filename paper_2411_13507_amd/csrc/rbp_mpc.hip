@@ -159,7 +159,16 @@ struct MpcCtx {
     const double* sg = S.X + k * mr;
     const double* ca = S.prm + Ly.Cr + ua * Ly.cs;
     const double* cb = S.prm + Ly.Cr + ub * Ly.cs;
-    double v = Hk(k)[9 * ua + ub], v1 = 0.0;
+    // the operands outside the row loop are loaded first, so they are in
+    // flight together with the first rows
+    const double* fa = S.prm + Ly.pf + ua / 3;
+    const double* fb = S.prm + Ly.pf + ub / 3;
+    const double hv = Hk(k)[9 * ua + ub];
+    const double s0 = sg[m], s1 = sg[m + 1], s2 = sg[m + 2], s3 = sg[m + 3];
+    const double fa0 = fa[0], fa3 = fa[3], fa6 = fa[6], fa9 = fa[9];
+    const double fb0 = fb[0], fb3 = fb[3], fb6 = fb[6], fb9 = fb[9];
+    const double pla = S.pl[4 * k + ua % 3], plb = S.pl[4 * k + ub % 3];
+    double v = hv, v1 = 0.0;
     int i = 0;
     for (; i + 8 <= m; i += 8) {         // loads of eight rows issued together
       double w[8], x[8], y[8];
@@ -173,11 +182,8 @@ struct MpcCtx {
     }
     for (; i < m; ++i) v += sg[i] * ca[i] * cb[i];
     v += v1;
-    const double* fa = S.prm + Ly.pf + ua / 3;
-    const double* fb = S.prm + Ly.pf + ub / 3;
-    const double tp = sg[m] * fa[0] * fb[0] + sg[m + 1] * fa[3] * fb[3] + sg[m + 2] * fa[6] * fb[6] +
-                      sg[m + 3] * fa[9] * fb[9];
-    return v + S.pl[4 * k + ua % 3] * S.pl[4 * k + ub % 3] * tp;
+    const double tp = s0 * fa0 * fb0 + s1 * fa3 * fb3 + s2 * fa6 * fb6 + s3 * fa9 * fb9;
+    return v + pla * plb * tp;
   }
 
   // Riccati factorisation of the Newton LQ with the barrier weights in S.X
@@ -227,12 +233,15 @@ struct MpcCtx {
         double wa0, wa1, wb0, wb1;
         ab_col(ua, dt, qa0, wa0, qa1, wa1);
         ab_col(ub, dt, qb0, wb0, qb1, wb1);
-        double v = wa0 * wb0 * S.P[6 * qa0 + qb0];
-        if (qb1 >= 0) v += wa0 * wb1 * S.P[6 * qa0 + qb1];
-        if (qa1 >= 0) {
-          v += wa1 * wb0 * S.P[6 * qa1 + qb0];
-          if (qb1 >= 0) v += wa1 * wb1 * S.P[6 * qa1 + qb1];
-        }
+        // absent second terms have weight 0 (ab_col): their loads use a
+        // valid entry instead of a branch, so all four are issued together
+        const int qa1c = qa1 >= 0 ? qa1 : qa0, qb1c = qb1 >= 0 ? qb1 : qb0;
+        const double p00 = S.P[6 * qa0 + qb0], p01 = S.P[6 * qa0 + qb1c];
+        const double p10 = S.P[6 * qa1c + qb0], p11 = S.P[6 * qa1c + qb1c];
+        double v = wa0 * wb0 * p00;
+        v += wa0 * wb1 * p01;
+        v += wa1 * wb0 * p10;
+        v += wa1 * wb1 * p11;
         v += ht_entry(k);
         S.Qh[9 * ua + ub] = v;
         S.Qh[9 * ub + ua] = v;
