@@ -255,20 +255,26 @@ struct MpcCtx {
         int a = 0, t = lane;
         while (t >= 6 - a) { t -= 6 - a; ++a; }
         const int b = a + t;
-        const double d0 = S.Qh[60];
+        // every entry this lane reads, loaded before the pivot chain starts
+        const double q60 = S.Qh[60], q69 = S.Qh[69], q78 = S.Qh[78], q70 = S.Qh[70], q79 = S.Qh[79],
+                     q80 = S.Qh[80];
+        const double qa0 = S.Qh[54 + a], qa1 = S.Qh[63 + a], qa2 = S.Qh[72 + a];
+        const double qb0 = S.Qh[54 + b], qb1 = S.Qh[63 + b], qb2 = S.Qh[72 + b];
+        const double qab = S.Qh[9 * a + b];
+        const double d0 = q60;
         const double i00 = rsqrt_nr(d0);
-        const double l10 = S.Qh[69] * i00, l20 = S.Qh[78] * i00;
-        const double d1 = S.Qh[70] - l10 * l10;
+        const double l10 = q69 * i00, l20 = q78 * i00;
+        const double d1 = q70 - l10 * l10;
         const double i11 = rsqrt_nr(d1);
-        const double l21 = (S.Qh[79] - l20 * l10) * i11;
-        const double d2 = S.Qh[80] - l20 * l20 - l21 * l21;
+        const double l21 = (q79 - l20 * l10) * i11;
+        const double d2 = q80 - l20 * l20 - l21 * l21;
         const double i22 = rsqrt_nr(d2);
-        const double ya0 = S.Qh[54 + a] * i00;
-        const double ya1 = (S.Qh[63 + a] - l10 * ya0) * i11;
-        const double ya2 = (S.Qh[72 + a] - l20 * ya0 - l21 * ya1) * i22;
-        const double yb0 = S.Qh[54 + b] * i00;
-        const double yb1 = (S.Qh[63 + b] - l10 * yb0) * i11;
-        const double yb2 = (S.Qh[72 + b] - l20 * yb0 - l21 * yb1) * i22;
+        const double ya0 = qa0 * i00;
+        const double ya1 = (qa1 - l10 * ya0) * i11;
+        const double ya2 = (qa2 - l20 * ya0 - l21 * ya1) * i22;
+        const double yb0 = qb0 * i00;
+        const double yb1 = (qb1 - l10 * yb0) * i11;
+        const double yb2 = (qb2 - l20 * yb0 - l21 * yb1) * i22;
         if (lane < 6) {
           double* Y = S.Y + 18 * k;
           Y[b] = yb0; Y[6 + b] = yb1; Y[12 + b] = yb2;
@@ -279,7 +285,7 @@ struct MpcCtx {
           if (!(d0 > 0.0 && d1 > 0.0 && d2 > 0.0) || !isfinite(i00 * i11 * i22)) S.tmp[kTmpFlag] = 1.0;
         }
         if (k > 0) {
-          const double v = S.Qh[9 * a + b] - (ya0 * yb0 + ya1 * yb1 + ya2 * yb2);
+          const double v = qab - (ya0 * yb0 + ya1 * yb1 + ya2 * yb2);
           S.P[6 * a + b] = v;
           S.P[6 * b + a] = v;
         }
