@@ -37,6 +37,7 @@ from dataclasses import dataclass
 from typing import Optional
 
 import numpy as np
+from scipy.optimize import linprog
 
 from . import qp as _qp
 
@@ -153,21 +154,65 @@ class MpcResult:
     W: Optional[list] = None
 
 
-def y_bound(inst: dict) -> float:
-    """|y|_inf bound over the feasible set when the reachable rows hold a
-    velocity box |v_{k+1}| <= vmax and an input box |v_{k+1} - v_k| <= amax dt
-    (as in the generated workloads): positions move at most N dt vmax from
-    the start, and u = (v_{k+1} - v_k)/dt."""
-    G, dt, N = np.asarray(inst["G"]), float(inst["dt"]), int(inst["N"])
-    vmax = max(float(np.max(G)), float(np.max(np.abs(inst["x0"][3:]))))
-    amax = float(np.max(G)) / dt
-    return float(np.max(np.abs(inst["x0"][:3])) + (N + 1) * dt * vmax + vmax + amax + 2.0)
+def feasible_box(inst: dict):
+    """An outer box of every feasible point, from the instance's own rows.
+
+    Relaxation: keep x_0 = x0, the dynamics and the reachable rows
+    F1 x_k + F2 x_{k+1} <= G; drop the plane rows and the terminal state.
+    Forward propagation over the steps: if x_k lies in the box B_k, then
+    (x_k, u_k) satisfies (F1 + F2 A) x_k + F2 B u_k <= G, so u_k and
+    x_{k+1} = A x_k + B u_k lie within the bounds of small LPs over
+    (x_k, u_k) in B_k x R^3 with those rows (one LP per bound), and B_{k+1}
+    is the box of x_{k+1}.  By induction every feasible y is in the boxes.
+    Each LP bound is widened by 1e-7 (1 + |bound|) against the LP's own
+    tolerances.  Returns (lo, hi) over y = [x_0..x_N, u_0..u_{N-1}, 1], or
+    None when some bound is infinite (the rows leave the set unbounded)."""
+    N, dt = int(inst["N"]), float(inst["dt"])
+    F1, F2, G = np.asarray(inst["F1"], float), np.asarray(inst["F2"], float), np.asarray(inst["G"], float)
+    Ad, Bd = dynamics(dt)
+    x0 = np.asarray(inst["x0"], float)
+    nx = 6 * (N + 1)
+    lo = np.zeros(nx + 3 * N + 1)
+    hi = np.zeros_like(lo)
+    lo[:6] = hi[:6] = x0
+    lo[-1] = hi[-1] = 1.0
+    # stage rows over z = (x_k, u_k)
+    Az = np.hstack([F1 + F2 @ Ad, F2 @ Bd])
+    # objectives: u_k (3) and x_{k+1} = [A B] z (6)
+    obj = np.vstack([np.hstack([np.zeros((3, 6)), np.eye(3)]), np.hstack([Ad, Bd])])
+    xl, xh = x0.copy(), x0.copy()
+    for k in range(N):
+        bounds = [(float(a), float(b)) for a, b in zip(xl, xh)] + [(None, None)] * 3
+        vlo, vhi = np.zeros(9), np.zeros(9)
+        for j in range(9):
+            for sgn in (1.0, -1.0):
+                res = linprog(sgn * obj[j], A_ub=Az if Az.size else None, b_ub=G if Az.size else None,
+                              bounds=bounds, method="highs")
+                if res.status != 0:
+                    return None
+                v = sgn * float(res.fun)
+                pad = 1e-7 * (1.0 + abs(v))
+                if sgn > 0:
+                    vlo[j] = v - pad
+                else:
+                    vhi[j] = v + pad
+        lo[nx + 3 * k:nx + 3 * k + 3], hi[nx + 3 * k:nx + 3 * k + 3] = vlo[:3], vhi[:3]
+        xl, xh = vlo[3:], vhi[3:]
+        lo[6 * (k + 1):6 * (k + 2)], hi[6 * (k + 1):6 * (k + 2)] = xl, xh
+    return lo, hi
+
+
+def y_bound(inst: dict):
+    """The bound the phase-1 Farkas check uses: ``feasible_box`` (None when
+    the reachable rows leave the relaxed set unbounded; then no instance is
+    certified infeasible)."""
+    return feasible_box(inst)
 
 
 def solve(inst: dict, tau: float = _qp.TAU) -> MpcResult:
     q = build(inst)
     N = q.N
-    ph = _qp.phase1(q.A, q.u, q.E, q.e, y_bound(inst), tau)
+    ph = _qp.phase1(q.A, q.u, q.E, q.e, lambda: y_bound(inst), tau)
     nanX, nanU = np.full((N + 1, 6), np.nan), np.full((N, 3), np.nan)
     if not ph.feasible:
         st = _qp.INFEASIBLE if ph.certified else _qp.UNCERTIFIED

@@ -44,9 +44,15 @@ class Phase1:
     verify_gap: float = 0.0
 
 
-def phase1(A, u, E, e, y_bound: float, tau: float = TAU) -> Phase1:
+def phase1(A, u, E, e, y_bound, tau: float = TAU) -> Phase1:
     """Phase-1 LP with row-normalised violations, then an FP64 re-check of
-    whichever certificate the LP hands back."""
+    whichever certificate the LP hands back.
+
+    ``y_bound`` encloses every feasible point, for the Farkas check: a scalar
+    Y (|y|_inf <= Y), a pair of arrays (lo, hi) (lo <= y <= hi), or None
+    when no bound is known (then infeasibility is never certified); or a
+    function returning one of these, called only when the LP reports
+    infeasibility."""
     m, n = A.shape
     nrm = np.linalg.norm(A, axis=1)
     An = A / nrm[:, None]
@@ -75,9 +81,19 @@ def phase1(A, u, E, e, y_bound: float, tau: float = TAU) -> Phase1:
         w = mu / nrm
         r = A.T @ w + E.T @ nu
         gap = -(u @ w + e @ nu)
-        # For any y with A y <= u, E y = e and |y|_inf <= y_bound:
-        # r.y = w.Ay + nu.Ey <= u.w + e.nu = -gap, while r.y >= -|r|_1 y_bound.
-        slack = gap - np.abs(r).sum() * y_bound
+        # For any y with A y <= u, E y = e inside the bound:
+        # r.y = w.Ay + nu.Ey <= u.w + e.nu = -gap, while r.y >= min over the
+        # bound of r.y (-|r|_1 Y for a scalar Y); no such y exists when that
+        # minimum exceeds -gap.
+        if callable(y_bound):
+            y_bound = y_bound()
+        if y_bound is None:
+            slack = -np.inf
+        elif np.isscalar(y_bound):
+            slack = gap - np.abs(r).sum() * float(y_bound)
+        else:
+            lo, hi = (np.asarray(a, float) for a in y_bound)
+            slack = gap + float(np.sum(np.minimum(r * lo, r * hi)))
         out.farkas_w, out.farkas_nu = w, nu
         out.feasible = False
         out.verify_gap = float(slack / max(1.0, w.sum()))

@@ -24,6 +24,16 @@ def _dev(a, dtype, device) -> torch.Tensor:
     return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).to(device).contiguous()
 
 
+def _check_out(owner, specs, device) -> None:
+    """Every (tensor, dtype, numel) of a caller-supplied output set must be a
+    contiguous tensor of that type and size on ``device``: the library
+    writes through the raw pointers."""
+    for t, dtype, n in specs:
+        if t.dtype != dtype or not t.is_contiguous() or t.numel() != n or t.device != device:
+            raise ValueError(f"{type(owner).__name__}: output of {t.numel()} {t.dtype} on {t.device}, "
+                             f"expected {n} contiguous {dtype} on {device}")
+
+
 @dataclass
 class SolveResult:
     P: torch.Tensor          # [3 * points_total] float64
@@ -88,6 +98,9 @@ class SegmentBatchGPU:
         with torch.cuda.device(d):
             _lib.check(L.rbp_build_batch(ctypes.byref(desc), _stream_handle(d), ctypes.byref(h)), "rbp_build_batch")
         self._h = h
+        # incremented by every forward pass: the library keeps the state of the
+        # last one only (the autograd node checks it before differentiating)
+        self.forward_generation = 0
         sz = _lib.BatchSizes()
         _lib.check(L.rbp_batch_get_sizes(h, ctypes.byref(sz)), "rbp_batch_get_sizes")
         self.points_total = int(sz.points_total)
@@ -133,8 +146,12 @@ class SegmentBatchGPU:
             if t.dtype != torch.float64 or not t.is_contiguous() or tuple(t.shape) != shape or t.device != self.device:
                 raise ValueError(f"expected contiguous float64 {shape} on {self.device}")
         if b_face is not None and (b_face.dtype != torch.float64 or not b_face.is_contiguous()
-                                   or b_face.numel() != self.b_face.numel()):
-            raise ValueError("b_face must be a contiguous float64 tensor shaped like the face table")
+                                   or b_face.numel() != self.b_face.numel() or b_face.device != self.device):
+            raise ValueError(f"b_face must be a contiguous float64 tensor shaped like the face table on {self.device}")
+        _check_out(o, ((o.P, torch.float64, 3 * self.points_total), (o.cost, torch.float64, self.N),
+                       (o.status, torch.int32, self.N), (o.kkt, torch.float64, self.N),
+                       (o.iters, torch.int32, 2 * self.N)), self.device)
+        self.forward_generation += 1
         rc = _lib.load().rbp_solve_batch(
             self._h, _ptr(x0), _ptr(goal), _ptr(b_face), ctypes.byref(opts), _ptr(o.P), _ptr(o.cost),
             _ptr(o.status), _ptr(o.kkt), _ptr(o.iters), _stream_handle(self.device))
@@ -145,12 +162,18 @@ class SegmentBatchGPU:
                  out: Optional[Gradients] = None) -> Gradients:
         """Implicit-KKT vector-Jacobian product of the last forward pass."""
         d, N = self.device, self.N
+        for t, n, name in ((grad_P, 3 * self.points_total, "grad_P"), (grad_cost, N, "grad_cost")):
+            if t is not None and (t.dtype != torch.float64 or not t.is_contiguous() or t.numel() != n
+                                  or t.device != d):
+                raise ValueError(f"{name} must be a contiguous float64 tensor of {n} elements on {d}")
         g = out or Gradients(
             x0=torch.empty((N, 6), dtype=torch.float64, device=d),
             goal=torch.empty((N, 3), dtype=torch.float64, device=d),
             b_inst=torch.empty(self.faces_total, dtype=torch.float64, device=d),
             flags=torch.empty(N, dtype=torch.int32, device=d),
         )
+        _check_out(g, ((g.x0, torch.float64, 6 * N), (g.goal, torch.float64, 3 * N),
+                       (g.b_inst, torch.float64, self.faces_total), (g.flags, torch.int32, N)), d)
         rc = _lib.load().rbp_backward(
             self._h, _ptr(grad_P), _ptr(grad_cost), _ptr(g.x0), _ptr(g.goal), _ptr(g.b_inst), _ptr(g.flags),
             _stream_handle(d))

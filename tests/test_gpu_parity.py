@@ -35,7 +35,10 @@ def gpu_solve(batch, opts=None, b_face=None, x0=None, goal=None):
 def opts(**kw):
     from paper_2411_13507_amd import _lib
     o = _lib.default_opts()
+    names = {f[0] for f in _lib.SolveOpts._fields_}
     for k, v in kw.items():
+        if k not in names:
+            raise AttributeError(f"rbp_solve_opts has no field {k!r}")
         setattr(o, k, v)
     return o
 

@@ -97,3 +97,106 @@ def test_loose_path_is_a_straight_line():
         for k in range(p + 1):
             frac = (s * p + k) / tot
             assert np.allclose(r.P[s, k], x0[:3] + frac * (goal - x0[:3]), atol=1e-9)
+
+
+def _join_state(P, T):
+    """Start state (b(0), b'(0)) of one segment, from numpy's power basis
+    (independent of the p/T (P_1 - P_0) formula the oracle rows use)."""
+    polys = power_basis(P, T)
+    pos = np.array([npoly.polyval(0.0, c) for c in polys])
+    vel = np.array([npoly.polyval(0.0, npoly.polyder(c, 1)) for c in polys])
+    return np.concatenate([pos, vel])
+
+
+def _reach_residuals(ch, P):
+    """H_s vec(P^s) - (h0_s + G_s x0_s) for every segment, with x0_s the
+    path's start state for s = 0 and the power-basis join state otherwise."""
+    out = []
+    for s, sg in enumerate(ch["segments"]):
+        xs = ch["x0"] if s == 0 else _join_state(P[s], ch["T"])
+        out.append(sg["H"] @ P[s].ravel() - (sg["h0"] + sg["G"] @ xs))
+    return out
+
+
+def _flip_join_velocity_sign(c, ch):
+    """A planted mistake on the CPU: the rows of every segment s >= 1 with the
+    sign of the join velocity's p/T G[:, 3:] terms flipped."""
+    p, T = ch["p"], ch["T"]
+    nseg = 3 * (p + 1)
+    A = c.A.copy()
+    row = 0
+    for s, sg in enumerate(ch["segments"]):
+        nf = sg["A_face"].shape[0]
+        row += nf * (p + 1) + 2 * 3 * p + 2 * 3 * (p - 1)
+        r = sg["H"].shape[0]
+        if s >= 1:
+            off = s * nseg
+            Gv = sg["G"][:, 3:]
+            A[row:row + r, off + 3:off + 6] += 2 * p / T * Gv
+            A[row:row + r, off:off + 3] -= 2 * p / T * Gv
+        row += r
+    assert row == A.shape[0]
+    return A
+
+
+def _solve_rows(c, A, ch):
+    ph = qp.phase1(A, c.u, c.E, c.e, chain.y_bound(ch))
+    if not (ph.feasible and ph.certified):
+        return None
+    r = qp.active_set(c.Q, A, c.u, c.E, c.e, ph.y, qp.initial_working_set(A, c.u, c.E, ph.y))
+    return r.y.reshape(c.S, c.p + 1, 3) if r.status == qp.SOLVED else None
+
+
+@pytest.fixture(scope="module")
+def tightened_paths():
+    """Solved paths with one reachable row of the second segment tightened
+    below its value at the optimum: the new optimum is unique and differs,
+    so that join-state row is active there (Thm. 2's rows for s >= 1 then
+    decide the solution)."""
+    b = gen.gen_cfg3(indices=range(10))
+    out = []
+    for i in range(b.n):
+        ch = b.chain(i)
+        r = chain.solve(ch)
+        if r.status != qp.SOLVED or len(ch["segments"]) < 2:
+            continue
+        res = _reach_residuals(ch, r.P)[1]
+        k = int(np.argmax(res))
+        seg = dict(ch["segments"][1])
+        seg["h0"] = seg["h0"].copy()
+        seg["h0"][k] += res[k] - 0.05           # 0.05 below the row's value at the optimum
+        ch2 = dict(ch, segments=[ch["segments"][0], seg] + ch["segments"][2:])
+        r2 = chain.solve(ch2)
+        if r2.status == qp.SOLVED:
+            out.append((ch2, r2, k))
+        if len(out) >= 4:
+            break
+    assert len(out) >= 3
+    return out
+
+
+def test_join_state_rows_hold_and_bind(tightened_paths):
+    """On the oracle's optima every segment's reachable rows hold with the
+    join state taken from the power basis, and the tightened row of segment
+    1 holds with equality."""
+    for ch, r, k in tightened_paths:
+        res = _reach_residuals(ch, r.P)
+        for s, v in enumerate(res):
+            assert np.all(v <= 1e-9), (s, v.max())
+        assert abs(res[1][k]) <= 1e-9, res[1][k]
+
+
+def test_join_state_pin_catches_a_sign_error(tightened_paths):
+    """The same check rejects the optima of the rows with the join
+    velocity's sign flipped: a plausible mistake in them does not pass."""
+    caught = 0
+    for ch, _, k in tightened_paths:
+        c = chain.build(ch)
+        P = _solve_rows(c, _flip_join_velocity_sign(c, ch), ch)
+        if P is None:
+            caught += 1        # the mutant even changes the class
+            continue
+        res = _reach_residuals(ch, P)
+        bad = any(np.any(v > 1e-7) for v in res) or abs(res[1][k]) > 1e-7
+        caught += int(bad)
+    assert caught == len(tightened_paths)

@@ -169,3 +169,100 @@ def test_plane_through_the_start_is_infeasible():
     inst["planes"][0, 3] = n @ inst["x0"][:3] + 0.05     # the fixed start is 0.05 on the wrong side
     r = mpc.solve(inst)
     assert r.status == qp.INFEASIBLE and r.s_star >= qp.TAU
+
+
+def _old_scalar_bound(inst):
+    """The earlier |y|_inf bound, which read max(G) as the velocity limit and
+    max(G)/dt as the input limit: valid for the generated box rows only."""
+    G, dt, N = np.asarray(inst["G"]), float(inst["dt"]), int(inst["N"])
+    vmax = max(float(np.max(G)), float(np.max(np.abs(inst["x0"][3:]))))
+    return float(np.max(np.abs(inst["x0"][:3])) + (N + 1) * dt * vmax + vmax + float(np.max(G)) / dt + 2.0)
+
+
+def _skewed_rows(dt):
+    """Reachable rows that are not a velocity box and an input box: two
+    nearly parallel pairs of velocity rows (|v_x - 0.98 v_y| and
+    |v_x - 0.99 v_y| at most 0.05 after normalisation), which leave v_y free
+    up to about 10 m/s although every right-hand side is small, a box on
+    v_z, and an input box |v_{k+1} - v_k| <= 0.4."""
+    r1, r2, g = [], [], []
+    for a, gg in (((1.0, -0.98, 0.0), 0.05), ((1.0, -0.99, 0.0), 0.05), ((0.0, 0.0, 1.0), 0.05)):
+        a = np.asarray(a) / np.linalg.norm(a)
+        for sgn in (1.0, -1.0):
+            z = np.zeros(6); w = np.zeros(6); w[3:] = sgn * a
+            r1.append(z); r2.append(w); g.append(gg)
+    for c in range(3):
+        for sgn in (1.0, -1.0):
+            z = np.zeros(6); w = np.zeros(6); z[3 + c] = -sgn; w[3 + c] = sgn
+            r1.append(z); r2.append(w); g.append(0.4)
+    return np.array(r1), np.array(r2), np.array(g)
+
+
+def _skewed_instance(N=40, dt=0.1):
+    F1, F2, G = _skewed_rows(dt)
+    return dict(N=N, dt=dt, Q=np.diag([1.0, 1, 1, 0.1, 0.1, 0.1]), R=0.01 * np.eye(3), w=1.0,
+                F1=F1, F2=F2, G=G, x0=np.zeros(6), ref=np.zeros((N + 1, 6)),
+                planes=np.tile(np.array([0.0, 0.0, 1.0, -1e3]), (N, 1)))
+
+
+def _exact_extreme(inst, idx, sgn):
+    """max of sgn * y[idx] over x_0 = x0, the dynamics and the reachable rows
+    (the relaxation the box encloses), by one LP over the whole horizon."""
+    from scipy.optimize import linprog
+    q = mpc.build(inst)
+    N = inst["N"]
+    m = len(inst["G"])
+    A = q.A[:N * m]                     # reachable rows come first
+    u = q.u[:N * m]
+    E, e = q.E, q.e
+    keep = np.r_[0:6 + 6 * N, E.shape[0] - 1]           # drop the terminal state
+    c = np.zeros(q.A.shape[1]); c[idx] = -sgn
+    res = linprog(c, A_ub=A, b_ub=u, A_eq=E[keep], b_eq=e[keep], bounds=[(None, None)] * len(c),
+                  method="highs")
+    assert res.status == 0
+    return -float(res.fun)
+
+
+def test_feasible_box_encloses_the_exact_extremes_of_skewed_rows():
+    """The box from the instance's own rows contains the exact LP extremes
+    of positions, velocities and inputs on rows that are not boxes, while the
+    earlier max(G) reading falls short of them (so it could have certified a
+    feasible instance as infeasible)."""
+    inst = _skewed_instance()
+    lo, hi = mpc.feasible_box(inst)
+    N = inst["N"]
+    iy_p = 6 * N + 1           # p_y at the last node
+    iy_v = 6 * (N // 2) + 4    # v_y half way
+    iu = 6 * (N + 1) + 3 * (N // 2) + 1
+    for idx in (iy_p, iy_v, iu, 6 * N):
+        top, bot = _exact_extreme(inst, idx, 1.0), -_exact_extreme(inst, idx, -1.0)
+        assert lo[idx] <= bot + 1e-9 and top <= hi[idx] + 1e-9, (idx, lo[idx], bot, top, hi[idx])
+    assert _exact_extreme(inst, iy_p, 1.0) > 1.2 * _old_scalar_bound(inst)
+
+
+def test_feasible_box_encloses_generated_optima(solved):
+    b, res = solved
+    for i, r in enumerate(res):
+        lo, hi = mpc.feasible_box(b.instance(i))
+        assert np.all(r.y >= lo - 1e-9) and np.all(r.y <= hi + 1e-9)
+
+
+def test_plane_through_the_start_is_infeasible_with_skewed_rows():
+    inst = _skewed_instance(N=12)
+    inst["planes"] = inst["planes"].copy()
+    inst["planes"][0] = [1.0, 0.0, 0.0, 0.05]      # the fixed start (origin) is 0.05 on the wrong side
+    r = mpc.solve(inst)
+    assert r.status == qp.INFEASIBLE and r.s_star >= qp.TAU
+
+
+def test_unbounded_rows_are_never_certified():
+    """Rows that leave the relaxed set unbounded give no box, and the
+    phase-1 check then certifies nothing (the class stays uncertified)."""
+    inst = _skewed_instance(N=6)
+    keep = [0, 1, 2, 3]                                # only the skewed velocity pairs: v_z and inputs free
+    inst["F1"], inst["F2"], inst["G"] = inst["F1"][keep], inst["F2"][keep], inst["G"][keep]
+    assert mpc.feasible_box(inst) is None
+    inst["planes"] = inst["planes"].copy()
+    inst["planes"][0] = [1.0, 0.0, 0.0, 0.05]
+    r = mpc.solve(inst)
+    assert r.status == qp.UNCERTIFIED
