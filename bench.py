@@ -2,10 +2,13 @@
 
 A step is one pass of the whole path over the 50,000-edge cluttered
 environment batch (degree-7 segments, 8-24 faces, 32 reachable rows, about
-30% infeasible): the forward solve (FP32 ADMM warm start + FP64 active-set
-polish, rbp_solve_batch) followed by the implicit-KKT backward
-(rbp_backward), inputs resident in HBM.  The value counts instances that end
-SOLVED with a scaled KKT residual <= 1e-6 or INFEASIBLE with a verified
+30% infeasible): the forward solve (rbp_solve_batch: an optional FP32 ADMM
+stage, then the FP64 active-set polish that decides every result) followed
+by the implicit-KKT backward (rbp_backward), inputs resident in HBM.  The
+solve options are the autotuner's pick for the batch; the line also reports
+the other precision form (FP32 ADMM + FP64 polish when the pick skips the
+ADMM), each with its own dtype.  The value counts instances that end SOLVED
+with a scaled KKT residual <= 1e-6 or INFEASIBLE with a verified
 certificate.  Printed as one JSON line.
 """
 from __future__ import annotations
@@ -38,7 +41,10 @@ def instance_sizes(b):
 
 def algorithmic_flops(b, iters):
     """Flops per instance of the forward kernel, from the instance sizes and
-    the measured iteration counts (ADMM iterations, polish steps)."""
+    the measured iteration counts (ADMM iterations, polish steps).  The ADMM
+    set-up (reachable-row Gram, K and its inverse) is counted only for
+    instances that ran ADMM iterations: the polish-only kernel never forms
+    them."""
     p, nf, r = instance_sizes(b)
     n = 3 * (p - 1)
     F = (p - 1) * nf
@@ -52,19 +58,37 @@ def algorithmic_flops(b, iters):
     final = 2 * nnz_full + n * n + 2 * (3 * (p + 1)) ** 2
     K = iters[:, 0].astype(np.int64)
     S = iters[:, 1].astype(np.int64)
-    return setup + K * admm_it + S * polish_step + final
+    return np.where(K > 0, setup, 0) + K * admm_it + S * polish_step + final
 
 
-def algorithmic_bytes(b, q_mean=8):
+def algorithmic_bytes(b, q_mean=8, store=True):
     """HBM bytes per instance of the forward kernel: problem data read once,
-    outputs and stored active set written once."""
+    outputs (and, when kept for the backward pass, the active set) written
+    once."""
     p, nf, r = instance_sizes(b)
     if getattr(b, "reach_idx", None) is None:
         reads = 8 * r * 3 * (p + 1) + 48 * r + 8 * r + 72 + 8 + 44 + 32 * nf
     else:                                    # shared blocks: read once per launch, not per instance
         reads = 72 + 8 + 44 + 32 * nf + 4 + (8 * b.H.size + 56 * b.h0.size) / max(b.n, 1)
-    writes = 24 * (p + 1) + 16 + 4 + 8 + 4 + 16 * q_mean
+    writes = 24 * (p + 1) + 16 + 4 + 8 + 4 + (16 * q_mean if store else 0)
     return reads + writes
+
+
+def roofline_record(flops, nbytes, t_launch):
+    """Bound of a launch from its algorithmic work: the resource whose time
+    at peak is larger (t_HBM = bytes / 8 TB/s, t_ALU = flops / 78.6 TFLOP/s)
+    is the binding one, and ``frac`` is achieved / peak for that resource."""
+    t_hbm = nbytes / (PEAK_HBM_GBS * 1e9)
+    t_alu = flops / (PEAK_VALU_TFLOPS * 1e12)
+    if t_hbm >= t_alu:
+        ach, peak, unit, bound = nbytes / t_launch / 1e9, PEAK_HBM_GBS, "GB/s", "hbm"
+    else:
+        ach, peak, unit, bound = flops / t_launch / 1e12, PEAK_VALU_TFLOPS, "TFLOP/s", "alu"
+    return {"bound": bound, "achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak,
+            "t_hbm_us": t_hbm * 1e6, "t_alu_us": t_alu * 1e6, "bytes_per_launch": nbytes,
+            "flops_per_launch": flops,
+            "alu_frac": flops / t_launch / 1e12 / PEAK_VALU_TFLOPS,
+            "hbm_frac": nbytes / t_launch / 1e9 / PEAK_HBM_GBS}
 
 
 def kernel_source_hash():
@@ -93,23 +117,56 @@ def _oracle_fwd_bwd(args):
     from oracle import segment
     inst, gbar = args
     r = segment.solve(inst)
+    g = None
     if segment.is_solved(r):
-        segment.gradients(r, gbar).combined(1.0)
-    return r.status
+        g = segment.gradients(r, gbar).combined(1.0)
+    return r.status, r.cost, r.P, g, segment.gradient_certified(r) if g is not None else False
 
 
 def cpu_baseline(b, gbar, n_sample=2000):
     """The FP64 oracle (phase-1 LP + active set + gradients) on the first
-    ``n_sample`` instances, over a process pool on the host cores."""
+    ``n_sample`` instances, over a process pool on the host cores.  Returns
+    the baseline record and the oracle's results (for the error figures)."""
     import multiprocessing as mp
     cores = min(16, os.cpu_count() or 1)
     insts = [(b.instance(i), gbar[i]) for i in range(n_sample)]
     t = time.perf_counter()
     with mp.get_context("fork").Pool(cores) as pool:
-        pool.map(_oracle_fwd_bwd, insts, chunksize=16)
+        res = pool.map(_oracle_fwd_bwd, insts, chunksize=16)
     dt = time.perf_counter() - t
-    return {"value": n_sample / dt, "unit": "solves/s", "cores": cores, "kind": "oracle",
-            "sample": f"first {n_sample} of the 50,000 edges, forward + gradients, {dt:.1f} s wall"}
+    return ({"value": n_sample / dt, "unit": "solves/s", "cores": cores, "kind": "oracle",
+             "sample": f"first {n_sample} of the 50,000 edges, forward + gradients, {dt:.1f} s wall"}, res)
+
+
+def errors_vs_oracle(b, orc, P, cost, status, gx0, ggoal, gb_inst):
+    """Per-result error of the GPU outputs against the FP64 oracle on the
+    instances the oracle ran (the first len(orc) of the batch): status
+    mismatches on certified instances, max relative cost error, max P* error
+    (|dP|_inf / (1 + |P|_inf)) and max gradient error (|dg|_2 / max(|g|_2,
+    1e-8), over instances whose gradient is well defined)."""
+    from oracle import qp
+    pt_off = np.concatenate([[0], np.cumsum(b.degree.astype(np.int64) + 1)])
+    nf = np.diff(b.poly_off.astype(np.int64))[b.poly_idx]
+    f_off = np.concatenate([[0], np.cumsum(nf)])
+    mism = cmp_ = 0
+    ce = pe = ge = 0.0
+    n_grad = 0
+    for i, (ost, ocost, oP, og, gcert) in enumerate(orc):
+        if ost in (qp.SOLVED, qp.INFEASIBLE):
+            mism += int(status[i] != ost)
+        if ost != qp.SOLVED or status[i] != qp.SOLVED:
+            continue
+        cmp_ += 1
+        ce = max(ce, abs(cost[i] - ocost) / (abs(ocost) + 1e-3))
+        Pg = P[3 * pt_off[i]:3 * pt_off[i + 1]].reshape(-1, 3)
+        pe = max(pe, float(np.abs(Pg - oP).max() / (1.0 + np.abs(oP).max())))
+        if gcert:
+            n_grad += 1
+            for mine, ref in ((gx0[i], og[0]), (ggoal[i], og[1]), (gb_inst[f_off[i]:f_off[i + 1]], og[2])):
+                ge = max(ge, float(np.linalg.norm(mine - ref) / max(np.linalg.norm(ref), 1e-8)))
+    return {"instances": len(orc), "status_mismatches_certified": mism, "solved_compared": cmp_,
+            "max_cost_rel_err": ce, "max_P_err": pe, "gradients_compared": n_grad, "max_grad_rel_err": ge,
+            "tolerances": {"cost": "1e-6 rel + 1e-9", "P": 1e-6, "grad": 1e-4}}
 
 
 def time_launches(fn, reps, stream):
@@ -406,10 +463,63 @@ def main():
     torch.cuda.synchronize()
     t_bwd = float(np.mean([e0.elapsed_time(e1) for e0, e1 in bevs])) / 1e3
 
-    flops = float(algorithmic_flops(b, iters).sum())
-    nbytes = float(algorithmic_bytes(b).sum())
-    achieved = flops / t_solve / 1e12
-    traffic = traffic_from_profile(b.n)
+    # roofline of the timed forward launch (store_for_backward off): only
+    # the work that launch executes is counted
+    fw_iters = out.iters.cpu().numpy()
+    flops = float(algorithmic_flops(b, fw_iters).sum())
+    nbytes = float(algorithmic_bytes(b, store=False).sum())
+    roof = roofline_record(flops, nbytes, t_solve)
+    roof["traffic"] = traffic_from_profile(b.n)
+    admm_on = int(opts.admm_iters) > 0
+    kernel_name = f"solve_kernel<float, 7, {'true' if admm_on else 'false'}>"
+    dtype = "fp32+fp64" if admm_on else "fp64"
+    roof["kernel"] = kernel_name
+    roof["launch_ms"] = t_solve * 1e3
+    # restore the headline forward + backward outputs for the error figures
+    gb.solve(x0, goal, opts=opts, out=out)
+    grads = gb.backward(gP, gC, out=grads)
+    torch.cuda.synchronize()
+
+    # the other precision form on the same batch: FP32 ADMM (MFMA Gram of the
+    # reachable rows, K^-1 in registers) + FP64 polish when the tuned options
+    # skip the ADMM, the polish alone otherwise
+    alt_opts = _lib.default_opts()
+    if admm_on:
+        alt_opts.admm_iters = 0
+    else:
+        alt_opts.admm_iters = 10
+    alt_opts.store_for_backward = 1
+    alt_out = gb.alloc_outputs()
+    alt_g = {}
+
+    def alt_step():
+        gb.solve(x0, goal, opts=alt_opts, out=alt_out)
+        alt_g["g"] = gb.backward(gP, gC, out=alt_g.get("g"))
+    t_alt = time_launches(alt_step, max(3, args.steps // 4), torch.cuda.current_stream(dev))
+    alt_f = _lib.SolveOpts.from_buffer_copy(alt_opts)
+    alt_f.store_for_backward = 0
+    t_alt_f = time_launches(lambda: gb.solve(x0, goal, opts=alt_f, out=alt_out), max(3, args.steps // 4),
+                            torch.cuda.current_stream(dev))
+    a_st = alt_out.status.cpu().numpy()
+    a_kk = alt_out.kkt.cpu().numpy()
+    a_it = alt_out.iters.cpu().numpy()
+    a_ok = int(((a_st == 0) & (a_kk <= KKT_OK)).sum() + (a_st == 1).sum())
+    a_roof = roofline_record(float(algorithmic_flops(b, a_it).sum()), nbytes, t_alt_f)
+    alt_rec = {"dtype": "fp64" if admm_on else "fp32+fp64", "admm_iters": int(alt_opts.admm_iters),
+               "rho": round(float(alt_opts.rho), 6),
+               "kernel": f"solve_kernel<float, 7, {'false' if admm_on else 'true'}>",
+               "fwd_bwd_ms": t_alt * 1e3, "fwd_ms": t_alt_f * 1e3, "solves_per_s": a_ok / t_alt,
+               "fwd_solves_per_s": a_ok / t_alt_f, "status_counts": np.bincount(a_st, minlength=6).tolist(),
+               "polish_steps_mean": float(a_it[:, 1].mean()),
+               "roofline": {k: a_roof[k] for k in ("bound", "achieved", "unit", "frac", "alu_frac", "hbm_frac")}}
+    # gradients of the alternative form are needed for its error figures
+    gb.solve(x0, goal, opts=alt_opts, out=alt_out)
+    alt_grads = gb.backward(gP, gC, out=alt_g.get("g"))
+    torch.cuda.synchronize()
+    alt_np = (alt_out.P.cpu().numpy(), alt_out.cost.cpu().numpy(), alt_out.status.cpu().numpy(),
+              alt_grads.x0.cpu().numpy(), alt_grads.goal.cpu().numpy(), alt_grads.b_inst.cpu().numpy())
+    main_np = (out.P.cpu().numpy(), out.cost.cpu().numpy(), out.status.cpu().numpy(),
+               grads.x0.cpu().numpy(), grads.goal.cpu().numpy(), grads.b_inst.cpu().numpy())
 
     plain = None
     if not args.no_plain:
@@ -439,8 +549,12 @@ def main():
         extras = extra_workloads(admm_iters=args.admm_iters, edges=b, main_opts=opts)
 
     cpu = None
+    err = alt_err = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(b, gbar)
+        cpu, orc = cpu_baseline(b, gbar)
+        err = errors_vs_oracle(b, orc, *main_np)
+        alt_err = errors_vs_oracle(b, orc, *alt_np)
+        alt_rec["error_vs_oracle"] = alt_err
 
     rec = {
         "metric": "segment-QP solves/s at KKT res <=1e-6, fwd+bwd (fwd, plain and % roofline alongside)",
@@ -453,18 +567,15 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "fp32+fp64",
+        "dtype": dtype,
         "data": "synthetic",
         "config": {"workload": "edges50k_p7_clutter", "instances": b.n, "degree": 7, "faces": "8-24",
                    "reach_rows": 32, "admm_iters": int(opts.admm_iters), "rho": round(float(opts.rho), 6),
                    "options": "autotuned" if tuned is not None else "fixed",
                    "obstacles": 200, "polytopes": 2000, "launch": launch},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_VALU_TFLOPS, "traffic": traffic,
-                     "kernel": "solve_kernel<float,7>", "launch_ms": t_solve * 1e3,
-                     "flops_per_launch": flops},
-        "hbm": {"algorithmic_bytes_per_launch": nbytes, "achieved_GBs": nbytes / t_solve / 1e9,
-                "frac": nbytes / t_solve / 1e9 / PEAK_HBM_GBS},
+        "roofline": roof,
+        "error_vs_oracle": err,
+        "other_precision_form": alt_rec,
         "fwd_solves_per_s": counted / t_solve,
         "bwd_ms": t_bwd * 1e3,
         "counts": {"solved_kkt_ok": n_ok, "infeasible_certified": n_inf, "other": int(b.n - counted)},

@@ -157,8 +157,12 @@ int rbp_build_batch(const rbp_problem_desc* desc, hipStream_t stream, rbp_batch*
 int rbp_batch_get_sizes(const rbp_batch* batch, rbp_batch_sizes* out);
 
 /*
- * Forward pass over all instances: FP32 ADMM warm start, then the FP64
- * active-set polish (Sec. III-B's per-edge QP, here with the segment cost).
+ * Forward pass over all instances: the segment QP above (the per-edge curve
+ * of the Bezier graph of Sec. II-B, dynamically feasible by Theorem 2 and
+ * collision-free by Property 1).  With opts->admm_iters > 0 an FP32 ADMM
+ * stage runs first and proposes a working set; with admm_iters == 0 it is
+ * skipped.  Either way the FP64 dual active-set polish decides every result:
+ * the exact optimum, or infeasibility with a Farkas vector verified in FP64.
  *   x0      [N][6]   start state (position, velocity); P_0 = x0[0:3]
  *   goal    [N][3]   end waypoint; P_p = goal
  *   b_face  [F] or NULL: replaces desc->b_face for this call (and backward)
@@ -375,7 +379,6 @@ int rbp_adjacent_hyperplanes(int32_t n_nodes, const double* X, int32_t n_obstacl
                              const double* box_hi, int32_t* box_index, double* point, double* plane,
                              hipStream_t stream);
 
-/* Static string for a call result or per-instance status code. */
 /*
  * Batched MPC refinement (eq. MPC, Sec. III-D).  Each instance refines a
  * path over a horizon of N steps of length dt for the double integrator in
@@ -464,6 +467,7 @@ int rbp_mpc_solve(rbp_mpc* mpc, const double* x0, const double* ref, const doubl
 /* Releases the solver (no-op for NULL); synchronises its last stream first. */
 void rbp_destroy_mpc(rbp_mpc* mpc);
 
+/* Static string for a call result or per-instance status code. */
 const char* rbp_status_string(int code);
 
 #ifdef __cplusplus
