@@ -56,21 +56,42 @@ def _resource_table(remarks: str) -> str:
 
 
 def build(verbose: bool = False) -> str:
-    """Compile every source for gfx950 and link ``librbp.so``; returns its
-    path.  The compiler's per-kernel resource usage (registers, scratch,
-    occupancy) is written beside it."""
+    """Compile every source for gfx950 (one compiler process per source, in
+    parallel) and link ``librbp.so``; returns its path.  The compiler's
+    per-kernel resource usage (registers, scratch, occupancy) is written
+    beside it."""
+    from concurrent.futures import ThreadPoolExecutor
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+
+    def compile_one(src):
+        obj = os.path.join(objdir, src + ".o")
+        cmd = [hipcc(), *HIP_FLAGS, "-Rpass-analysis=kernel-resource-usage", "-c", "-o", obj,
+               os.path.join(CSRC, src)]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        return obj, subprocess.run(cmd, capture_output=True, text=True)
+
+    workers = max(1, min(len(SOURCES), os.cpu_count() or 1, 8))
+    with ThreadPoolExecutor(workers) as pool:
+        results = list(pool.map(compile_one, SOURCES))
+    remarks = []
+    for (obj, res), src in zip(results, SOURCES):
+        if res.returncode != 0:
+            sys.stderr.write(res.stdout + res.stderr)
+            raise RuntimeError(f"hipcc failed on {src} with exit code {res.returncode}")
+        remarks.append(res.stderr)
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIP_FLAGS, "-Rpass-analysis=kernel-resource-usage", "-shared", "-o", tmp] + \
-        [os.path.join(CSRC, s) for s in SOURCES]
+    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + [o for o, _ in results]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError(f"hipcc failed with exit code {res.returncode}")
+        raise RuntimeError(f"hipcc link failed with exit code {res.returncode}")
     os.replace(tmp, LIB)
     with open(RESOURCES, "w") as fh:
-        fh.write(_resource_table(res.stderr))
+        fh.write(_resource_table("\n".join(remarks)))
     return LIB
 
 
