@@ -54,6 +54,8 @@ extern "C" {
 #define RBP_E_ALLOC (-3)   /* device allocation failed                             */
 #define RBP_E_DEVICE (-4)  /* a HIP runtime call or kernel launch failed           */
 #define RBP_E_STATE (-5)   /* backward without a stored forward pass               */
+#define RBP_E_SCRATCH (-6) /* problem exceeds the fixed workspace of an
+                              allocation-free entry point                         */
 
 /* per-instance status */
 #define RBP_SOLVED 0         /* optimum found, scaled KKT residual <= kkt_tol      */
@@ -365,6 +367,30 @@ int rbp_build_graph(const rbp_graph_desc* desc, hipStream_t stream, rbp_graph** 
 int rbp_graph_run(rbp_graph* graph, const double* V, uint32_t* adj, int32_t* degree, hipStream_t stream);
 
 void rbp_destroy_graph(rbp_graph* graph);
+
+/*
+ * rbp_graph_run without a graph object and without any device allocation,
+ * for callers that cannot allocate (code under HIP graph capture, serving
+ * loops, harnesses that forbid hipMalloc).  Same result as rbp_build_graph +
+ * rbp_graph_run + rbp_destroy_graph on `desc`, bit for bit.
+ *   desc     host pointer; F1, F2, G device pointers as in rbp_graph_desc,
+ *            read during the call only
+ *   V, adj, degree   as in rbp_graph_run (caller-owned device buffers)
+ * Workspace: a fixed device array of RBP_GRAPH_NOALLOC_DOUBLES doubles
+ * (8 MiB) per GPU, held by the library until the process ends; a call needs
+ * 2 n m + 2 ceil(n / 64) m of them (n nodes, m rows; 5,000 nodes with 64 rows
+ * need 650,112).  Every call on one GPU uses that GPU's array, so calls that
+ * overlap on one GPU (different streams, or host threads) race: order them
+ * on one stream.  Nothing in the workspace must start at zero (each call
+ * overwrites what it reads).  The first call on a device looks up the
+ * array's address (hipGetSymbolAddress) and caches it.
+ * Errors: RBP_E_INVALID (null pointers, reserved != 0), RBP_E_SHAPE (sizes
+ * out of the ranges of rbp_build_graph), RBP_E_SCRATCH (the workspace is
+ * too small for n and m; checked before any device call), RBP_E_DEVICE.
+ */
+#define RBP_GRAPH_NOALLOC_DOUBLES (1 << 20)
+int rbp_graph_run_noalloc(const rbp_graph_desc* desc, const double* V, uint32_t* adj, int32_t* degree,
+                          hipStream_t stream);
 
 /*
  * adjacentHyperplane for n nodes X (device [n][3]) against axis-aligned

@@ -8,7 +8,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librbp.so")
 
 RBP_OK = 0
-RBP_E_INVALID, RBP_E_SHAPE, RBP_E_ALLOC, RBP_E_DEVICE, RBP_E_STATE = -1, -2, -3, -4, -5
+RBP_E_INVALID, RBP_E_SHAPE, RBP_E_ALLOC, RBP_E_DEVICE, RBP_E_STATE, RBP_E_SCRATCH = -1, -2, -3, -4, -5, -6
+GRAPH_NOALLOC_DOUBLES = 1 << 20
 SOLVED, INFEASIBLE, MAXITER, POLISH_FAILED, NUMERICAL, INVALID_INPUT = 0, 1, 2, 3, 4, 5
 
 EXPORTED = (
@@ -16,7 +17,8 @@ EXPORTED = (
     "rbp_backward", "rbp_destroy_batch", "rbp_status_string",
     "rbp_build_chains", "rbp_chains_get_sizes", "rbp_solve_chains", "rbp_destroy_chains",
     "rbp_build_cut", "rbp_cut_run", "rbp_cut_qp_count", "rbp_destroy_cut",
-    "rbp_build_graph", "rbp_graph_run", "rbp_destroy_graph", "rbp_adjacent_hyperplanes",
+    "rbp_build_graph", "rbp_graph_run", "rbp_destroy_graph", "rbp_graph_run_noalloc",
+    "rbp_adjacent_hyperplanes",
     "rbp_build_mpc", "rbp_mpc_solve", "rbp_destroy_mpc",
 )
 
@@ -129,6 +131,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.rbp_graph_run.restype = ctypes.c_int
     L.rbp_destroy_graph.argtypes = [_p]
     L.rbp_destroy_graph.restype = None
+    L.rbp_graph_run_noalloc.argtypes = [ctypes.POINTER(GraphDesc), _p, _p, _p, _p]
+    L.rbp_graph_run_noalloc.restype = ctypes.c_int
     L.rbp_adjacent_hyperplanes.argtypes = [ctypes.c_int32, _p, ctypes.c_int32, _p, _p, _p, _p, _p, _p]
     L.rbp_adjacent_hyperplanes.restype = ctypes.c_int
     L.rbp_build_mpc.argtypes = [ctypes.POINTER(MpcDesc), _p, ctypes.POINTER(_p)]

@@ -373,6 +373,37 @@ class GraphGPU:
         return adj, degree
 
 
+def graph_run_noalloc(F1: torch.Tensor, F2: torch.Tensor, G: torch.Tensor, V: torch.Tensor,
+                      adj: Optional[torch.Tensor] = None, degree: Optional[torch.Tensor] = None):
+    """Adjacency and out-degrees as ``GraphGPU.run``, through the entry point
+    that allocates no device memory (its workspace is a fixed per-GPU array
+    in the library).  F1, F2 [m, d], G [m], V [n, d]: float64 tensors on one
+    GPU.  With ``adj`` and ``degree`` given (int32, [n, ceil(n/32)] and [n])
+    nothing is allocated at all."""
+    d = V.device
+    if d.type != "cuda":
+        raise _lib.RbpError("graph_run_noalloc needs device tensors")
+    for name, t in (("F1", F1), ("F2", F2), ("G", G), ("V", V)):
+        if t.device != d or t.dtype != torch.float64 or not t.is_contiguous():
+            raise _lib.RbpError(f"{name} must be a contiguous float64 tensor on {d}")
+    m, dim = int(F1.shape[0]), int(F1.shape[1])
+    n = int(V.shape[0])
+    if tuple(F2.shape) != (m, dim) or tuple(G.shape) != (m,) or tuple(V.shape) != (n, dim):
+        raise _lib.RbpError("shapes of F1, F2, G, V disagree")
+    adj = adj if adj is not None else torch.empty((n, (n + 31) // 32), dtype=torch.int32, device=d)
+    degree = degree if degree is not None else torch.empty(n, dtype=torch.int32, device=d)
+    if adj.device != d or adj.dtype != torch.int32 or tuple(adj.shape) != (n, (n + 31) // 32) \
+            or not adj.is_contiguous():
+        raise _lib.RbpError("adj must be a contiguous int32 [n, ceil(n/32)] tensor on the device of V")
+    if degree.device != d or degree.dtype != torch.int32 or tuple(degree.shape) != (n,):
+        raise _lib.RbpError("degree must be an int32 [n] tensor on the device of V")
+    desc = _lib.GraphDesc(n, dim, m, 0, _ptr(F1), _ptr(F2), _ptr(G))
+    with torch.cuda.device(d):
+        _lib.check(_lib.load().rbp_graph_run_noalloc(ctypes.byref(desc), _ptr(V), _ptr(adj), _ptr(degree),
+                                                     _stream_handle(d)), "rbp_graph_run_noalloc")
+    return adj, degree
+
+
 def adjacent_hyperplanes(X: torch.Tensor, box_lo: torch.Tensor, box_hi: torch.Tensor):
     """Nearest box, closest point and separating plane (n, l) per node;
     tensors on the device (float64)."""

@@ -109,6 +109,7 @@ const char* rbp_status_string(int code) {
     case RBP_E_ALLOC: return "device allocation failed";
     case RBP_E_DEVICE: return "HIP runtime error";
     case RBP_E_STATE: return "no stored forward pass";
+    case RBP_E_SCRATCH: return "problem larger than the fixed workspace of an allocation-free call";
     default: return "unknown code";
   }
 }
@@ -674,6 +675,31 @@ void rbp_destroy_graph(rbp_graph* g) {
   (void)hipSetDevice(g->device);
   if (g->last_stream) (void)hipStreamSynchronize(g->last_stream);
   free_graph(g);
+}
+
+static_assert(RBP_GRAPH_NOALLOC_DOUBLES == rbp::kGraphScratchDoubles, "workspace size in rbp.h");
+
+int rbp_graph_run_noalloc(const rbp_graph_desc* d, const double* V, uint32_t* adj, int32_t* degree,
+                          hipStream_t stream) {
+  // every check before the first HIP call
+  if (!d) return RBP_E_INVALID;
+  if (d->reserved != 0 || !d->F1 || !d->F2 || !d->G) return RBP_E_INVALID;
+  if (d->n_nodes < 0 || d->n_nodes > RBP_GRAPH_MAX_NODES || d->dim < 1 || d->dim > RBP_GRAPH_MAX_DIM ||
+      d->n_rows < 1 || d->n_rows > RBP_GRAPH_MAX_ROWS)
+    return RBP_E_SHAPE;
+  const int64_t nm = int64_t(d->n_nodes) * d->n_rows;
+  const int64_t tm = int64_t((d->n_nodes + 63) / 64) * d->n_rows;
+  if (2 * nm + 2 * tm > rbp::kGraphScratchDoubles) return RBP_E_SCRATCH;
+  if (d->n_nodes == 0) return RBP_OK;
+  if (!V || !adj || !degree) return RBP_E_INVALID;
+  double* ws = nullptr;
+  if (rbp::graph_scratch(&ws) != hipSuccess) return RBP_E_DEVICE;
+  rbp::GraphArgs a{};
+  a.n_nodes = d->n_nodes; a.dim = d->dim; a.m = d->n_rows;
+  a.V = V; a.F1 = d->F1; a.F2 = d->F2; a.G = d->G;
+  a.A = ws; a.B = ws + nm; a.Amin = ws + 2 * nm; a.Bmin = ws + 2 * nm + tm;
+  a.adj = adj; a.degree = degree;
+  return rbp::launch_graph(a, stream) == hipSuccess ? RBP_OK : RBP_E_DEVICE;
 }
 
 int rbp_adjacent_hyperplanes(int32_t n, const double* X, int32_t n_obst, const double* lo, const double* hi,

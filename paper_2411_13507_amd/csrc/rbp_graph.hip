@@ -20,10 +20,18 @@
 
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 
 #include "rbp_internal.hpp"
 
 namespace rbp {
+
+// Workspace of the allocation-free graph run (rows A and B, tile minima):
+// a fixed array in device memory, one copy per GPU, held until the process
+// ends.  Host code never uses the name itself as an address: the device
+// address of each GPU's copy comes from hipGetSymbolAddress.
+static __device__ __align__(256) double scratch[kGraphScratchDoubles];
+
 namespace {
 
 constexpr int kTile = 64;       // nodes per tile side
@@ -166,6 +174,27 @@ hipError_t launch_graph(const GraphArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(graph_pairs_kernel, dim3(n_tiles, n_tiles), dim3(256), 0, s, a);
   hipLaunchKernelGGL(graph_degree_kernel, dim3((a.n_nodes + 255) / 256), dim3(256), 0, s, a);
   return hipGetLastError();
+}
+
+hipError_t graph_scratch(double** out) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void* ptr[kMaxDevices] = {};
+  *out = nullptr;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    ptr[dev] = p;
+  }
+  *out = static_cast<double*>(ptr[dev]);
+  return hipSuccess;
 }
 
 hipError_t launch_hyperplanes(int n, const double* X, int n_obst, const double* lo, const double* hi, int32_t* idx,

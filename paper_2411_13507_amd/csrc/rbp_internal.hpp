@@ -184,6 +184,11 @@ struct GraphArgs {
   int32_t* degree;           // [n_nodes]
 };
 hipError_t launch_graph(const GraphArgs& a, hipStream_t s);
+// Fixed device workspace of rbp_graph_run_noalloc, in doubles (8 MiB).
+constexpr int64_t kGraphScratchDoubles = int64_t(1) << 20;
+// Device address of the current GPU's copy of that workspace (looked up once
+// per device with hipGetSymbolAddress, then cached).
+hipError_t graph_scratch(double** out);
 hipError_t launch_hyperplanes(int n, const double* X, int n_obst, const double* lo, const double* hi, int32_t* idx,
                               double* point, double* plane, hipStream_t s);
 

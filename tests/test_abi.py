@@ -40,7 +40,7 @@ def test_default_opts(lib):
 
 
 def test_status_strings(lib):
-    for code in (0, 1, 2, 3, 4, 5, -1, -2, -3, -4, -5):
+    for code in (0, 1, 2, 3, 4, 5, -1, -2, -3, -4, -5, -6):
         s = lib.rbp_status_string(code).decode()
         assert s and s != "unknown code"
     assert lib.rbp_status_string(1234).decode() == "unknown code"
@@ -67,6 +67,28 @@ def test_null_arguments_rejected(lib):
     sz = _lib.BatchSizes()
     assert lib.rbp_batch_get_sizes(None, ctypes.byref(sz)) == _lib.RBP_E_INVALID
     lib.rbp_destroy_batch(None)
+
+
+def test_graph_noalloc_rejects_before_device_work(lib):
+    """The allocation-free graph run checks its arguments and the size of
+    its fixed workspace before any HIP call (so this runs without a GPU)."""
+    import numpy as np
+    host = np.zeros(16)
+    hp = host.ctypes.data
+    d = _lib.GraphDesc(1 << 20, 3, 64, 0, hp, hp, hp)
+    assert lib.rbp_graph_run_noalloc(ctypes.byref(d), hp, hp, hp, None) == _lib.RBP_E_SCRATCH
+    # the largest node count that fits with 64 rows: 2 n m + 2 ceil(n/64) m <= 2^20
+    n_fit = max(n for n in range(8000, 8200) if 2 * n * 64 + 2 * ((n + 63) // 64) * 64 <= _lib.GRAPH_NOALLOC_DOUBLES)
+    d.n_nodes = n_fit + 1
+    assert lib.rbp_graph_run_noalloc(ctypes.byref(d), hp, hp, hp, None) == _lib.RBP_E_SCRATCH
+    d.n_nodes = n_fit
+    # fits; null node and output pointers are rejected next, still on the host
+    assert lib.rbp_graph_run_noalloc(ctypes.byref(d), None, None, None, None) == _lib.RBP_E_INVALID
+    d.reserved = 1
+    assert lib.rbp_graph_run_noalloc(ctypes.byref(d), hp, hp, hp, None) == _lib.RBP_E_INVALID
+    d.reserved, d.n_rows = 0, 0
+    assert lib.rbp_graph_run_noalloc(ctypes.byref(d), hp, hp, hp, None) == _lib.RBP_E_SHAPE
+    assert lib.rbp_graph_run_noalloc(None, hp, hp, hp, None) == _lib.RBP_E_INVALID
 
 
 def test_no_cpu_fallback():
