@@ -307,6 +307,9 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
       ddn = sqrt(in.T) / K.wn_acc[dk];
     }
   }
+  // the velocity rows chained from both pinned ends bound every coordinate of
+  // P_p - P_0 by vmax T: beyond that the instance is infeasible
+  if (lane < 3) fixed_viol |= fabs(sel3(lane, in.dg[0], in.dg[1], in.dg[2])) > in.vmax * in.T * (1.0 + 1e-12);
   // ---- reachable rows: lane l owns rows l and l + 64
   double ru[2] = {0, 0}, rcst[2] = {0, 0}, rdn[2] = {0, 0};
 #pragma unroll
@@ -591,6 +594,41 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
       acc += (t <= vs) ? w : 0.0;
     }
     v0 = -in.T15 * 2.0 * in.iT3 * sel3(vc, in.dg[0], in.dg[1], in.dg[2]) * acc;
+  }
+  // Upper bound Uw of the whitened objective 1/2 |L^T x - v0|^2 over the box
+  // that holds every feasible x (velocity rows chained from both pinned
+  // ends).  With centre x_c, half-widths w and the unconstrained minimiser
+  // x_u = L^-T v0:  |L^T x - v0| <= |L^T (x_c - x_u)| + |L^T (x - x_c)|, and
+  // |L^T d|^2 = d^T P d <= sum_ij |P_ij| |d_i| |d_j|  (P = 2 Q_ff).  A dual
+  // value above Uw proves that no feasible point exists (weak duality).
+  double Uw = 0.0;
+  {
+    double bc = 0.0, bw = 0.0;
+    if (vl) L.vD[lane] = v0;
+    __syncthreads();
+    if (vl) {
+      const int k = vs + 1;
+      const double vv = in.vmax * in.T / P, dgc = sel3(vc, in.dg[0], in.dg[1], in.dg[2]);
+      const double lo = fmax(-k * vv, dgc - (P - k) * vv), hi = fmin(k * vv, dgc + (P - k) * vv);
+      bc = 0.5 * (lo + hi) - unwhiten_at<P>(L.cL1i, in.T15, L.vD, lane);
+      bw = fmax(0.5 * (hi - lo), 0.0);
+    }
+    __syncthreads();
+    if (vl) { L.vD[lane] = bc; L.vE[lane] = bw; }
+    __syncthreads();
+    double pc = 0.0, pw = 0.0;
+    if (vl) {
+#pragma unroll
+      for (int t = 0; t < NFP; ++t) {
+        const double qv = K.Q1[vs + 1][t + 1];
+        pc += qv * L.vD[3 * t + vc];
+        pw += fabs(qv) * L.vE[3 * t + vc];
+      }
+    }
+    const double cc = 2.0 * in.iT3 * wsum(bc * pc), ww = 2.0 * in.iT3 * wsum(bw * pw);
+    const double rt = sqrt(fmax(cc, 0.0)) + sqrt(fmax(ww, 0.0));
+    Uw = 0.5 * rt * rt;
+    __syncthreads();
   }
 
   // --- owner helpers: key = 2*id + (side>0)
@@ -928,6 +966,38 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
     __syncthreads();
   };
 
+  // Dual bound with multipliers lamp >= 0 on the entering row and max(lam, 0)
+  // on the working set: for every feasible x, f(x) >= L(x, mu) >= min_x L =
+  // c0 - mu'b - 1/2 |L^-1 (q + rho)|^2  (rho = sum mu_k a_k, b the rows'
+  // right-hand sides), in whitened form D = 1/2 |v0|^2 - mu'b -
+  // 1/2 |L^-1 rho - v0|^2.  D > Uw (every objective value in the box) means
+  // no feasible point exists.  Rows and right-hand sides are rebuilt here
+  // from the instance data in FP64; the margin covers rounding.
+  auto dual_bound_certified = [&](int id, int side, double e_full, double c_full, double lp) -> bool {
+    if (lane < q) L.lam[lane] = fmax(lamr, 0.0);
+    __syncthreads();
+    double rx = 0.0;
+    if (vl) {
+      const int pt = vs + 1;
+      rx = lp * double(side) * in.coef(id, pt, vc, L.Af, L.Hd);
+      for (int k = 0; k < q; ++k) rx += L.lam[k] * double(L.actside[k]) * in.coef(L.actid[k], pt, vc, L.Af, L.Hd);
+    }
+    double mb = lp * (e_full - c_full), mbabs = fabs(mb);
+    for (int k = 0; k < q; ++k) {
+      const double t = L.lam[k] * (L.acte[k] - L.actc[k]);
+      mb += t;
+      mbabs += fabs(t);
+    }
+    if (vl) L.vE[lane] = rx;
+    __syncthreads();
+    const double wr = vl ? whiten_at<P>(L.cL1i, in.T15, L.vE, lane) - v0 : 0.0;
+    const double hv = 0.5 * wsum(v0 * v0), hr = 0.5 * wsum(wr * wr);
+    const double D = hv - mb - hr;
+    __syncthreads();
+    return D > Uw + 1e-9 * (hv + hr + mbabs + Uw) + 1e-12;
+  };
+  int bound_tries = 0;
+
   bool certified_infeasible = false;
   while (true) {
     refresh_y();
@@ -1023,6 +1093,20 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
       if (lane < q) lamr -= t * rv;
       lamp += t;
       if (zfull) splus -= t * zz;
+      // dual value of the step's multipliers (the working-set rows are tight):
+      // once it passes the box bound, try the FP64 certificate
+      if (bound_tries < 4) {
+        const double dv = vl ? vw - v0 : 0.0;
+        const double dval = 0.5 * wsum(dv * dv) + lamp * fmax(splus, 0.0);
+        if (dval > Uw * (1.0 + 1e-9) + 1e-12) {
+          ++bound_tries;
+          if (dual_bound_certified(id, side, e_full, c_full, lamp)) {
+            certified_infeasible = true;
+            status = kInfeasible;
+            break;
+          }
+        }
+      }
       if (t2 <= t1) {
         append(sqrt(zz), id, side, e_full, c_full, rv);
         if (lane == q - 1) lamr = lamp;
