@@ -164,7 +164,10 @@ int rbp_batch_get_sizes(const rbp_batch* batch, rbp_batch_sizes* out);
  * collision-free by Property 1).  With opts->admm_iters > 0 an FP32 ADMM
  * stage runs first and proposes a working set; with admm_iters == 0 it is
  * skipped.  Either way the FP64 dual active-set polish decides every result:
- * the exact optimum, or infeasibility with a Farkas vector verified in FP64.
+ * the exact optimum, or infeasibility with a certificate verified in FP64 (a
+ * Farkas vector, or a dual value of the polish's multipliers above every
+ * objective value in the box that the velocity rows chained from both pinned
+ * ends give: weak duality).
  *   x0      [N][6]   start state (position, velocity); P_0 = x0[0:3]
  *   goal    [N][3]   end waypoint; P_p = goal
  *   b_face  [F] or NULL: replaces desc->b_face for this call (and backward)
@@ -250,7 +253,10 @@ int rbp_chains_get_sizes(const rbp_chains* chains, rbp_batch_sizes* out);
 /*
  * Forward pass over all paths: FP32 ADMM warm start (admm_iters > 0) with a
  * banded KKT matrix in LDS, FP64 dual active-set polish with banded Cholesky
- * solves.  Two launches on the stream: every path first runs with a small
+ * solves.  Infeasibility is reported only with a certificate checked in FP64:
+ * a Farkas vector, or a dual value of the polish's multipliers above every
+ * objective value in the box that the chained velocity rows give (weak
+ * duality).  Two launches on the stream: every path first runs with a small
  * working set; the few whose working set outgrows it are solved again by a
  * second launch at the full size, which also rewrites their outputs (until
  * it has run, status_out may hold an internal value).

@@ -209,6 +209,13 @@ __device__ __forceinline__ void chain_instance(const ChainArgs& A, const int ch,
     }
   }
   if (__ballot(bad) != 0ull) { finish(kInvalid); return; }
+  // the velocity rows chained along the joined polygon (S p edges) bound
+  // every coordinate of goal - start by S vmax T: beyond that no path exists
+  if (__ballot(lane < 3 && fabs(sel3(lane, dg[0], dg[1], dg[2])) > S * A.vmax * T * (1.0 + 1e-12)) != 0ull) {
+    if (lane == 0 && A.iters_out) { A.iters_out[2 * ch] = 0; A.iters_out[2 * ch + 1] = 0; }
+    finish(kInfeasible);
+    return;
+  }
 
   // ---- row helpers (local row numbering within segment s)
   // value of row (s, loc) on the control points of segment s (array Pp, stride 1)
@@ -746,6 +753,56 @@ __device__ __forceinline__ void chain_instance(const ChainArgs& A, const int ch,
   // ======================================================================
   const int QC = D.q_cap;
   for (int e = lane; e < (m + 31) / 32; e += kWave) L.actbits[e] = 0u;
+  // box of every feasible point (velocity rows chained along the joined
+  // polygon from both pinned ends): free coordinate e belongs to global point
+  // g = e/3 + 1 at polygon position pos(g)
+  auto box_of = [&](int e, double& lo, double& hi) {
+    const int g = e / 3 + 1, c = e - 3 * (e / 3);
+    int pos;
+    if (g <= P) pos = g;
+    else { const int s2 = (g - P - 1) / (P - 2) + 1; pos = s2 * P + 3 + (g - P - 1) % (P - 2); }
+    const double vv = A.vmax * T / P, dgc = sel3(c, dg[0], dg[1], dg[2]);
+    lo = fmax(-pos * vv, dgc - (S * P - pos) * vv);
+    hi = fmin(pos * vv, dgc + (S * P - pos) * vv);
+  };
+  // (G1 (x) I3) v at free coordinate e (band storage of the Hessian), with
+  // |G1| entries when ``absval``
+  auto gmul_at = [&](const double* v, int e, bool absval) -> double {
+    const int i = e / 3, c = e - 3 * (e / 3);
+    double acc = 0.0;
+    for (int d = -P; d <= P; ++d) {
+      const int j = i + d;
+      if (j < 0 || j >= NF) continue;
+      const int hi_ = i > j ? i : j, lo_ = i > j ? j : i;
+      const double gv = L.G1b[(hi_ + 1) * (P + 1) + (hi_ - lo_)];
+      acc += (absval ? fabs(gv) : gv) * v[3 * j + c];
+    }
+    return acc;
+  };
+  // Ub bounds 1/2 (x - x_u)' G (x - x_u) over the box: with centre x_c and
+  // half-widths w, |x - x_u|_G <= |x_c - x_u|_G + |x - x_c|_G and
+  // d' G d <= sum_ij |G_ij| |d_i| |d_j|.  A dual value (relative to the
+  // unconstrained minimum) above Ub proves that no feasible path exists.
+  double Ub = 0.0;
+  {
+    for (int e = lane; e < n; e += kWave) {
+      double lo, hi;
+      box_of(e, lo, hi);
+      L.zv[e] = 0.5 * (lo + hi) - L.xu[e];
+      L.w[e] = fmax(0.5 * (hi - lo), 0.0);
+    }
+    __syncthreads();
+    double cc = 0.0, ww = 0.0;
+    for (int e = lane; e < n; e += kWave) {
+      cc += L.zv[e] * gmul_at(L.zv, e, false);
+      ww += L.w[e] * gmul_at(L.w, e, true);
+    }
+    cc = wave::sum(cc);
+    ww = wave::sum(ww);
+    const double rt = sqrt(fmax(cc, 0.0)) + sqrt(fmax(ww, 0.0));
+    Ub = 0.5 * rt * rt;
+    __syncthreads();
+  }
   for (int e = lane; e < n; e += kWave) L.x[e] = L.xu[e];
   __syncthreads();
   int q = 0, steps = 0, status = kPolishFailed;
@@ -1019,12 +1076,47 @@ __device__ __forceinline__ void chain_instance(const ChainArgs& A, const int ch,
     if (mn >= 0.0) break;
     drop(kd);
   }
+  // dual value relative to the unconstrained minimum, 1/2 |N lam|^2 in the
+  // metric G^-1 at the warm start; each step adds t (s+ - t zz / 2)
+  double dual = 0.0;
   if (q > 0) {
     n_times(lam0, lam1, L.w);
+    {
+      double f0, f1, f2;
+      gfwd(L.w, f0, f1, f2);
+      dual = 0.5 * wave::sum(lane < NF ? f0 * f0 + f1 * f1 + f2 * f2 : 0.0);
+    }
     gsolve(L.w, L.zv);
     for (int e = lane; e < n; e += kWave) L.x[e] = L.xu[e] - L.zv[e];
     __syncthreads();
   }
+  // FP64 check of the dual bound for multipliers lp >= 0 on the entering
+  // row (normal in np) and max(lam, 0) on the working set: every feasible
+  // x has f(x) >= min_x f(x) + rho'x - mu'e = f(x_u) + rho'x_u -
+  // 1/2 rho' G^-1 rho - mu'e  (rho = sum mu_k n_k); certified when that
+  // exceeds f(x_u) + Ub.  Uses L.w and L.zv as scratch.
+  auto dual_bound_certified = [&](double e_free, double lp) -> bool {
+    const double m0 = e0 < q ? fmax(lam0, 0.0) : 0.0, m1 = e1 < q ? fmax(lam1, 0.0) : 0.0;
+    n_times(m0, m1, L.w);
+    double mb = lp * e_free, mbabs = fabs(mb);
+    for (int k = 0; k < q; ++k) {
+      const double t = pick(m0, m1, k) * L.acte[k];
+      mb += t;
+      mbabs += fabs(t);
+    }
+    for (int e = lane; e < n; e += kWave) L.zv[e] = lp * L.np[e] + L.w[e];
+    __syncthreads();
+    double f0, f1, f2;
+    gfwd(L.zv, f0, f1, f2);
+    const double rgr = wave::sum(lane < NF ? f0 * f0 + f1 * f1 + f2 * f2 : 0.0);
+    double rxu = 0.0;
+    for (int e = lane; e < n; e += kWave) rxu += L.zv[e] * L.xu[e];
+    rxu = wave::sum(rxu);
+    const double D = rxu - 0.5 * rgr - mb;
+    __syncthreads();
+    return D > Ub + 1e-9 * (fabs(rxu) + 0.5 * rgr + mbabs + Ub) + 1e-12;
+  };
+  int bound_tries = 0;
 
   // ---- main loop
   bool infeasible = false;
@@ -1119,13 +1211,8 @@ __device__ __forceinline__ void chain_instance(const ChainArgs& A, const int ch,
         bool empty = false;
         for (int e = lane; e < n; e += kWave) {
           const double rr = L.np[e] + L.w[e];
-          const int g = e / 3 + 1, c = e - 3 * (e / 3);
-          int pos;
-          if (g <= P) pos = g;
-          else { const int s2 = (g - P - 1) / (P - 2) + 1; pos = s2 * P + 3 + (g - P - 1) % (P - 2); }
-          const double vv = A.vmax * T / P, dgc = sel3(c, dg[0], dg[1], dg[2]);
-          const double lo = fmax(-pos * vv, dgc - (S * P - pos) * vv);
-          const double hi = fmin(pos * vv, dgc + (S * P - pos) * vv);
+          double lo, hi;
+          box_of(e, lo, hi);
           empty |= lo > hi;
           mb += rr > 0.0 ? rr * lo : rr * hi;
         }
@@ -1136,6 +1223,7 @@ __device__ __forceinline__ void chain_instance(const ChainArgs& A, const int ch,
         break;
       }
       const double t = fmin(t1, t2);
+      dual += t * (splus - 0.5 * t * (zfull ? zz : 0.0));
       if (zfull) {
         for (int e = lane; e < n; e += kWave) L.x[e] -= t * L.zv[e];
       }
@@ -1144,6 +1232,15 @@ __device__ __forceinline__ void chain_instance(const ChainArgs& A, const int ch,
       lamp += t;
       if (zfull) splus -= t * zz;
       __syncthreads();
+      // the dual value passed the box bound: try the FP64 certificate
+      if (bound_tries < 4 && dual > Ub * (1.0 + 1e-9) + 1e-12) {
+        ++bound_tries;
+        if (dual_bound_certified(e_free, lamp)) {
+          status = kInfeasible;
+          infeasible = true;
+          break;
+        }
+      }
       if (t2 <= t1) {
         append_factor(id, side, c0, c1, zz);
         if (e0 == q - 1) lam0 = lamp;
