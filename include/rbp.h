@@ -478,10 +478,17 @@ int rbp_build_mpc(const rbp_mpc_desc* desc, hipStream_t stream, rbp_mpc** out);
  *   U       [n][N][3]     inputs
  *   cost    [n]           objective value
  *   status  [n]           RBP_SOLVED (scaled KKT residual of the returned
- *                         point <= 1e-6), RBP_MAXITER (stopped before that:
- *                         iteration cap, or a Newton system that broke down;
- *                         infeasible instances end here and are not
- *                         certified), RBP_NUMERICAL (converged by the
+ *                         point <= 1e-6), RBP_INFEASIBLE (a certificate
+ *                         checked in FP64: with the last multipliers w >= 0
+ *                         and a least-squares terminal costate, the affine
+ *                         function sum w_i (row_i - bound_i) + pi'(x_N - r_N)
+ *                         of the inputs is positive over the whole input box
+ *                         that the rows acting on u alone allow; X, U NaN,
+ *                         cost +inf), RBP_MAXITER (stopped before a KKT
+ *                         residual <= 1e-6 without such a certificate:
+ *                         iteration cap or a Newton system that broke down;
+ *                         also every infeasible instance when no row bounds
+ *                         the inputs alone), RBP_NUMERICAL (converged by the
  *                         tolerances above, residual still above 1e-6),
  *                         RBP_INVALID_INPUT (non-finite input or a zero
  *                         plane normal; X, U, cost are NaN).  Otherwise X,

@@ -2,6 +2,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
+#include <limits>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -715,6 +717,8 @@ struct rbp_mpc {
   int device = 0;
   rbp_mpc_desc desc{};
   double* params = nullptr;
+  double ulo[3] = {0, 0, 0}, uhi[3] = {0, 0, 0};
+  int ubox_ok = 0;
   hipStream_t last_stream = nullptr;
 };
 
@@ -813,6 +817,57 @@ int mpc_params(const rbp_mpc_desc& d, const std::vector<double>& F1, const std::
   return RBP_OK;
 }
 
+// Box of every input u_k allowed by the reachable rows that act on the input
+// alone: rows of F1 x_k + F2 x_{k+1} <= G whose coefficients on x_k vanish
+// exactly once x_{k+1} = A x_k + B u_k is substituted, g'u <= G_i with
+// g = (F2 B)_i.  Bound propagation over the three components from an
+// unbounded start (each row bounds one component given the bounds of the
+// others); the result is widened by 1e-12 (1 + |bound|) against rounding.
+// Returns false when a component stays unbounded.
+bool mpc_input_box(int m, double dt, const std::vector<double>& F1, const std::vector<double>& F2,
+                   const std::vector<double>& G, double lo[3], double hi[3]) {
+  const double h2 = 0.5 * dt * dt;
+  std::vector<std::array<double, 3>> gs;
+  std::vector<double> ds;
+  for (int i = 0; i < m; ++i) {
+    bool input_only = true;
+    for (int a = 0; a < 6 && input_only; ++a) {
+      // (F1 + F2 A) column a; A = [[I, dt I], [0, I]]
+      double v = F1[size_t(6 * i + a)] + F2[size_t(6 * i + a)];
+      if (a >= 3) v += dt * F2[size_t(6 * i + a - 3)];
+      input_only = v == 0.0;
+    }
+    if (!input_only) continue;
+    std::array<double, 3> g{};
+    for (int c = 0; c < 3; ++c) g[c] = h2 * F2[size_t(6 * i + c)] + dt * F2[size_t(6 * i + 3 + c)];
+    gs.push_back(g);
+    ds.push_back(G[size_t(i)]);
+  }
+  const double inf = std::numeric_limits<double>::infinity();
+  for (int c = 0; c < 3; ++c) { lo[c] = -inf; hi[c] = inf; }
+  for (int sweep = 0; sweep < 8; ++sweep)
+    for (size_t r = 0; r < gs.size(); ++r)
+      for (int c = 0; c < 3; ++c) {
+        const double gc = gs[r][c];
+        if (gc == 0.0) continue;
+        double rest = 0.0;   // min of the other terms
+        for (int c2 = 0; c2 < 3; ++c2) {
+          if (c2 == c || gs[r][c2] == 0.0) continue;
+          rest += gs[r][c2] > 0.0 ? gs[r][c2] * lo[c2] : gs[r][c2] * hi[c2];
+        }
+        if (!std::isfinite(rest)) continue;
+        const double b = (ds[r] - rest) / gc;
+        if (gc > 0.0) hi[c] = std::min(hi[c], b);
+        else lo[c] = std::max(lo[c], b);
+      }
+  for (int c = 0; c < 3; ++c) {
+    if (!std::isfinite(lo[c]) || !std::isfinite(hi[c]) || lo[c] > hi[c]) return false;
+    lo[c] -= 1e-12 * (1.0 + std::fabs(lo[c]));
+    hi[c] += 1e-12 * (1.0 + std::fabs(hi[c]));
+  }
+  return true;
+}
+
 bool sym_psd_diag(const double* M, int n) {
   for (int a = 0; a < n; ++a) {
     if (!std::isfinite(M[n * a + a]) || M[n * a + a] < 0.0) return false;
@@ -861,6 +916,7 @@ int rbp_build_mpc(const rbp_mpc_desc* d, hipStream_t stream, rbp_mpc** out) {
   if (!q) return RBP_E_ALLOC;
   q->device = dev;
   q->desc = *d;
+  q->ubox_ok = mpc_input_box(m, d->dt, F1, F2, G, q->ulo, q->uhi) ? 1 : 0;
   if ((rc = dalloc(&q->params, prm.size()))) { delete q; return rc; }
   if (hipMemcpyAsync(q->params, prm.data(), prm.size() * sizeof(double), hipMemcpyHostToDevice, stream) ||
       hipStreamSynchronize(stream)) {
@@ -886,6 +942,8 @@ int rbp_mpc_solve(rbp_mpc* q, const double* x0, const double* ref, const double*
   a.params = q->params;
   a.x0 = x0; a.ref = ref; a.planes = planes;
   a.X = X; a.U = U; a.cost = cost; a.status = status; a.kkt = kkt; a.iters = iters;
+  for (int c = 0; c < 3; ++c) { a.ulo[c] = q->ulo[c]; a.uhi[c] = q->uhi[c]; }
+  a.ubox_ok = q->ubox_ok;
   if (rbp::launch_mpc(a, stream) != hipSuccess) return RBP_E_DEVICE;
   q->last_stream = stream;
   return RBP_OK;

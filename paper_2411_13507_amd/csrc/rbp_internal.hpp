@@ -231,6 +231,10 @@ struct MpcArgs {
   int32_t* status;           // [n]
   double* kkt;               // [n]
   int32_t* iters;            // [n] or null
+  // box of every input u_k from the rows that act on the input alone
+  // (ubox_ok = 0: those rows leave some component unbounded, no certificate)
+  double ulo[3], uhi[3];
+  int ubox_ok;
 };
 size_t mpc_lds_bytes(int N, int m);
 hipError_t launch_mpc(const MpcArgs& a, hipStream_t s);

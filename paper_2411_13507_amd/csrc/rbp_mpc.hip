@@ -37,7 +37,7 @@ namespace rbp {
 namespace {
 
 constexpr int kW = 64;
-constexpr int kSolved = 0, kMaxIter = 2, kNumerical = 4, kInvalid = 5;
+constexpr int kSolved = 0, kInfeasible = 1, kMaxIter = 2, kNumerical = 4, kInvalid = 5;
 
 // LDS carve, in doubles.  The per-row state (slack, multiplier, primal
 // residual, Newton weight) lives in registers of the lane that owns the row;
@@ -438,14 +438,21 @@ struct MpcCtx {
 
   // least-squares costates and the u-stationarity residual rho_k (into
   // S.rho), with the multipliers in S.X; returns max |rho| and the scale of
-  // the gradient terms
-  __device__ __forceinline__ void dual_residual(double& rmax, double& gscale) {
+  // the gradient terms.  kCost = false leaves the cost out: rho is then the
+  // gradient in the inputs of sum_i w_i c_i'z + pi'x_N along trajectories of
+  // the dynamics from x0, with the terminal costate pi (returned in pi6 when
+  // given) chosen by least squares.
+  template <bool kCost = true>
+  __device__ __forceinline__ void dual_residual(double& rmax, double& gscale, double* pi6 = nullptr) {
     double gs = 0.0;
     for (int e = lane; e < 9 * N; e += kW) {
       const int k = e / 9, a = e - 9 * (e / 9);
-      const double* H = Hk(k);
-      double hz = hk(k, a);
-      for (int b = 0; b < 9; ++b) hz += H[9 * a + b] * S.z[9 * k + b];
+      double hz = 0.0;
+      if constexpr (kCost) {
+        const double* H = Hk(k);
+        hz = hk(k, a);
+        for (int b = 0; b < 9; ++b) hz += H[9 * a + b] * S.z[9 * k + b];
+      }
       const double ct = ct_times(k, a, S.X + k * mr);
       S.g[e] = hz + ct;
       gs = fmax(gs, fmax(fabs(hz), fabs(ct)));
@@ -514,6 +521,9 @@ struct MpcCtx {
       const double b1 = -t_af[cc], b2 = -dt * t_f[cc];
       pp[cc] = (a22 * b1 - a12 * b2) / det;
       pv[cc] = (a11 * b2 - a12 * b1) / det;
+    }
+    if (pi6) {
+      for (int cc = 0; cc < 3; ++cc) { pi6[cc] = pp[cc]; pi6[3 + cc] = pv[cc]; }
     }
     __syncthreads();
     double rm = 0.0;
@@ -761,11 +771,77 @@ __global__ __launch_bounds__(kW) void mpc_kernel(MpcArgs A) {
     A.X[xo + 6 * N + lane] = v;
   }
   for (int e = lane; e < 3 * N; e += kW) A.U[(int64_t)inst * 3 * N + e] = S.z[9 * (e / 3) + 6 + e % 3];
+  const bool solved = kkt <= 1e-6 && isfinite(cost);
   if (lane == 0) {
     A.cost[inst] = cost;
     A.kkt[inst] = kkt;
-    A.status[inst] = (kkt <= 1e-6 && isfinite(cost)) ? kSolved : (converged ? kNumerical : kMaxIter);
+    A.status[inst] = solved ? kSolved : (converged ? kNumerical : kMaxIter);
     if (A.iters) A.iters[inst] = it;
+  }
+  if (solved || converged || !A.ubox_ok) return;
+
+  // ---- infeasibility certificate for a horizon the iterations did not solve.
+  // With w >= 0 on the rows (the last multipliers, scaled to max 1) and the
+  // terminal costate pi, Phi(u) = sum_i w_i (c_i'z(u) - d_i) + pi'(x_N(u) - r_N)
+  // is affine in the inputs u along trajectories of the dynamics from x0,
+  // Phi(u) = Phi(0) + rho'u, and Phi(u) <= 0 for every feasible u.  Every
+  // feasible u_k also lies in the input box of the rows that act on u alone.
+  // So Phi(0) + min over the box of rho'u > 0 proves that no feasible
+  // trajectory exists (FP64, with a margin for rounding).
+  {
+    double lm = 0.0;
+    C.template for_rows<RS, false, false>([&](int j, int, double, double, double) { lm = fmax(lm, rl[j]); });
+    lm = wave::max(lm);
+    const double isc = (lm > 0.0 && isfinite(lm)) ? 1.0 / lm : 0.0;
+    C.template for_rows<RS, false, false>([&](int j, int r, double, double, double) { S.X[r] = rl[j] * isc; });
+    __syncthreads();
+    double rdm = 0.0, gsc = 0.0, pi6[6];
+    C.template dual_residual<false>(rdm, gsc, pi6);
+    // free response: zero inputs from x0
+    for (int e = lane; e < 9 * N; e += kW) {
+      const int k = e / 9, a = e - 9 * (e / 9);
+      S.z[e] = a < 3 ? x0[a] + k * dt * x0[3 + a] : (a < 6 ? x0[a] : 0.0);
+    }
+    __syncthreads();
+    double phi = 0.0, pab = 0.0;
+    C.template for_rows<RS, true, false>([&](int, int r, double cz, double, double d) {
+      const double w = S.X[r];
+      phi += w * (cz - d);
+      pab += w * (fabs(cz) + fabs(d));
+    });
+    phi = wave::sum(phi);
+    pab = wave::sum(pab);
+    double tn = 0.0, tnab = 0.0;
+    for (int c = 0; c < 3; ++c) {
+      const double ep = x0[c] + N * dt * x0[3 + c] - S.ref[6 * N + c], ev = x0[3 + c] - S.ref[6 * N + 3 + c];
+      tn += pi6[c] * ep + pi6[3 + c] * ev;
+      tnab += fabs(pi6[c] * ep) + fabs(pi6[3 + c] * ev);
+    }
+    double mb = 0.0, mbab = 0.0, umax = 0.0;
+    for (int e = lane; e < 3 * N; e += kW) {
+      const int c = e - 3 * (e / 3);
+      const double lo = c == 0 ? A.ulo[0] : (c == 1 ? A.ulo[1] : A.ulo[2]);
+      const double hi = c == 0 ? A.uhi[0] : (c == 1 ? A.uhi[1] : A.uhi[2]);
+      const double r = S.rho[e];
+      mb += r > 0.0 ? r * lo : r * hi;
+      mbab += fabs(r) * fmax(fabs(lo), fabs(hi));
+      umax = fmax(umax, fmax(fabs(lo), fabs(hi)));
+    }
+    mb = wave::sum(mb);
+    mbab = wave::sum(mbab);
+    umax = wave::max(umax);
+    // rounding: relative 1e-9 of every magnitude that entered, including the
+    // costate recursion behind rho (N stages, growth N dt)
+    const double margin = 1e-9 * (pab + tnab + mbab + 3.0 * N * umax * gsc * N * (1.0 + N * dt)) + 1e-300;
+    if (phi + tn + mb > margin && isfinite(phi + tn + mb)) {
+      for (int e = lane; e < 6 * (N + 1); e += kW) A.X[xo + e] = __builtin_nan("");
+      for (int e = lane; e < 3 * N; e += kW) A.U[(int64_t)inst * 3 * N + e] = __builtin_nan("");
+      if (lane == 0) {
+        A.cost[inst] = __builtin_huge_val();
+        A.kkt[inst] = __builtin_nan("");
+        A.status[inst] = kInfeasible;
+      }
+    }
   }
 }
 

@@ -89,13 +89,17 @@ def test_mpc_full_batch(gpu_available):
     out = run(b)
     ok = out["status"] == qp.SOLVED
     print("statuses", np.bincount(out["status"], minlength=6).tolist(), flush=True)
+    # every horizon ends solved or certified infeasible
+    assert set(np.unique(out["status"]).tolist()) <= {qp.SOLVED, qp.INFEASIBLE}
     assert ok.mean() >= 0.995
     assert np.all(out["kkt"][ok] <= TOL)
-    # every instance the GPU did not solve is one the oracle certifies infeasible
+    # every horizon the GPU certifies infeasible is one the oracle certifies
+    # infeasible (statuses bit-exact there), with the infeasible outputs
     rest = [int(i) for i in np.nonzero(~ok)[0]]
     with mp.get_context("fork").Pool(8) as pool:
         orc = pool.map(_oracle, [b.instance(i) for i in rest])
     assert all(o[0] == qp.INFEASIBLE for o in orc), [(i, o[0]) for i, o in zip(rest, orc)]
+    assert np.all(np.isinf(out["cost"][rest])) and np.isnan(out["X"][rest]).all()
     check_properties(b.subset(np.nonzero(ok)[0]), {k: v[ok] for k, v in out.items()})
     idx = np.random.default_rng(41).choice(np.nonzero(ok)[0], 48, replace=False)
     compare(b, out, [int(i) for i in idx], "mpc4096-sampled")
@@ -120,7 +124,7 @@ def test_mpc_horizons_and_row_counts(gpu_available, N, m_extra):
     assert len(ok) >= b.n // 2
     for i, o in zip(idx, orc):
         if o[0] == qp.INFEASIBLE:
-            assert out["status"][i] != qp.SOLVED
+            assert out["status"][i] == qp.INFEASIBLE, (i, out["status"][i])
     compare(b, out, ok, f"mpc-N{N}-m{b.G.size}")
 
 
@@ -135,8 +139,28 @@ def test_mpc_invalid_and_infeasible(gpu_available):
     from paper_2411_13507_amd import _lib
     assert out["status"][1] == _lib.INVALID_INPUT and out["status"][2] == _lib.INVALID_INPUT
     assert np.isnan(out["X"][1]).all() and np.isnan(out["cost"][2])
-    assert out["status"][3] != qp.SOLVED
+    assert ompc.solve(b.instance(3) | {"x0": b.x0[3], "planes": planes[3]}).status == qp.INFEASIBLE
+    assert out["status"][3] == qp.INFEASIBLE and np.isinf(out["cost"][3]) and np.isnan(out["U"][3]).all()
     compare(b, out, [0, 4, 5], "mpc-rest")
+
+
+def test_mpc_no_certificate_without_an_input_box(gpu_available):
+    """With only the velocity box as reachable rows no row acts on the input
+    alone, so no input box exists and an infeasible horizon (a plane that
+    cuts the fixed start) may not be reported infeasible: it ends without a
+    verified answer.  The other horizons still match the oracle."""
+    b = gen.gen_mpc(4)
+    b.F1, b.F2, b.G = b.F1[:6].copy(), b.F2[:6].copy(), b.G[:6].copy()
+    planes = b.planes.copy()
+    n = planes[1, 0, :3]
+    planes[1, 0, 3] = n @ b.x0[1, :3] + 0.05 * np.linalg.norm(n)
+    assert ompc.solve(b.instance(1) | {"planes": planes[1]}).status == qp.INFEASIBLE
+    out = run(b, planes=planes)
+    assert out["status"][1] not in (qp.SOLVED, qp.INFEASIBLE), out["status"][1]
+    with mp.get_context("fork").Pool(4) as pool:
+        orc = pool.map(_oracle, [b.instance(i) for i in (0, 2, 3)])
+    for i, o in zip((0, 2, 3), orc):
+        assert out["status"][i] == o[0], (i, out["status"][i], o[0])
 
 
 def test_mpc_graph_capture_replays(gpu_available):
