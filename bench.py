@@ -93,7 +93,7 @@ def roofline_record(flops, nbytes, t_launch):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("rbp_kernels.hip", "rbp_api.cpp", "rbp_internal.hpp", "rbp_consts.hpp", "rbp_wave.hpp"):
+    for f in ("rbp_kernels.hip", "rbp_segment.hpp", "rbp_api.cpp", "rbp_internal.hpp", "rbp_consts.hpp", "rbp_wave.hpp"):
         with open(os.path.join(ROOT, "paper_2411_13507_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -211,8 +211,8 @@ def _variant(sb, main_opts, reps, stream):
         sg.solve(sx0, sgoal, opts=main_opts, out=sres)
         holder["g"] = sg.backward(sgP, sgC, out=holder.get("g"))
     t = time_launches(fb, reps, stream)
-    fo = _lib.default_opts()
-    fo.admm_iters, fo.rho, fo.store_for_backward = main_opts.admm_iters, main_opts.rho, 0
+    fo = _lib.SolveOpts.from_buffer_copy(main_opts)
+    fo.store_for_backward = 0
     t_f = time_launches(lambda: sg.solve(sx0, sgoal, opts=fo, out=sres), reps, stream)
     st = sres.status.cpu().numpy()
     kk = sres.kkt.cpu().numpy()
@@ -250,19 +250,36 @@ def extra_workloads(reps=3, admm_iters=-1, edges=None, main_opts=None):
     x0, goal = torch.as_tensor(b.x0, device=dev), torch.as_tensor(b.goal, device=dev)
     res = gb.alloc_outputs()
     from paper_2411_13507_amd import autotune
+    tuning = None
     if admm_iters >= 0:
         uo = _lib.default_opts()
         uo.admm_iters = admm_iters
     else:
         uo = autotune.tune(b, sample=b.n, reps=2, use_cache=False)
+        tuning = autotune.tune.last
     uo.store_for_backward = 0
-    t = time_launches(lambda: gb.solve(x0, goal, opts=uo, out=res), reps, stream)
+    # the tuned solve (every launch of its schedule) captured in one HIP graph
+    gb.solve(x0, goal, opts=uo, out=res)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream(device=dev)
+    side.wait_stream(stream)
+    with torch.cuda.stream(side):
+        gb.solve(x0, goal, opts=uo, out=res)
+    stream.wait_stream(side)
+    ugraph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(ugraph):
+        gb.solve(x0, goal, opts=uo, out=res)
+    t = time_launches(ugraph.replay, reps, stream)
     st = res.status.cpu().numpy()
     kk = res.kkt.cpu().numpy()
     ok = int(((st == 0) & (kk <= KKT_OK)).sum() + (st == 1).sum())
-    out["uneven200k_p3to9"] = {"fwd_ms": t * 1e3, "solves_per_s": ok / t, "instances": b.n,
+    out["uneven200k_p3to9"] = {"fwd_ms": t * 1e3, "solves_per_s": ok / t, "instances": b.n, "launch": "hipgraph",
                                "admm_iters": int(uo.admm_iters), "rho": round(float(uo.rho), 6),
-                               "status_counts": np.bincount(st, minlength=6).tolist()}
+                               "schedule": int(uo.schedule), "launch_shape": int(uo.launch_shape),
+                               "status_counts": np.bincount(st, minlength=6).tolist(),
+                               "tuning_ms": None if tuning is None else {"admm/rho": tuning["ms"],
+                                                                         "launch": tuning["ms_launch"]}}
+    del ugraph
     gb.close()
     del b, gb, res
     # graph cut (Alg. 2 + Cut-QP): 50,000 edges x 200 box obstacles, codes and
@@ -393,7 +410,9 @@ def main():
         # (every candidate reaches the same optima; see autotune.py)
         from paper_2411_13507_amd import autotune
         opts = autotune.tune(b, sample=b.n, reps=3, use_cache=False)
-        tuned = {"admm_iters": int(opts.admm_iters), "rho": round(float(opts.rho), 6)}
+        tuned = {"admm_iters": int(opts.admm_iters), "rho": round(float(opts.rho), 6),
+                 "schedule": int(opts.schedule), "launch_shape": int(opts.launch_shape),
+                 "launch_ms": autotune.tune.last["ms_launch"]}
     out = gb.alloc_outputs()
     grads = None
 
@@ -439,9 +458,7 @@ def main():
     value = counted / dt
 
     # forward kernel alone, HIP events on the launch stream
-    fopts = _lib.default_opts()
-    fopts.admm_iters = opts.admm_iters
-    fopts.rho = opts.rho
+    fopts = _lib.SolveOpts.from_buffer_copy(opts)
     fopts.store_for_backward = 0
     stream = torch.cuda.current_stream(dev)
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
@@ -471,7 +488,13 @@ def main():
     roof = roofline_record(flops, nbytes, t_solve)
     roof["traffic"] = traffic_from_profile(b.n)
     admm_on = int(opts.admm_iters) > 0
-    kernel_name = f"solve_kernel<float, 7, {'true' if admm_on else 'false'}>"
+    if int(opts.schedule) == 1:
+        kernel_name = f"solve_kernel_all<{'true' if admm_on else 'false'}>"
+    elif int(opts.launch_shape) != 0:
+        wpg, wpe = {1: (1, 1), 2: (2, 2)}[int(opts.launch_shape)]
+        kernel_name = f"solve_kernel_shape<7, {'true' if admm_on else 'false'}, {wpg}, {wpe}>"
+    else:
+        kernel_name = f"solve_kernel<float, 7, {'true' if admm_on else 'false'}>"
     dtype = "fp32+fp64" if admm_on else "fp64"
     roof["kernel"] = kernel_name
     roof["launch_ms"] = t_solve * 1e3
@@ -571,7 +594,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "edges50k_p7_clutter", "instances": b.n, "degree": 7, "faces": "8-24",
                    "reach_rows": 32, "admm_iters": int(opts.admm_iters), "rho": round(float(opts.rho), 6),
-                   "options": "autotuned" if tuned is not None else "fixed",
+                   "schedule": int(opts.schedule), "launch_shape": int(opts.launch_shape),
+                   "options": "autotuned" if tuned is not None else "fixed", "tuning": tuned,
                    "obstacles": 200, "polytopes": 2000, "launch": launch},
         "roofline": roof,
         "error_vs_oracle": err,

@@ -127,6 +127,19 @@ typedef struct rbp_solve_opts {
   int32_t store_for_backward; /* keep the active set for rbp_backward             */
   int32_t plain;              /* 1: FP64 iterations, one kernel launch per
                                  instance (the unbatched baseline)                */
+  int32_t launch_shape;       /* grouped schedule: 0 = one instance (wavefront)
+                                 per workgroup, registers sized for two
+                                 wavefronts per SIMD; 1 = one per workgroup,
+                                 registers for one wavefront per SIMD; 2 = two
+                                 instances per workgroup, each wavefront on its
+                                 own LDS slice.  Ignored with plain, with
+                                 schedule 1, and with FP64 iterations       */
+  int32_t schedule;           /* 0 = one launch per (degree, reachable-row
+                                 class) group, LDS sized per group; 1 = one
+                                 launch for the whole batch (degree chosen in
+                                 the kernel, LDS sized for the largest
+                                 instance).  The backward pass follows the
+                                 schedule of the forward pass it differentiates */
 } rbp_solve_opts;
 
 /* Sizes of the variable-length outputs of a batch (host struct). */
@@ -141,7 +154,7 @@ typedef struct rbp_batch rbp_batch;
 
 /* Fills *o with the defaults: admm_iters 10, rho 0.1, alpha 1.6,
  * max_polish_steps 0, feas_tol 1e-11, kkt_tol 1e-6, store_for_backward 1,
- * plain 0. */
+ * plain 0, launch_shape 0, schedule 0. */
 void rbp_default_opts(rbp_solve_opts* o);
 
 /*

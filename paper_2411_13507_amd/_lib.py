@@ -71,6 +71,7 @@ class SolveOpts(ctypes.Structure):
         ("admm_iters", ctypes.c_int32), ("rho", ctypes.c_float), ("alpha", ctypes.c_float),
         ("max_polish_steps", ctypes.c_int32), ("feas_tol", ctypes.c_double),
         ("kkt_tol", ctypes.c_double), ("store_for_backward", ctypes.c_int32), ("plain", ctypes.c_int32),
+        ("launch_shape", ctypes.c_int32), ("schedule", ctypes.c_int32),
     ]
 
 

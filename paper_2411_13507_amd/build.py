@@ -12,8 +12,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librbp.so")
-SOURCES = ["rbp_kernels.hip", "rbp_chain.hip", "rbp_cut.hip", "rbp_graph.hip", "rbp_mpc.hip", "rbp_api.cpp"]
-HEADERS = ["rbp_consts.hpp", "rbp_internal.hpp", "rbp_wave.hpp"]
+SOURCES = ["rbp_kernels.hip", "rbp_kernels_var.hip", "rbp_chain.hip", "rbp_cut.hip", "rbp_graph.hip", "rbp_mpc.hip", "rbp_api.cpp"]
+HEADERS = ["rbp_consts.hpp", "rbp_internal.hpp", "rbp_segment.hpp", "rbp_wave.hpp"]
 
 # device-code flags: gfx950 only; packed FP32 instructions disabled (the
 # compiler would otherwise form v_pk_* FP32 ops from scalar code)

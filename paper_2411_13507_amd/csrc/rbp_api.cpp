@@ -41,10 +41,13 @@ struct rbp_batch {
   double* fw_bface = nullptr;   // copy of the b_face actually used
   int64_t F_total = 0;
   bool has_forward = false;
+  int32_t fw_schedule = 0;      // schedule of the stored forward pass
   hipStream_t last_stream = nullptr;
 };
 
 namespace {
+// LDS of one workgroup on gfx950
+constexpr size_t kLdsBytes = 160 * 1024;
 
 std::mutex g_const_mu;
 std::vector<int> g_const_done;
@@ -52,7 +55,8 @@ std::vector<int> g_const_done;
 int ensure_constants(int device) {
   std::lock_guard<std::mutex> lk(g_const_mu);
   if (std::find(g_const_done.begin(), g_const_done.end(), device) != g_const_done.end()) return RBP_OK;
-  if (rbp::upload_constants(device) != hipSuccess) return RBP_E_DEVICE;
+  if (rbp::upload_constants(device) != hipSuccess || rbp::upload_constants_var(device) != hipSuccess)
+    return RBP_E_DEVICE;
   g_const_done.push_back(device);
   return RBP_OK;
 }
@@ -96,6 +100,8 @@ void rbp_default_opts(rbp_solve_opts* o) {
   o->kkt_tol = 1e-6;
   o->store_for_backward = 1;
   o->plain = 0;
+  o->launch_shape = 0;
+  o->schedule = 0;
 }
 
 const char* rbp_status_string(int code) {
@@ -250,7 +256,8 @@ int rbp_solve_batch(rbp_batch* b, const double* x0, const double* goal, const do
   rbp_default_opts(&o);
   if (opts_in) o = *opts_in;
   if (o.admm_iters < 0 || !(o.rho > 0.0f) || !(o.alpha > 0.0f) || !(o.alpha < 2.0f) || o.max_polish_steps < 0 ||
-      !(o.feas_tol > 0.0) || !(o.kkt_tol > 0.0))
+      !(o.feas_tol > 0.0) || !(o.kkt_tol > 0.0) || o.launch_shape < 0 || o.launch_shape > 2 ||
+      o.schedule < 0 || o.schedule > 1)
     return RBP_E_INVALID;
   b->has_forward = false;
   if (b->N == 0) return RBP_OK;
@@ -280,6 +287,12 @@ int rbp_solve_batch(rbp_batch* b, const double* x0, const double* goal, const do
       a.inst_base = i;
       e = rbp::launch_solve(a, 1, stream, true, b->degree_host[i]);
     }
+  } else if (o.schedule == 1) {
+    a.order = b->d_order;
+    a.dims = rbp::make_dims(b->pmax, b->rmax, b->nfmax, 4, o.admm_iters > 0);
+    a.inst_base = 0;
+    a.N = b->N;
+    e = rbp::launch_solve_all(a, b->N, stream);
   } else {
     a.order = b->d_order;
     for (size_t k = 0; k < b->groups.size() && e == hipSuccess; ++k) {
@@ -287,11 +300,16 @@ int rbp_solve_batch(rbp_batch* b, const double* x0, const double* goal, const do
       a.dims = rbp::make_dims(g.p, g.rmax, g.nfmax, 4, o.admm_iters > 0);
       a.inst_base = g.start;
       a.N = g.start + g.count;
-      e = rbp::launch_solve(a, g.count, stream, false, g.p);
+      // two instances per workgroup only while both slices fit the LDS
+      int shape = o.launch_shape;
+      if (rbp::kShapeWaves[shape] * size_t(a.dims.bytes) > kLdsBytes) shape = rbp::kShapeW1E2;
+      e = shape == rbp::kShapeW1E2 ? rbp::launch_solve(a, g.count, stream, false, g.p)
+                                   : rbp::launch_solve_shape(a, g.count, stream, g.p, shape);
     }
   }
   if (e != hipSuccess) return RBP_E_DEVICE;
   b->last_stream = stream;
+  b->fw_schedule = o.schedule;
   if (o.store_for_backward) {
     const size_t n1 = size_t(b->N);
     if (hipMemcpyAsync(b->fw_P, P_out, size_t(3 * b->pt_total) * sizeof(double), hipMemcpyDeviceToDevice, stream) ||
@@ -327,6 +345,13 @@ int rbp_backward(rbp_batch* b, const double* grad_P, const double* grad_cost, do
   a.grad_x0 = grad_x0; a.grad_goal = grad_goal; a.grad_b = grad_b; a.flags = flags_out;
   a.order = b->d_order;
   a.st_stride = b->nmax;
+  if (b->fw_schedule == 1) {
+    a.dims = rbp::make_dims(b->pmax, b->rmax, b->nfmax, 8, false);
+    a.inst_base = 0;
+    if (rbp::launch_backward_all(a, b->N, stream) != hipSuccess) return RBP_E_DEVICE;
+    b->last_stream = stream;
+    return RBP_OK;
+  }
   for (size_t k = 0; k < b->groups.size(); ++k) {
     const rbp_batch::Group& g = b->groups[k];
     a.dims = rbp::make_dims(g.p, g.rmax, g.nfmax, 8, false);

@@ -245,7 +245,18 @@ ChainDims make_chain_dims(int p, int s_cap, int nf_cap, int r_cap, int q_cap, bo
 hipError_t upload_chain_constants(int device);
 hipError_t launch_chains(const ChainArgs& a, hipStream_t s);
 hipError_t upload_constants(int device);
+// launch shapes of the grouped solve: waves (instances) per workgroup and the
+// waves per SIMD the register budget is sized for
+constexpr int kShapeW1E2 = 0, kShapeW1E1 = 1, kShapeW2E2 = 2;
+constexpr int kShapeWaves[3] = {1, 1, 2};
+// default shape (rbp_kernels.hip)
 hipError_t launch_solve(const SolveArgs& a, int n_blocks, hipStream_t s, bool fp64_iters, int pfix);
 hipError_t launch_backward(const BackArgs& a, int n_blocks, hipStream_t s, int pfix);
+// other shapes and the single-launch schedule (rbp_kernels_var.hip, FP32
+// iterations or polish only); that unit has its own constant table
+hipError_t upload_constants_var(int device);
+hipError_t launch_solve_shape(const SolveArgs& a, int n_inst, hipStream_t s, int pfix, int shape);
+hipError_t launch_solve_all(const SolveArgs& a, int n_inst, hipStream_t s);
+hipError_t launch_backward_all(const BackArgs& a, int n_inst, hipStream_t s);
 
 }  // namespace rbp

@@ -3,10 +3,13 @@ resource-usage remarks that the build writes beside librbp.so.
 
 Per-lane scratch (private memory) is spill, a dynamically indexed register
 array or the frame of an out-of-line call: it turns register or LDS data into
-memory traffic.  The segment kernels of
-degree 3-8, the backward, graph-cut and graph-building and MPC kernels must
-have none, nor the path kernel; the degree-9 segment kernels are at the 256-VGPR
-limit and are allowed their (stated) spill."""
+memory traffic.  The default-shape segment kernels of degree 3-7 (and the
+polish-only one of degree 8), the backward, graph-cut and graph-building and
+MPC kernels must have none, nor the path kernel or the one-wavefront-per-SIMD
+shape.  Stated exceptions: the degree-9 segment kernels and the degree-8 ones
+with ADMM iterations are at the 256-VGPR limit; the two-instances-per-
+workgroup shape spills (it is an option the autotuner weighs, timed with its
+spill); the single-launch kernels hold every degree's code in one kernel."""
 import csv
 import os
 import re
@@ -15,7 +18,8 @@ import pytest
 
 from paper_2411_13507_amd import build
 
-ALLOWED = {r"solve_kernelI[fd]Li9E": 128}
+ALLOWED = {r"solve_kernelI[fd]Li9E": 128, r"solve_kernelI[fd]Li8ELb1": 16,
+           r"solve_kernel_shapeILi[3-9]ELb[01]ELi2ELi2": 256, r"(solve|backward)_kernel_all": 1024}
 
 
 @pytest.fixture(scope="module")
