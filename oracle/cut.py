@@ -195,3 +195,162 @@ def heuristic(P, lo, hi, tol2: float = 0.0) -> Tuple[int, int, float]:
         return FREE, BY_PLANE, np.nan
     d2 = cut_qp(P, lo, hi).dist2
     return (FREE if d2 > tol2 else CUT), BY_QP, d2
+
+
+# ---------------------------------------------------------------------------
+# General convex polytope obstacles O = {x : A x <= b} (Assumption 1 of
+# Sec. III-A: every obstacle is a convex polytope, given by n_c halfspaces).
+#
+# The Cut-QP is then  min |delta|^2  over convex weights lam and slacks delta
+# with A P^T lam <= b + delta.  For fixed lam the best slack is
+# delta = (M lam - b)_+ with M = A P^T (n_c x (p+1)), so the optimum is
+#   v* = min over the simplex of f(lam) = |(M lam - b)_+|^2,
+# a convex, continuously differentiable function; v* = 0 exactly when
+# conv(P) and O meet.  Its Lagrange dual (multipliers mu >= 0 of the rows) is
+#   max over mu >= 0 of  h(mu) = min_j mu . (M e_j - b) - |mu|^2 / 4,
+# and h(mu) <= v* <= f(lam) for every mu >= 0 and every lam in the simplex
+# (weak duality; equality at the optimum, where mu = 2 delta*).  The oracle
+# returns v* enclosed by these two bounds.
+# ---------------------------------------------------------------------------
+@dataclass
+class CutQPPoly:
+    value: float            # f at the returned weights (upper bound of v*)
+    lower: float            # dual bound h(mu) (lower bound of v*)
+    lam: np.ndarray         # convex weights
+    delta: np.ndarray       # (M lam - b)_+
+
+
+def _project_simplex(v: np.ndarray) -> np.ndarray:
+    """Euclidean projection onto {lam >= 0, sum lam = 1} (sort and threshold)."""
+    u = np.sort(v)[::-1]
+    css = np.cumsum(u) - 1.0
+    k = np.arange(1, v.size + 1)
+    rho = np.nonzero(u - css / k > 0)[0][-1]
+    theta = css[rho] / (rho + 1.0)
+    return np.maximum(v - theta, 0.0)
+
+
+def poly_f(M, b, lam) -> float:
+    r = np.maximum(M @ lam - b, 0.0)
+    return float(r @ r)
+
+
+def poly_dual(M, b, mu) -> float:
+    """h(mu) = min_j mu . (M e_j - b) - |mu|^2 / 4 (a lower bound of the
+    Cut-QP optimum for every mu >= 0)."""
+    return float(np.min(mu @ (M - b[:, None])) - 0.25 * mu @ mu)
+
+
+def poly_lp_margin(P, A, b) -> float:
+    """s* = min over the simplex of max_k (a_k . P^T lam - b_k) / |a_k|: < 0
+    when conv(P) reaches into the interior of O, > 0 when they are apart."""
+    P, A, b = (np.asarray(a, float) for a in (P, A, b))
+    nrm = np.linalg.norm(A, axis=1)
+    AP = (A / nrm[:, None]) @ P.T
+    m = P.shape[0]
+    c = np.zeros(m + 1); c[-1] = 1.0
+    res = linprog(c, A_ub=np.concatenate([AP, -np.ones((A.shape[0], 1))], axis=1), b_ub=b / nrm,
+                  A_eq=np.concatenate([np.ones((1, m)), np.zeros((1, 1))], axis=1), b_eq=[1.0],
+                  bounds=[(0, None)] * m + [(None, None)], method="highs")
+    return float(res.x[-1])
+
+
+def _refine(M, b, lam):
+    """Exact minimiser on the pieces of the current point: with S the rows
+    that are violated and J the weights that are positive, minimise
+    |M_SJ lam_J - b_S|^2 subject to sum lam_J = 1 (a linear KKT system); the
+    candidate is kept only when it stays in the simplex."""
+    S = np.nonzero(M @ lam - b > 0)[0]
+    J = np.nonzero(lam > 1e-13)[0]
+    if S.size == 0 or J.size == 0:
+        return lam
+    MS = M[np.ix_(S, J)]
+    k = J.size
+    K = np.zeros((k + 1, k + 1))
+    K[:k, :k] = 2.0 * MS.T @ MS
+    K[:k, k] = 1.0
+    K[k, :k] = 1.0
+    rhs = np.concatenate([2.0 * MS.T @ b[S], [1.0]])
+    try:
+        sol = np.linalg.lstsq(K, rhs, rcond=None)[0]
+    except np.linalg.LinAlgError:
+        return lam
+    cand = np.zeros_like(lam)
+    cand[J] = sol[:k]
+    if np.all(cand >= -1e-15):
+        cand = np.maximum(cand, 0.0)
+        cand /= cand.sum()
+        return cand
+    return lam
+
+
+def cut_qp_poly(P, A, b) -> CutQPPoly:
+    """Optimum of the Cut-QP for the obstacle {A x <= b}: zero (with the LP's
+    common point) when conv(P) meets it; otherwise f minimised over the
+    simplex by SLSQP from several starts, each result refined on its pieces
+    (``_refine``); the best upper bound and the dual bound at mu = 2 delta
+    enclose the optimum."""
+    from scipy.optimize import minimize
+    P, A, b = (np.asarray(a, float) for a in (P, A, b))
+    M = A @ P.T
+    m = P.shape[0]
+    # common point: feasibility LP over the simplex
+    res = linprog(np.zeros(m), A_ub=M, b_ub=b, A_eq=np.ones((1, m)), b_eq=[1.0],
+                  bounds=[(0, None)] * m, method="highs")
+    if res.status == 0:
+        lam = _project_simplex(res.x)
+        if poly_f(M, b, lam) == 0.0:
+            return CutQPPoly(0.0, 0.0, lam, np.zeros(A.shape[0]))
+    fun = lambda l: poly_f(M, b, l)
+    jac = lambda l: 2.0 * M.T @ np.maximum(M @ l - b, 0.0)
+    cons = [{"type": "eq", "fun": lambda l: np.sum(l) - 1.0, "jac": lambda l: np.ones(m)}]
+    starts = [np.full(m, 1.0 / m)] + [np.eye(m)[j] for j in range(m)]
+    best = None
+    for x0 in starts:
+        r = minimize(fun, x0, jac=jac, bounds=[(0, 1)] * m, constraints=cons, method="SLSQP",
+                     options={"ftol": 1e-16, "maxiter": 500})
+        lam = _project_simplex(r.x)
+        for _ in range(3):
+            lam = _refine(M, b, lam)
+        if best is None or poly_f(M, b, lam) < poly_f(M, b, best):
+            best = lam
+    delta = np.maximum(M @ best - b, 0.0)
+    return CutQPPoly(float(delta @ delta), poly_dual(M, b, 2.0 * delta), best, delta)
+
+
+def poly_closest_point(P, A, b) -> np.ndarray:
+    """closestPoint of Alg. 2 (reading) for a polytope: the point of O nearest
+    the centroid of the control points (a strictly convex QP, solved by the
+    primal active-set method from the LP's Chebyshev centre)."""
+    from .qp import active_set
+    P, A, b = (np.asarray(a, float) for a in (P, A, b))
+    c = P.mean(axis=0)
+    nrm = np.linalg.norm(A, axis=1)
+    # Chebyshev centre: max r with A x + |a| r <= b
+    res = linprog(np.array([0.0, 0.0, 0.0, -1.0]), A_ub=np.concatenate([A, nrm[:, None]], axis=1), b_ub=b,
+                  bounds=[(None, None)] * 3 + [(0, None)], method="highs")
+    x0 = res.x[:3]
+    # min |x - c|^2 = x'x - 2 c'x + const: shift y = x - c so the objective is y'y
+    r = active_set(np.eye(3), A, b - A @ c, np.zeros((0, 3)), np.zeros(0), x0 - c, [])
+    return r.y + c
+
+
+def poly_support(A, b, n) -> float:
+    """max over O of n . x (an LP)."""
+    res = linprog(-np.asarray(n, float), A_ub=A, b_ub=b, bounds=[(None, None)] * 3, method="highs")
+    return float(-res.fun)
+
+
+def heuristic_poly(P, A, b, tol2: float = 0.0):
+    """Alg. 2 for one (edge, polytope) pair, as ``heuristic`` does for a box:
+    (code, step that decided, Cut-QP value when step 3 ran else NaN)."""
+    P, A, b = (np.asarray(a, float) for a in (P, A, b))
+    if np.any(np.all(P @ A.T <= b, axis=1)):
+        return CUT, BY_POINT, np.nan
+    vo = poly_closest_point(P, A, b)
+    n = P.mean(axis=0) - vo
+    l = poly_support(A, b, n)
+    if np.any(n != 0.0) and np.all(P @ n > l):
+        return FREE, BY_PLANE, np.nan
+    v = cut_qp_poly(P, A, b).value
+    return (FREE if v > tol2 else CUT), BY_QP, v

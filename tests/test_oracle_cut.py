@@ -141,3 +141,138 @@ def test_workload_shape():
     assert np.all(b.box_hi > b.box_lo)
     b2 = gen.gen_cut(n_nodes=500, k_nn=10, n_obst=50)
     assert np.array_equal(b.P, b2.P)
+
+
+# ---------------------------------------------------------------------------
+# Polytope obstacles {x : A x <= b}
+# ---------------------------------------------------------------------------
+def rand_polytope(rng, k=None):
+    off, A, b = gen.polytope_obstacles(1, rng, extent=2.0)
+    return A, b
+
+
+def test_box_as_polytope_is_the_squared_distance():
+    """With the box's six unit rows the Cut-QP optimum is the squared
+    Euclidean distance between conv(P) and the box (computed independently
+    by the hull-projection routine)."""
+    rng = np.random.default_rng(21)
+    for _ in range(60):
+        lo, hi = rand_box(rng)
+        P = rng.uniform(-3, 3, (8, 3)) * rng.uniform(0.1, 1.0) + rng.uniform(-3, 3, 3)
+        A, b = cut.box_rows(lo, hi)
+        want = cut.cut_qp(P, lo, hi).dist2
+        got = cut.cut_qp_poly(P, A, b)
+        assert abs(got.value - want) <= 1e-12 * (1 + want), (got.value, want)
+
+
+def test_single_point_closed_form():
+    """All control points equal to x: the only convex combination is x, and
+    the optimum is |(A x - b)_+|^2."""
+    rng = np.random.default_rng(22)
+    for _ in range(100):
+        A, b = rand_polytope(rng)
+        x = rng.uniform(-2, 4, 3)
+        want = float(np.sum(np.maximum(A @ x - b, 0.0) ** 2))
+        assert abs(cut.cut_qp_poly(np.tile(x, (8, 1)), A, b).value - want) <= 1e-12 * (1 + want)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_polytope_value_enclosed_by_duality_and_sampling(seed):
+    """Weak duality: the dual value h(2 delta) <= optimum <= f(lam) at the
+    returned weights, and the two meet; every sampled convex combination has
+    f >= the optimum."""
+    rng = np.random.default_rng(300 + seed)
+    for _ in range(15):
+        A, b = rand_polytope(rng)
+        P = rng.uniform(-2, 2, (8, 3)) * rng.uniform(0.2, 1.0) + rng.uniform(-2, 4, 3)
+        r = cut.cut_qp_poly(P, A, b)
+        assert r.lower <= r.value + 1e-13 * (1 + r.value)
+        assert r.value - r.lower <= 1e-10 * (1 + r.value), (r.value, r.lower)
+        assert abs(r.lam.sum() - 1.0) <= 1e-14 and np.all(r.lam >= 0)
+        M = A @ P.T
+        lam = rng.dirichlet(np.ones(8) * 0.3, size=3000)
+        F = np.sum(np.maximum(lam @ M.T - b, 0.0) ** 2, axis=1)
+        assert r.value <= F.min() + 1e-12
+        # any mu >= 0 is a lower bound
+        for _ in range(20):
+            mu = rng.exponential(1.0, A.shape[0]) * rng.uniform(0, 3)
+            assert cut.poly_dual(M, b, mu) <= r.value + 1e-12
+
+
+def test_polytope_zero_exactly_when_the_lp_finds_a_common_point():
+    rng = np.random.default_rng(23)
+    n_zero = n_pos = 0
+    for _ in range(150):
+        A, b = rand_polytope(rng)
+        P = rng.uniform(-1.5, 1.5, (8, 3)) * rng.uniform(0.2, 1.0) + rng.uniform(-1, 3, 3)
+        s = cut.poly_lp_margin(P, A, b)
+        if abs(s) < cut.TAU:
+            continue
+        v = cut.cut_qp_poly(P, A, b).value
+        if s < 0:
+            assert v == 0.0
+            n_zero += 1
+        else:
+            assert v > 0.0
+            n_pos += 1
+    assert n_zero > 10 and n_pos > 10
+
+
+def test_polytope_scaling_and_translation():
+    """Scaling every row and offset by s scales the optimum by s^2;
+    translating the control points by t and the offsets by A t leaves it."""
+    rng = np.random.default_rng(24)
+    for _ in range(30):
+        A, b = rand_polytope(rng)
+        P = rng.uniform(-2, 2, (8, 3)) * 0.5 + rng.uniform(-2, 4, 3)
+        v = cut.cut_qp_poly(P, A, b).value
+        s = rng.uniform(0.3, 3.0)
+        assert abs(cut.cut_qp_poly(P, s * A, s * b).value - s * s * v) <= 1e-11 * (1 + s * s * v)
+        t = rng.uniform(-5, 5, 3)
+        assert abs(cut.cut_qp_poly(P + t, A, b + A @ t).value - v) <= 1e-11 * (1 + v)
+
+
+def test_polytope_closest_point_kkt():
+    """The closest point of O to the centroid: inside O a point is its own
+    projection; outside, c - x* is a non-negative combination of the rows
+    tight at x* (checked by non-negative least squares)."""
+    from scipy.optimize import nnls
+    rng = np.random.default_rng(25)
+    for _ in range(60):
+        A, b = rand_polytope(rng)
+        P = rng.uniform(-2, 2, (8, 3)) * 0.3 + rng.uniform(-2, 4, 3)
+        c = P.mean(axis=0)
+        x = cut.poly_closest_point(P, A, b)
+        assert np.all(A @ x <= b + 1e-10)
+        if np.all(A @ c <= b):
+            assert np.abs(x - c).max() <= 1e-12
+            continue
+        tight = np.nonzero(A @ x >= b - 1e-9)[0]
+        mu, res = nnls(A[tight].T, c - x)
+        assert res <= 1e-9 * (1 + np.abs(c - x).max())
+
+
+def test_polytope_heuristic_steps_are_certificates():
+    """Step 1: a control point inside O (so v* = 0); step 2: the plane keeps
+    O on its near side (LP support) and every control point beyond it (so
+    v* > 0); step 3 agrees with the LP decision on certified margins."""
+    b = gen.gen_cut(n_nodes=200, k_nn=5, n_obst=0, n_poly=25)
+    rng = np.random.default_rng(26)
+    seen = set()
+    for e in rng.choice(b.n_edges, 25, replace=False):
+        for j in range(b.n_polytopes):
+            A, bb = b.polytope(j)
+            P = b.P[e]
+            code, step, v = cut.heuristic_poly(P, A, bb)
+            seen.add(step)
+            if step == cut.BY_POINT:
+                assert code == cut.CUT and np.any(np.all(P @ A.T <= bb, axis=1))
+            elif step == cut.BY_PLANE:
+                n = P.mean(axis=0) - cut.poly_closest_point(P, A, bb)
+                l = cut.poly_support(A, bb, n)
+                assert code == cut.FREE and np.all(P @ n > l)
+            else:
+                s = cut.poly_lp_margin(P, A, bb)
+                if abs(s) >= cut.TAU:
+                    assert (code == cut.FREE) == (s > 0)
+    assert cut.BY_PLANE in seen

@@ -619,41 +619,84 @@ def generate_chains(n: int = 8192, workers: Optional[int] = None) -> ChainBatch:
 # ---------------------------------------------------------------------------
 @dataclass
 class CutBatch:
-    """Edges (degree-p Bezier control points) and axis-aligned box obstacles.
+    """Edges (degree-p Bezier control points) and obstacles: axis-aligned
+    boxes, then convex polytopes {x : A x <= b}.
 
     P[e, k, c]: coordinate c of control point k of edge e; box_lo/box_hi:
-    [n_obstacles, 3]."""
+    [n_boxes, 3]; polytope j owns rows pob_off[j] .. pob_off[j+1]-1 of
+    pob_A [rows, 3] and pob_b [rows].  Obstacle o < n_boxes is box o, obstacle
+    n_boxes + j is polytope j."""
     name: str
     degree: int
     P: np.ndarray
     box_lo: np.ndarray
     box_hi: np.ndarray
+    pob_off: np.ndarray = field(default_factory=lambda: np.zeros(1, np.int32))
+    pob_A: np.ndarray = field(default_factory=lambda: np.zeros((0, 3)))
+    pob_b: np.ndarray = field(default_factory=lambda: np.zeros(0))
 
     @property
     def n_edges(self) -> int:
         return self.P.shape[0]
 
     @property
-    def n_obstacles(self) -> int:
+    def n_boxes(self) -> int:
         return self.box_lo.shape[0]
+
+    @property
+    def n_polytopes(self) -> int:
+        return len(self.pob_off) - 1
+
+    @property
+    def n_obstacles(self) -> int:
+        return self.n_boxes + self.n_polytopes
+
+    def polytope(self, j: int):
+        a, z = self.pob_off[j], self.pob_off[j + 1]
+        return self.pob_A[a:z], self.pob_b[a:z]
+
+
+def polytope_obstacles(n: int, rng: np.random.Generator, extent: float = 10.0):
+    """Convex polytope obstacles: centre c uniform in [0, extent]^3, the six
+    axis faces at half-widths U[0.1, 0.75] plus 2-10 cuts with unit Gaussian
+    normals at offset n.c + U[0.1, 0.75] (bounded, centre inside; sizes like
+    the box obstacles').  Returns (row offsets, A, b)."""
+    off, As, bs = [0], [], []
+    for _ in range(n):
+        c = rng.uniform(0.0, extent, 3)
+        w = rng.uniform(0.1, 0.75, 3)
+        k = int(rng.integers(2, 11))
+        N = rng.standard_normal((k, 3))
+        N /= np.linalg.norm(N, axis=1, keepdims=True)
+        A = np.concatenate([np.eye(3), -np.eye(3), N])
+        b = np.concatenate([c + w, -(c - w), N @ c + rng.uniform(0.1, 0.75, k)])
+        As.append(A); bs.append(b); off.append(off[-1] + A.shape[0])
+    return (np.asarray(off, np.int32), np.ascontiguousarray(np.concatenate(As)) if As else np.zeros((0, 3)),
+            np.ascontiguousarray(np.concatenate(bs)) if bs else np.zeros(0))
 
 
 def gen_cut(n_nodes: int = 5000, k_nn: int = 10, n_obst: int = 200, p: int = 7, cfg: int = 5,
-            bend: float = 0.15) -> CutBatch:
+            bend: float = 0.15, n_poly: int = 0) -> CutBatch:
     """Graph edges over the obstacle field of the cluttered environment: nodes
     uniform in [0, 10]^3 outside every obstacle, each joined to its k nearest
     neighbours (about n_nodes * k_nn edges; 5,000 nodes and 10 neighbours give
     the 50,000 edges of Sec. IV-A), the curve of an edge being the straight
     degree-p segment between its nodes with the interior control points moved
     by N(0, bend * length) per coordinate (curved edges).  Obstacles: the
-    first n_obst boxes of the environment."""
+    first n_obst boxes of the environment, then n_poly convex polytopes
+    (``polytope_obstacles``, their own seed stream)."""
     env = environment(1)
     lo, hi = env.obs_lo[:n_obst], env.obs_hi[:n_obst]
     rng = np.random.default_rng(np.random.SeedSequence(1000 + cfg, spawn_key=(3,)))
+    pob_off, pob_A, pob_b = polytope_obstacles(
+        n_poly, np.random.default_rng(np.random.SeedSequence(1000 + cfg, spawn_key=(6,))))
     nodes = []
     while len(nodes) < n_nodes:
         c = rng.uniform(0.0, 10.0, size=(2 * n_nodes, 3))
         ok = ~np.any(np.all((c[:, None, :] >= lo[None]) & (c[:, None, :] <= hi[None]), axis=2), axis=1)
+        for j in range(n_poly):
+            Aj, bj = pob_A[pob_off[j]:pob_off[j + 1]], pob_b[pob_off[j]:pob_off[j + 1]]
+            ok &= ~np.all(c @ Aj.T <= bj, axis=1)
         nodes.extend(c[ok][: n_nodes - len(nodes)])
     V = np.asarray(nodes)
     d2 = ((V[:, None, :] - V[None, :, :]) ** 2).sum(-1)
@@ -666,8 +709,9 @@ def gen_cut(n_nodes: int = 5000, k_nn: int = 10, n_obst: int = 200, p: int = 7, 
     P = a[:, None, :] + t[None, :, None] * (b - a)[:, None, :]
     length = np.linalg.norm(b - a, axis=1)
     P[:, 1:p, :] += rng.standard_normal((len(src), p - 1, 3)) * (bend * length)[:, None, None]
-    return CutBatch(name=f"cut{len(src)}_o{n_obst}", degree=p, P=np.ascontiguousarray(P),
-                    box_lo=np.ascontiguousarray(lo), box_hi=np.ascontiguousarray(hi))
+    return CutBatch(name=f"cut{len(src)}_o{n_obst}" + (f"_p{n_poly}" if n_poly else ""), degree=p,
+                    P=np.ascontiguousarray(P), box_lo=np.ascontiguousarray(lo), box_hi=np.ascontiguousarray(hi),
+                    pob_off=pob_off, pob_A=pob_A, pob_b=pob_b)
 
 
 # ---------------------------------------------------------------------------
