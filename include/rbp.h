@@ -290,45 +290,76 @@ void rbp_destroy_chains(rbp_chains* chains);
 /* ------------------------------------------------------------------------
  * Cutting graph edges against obstacles (Sec. III-B, Alg. 2, eq. Cut-QP).
  *
- * A pair is an edge, the control points of its degree-p Bezier curve, and
- * an axis-aligned box obstacle lo <= x <= hi.  By the convex-hull property
- * (Property 1) the curve is free of the box when conv(P) and the box are
- * disjoint.  Each pair runs Alg. 2: (1) a control point inside the box ->
- * may collide; (2) every control point strictly beyond the box's supporting
- * plane with normal centroid - clamp(centroid) -> free; (3) otherwise the
- * Cut-QP, whose optimum |delta*|^2 is, for a box, the squared distance
- * between conv(P) and the box: free when it is positive.
+ * A pair is an edge, the control points P of its degree-p Bezier curve, and
+ * a convex obstacle O (Assumption 1): an axis-aligned box lo <= x <= hi, or a
+ * convex polytope {x : A x <= b} of n_c halfspaces.  By the convex-hull
+ * property (Property 1) the curve is free of O when conv(P) and O are
+ * disjoint.  Each pair runs Alg. 2: (1) a control point inside O -> may
+ * collide; (2) every control point strictly beyond the supporting plane of O
+ * whose normal points from the point of O nearest the centroid of P to that
+ * centroid -> free; (3) otherwise the Cut-QP
+ *     min |delta|^2  over convex weights lam and slacks delta,
+ *     A P^T lam <= b + delta,
+ * free when its optimum |delta*|^2 is positive.  For a box (unit rows) the
+ * optimum is the squared distance between conv(P) and the box; for a
+ * polytope it is min over conv(P) of |(A x - b)_+|^2.  Step 3 decides
+ * free / may collide by the distance between conv(P) and O (GJK: zero
+ * exactly when the Cut-QP optimum is zero; below 1e-24 max(1, |P|)^2 counts
+ * as zero) and computes the optimum itself by accelerated projected gradient
+ * on the weights, stopped by the Lagrange-dual gap.
  * ------------------------------------------------------------------------ */
+#define RBP_CUT_MAX_POLY_ROWS 32   /* halfspaces per polytope obstacle            */
+#define RBP_CUT_MAX_POLY_VERTS 64  /* vertices per polytope obstacle              */
+
 typedef struct rbp_cut_desc {
   int32_t n_edges;            /* >= 0                                         */
-  int32_t n_obstacles;        /* >= 0                                         */
+  int32_t n_obstacles;        /* box obstacles, >= 0                          */
   int32_t degree;             /* 1..RBP_MAX_DEGREE, the same for every edge    */
   int32_t reserved;           /* 0                                            */
   const double* box_lo;       /* device [n_obstacles][3]                      */
   const double* box_hi;       /* device [n_obstacles][3], hi >= lo             */
+  /* Polytope obstacles, numbered n_obstacles .. n_obstacles + n_polytopes - 1
+   * in the outputs.  Each must be bounded with a non-empty interior (a
+   * convex polytope); rbp_build_cut checks this (RBP_E_SHAPE otherwise). */
+  int32_t n_polytopes;        /* >= 0                                         */
+  int32_t reserved2;          /* 0                                            */
+  const int32_t* pob_off;     /* device [n_polytopes+1]: polytope j owns rows
+                                 pob_off[j] .. pob_off[j+1]-1, pob_off[0] = 0,
+                                 4..RBP_CUT_MAX_POLY_ROWS rows each            */
+  const double* pob_A;        /* device [rows][3] outward normals (non-zero)  */
+  const double* pob_b;        /* device [rows]: the polytope is A x <= b       */
 } rbp_cut_desc;
 
 typedef struct rbp_cut rbp_cut;
 
-/* Upper bound on n_edges * n_obstacles (the undecided-pair list is sized
- * for every pair). */
+/* Upper bound on n_edges * (n_obstacles + n_polytopes) (the undecided-pair
+ * list is sized for every pair). */
 #define RBP_CUT_MAX_PAIRS (1LL << 28)
 
 /*
  * Keeps the obstacle arrays (device pointers, owned by the caller, which
- * must keep them alive) and allocates the undecided-pair list.
- * Errors: RBP_E_INVALID (null pointers, negative counts), RBP_E_SHAPE
- * (degree out of range, more than RBP_CUT_MAX_PAIRS pairs), RBP_E_ALLOC.
+ * must keep them alive) and allocates the undecided-pair list.  Polytope
+ * rows are copied to the host (the call synchronises `stream`) to enumerate
+ * each polytope's vertices (intersections of three of its planes that
+ * satisfy every row, duplicates merged), which the supporting planes and the
+ * distance of step 3 use; the vertex table is uploaded and owned by the
+ * object.
+ * Errors: RBP_E_INVALID (null pointers, negative counts, reserved fields not
+ * 0), RBP_E_SHAPE (degree out of range, more than RBP_CUT_MAX_PAIRS pairs,
+ * row counts out of range, a zero or non-finite row, a polytope that is
+ * unbounded, empty or flat, or with more than RBP_CUT_MAX_POLY_VERTS
+ * vertices), RBP_E_ALLOC, RBP_E_DEVICE.
  */
 int rbp_build_cut(const rbp_cut_desc* desc, hipStream_t stream, rbp_cut** out);
 
 /*
  * Classifies every (edge, obstacle) pair; stream-ordered, asynchronous.
  *   P          device [n_edges][degree+1][3] control points (point-major)
- *   code       device [n_obstacles][n_edges] uint8: 1 free, 0 may collide
+ *   code       device [n_obst][n_edges] uint8: 1 free, 0 may collide, with
+ *              n_obst = n_obstacles + n_polytopes (boxes first)
  *   step       nullable, same shape: the step of Alg. 2 that decided (1, 2, 3)
- *   qp_dist2   nullable, same shape, double: |delta*|^2 where step 3 ran,
- *              NaN where the heuristic decided
+ *   qp_dist2   nullable, same shape, double: the Cut-QP optimum |delta*|^2
+ *              where step 3 ran, NaN where the heuristic decided
  *   n_collide  device [n_edges] int32: obstacles the edge may collide with
  *              (0 = the edge stays in the cut graph)
  * Codes are obstacle-major: pair (e, o) is at o * n_edges + e.

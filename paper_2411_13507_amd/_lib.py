@@ -48,6 +48,8 @@ class CutDesc(ctypes.Structure):
     _fields_ = [
         ("n_edges", ctypes.c_int32), ("n_obstacles", ctypes.c_int32), ("degree", ctypes.c_int32),
         ("reserved", ctypes.c_int32), ("box_lo", _p), ("box_hi", _p),
+        ("n_polytopes", ctypes.c_int32), ("reserved2", ctypes.c_int32), ("pob_off", _p), ("pob_A", _p),
+        ("pob_b", _p),
     ]
 
 

@@ -268,10 +268,12 @@ class CutResult:
 
 
 class CutGPU:
-    """Graph edges cut against axis-aligned box obstacles on one GPU (Alg. 2
-    with the Cut-QP for the undecided pairs).  ``problem`` has box_lo and
-    box_hi ([n_obstacles, 3]) and degree, e.g. ``workloads.gen.CutBatch``;
-    the edges' control points are passed to each run."""
+    """Graph edges cut against convex obstacles on one GPU (Alg. 2 with the
+    Cut-QP for the undecided pairs).  ``problem`` has box_lo and box_hi
+    ([n_boxes, 3]), optionally polytopes (pob_off [n_poly+1], pob_A [rows, 3],
+    pob_b [rows]; numbered after the boxes) and degree, e.g.
+    ``workloads.gen.CutBatch``; the edges' control points are passed to each
+    run."""
 
     def __init__(self, problem, n_edges: int, device: str = "cuda"):
         if not torch.cuda.is_available():
@@ -283,8 +285,17 @@ class CutGPU:
         d = self.device
         self.box_lo = _dev(problem.box_lo, torch.float64, d)
         self.box_hi = _dev(problem.box_hi, torch.float64, d)
-        self.n_edges, self.n_obst, self.degree = int(n_edges), int(self.box_lo.shape[0]), int(problem.degree)
-        desc = _lib.CutDesc(self.n_edges, self.n_obst, self.degree, 0, _ptr(self.box_lo), _ptr(self.box_hi))
+        pob_off = getattr(problem, "pob_off", None)
+        n_poly = 0 if pob_off is None else int(len(pob_off) - 1)
+        if n_poly > 0:
+            self.pob_off = _dev(np.asarray(pob_off), torch.int32, d)
+            self.pob_A = _dev(problem.pob_A, torch.float64, d)
+            self.pob_b = _dev(problem.pob_b, torch.float64, d)
+        n_box = int(self.box_lo.shape[0])
+        self.n_edges, self.n_obst, self.degree = int(n_edges), n_box + n_poly, int(problem.degree)
+        desc = _lib.CutDesc(self.n_edges, n_box, self.degree, 0, _ptr(self.box_lo), _ptr(self.box_hi), n_poly, 0,
+                            _ptr(self.pob_off) if n_poly else None, _ptr(self.pob_A) if n_poly else None,
+                            _ptr(self.pob_b) if n_poly else None)
         h = ctypes.c_void_p()
         with torch.cuda.device(d):
             _lib.check(L.rbp_build_cut(ctypes.byref(desc), _stream_handle(d), ctypes.byref(h)), "rbp_build_cut")

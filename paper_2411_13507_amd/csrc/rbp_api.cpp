@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <array>
 #include <limits>
+#include <climits>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -562,36 +563,159 @@ struct rbp_cut {
   int64_t* list = nullptr;
   int64_t cap = 0;
   int qp_blocks = 0;
+  int32_t* pv_off = nullptr;    // vertex table of the polytope obstacles
+  double* pv = nullptr;
   hipStream_t last_stream = nullptr;
 };
+
+namespace {
+void free_cut(rbp_cut* c) {
+  for (void* p : {static_cast<void*>(c->counter), static_cast<void*>(c->list), static_cast<void*>(c->pv_off),
+                  static_cast<void*>(c->pv)})
+    if (p) (void)hipFree(p);
+  delete c;
+}
+
+// Vertices of {x : a_k . x <= b_k, k < m} in R^3: every intersection point of
+// three planes with independent normals that satisfies all rows (to a
+// relative 1e-9), points closer than that merged.  Appends to `out` and
+// returns the count, or -1 past `cap`.
+int polytope_vertices(const double* A, const double* b, int m, int cap, std::vector<double>& out) {
+  const size_t base = out.size();
+  double scale = 1.0;
+  for (int k = 0; k < m; ++k) scale = std::max(scale, std::fabs(b[k]));
+  int count = 0;
+  for (int i = 0; i < m; ++i)
+    for (int j = i + 1; j < m; ++j)
+      for (int k = j + 1; k < m; ++k) {
+        const double* a0 = A + 3 * i;
+        const double* a1 = A + 3 * j;
+        const double* a2 = A + 3 * k;
+        // Cramer's rule: x = (b_i (a1 x a2) + b_j (a2 x a0) + b_k (a0 x a1)) / det
+        const double c12[3] = {a1[1] * a2[2] - a1[2] * a2[1], a1[2] * a2[0] - a1[0] * a2[2], a1[0] * a2[1] - a1[1] * a2[0]};
+        const double c20[3] = {a2[1] * a0[2] - a2[2] * a0[1], a2[2] * a0[0] - a2[0] * a0[2], a2[0] * a0[1] - a2[1] * a0[0]};
+        const double c01[3] = {a0[1] * a1[2] - a0[2] * a1[1], a0[2] * a1[0] - a0[0] * a1[2], a0[0] * a1[1] - a0[1] * a1[0]};
+        const double det = a0[0] * c12[0] + a0[1] * c12[1] + a0[2] * c12[2];
+        const double n0 = std::sqrt(a0[0] * a0[0] + a0[1] * a0[1] + a0[2] * a0[2]);
+        const double n1 = std::sqrt(a1[0] * a1[0] + a1[1] * a1[1] + a1[2] * a1[2]);
+        const double n2 = std::sqrt(a2[0] * a2[0] + a2[1] * a2[1] + a2[2] * a2[2]);
+        if (!(std::fabs(det) > 1e-10 * n0 * n1 * n2)) continue;
+        double x[3];
+        for (int c = 0; c < 3; ++c) x[c] = (b[i] * c12[c] + b[j] * c20[c] + b[k] * c01[c]) / det;
+        bool ok = true;
+        for (int r = 0; r < m && ok; ++r) {
+          const double* ar = A + 3 * r;
+          const double nr = std::sqrt(ar[0] * ar[0] + ar[1] * ar[1] + ar[2] * ar[2]);
+          ok = ar[0] * x[0] + ar[1] * x[1] + ar[2] * x[2] <= b[r] + 1e-9 * nr * scale;
+        }
+        if (!ok) continue;
+        bool dup = false;
+        for (int v = 0; v < count && !dup; ++v) {
+          const double* y = out.data() + base + 3 * v;
+          dup = std::fabs(x[0] - y[0]) <= 1e-9 * scale && std::fabs(x[1] - y[1]) <= 1e-9 * scale &&
+                std::fabs(x[2] - y[2]) <= 1e-9 * scale;
+        }
+        if (dup) continue;
+        if (count >= cap) return -1;
+        out.insert(out.end(), x, x + 3);
+        ++count;
+      }
+  return count;
+}
+
+// A polytope {A x <= b} is bounded exactly when its recession cone
+// {d : A d <= 0} is {0}: the vertices of that cone cut by the cube
+// |d_i| <= 1 are then only the origin.
+bool polytope_bounded(const double* A, int m) {
+  std::vector<double> Ab(size_t(3 * (m + 6)), 0.0), bb(size_t(m + 6), 0.0);
+  std::copy(A, A + 3 * m, Ab.begin());
+  for (int c = 0; c < 3; ++c) {
+    Ab[size_t(3 * (m + 2 * c) + c)] = 1.0;
+    bb[size_t(m + 2 * c)] = 1.0;
+    Ab[size_t(3 * (m + 2 * c + 1) + c)] = -1.0;
+    bb[size_t(m + 2 * c + 1)] = 1.0;
+  }
+  std::vector<double> v;
+  const int n = polytope_vertices(Ab.data(), bb.data(), m + 6, 4096, v);
+  if (n < 0) return false;
+  for (double x : v)
+    if (std::fabs(x) > 1e-7) return false;
+  return true;
+}
+}  // namespace
 
 int rbp_build_cut(const rbp_cut_desc* d, hipStream_t stream, rbp_cut** out) {
   if (!d || !out) return RBP_E_INVALID;
   *out = nullptr;
-  if (d->n_edges < 0 || d->n_obstacles < 0 || d->reserved != 0) return RBP_E_INVALID;
+  if (d->n_edges < 0 || d->n_obstacles < 0 || d->reserved != 0 || d->n_polytopes < 0 || d->reserved2 != 0)
+    return RBP_E_INVALID;
   if (d->n_obstacles > 0 && (!d->box_lo || !d->box_hi)) return RBP_E_INVALID;
+  if (d->n_polytopes > 0 && (!d->pob_off || !d->pob_A || !d->pob_b)) return RBP_E_INVALID;
   if (d->degree < 1 || d->degree > RBP_MAX_DEGREE) return RBP_E_SHAPE;
-  const int64_t pairs = int64_t(d->n_edges) * d->n_obstacles;
-  if (pairs > RBP_CUT_MAX_PAIRS) return RBP_E_SHAPE;
+  const int64_t n_obst = int64_t(d->n_obstacles) + d->n_polytopes;
+  const int64_t pairs = int64_t(d->n_edges) * n_obst;
+  if (pairs > RBP_CUT_MAX_PAIRS || n_obst > INT32_MAX) return RBP_E_SHAPE;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return RBP_E_DEVICE;
+  // polytope obstacles: rows to the host, vertex enumeration, checks
+  std::vector<int32_t> poff, vo(size_t(d->n_polytopes) + 1, 0);
+  std::vector<double> pA, pb, verts;
+  int rc = RBP_OK;
+  if (d->n_polytopes > 0) {
+    if ((rc = d2h(poff, d->pob_off, size_t(d->n_polytopes) + 1, stream))) return rc;
+    if (hipStreamSynchronize(stream) != hipSuccess) return RBP_E_DEVICE;
+    if (poff[0] != 0) return RBP_E_SHAPE;
+    for (int j = 0; j < d->n_polytopes; ++j) {
+      const int m = poff[j + 1] - poff[j];
+      if (m < 4 || m > RBP_CUT_MAX_POLY_ROWS) return RBP_E_SHAPE;
+    }
+    const size_t rows = size_t(poff[d->n_polytopes]);
+    if ((rc = d2h(pA, d->pob_A, 3 * rows, stream)) || (rc = d2h(pb, d->pob_b, rows, stream))) return rc;
+    if (hipStreamSynchronize(stream) != hipSuccess) return RBP_E_DEVICE;
+    for (size_t r = 0; r < rows; ++r) {
+      const double nn = pA[3 * r] * pA[3 * r] + pA[3 * r + 1] * pA[3 * r + 1] + pA[3 * r + 2] * pA[3 * r + 2];
+      if (!(nn > 0.0) || !std::isfinite(nn) || !std::isfinite(pb[r])) return RBP_E_SHAPE;
+    }
+    for (int j = 0; j < d->n_polytopes; ++j) {
+      const int r0 = poff[j], m = poff[j + 1] - r0;
+      if (!polytope_bounded(pA.data() + 3 * r0, m)) return RBP_E_SHAPE;
+      const size_t first = verts.size();
+      const int nv = polytope_vertices(pA.data() + 3 * r0, pb.data() + r0, m, RBP_CUT_MAX_POLY_VERTS, verts);
+      if (nv < 4) return RBP_E_SHAPE;   // empty, flat or too many vertices
+      // full-dimensional: some four vertices span a tetrahedron
+      const double* V = verts.data() + first;
+      double ext = 0.0, vol = 0.0;
+      for (int q = 0; q < 3 * nv; ++q) ext = std::max(ext, std::fabs(V[q] - V[q % 3]));
+      for (int a = 1; a < nv && !(vol > 1e-9 * ext * ext * ext); ++a)
+        for (int bq = a + 1; bq < nv; ++bq)
+          for (int cq = bq + 1; cq < nv; ++cq) {
+            double u[3], w[3], z[3];
+            for (int k = 0; k < 3; ++k) { u[k] = V[3 * a + k] - V[k]; w[k] = V[3 * bq + k] - V[k]; z[k] = V[3 * cq + k] - V[k]; }
+            const double det = u[0] * (w[1] * z[2] - w[2] * z[1]) - u[1] * (w[0] * z[2] - w[2] * z[0]) +
+                               u[2] * (w[0] * z[1] - w[1] * z[0]);
+            vol = std::max(vol, std::fabs(det));
+          }
+      if (!(vol > 1e-9 * ext * ext * ext)) return RBP_E_SHAPE;
+      vo[size_t(j) + 1] = vo[size_t(j)] + nv;
+    }
+  }
   auto* c = new (std::nothrow) rbp_cut();
   if (!c) return RBP_E_ALLOC;
   c->device = dev;
   c->desc = *d;
   c->cap = std::max<int64_t>(pairs, 1);
-  int rc;
-  if ((rc = dalloc(&c->counter, 1)) || (rc = dalloc(&c->list, size_t(c->cap)))) {
-    if (c->counter) (void)hipFree(c->counter);
-    delete c;
+  if ((rc = dalloc(&c->counter, 1)) || (rc = dalloc(&c->list, size_t(c->cap))) ||
+      (rc = dalloc(&c->pv_off, vo.size())) || (rc = dalloc(&c->pv, std::max<size_t>(verts.size(), 3)))) {
+    free_cut(c);
     return rc;
   }
   // the count reads 0 until the first run (which zeroes it with a kernel)
   if (hipMemsetAsync(c->counter, 0, sizeof(unsigned long long), stream) != hipSuccess ||
+      hipMemcpyAsync(c->pv_off, vo.data(), vo.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream) ||
+      (!verts.empty() &&
+       hipMemcpyAsync(c->pv, verts.data(), verts.size() * sizeof(double), hipMemcpyHostToDevice, stream)) ||
       hipStreamSynchronize(stream) != hipSuccess) {
-    (void)hipFree(c->counter);
-    (void)hipFree(c->list);
-    delete c;
+    free_cut(c);
     return RBP_E_DEVICE;
   }
   int n_cu = 0;
@@ -607,10 +731,12 @@ int rbp_cut_run(rbp_cut* c, const double* P, uint8_t* code, uint8_t* step, doubl
   if (!c) return RBP_E_INVALID;
   const rbp_cut_desc& d = c->desc;
   if (d.n_edges == 0) return RBP_OK;
-  if (!P || !n_collide || (d.n_obstacles > 0 && !code)) return RBP_E_INVALID;
+  const int n_obst = d.n_obstacles + d.n_polytopes;
+  if (!P || !n_collide || (n_obst > 0 && !code)) return RBP_E_INVALID;
   rbp::CutArgs a{};
-  a.n_edges = d.n_edges; a.n_obst = d.n_obstacles; a.degree = d.degree;
+  a.n_edges = d.n_edges; a.n_obst = n_obst; a.n_box = d.n_obstacles; a.degree = d.degree;
   a.P = P; a.box_lo = d.box_lo; a.box_hi = d.box_hi;
+  a.pob_off = d.pob_off; a.pob_A = d.pob_A; a.pob_b = d.pob_b; a.pv_off = c->pv_off; a.pv = c->pv;
   a.code = code; a.step = step; a.qp_dist2 = qp_dist2; a.n_collide = n_collide;
   a.counter = c->counter; a.list = c->list; a.list_cap = c->cap;
   if (rbp::launch_cut(a, stream, c->qp_blocks) != hipSuccess) return RBP_E_DEVICE;
@@ -632,9 +758,7 @@ void rbp_destroy_cut(rbp_cut* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   if (c->last_stream) (void)hipStreamSynchronize(c->last_stream);
-  if (c->counter) (void)hipFree(c->counter);
-  if (c->list) (void)hipFree(c->list);
-  delete c;
+  free_cut(c);
 }
 
 struct rbp_graph {

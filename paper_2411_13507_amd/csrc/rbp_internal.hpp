@@ -156,9 +156,15 @@ struct ChainArgs {
 // ---- cutting graph edges against box obstacles (rbp_cut.hip)
 struct CutArgs {
   int n_edges, n_obst, degree;
+  int n_box;                 // obstacles 0 .. n_box-1 are boxes, the rest polytopes
   const double* P;           // [n_edges][degree+1][3]
-  const double* box_lo;      // [n_obst][3]
-  const double* box_hi;      // [n_obst][3]
+  const double* box_lo;      // [n_box][3]
+  const double* box_hi;      // [n_box][3]
+  const int32_t* pob_off;    // [n_obst - n_box + 1] row offsets of the polytopes
+  const double* pob_A;       // [rows][3]
+  const double* pob_b;       // [rows]
+  const int32_t* pv_off;     // [n_obst - n_box + 1] vertex offsets
+  const double* pv;          // [vertices][3]
   uint8_t* code;             // [n_obst][n_edges]: 1 free, 0 may collide
   uint8_t* step;             // nullable [n_obst][n_edges]: 1, 2 or 3 (Alg. 2 step that decided)
   double* qp_dist2;          // nullable [n_obst][n_edges]: |delta*|^2 where step 3 ran, NaN elsewhere
