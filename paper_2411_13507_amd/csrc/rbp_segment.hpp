@@ -81,6 +81,7 @@ __device__ __forceinline__ double sel3(int c, double a, double b, double d) {
 template <typename Real>
 struct Lds {
   double *Hd, *Af, *rowval, *ybuf, *qbuf, *vA, *vB, *vC, *vD, *vE, *scal, *acte, *actc, *lam;
+  double *blo, *bhi;               // box that holds every feasible point (free variables)
   int *actid, *actside;
   Real *HfT, *Aff, *vbuf, *xb1, *xb2, *Kx;
   double *Q1, *Rm;
@@ -101,6 +102,8 @@ __device__ Lds<Real> carve(char* s, const LdsDims& D) {
   L.vC = L.vB + D.nmax;
   L.vD = L.vC + D.nmax;
   L.vE = L.vD + D.nmax;
+  L.blo = L.vE + D.nmax;
+  L.bhi = L.blo + D.nmax;
   L.scal = (double*)(s + D.o_scal);
   L.acte = (double*)(s + D.o_acte);
   L.actc = L.acte + D.nmax;
@@ -622,21 +625,25 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
     }
     v0 = -in.T15 * 2.0 * in.iT3 * sel3(vc, in.dg[0], in.dg[1], in.dg[2]) * acc;
   }
-  // Upper bound Uw of the whitened objective 1/2 |L^T x - v0|^2 over the box
-  // that holds every feasible x (velocity rows chained from both pinned
-  // ends).  With centre x_c, half-widths w and the unconstrained minimiser
+  // Box that holds every feasible x, in LDS (blo, bhi): the velocity rows
+  // chained from both pinned ends.
+  if (vl) {
+    const int k = vs + 1;
+    const double vv = in.vmax * in.T / P, dgc = sel3(vc, in.dg[0], in.dg[1], in.dg[2]);
+    L.blo[lane] = fmax(-k * vv, dgc - (P - k) * vv);
+    L.bhi[lane] = fmin(k * vv, dgc + (P - k) * vv);
+  }
+  // Upper bound of the whitened objective 1/2 |L^T x - v0|^2 over the box.
+  // With centre x_c, half-widths w and the unconstrained minimiser
   // x_u = L^-T v0:  |L^T x - v0| <= |L^T (x_c - x_u)| + |L^T (x - x_c)|, and
   // |L^T d|^2 = d^T P d <= sum_ij |P_ij| |d_i| |d_j|  (P = 2 Q_ff).  A dual
-  // value above Uw proves that no feasible point exists (weak duality).
-  double Uw = 0.0;
-  {
+  // value above it proves that no feasible point exists (weak duality).
+  auto box_bound = [&]() -> double {
     double bc = 0.0, bw = 0.0;
     if (vl) L.vD[lane] = v0;
     bsync<kWS>();
     if (vl) {
-      const int k = vs + 1;
-      const double vv = in.vmax * in.T / P, dgc = sel3(vc, in.dg[0], in.dg[1], in.dg[2]);
-      const double lo = fmax(-k * vv, dgc - (P - k) * vv), hi = fmin(k * vv, dgc + (P - k) * vv);
+      const double lo = L.blo[lane], hi = L.bhi[lane];
       bc = 0.5 * (lo + hi) - unwhiten_at<P>(L.cL1i, in.T15, L.vD, lane);
       bw = fmax(0.5 * (hi - lo), 0.0);
     }
@@ -654,9 +661,10 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
     }
     const double cc = 2.0 * in.iT3 * wsum(bc * pc), ww = 2.0 * in.iT3 * wsum(bw * pw);
     const double rt = sqrt(fmax(cc, 0.0)) + sqrt(fmax(ww, 0.0));
-    Uw = 0.5 * rt * rt;
     bsync<kWS>();
-  }
+    return 0.5 * rt * rt;
+  };
+  double Uw = box_bound();
 
   // --- owner helpers: key = 2*id + (side>0)
   auto slot_of = [&](int id, int& own_lane, int& bit) {
@@ -1277,13 +1285,31 @@ __device__ void backward_instance(const BackArgs& A, const int inst, char* smem)
     if (A.flags && lane == 0) A.flags[inst] = 0;
     return;
   }
-  (void)stage_rows<NC, HDS>(L.Hd, A.H + in.hb, r * NC, lane);
   for (int e = lane; e < nf * 3; e += kWave) L.Af[e] = A.A_face[3 * (int64_t)in.f0 + e];
   const int64_t sb = (int64_t)inst * A.st_stride;
   if (lane < q) {
     L.actid[lane] = A.st_id[sb + lane];
     L.actside[lane] = A.st_side[sb + lane];
     L.lam[lane] = A.st_lam[sb + lane];
+  }
+  __syncthreads();
+  // only the active reachable rows enter the adjoint: stage those (the
+  // others are never read), four loads in flight per lane
+  for (int base = 0; base < q * NC; base += 4 * kWave) {
+    double v[4];
+    int dst[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int t = base + u * kWave + lane;
+      const int k = t / NC, e = t - NC * (t / NC);
+      const int id = t < q * NC ? L.actid[k] : -1;
+      const bool take = id >= in.RB;
+      dst[u] = take ? (id - in.RB) * HDS + e : -1;
+      v[u] = take ? A.H[in.hb + (int64_t)(id - in.RB) * NC + e] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (dst[u] >= 0) L.Hd[dst[u]] = v[u];
   }
   // solution in the shifted frame
   double P0[3];

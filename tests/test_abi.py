@@ -37,6 +37,7 @@ def test_default_opts(lib):
     assert o.admm_iters == 10 and abs(o.rho - 0.1) < 1e-7 and abs(o.alpha - 1.6) < 1e-6
     assert o.max_polish_steps == 0 and o.store_for_backward == 1 and o.plain == 0
     assert o.feas_tol == 1e-11 and o.kkt_tol == 1e-6
+    assert o.launch_shape == 0 and o.schedule == 0
 
 
 def test_status_strings(lib):
