@@ -779,10 +779,14 @@ __device__ __forceinline__ void chain_instance(const ChainArgs& A, const int ch,
     }
     return acc;
   };
-  // Ub bounds 1/2 (x - x_u)' G (x - x_u) over the box: with centre x_c and
-  // half-widths w, |x - x_u|_G <= |x_c - x_u|_G + |x - x_c|_G and
-  // d' G d <= sum_ij |G_ij| |d_i| |d_j|.  A dual value (relative to the
-  // unconstrained minimum) above Ub proves that no feasible path exists.
+  // Ub bounds 1/2 (x - x_u)' G (x - x_u) (the path's cost, whose unconstrained
+  // minimum is 0: the straight line at constant speed) over the feasible
+  // points, by the smaller of: over the box, with centre x_c and half-widths
+  // w, |x - x_u|_G <= |x_c - x_u|_G + |x - x_c|_G and d' G d <= sum_ij |G_ij|
+  // |d_i| |d_j|; and S 3 amax^2 T, since the acceleration rows bound every
+  // coordinate of every control point of each segment's b'' by amax.  A dual
+  // value (relative to the unconstrained minimum) above Ub proves that no
+  // feasible path exists.
   double Ub = 0.0;
   {
     for (int e = lane; e < n; e += kWave) {
@@ -800,7 +804,7 @@ __device__ __forceinline__ void chain_instance(const ChainArgs& A, const int ch,
     cc = wave::sum(cc);
     ww = wave::sum(ww);
     const double rt = sqrt(fmax(cc, 0.0)) + sqrt(fmax(ww, 0.0));
-    Ub = 0.5 * rt * rt;
+    Ub = fmin(0.5 * rt * rt, 3.0 * S * A.amax * A.amax * T * (1.0 + 1e-12));
     __syncthreads();
   }
   for (int e = lane; e < n; e += kWave) L.x[e] = L.xu[e];

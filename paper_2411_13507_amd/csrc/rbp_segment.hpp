@@ -633,11 +633,19 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
     L.blo[lane] = fmax(-k * vv, dgc - (P - k) * vv);
     L.bhi[lane] = fmin(k * vv, dgc + (P - k) * vv);
   }
-  // Upper bound of the whitened objective 1/2 |L^T x - v0|^2 over the box.
-  // With centre x_c, half-widths w and the unconstrained minimiser
-  // x_u = L^-T v0:  |L^T x - v0| <= |L^T (x_c - x_u)| + |L^T (x - x_c)|, and
-  // |L^T d|^2 = d^T P d <= sum_ij |P_ij| |d_i| |d_j|  (P = 2 Q_ff).  A dual
-  // value above it proves that no feasible point exists (weak duality).
+  // Upper bound of the whitened objective 1/2 |L^T x - v0|^2 over the
+  // feasible points; a dual value above it proves that none exists (weak
+  // duality).  The objective equals the cost int |b''|^2 (its minimum over
+  // the free points is 0: the straight line at constant speed), and two
+  // bounds hold:
+  //  * the acceleration rows bound every coordinate of every control point of
+  //    b'' by amax, so |b''(t)|^2 <= 3 amax^2 (convex hull) and the cost is at
+  //    most 3 amax^2 T;
+  //  * over the box, with centre x_c, half-widths w and the unconstrained
+  //    minimiser x_u = L^-T v0: |L^T x - v0| <= |L^T (x_c - x_u)| +
+  //    |L^T (x - x_c)| and |L^T d|^2 = d^T P d <= sum_ij |P_ij| |d_i| |d_j|
+  //    (P = 2 Q_ff).
+  // The smaller is returned.
   auto box_bound = [&]() -> double {
     double bc = 0.0, bw = 0.0;
     if (vl) L.vD[lane] = v0;
@@ -662,7 +670,7 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
     const double cc = 2.0 * in.iT3 * wsum(bc * pc), ww = 2.0 * in.iT3 * wsum(bw * pw);
     const double rt = sqrt(fmax(cc, 0.0)) + sqrt(fmax(ww, 0.0));
     bsync<kWS>();
-    return 0.5 * rt * rt;
+    return fmin(0.5 * rt * rt, 3.0 * in.amax * in.amax * in.T * (1.0 + 1e-12));
   };
   double Uw = box_bound();
 
