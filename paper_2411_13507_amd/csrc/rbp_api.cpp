@@ -29,6 +29,8 @@ struct rbp_batch {
   int64_t* d_pt_off = nullptr;
   int64_t* d_face_off = nullptr;
   int32_t* d_order = nullptr;
+  rbp::InstDesc* d_desc = nullptr;     // descriptors in work-order position
+  std::vector<int32_t> pos_host;       // work-order position of each instance
   // forward state kept for backward
   int32_t nmax = 0;
   int32_t* st_q = nullptr;
@@ -72,7 +74,7 @@ int dalloc(T** p, size_t n) {
 
 void free_batch(rbp_batch* b) {
   if (!b) return;
-  void* ptrs[] = {b->d_pt_off, b->d_face_off, b->d_order, b->st_q, b->st_id, b->st_side,
+  void* ptrs[] = {b->d_pt_off, b->d_face_off, b->d_order, b->d_desc, b->st_q, b->st_id, b->st_side,
                   b->st_lam, b->fw_P, b->fw_status, b->fw_x0, b->fw_goal, b->fw_bface};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -215,12 +217,32 @@ int rbp_build_batch(const rbp_problem_desc* d, hipStream_t stream, rbp_batch** o
     }
     b->degree_host = deg;
   }
+  // descriptors in work-order position and the inverse permutation
+  std::vector<rbp::InstDesc> desc(static_cast<size_t>(N));
+  b->pos_host.assign(size_t(N), 0);
+  for (int k = 0; k < N; ++k) {
+    const int i = order[k];
+    const int blk_i = blk(i);
+    rbp::InstDesc& q = desc[size_t(k)];
+    q.inst = i;
+    q.p = deg[i];
+    q.f0 = poff[pidx[i]];
+    q.nf = poff[pidx[i] + 1] - poff[pidx[i]];
+    q.r = int32_t(roff[blk_i + 1] - roff[blk_i]);
+    q.pad0 = 0;
+    q.r0 = roff[blk_i];
+    q.hb = hoff[blk_i];
+    q.po = pt_off[i];
+    q.fo = face_off[i];
+    q.pad1 = 0;
+    b->pos_host[size_t(i)] = k;
+  }
   b->pt_total = pt_off[N];
   b->face_total = face_off[N];
   b->nmax = 3 * (b->pmax - 1);
   const size_t n1 = size_t(N);
   if ((rc = dalloc(&b->d_pt_off, n1 + 1)) || (rc = dalloc(&b->d_face_off, n1 + 1)) ||
-      (rc = dalloc(&b->d_order, n1)) || (rc = dalloc(&b->st_q, n1)) ||
+      (rc = dalloc(&b->d_order, n1)) || (rc = dalloc(&b->d_desc, n1)) || (rc = dalloc(&b->st_q, n1)) ||
       (rc = dalloc(&b->st_id, n1 * b->nmax)) || (rc = dalloc(&b->st_side, n1 * b->nmax)) ||
       (rc = dalloc(&b->st_lam, n1 * b->nmax)) || (rc = dalloc(&b->fw_P, size_t(3 * b->pt_total))) ||
       (rc = dalloc(&b->fw_status, n1)) || (rc = dalloc(&b->fw_x0, 6 * n1)) ||
@@ -231,6 +253,7 @@ int rbp_build_batch(const rbp_problem_desc* d, hipStream_t stream, rbp_batch** o
   if (hipMemcpyAsync(b->d_pt_off, pt_off.data(), (n1 + 1) * sizeof(int64_t), hipMemcpyHostToDevice, stream) ||
       hipMemcpyAsync(b->d_face_off, face_off.data(), (n1 + 1) * sizeof(int64_t), hipMemcpyHostToDevice, stream) ||
       (N > 0 && hipMemcpyAsync(b->d_order, order.data(), n1 * sizeof(int32_t), hipMemcpyHostToDevice, stream)) ||
+      (N > 0 && hipMemcpyAsync(b->d_desc, desc.data(), n1 * sizeof(rbp::InstDesc), hipMemcpyHostToDevice, stream)) ||
       hipStreamSynchronize(stream)) {
     free_batch(b);
     return RBP_E_DEVICE;
@@ -281,11 +304,13 @@ int rbp_solve_batch(rbp_batch* b, const double* x0, const double* goal, const do
   a.admm_iters = o.admm_iters; a.rho = o.rho; a.alpha = o.alpha;
   a.max_steps = o.max_polish_steps; a.feas_tol = o.feas_tol; a.kkt_tol = o.kkt_tol;
   hipError_t e = hipSuccess;
+  a.desc = b->d_desc;
   if (o.plain) {
-    a.order = nullptr;
+    a.order = b->d_order;
     a.dims = rbp::make_dims(b->pmax, b->rmax, b->nfmax, 8, o.admm_iters > 0);
     for (int i = 0; i < b->N && e == hipSuccess; ++i) {
-      a.inst_base = i;
+      a.inst_base = b->pos_host[size_t(i)];
+      a.N = a.inst_base + 1;
       e = rbp::launch_solve(a, 1, stream, true, b->degree_host[i]);
     }
   } else if (o.schedule == 1) {
@@ -345,6 +370,7 @@ int rbp_backward(rbp_batch* b, const double* grad_P, const double* grad_cost, do
   a.grad_P = grad_P; a.grad_cost = grad_cost;
   a.grad_x0 = grad_x0; a.grad_goal = grad_goal; a.grad_b = grad_b; a.flags = flags_out;
   a.order = b->d_order;
+  a.desc = b->d_desc;
   a.st_stride = b->nmax;
   if (b->fw_schedule == 1) {
     a.dims = rbp::make_dims(b->pmax, b->rmax, b->nfmax, 8, false);

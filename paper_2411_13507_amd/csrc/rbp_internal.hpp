@@ -32,6 +32,17 @@ struct LdsDims {
   int bytes;
 };
 
+// Per-instance descriptor in work-order position, built by rbp_build_batch
+// from the index arrays: one block reads its instance's offsets with a few
+// uniform loads instead of a chain of dependent ones.
+struct alignas(16) InstDesc {
+  int32_t inst, p, f0, nf;   // instance, degree, first face of its polytope, faces
+  int32_t r, pad0;           // reachable rows
+  int64_t r0;                // first reachable row (h0, G)
+  int64_t hb, po;            // element offset of its H block, control-point offset of P
+  int64_t fo, pad1;          // offset of its faces in grad_b
+};
+
 struct SolveArgs {
   int N;                     // solve: end of the launch's range in the work order
   const int32_t* degree;
@@ -52,6 +63,7 @@ struct SolveArgs {
   const double* goal;
   const int64_t* pt_off;     // per-instance offset in control points (sum of p+1)
   const int32_t* order;      // work order (nullable): block b solves order[b]
+  const InstDesc* desc;      // [N] descriptors in work-order position
   int inst_base;             // first work-order position of the launch (block b -> inst_base + b)
   double* P_out;
   double* cost_out;
@@ -77,6 +89,7 @@ struct SolveArgs {
 struct BackArgs {
   int N;                     // end of the launch's range in the work order
   const int32_t* order;      // work order (nullable): block b handles order[inst_base + b]
+  const InstDesc* desc;      // [N] descriptors in work-order position
   int inst_base;
   int st_stride;
   const int32_t* degree;

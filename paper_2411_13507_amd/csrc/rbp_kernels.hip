@@ -14,9 +14,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void so
   extern __shared__ __attribute__((aligned(16))) char smem[];
   const int b = blockIdx.x + A.inst_base;
   if (b >= A.N) return;
-  const int inst = A.order ? A.order[b] : b;
-  if (A.degree[inst] == P) solve_instance<P, Real, kAdmm>(A, inst, smem);
-  else if (threadIdx.x == 0) A.status_out[inst] = kInvalid;
+  const InstDesc dsc = A.desc[b];
+  if (dsc.p == P) solve_instance<P, Real, kAdmm>(A, dsc, smem);
+  else if (threadIdx.x == 0) A.status_out[dsc.inst] = kInvalid;
 }
 
 // One launch per group of the work order (same degree P): block b handles
@@ -26,8 +26,8 @@ __global__ __launch_bounds__(64) void backward_kernel(BackArgs A) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
   const int b = blockIdx.x + A.inst_base;
   if (b >= A.N) return;
-  const int inst = A.order ? A.order[b] : b;
-  if (A.degree[inst] == P) backward_instance<P>(A, inst, smem);
+  const InstDesc dsc = A.desc[b];
+  if (dsc.p == P) backward_instance<P>(A, dsc, smem);
 }
 
 }  // namespace
@@ -51,7 +51,7 @@ LdsDims make_dims(int pmax, int r_cap, int nf_cap, int real_bytes, bool admm) {
   d.o_lam = take(d.nmax * 8);
   d.o_actid = take(d.nmax * 4);
   d.o_actside = take(d.nmax * 4);
-  d.o_cst = take((admm ? 2 * kMaxFree * kMaxFree + kMaxPts * kMaxPts : kMaxFree * kMaxFree) * 8);
+  d.o_cst = take(((admm ? 2 : 1) * kMaxFree * kMaxFree + kMaxPts * kMaxPts) * 8);
   d.o_Rd = take(d.nmax * 8);
   d.o_region = o;
   // iteration scratch in the precision of the iterations

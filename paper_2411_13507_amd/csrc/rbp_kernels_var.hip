@@ -19,11 +19,11 @@ __global__ __launch_bounds__(64 * WPG) __attribute__((amdgpu_waves_per_eu(WPE)))
   const int w = threadIdx.x >> 6;
   const int b = blockIdx.x * WPG + w + A.inst_base;
   if (b >= A.N) return;
-  const int inst = A.order ? A.order[b] : b;
+  const InstDesc dsc = A.desc[b];
   // (one wavefront: the LDS base stays a constant)
   char* my = WPG == 1 ? smem : smem + size_t(w) * size_t(A.dims.bytes);
-  if (A.degree[inst] == P) solve_instance<P, float, kAdmm, (WPG > 1), 10 * WPG + WPE>(A, inst, my);
-  else if ((threadIdx.x & (kWave - 1)) == 0) A.status_out[inst] = kInvalid;
+  if (dsc.p == P) solve_instance<P, float, kAdmm, (WPG > 1), 10 * WPG + WPE>(A, dsc, my);
+  else if ((threadIdx.x & (kWave - 1)) == 0) A.status_out[dsc.inst] = kInvalid;
 }
 
 // The whole batch in one launch: block b solves order[b] whatever its degree
@@ -34,16 +34,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void so
   extern __shared__ __attribute__((aligned(16))) char smem[];
   const int b = blockIdx.x + A.inst_base;
   if (b >= A.N) return;
-  const int inst = A.order ? A.order[b] : b;
-  switch (A.degree[inst]) {
-    case 3: solve_instance<3, float, kAdmm, false, 99>(A, inst, smem); break;
-    case 4: solve_instance<4, float, kAdmm, false, 99>(A, inst, smem); break;
-    case 5: solve_instance<5, float, kAdmm, false, 99>(A, inst, smem); break;
-    case 6: solve_instance<6, float, kAdmm, false, 99>(A, inst, smem); break;
-    case 7: solve_instance<7, float, kAdmm, false, 99>(A, inst, smem); break;
-    case 8: solve_instance<8, float, kAdmm, false, 99>(A, inst, smem); break;
-    case 9: solve_instance<9, float, kAdmm, false, 99>(A, inst, smem); break;
-    default: if (threadIdx.x == 0) A.status_out[inst] = kInvalid; break;
+  const InstDesc dsc = A.desc[b];
+  switch (dsc.p) {
+    case 3: solve_instance<3, float, kAdmm, false, 99>(A, dsc, smem); break;
+    case 4: solve_instance<4, float, kAdmm, false, 99>(A, dsc, smem); break;
+    case 5: solve_instance<5, float, kAdmm, false, 99>(A, dsc, smem); break;
+    case 6: solve_instance<6, float, kAdmm, false, 99>(A, dsc, smem); break;
+    case 7: solve_instance<7, float, kAdmm, false, 99>(A, dsc, smem); break;
+    case 8: solve_instance<8, float, kAdmm, false, 99>(A, dsc, smem); break;
+    case 9: solve_instance<9, float, kAdmm, false, 99>(A, dsc, smem); break;
+    default: if (threadIdx.x == 0) A.status_out[dsc.inst] = kInvalid; break;
   }
 }
 
@@ -52,15 +52,15 @@ __global__ __launch_bounds__(64) void backward_kernel_all(BackArgs A) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
   const int b = blockIdx.x + A.inst_base;
   if (b >= A.N) return;
-  const int inst = A.order ? A.order[b] : b;
-  switch (A.degree[inst]) {
-    case 3: backward_instance<3>(A, inst, smem); break;
-    case 4: backward_instance<4>(A, inst, smem); break;
-    case 5: backward_instance<5>(A, inst, smem); break;
-    case 6: backward_instance<6>(A, inst, smem); break;
-    case 7: backward_instance<7>(A, inst, smem); break;
-    case 8: backward_instance<8>(A, inst, smem); break;
-    case 9: backward_instance<9>(A, inst, smem); break;
+  const InstDesc dsc = A.desc[b];
+  switch (dsc.p) {
+    case 3: backward_instance<3>(A, dsc, smem); break;
+    case 4: backward_instance<4>(A, dsc, smem); break;
+    case 5: backward_instance<5>(A, dsc, smem); break;
+    case 6: backward_instance<6>(A, dsc, smem); break;
+    case 7: backward_instance<7>(A, dsc, smem); break;
+    case 8: backward_instance<8>(A, dsc, smem); break;
+    case 9: backward_instance<9>(A, dsc, smem); break;
     default: break;
   }
 }

@@ -230,7 +230,7 @@ __device__ __forceinline__ bool stage_rows(double* dst, const double* __restrict
 // whereas one shared by several kernels may be called out of line, with its
 // arguments in a private-memory frame.
 template <int P, typename Real, bool kAdmm, bool kWS = false, int kTag = 0>
-__device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
+__device__ void solve_instance(const SolveArgs& A, const InstDesc& idesc, char* smem) {
   using I = Inst<P>;
   constexpr int NFP = I::NFP, N = I::N, NC = I::NC, ND = I::ND, NS = I::NS, HDS = I::HDS;
   const int lane = kWS ? int(threadIdx.x & (kWave - 1)) : int(threadIdx.x);
@@ -239,16 +239,17 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
   Lds<Real> L = carve<Real>(smem, D);
   const int HS = hft_stride(D);
 
+  // every global load of the set-up depends only on the descriptor: they are
+  // all issued before the first wait (staging barrier)
+  const int inst = idesc.inst;
   I in;
   in.T = A.T[inst];
-  const int poly = A.poly_idx[inst];
-  in.f0 = A.poly_off[poly];
-  in.nf = A.poly_off[poly + 1] - in.f0;
-  const int rblk = A.reach_idx ? A.reach_idx[inst] : inst;
-  in.r0 = A.reach_off[rblk];
-  in.r = int(A.reach_off[rblk + 1] - in.r0);
-  in.hb = A.H_off[rblk];
-  in.po = A.pt_off[inst];
+  in.f0 = idesc.f0;
+  in.nf = idesc.nf;
+  in.r0 = idesc.r0;
+  in.r = idesc.r;
+  in.hb = idesc.hb;
+  in.po = idesc.po;
   in.F = NFP * in.nf;
   in.RB = in.F + ND;
   in.m = in.RB + in.r;
@@ -276,6 +277,18 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
     }
   };
 
+  // per-lane inputs of the row set-up, loaded ahead of the staging
+  const double bj_in = lane < nf ? A.b_face[in.f0 + lane] : 0.0;
+  double h0_in[2] = {0.0, 0.0}, g_in[2][6];
+#pragma unroll
+  for (int sl = 0; sl < 2; ++sl) {
+    const int l = lane + kWave * sl;
+    const bool on = l < r;
+    h0_in[sl] = on ? A.h0[in.r0 + l] : 0.0;
+#pragma unroll
+    for (int e = 0; e < 6; ++e) g_in[sl][e] = on ? A.G[6 * (in.r0 + l) + e] : 0.0;
+  }
+
   // ---- stage instance data in LDS
   bad |= stage_rows<NC, HDS>(L.Hd, A.H + in.hb, r * NC, lane);
   for (int e = lane; e < nf * 3; e += kWave) L.Af[e] = A.A_face[3 * (int64_t)in.f0 + e];
@@ -286,9 +299,9 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
   // degree tables read with lane-dependent indices (the Hessian and the
   // difference-row Gram only for the ADMM matrix)
   for (int e = lane; e < kMaxFree * kMaxFree; e += kWave) L.cL1i[e] = (&K.L1inv[0][0])[e];
+  for (int e = lane; e < kMaxPts * kMaxPts; e += kWave) L.cQ1[e] = (&K.Q1[0][0])[e];
   if constexpr (kAdmm) {
     for (int e = lane; e < kMaxFree * kMaxFree; e += kWave) L.cGd[e] = (&K.Gdiff[0][0])[e];
-    for (int e = lane; e < kMaxPts * kMaxPts; e += kWave) L.cQ1[e] = (&K.Q1[0][0])[e];
   }
   bsync<kWS>();
 
@@ -298,7 +311,7 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
   bool fixed_viol = false;
   if (fl) {
     fa0 = L.Af[3 * lane]; fa1 = L.Af[3 * lane + 1]; fa2 = L.Af[3 * lane + 2];
-    const double bj = A.b_face[in.f0 + lane];
+    const double bj = bj_in;
     fu = bj - (fa0 * in.P0[0] + fa1 * in.P0[1] + fa2 * in.P0[2]);
     fan = sqrt(fa0 * fa0 + fa1 * fa1 + fa2 * fa2);
     bad |= !(fan > 0.0) || !isfinite(bj) || !isfinite(fan);
@@ -347,8 +360,8 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
     const int l = lane + kWave * sl;
     if (l < r) {
       const double* hr = L.Hd + l * HDS;
-      double b = A.h0[in.r0 + l];
-      for (int e = 0; e < 6; ++e) b += A.G[6 * (in.r0 + l) + e] * in.x0[e];
+      double b = h0_in[sl];
+      for (int e = 0; e < 6; ++e) b += g_in[sl][e] * in.x0[e];
       double s0 = 0, s1 = 0, s2 = 0;
       for (int k = 0; k <= P; ++k) { s0 += hr[3 * k]; s1 += hr[3 * k + 1]; s2 += hr[3 * k + 2]; }
       b -= s0 * in.P0[0] + s1 * in.P0[1] + s2 * in.P0[2];
@@ -662,7 +675,7 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
     if (vl) {
 #pragma unroll
       for (int t = 0; t < NFP; ++t) {
-        const double qv = K.Q1[vs + 1][t + 1];
+        const double qv = L.cQ1[kMaxPts * (vs + 1) + t + 1];
         pc += qv * L.vD[3 * t + vc];
         pw += fabs(qv) * L.vE[3 * t + vc];
       }
@@ -1204,7 +1217,7 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
   if (lane < NC) {
     const int pt = lane / 3, c = lane - 3 * (lane / 3);
 #pragma unroll
-    for (int b = 0; b <= P; ++b) qy += K.Q1[pt][b] * L.ybuf[3 * b + c];
+    for (int b = 0; b <= P; ++b) qy += L.cQ1[kMaxPts * pt + b] * L.ybuf[3 * b + c];
     qy *= in.iT3;
     L.qbuf[lane] = qy;
   }
@@ -1259,23 +1272,22 @@ __device__ void solve_instance(const SolveArgs& A, const int inst, char* smem) {
 //   d l / d goal = (omega_E - gf nu)_goal
 // ==========================================================================
 template <int P>
-__device__ void backward_instance(const BackArgs& A, const int inst, char* smem) {
+__device__ void backward_instance(const BackArgs& A, const InstDesc& idesc, char* smem) {
   using I = Inst<P>;
   constexpr int NFP = I::NFP, N = I::N, NC = I::NC, ND = I::ND, NS = I::NS, HDS = I::HDS;
   const int lane = threadIdx.x;
   const DegConst& K = c_deg[P];
   const LdsDims& D = A.dims;
   Lds<double> L = carve<double>(smem, D);
+  const int inst = idesc.inst;
   I in;
   in.T = A.T[inst];
-  const int poly = A.poly_idx[inst];
-  in.f0 = A.poly_off[poly];
-  in.nf = A.poly_off[poly + 1] - in.f0;
-  const int rblk = A.reach_idx ? A.reach_idx[inst] : inst;
-  in.r0 = A.reach_off[rblk];
-  in.r = int(A.reach_off[rblk + 1] - in.r0);
-  in.hb = A.H_off[rblk];
-  in.po = A.pt_off[inst];
+  in.f0 = idesc.f0;
+  in.nf = idesc.nf;
+  in.r0 = idesc.r0;
+  in.r = idesc.r;
+  in.hb = idesc.hb;
+  in.po = idesc.po;
   in.F = NFP * in.nf;
   in.RB = in.F + ND;
   in.m = in.RB + in.r;
@@ -1283,7 +1295,7 @@ __device__ void backward_instance(const BackArgs& A, const int inst, char* smem)
   in.iT3 = 1.0 / (in.T * in.T * in.T);
   in.sv = double(P) / in.T;
   in.sa = double(P) * (P - 1) / (in.T * in.T);
-  const int64_t fo = A.face_off[inst];
+  const int64_t fo = idesc.fo;
   const int nf = in.nf, r = in.r;
   const int q = (A.status[inst] == kSolved) ? A.st_q[inst] : -1;
   if (q < 0) {
