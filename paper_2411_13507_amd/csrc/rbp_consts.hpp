@@ -30,6 +30,9 @@ struct DegConst {
   double wn_vel[kMaxDeg];             // whitened norm of velocity row k (T = 1)
   double wn_acc[kMaxDeg];             // whitened norm of acceleration row k (T = 1)
   double Gdiff[kMaxFree][kMaxFree];   // sum over vel/acc rows of a a^T / |L1inv a|^2 (T = 1)
+  double rkappa[kMaxFree];            // 1 / sqrt(kappa)
+  double rwn_vel[kMaxDeg];            // 1 / wn_vel
+  double rwn_acc[kMaxDeg];            // 1 / wn_acc
 };
 
 inline double binom(int n, int k) {
@@ -114,6 +117,9 @@ inline bool build_degree(int p, DegConst& c) {
     if (k >= 1 && k <= nf) a1[k - 1] += sa;
     whiten_norm_and_gram(a1, &c.wn_acc[k]);
   }
+  for (int k = 0; k < nf; ++k) c.rkappa[k] = 1.0 / std::sqrt(c.kappa[k]);
+  for (int k = 0; k < p; ++k) c.rwn_vel[k] = 1.0 / c.wn_vel[k];
+  for (int k = 0; k < p - 1; ++k) c.rwn_acc[k] = 1.0 / c.wn_acc[k];
   return true;
 }
 

@@ -168,31 +168,33 @@ struct Inst {
 };
 
 // whitening: (L^-1 a)_i for var i = 3s + c, a given on the free vars in ``a``;
-// Li = rows of L1inv (stride kMaxFree, in LDS or constant memory).  Fixed
-// trip count so that every load issues before the first use.
+// Li = rows of L1inv (stride kMaxFree, in LDS or constant memory; lower
+// triangular with explicit zeros above the diagonal, so the full row can be
+// summed: a is finite).  Fixed trip count, every load issued before the
+// first product.
 template <int P>
 __device__ __forceinline__ double whiten_at(const double* Li, double T15, const double* a, int i) {
   constexpr int NFP = P - 1;
   const int s = i / 3, c = i - 3 * (i / 3);
+  double w[NFP], x[NFP];
+#pragma unroll
+  for (int t = 0; t < NFP; ++t) { w[t] = Li[kMaxFree * s + t]; x[t] = a[3 * t + c]; }
   double acc = 0.0;
 #pragma unroll
-  for (int t = 0; t < NFP; ++t) {
-    const double w = Li[kMaxFree * s + t], x = a[3 * t + c];
-    acc += (t <= s) ? w * x : 0.0;
-  }
+  for (int t = 0; t < NFP; ++t) acc += w[t] * x[t];
   return T15 * acc;
 }
-// un-whitening: (L^-T v)_i
+// un-whitening: (L^-T v)_i (column s of L1inv, zero above row s)
 template <int P>
 __device__ __forceinline__ double unwhiten_at(const double* Li, double T15, const double* v, int i) {
   constexpr int NFP = P - 1;
   const int s = i / 3, c = i - 3 * (i / 3);
+  double w[NFP], x[NFP];
+#pragma unroll
+  for (int t = 0; t < NFP; ++t) { w[t] = Li[kMaxFree * t + s]; x[t] = v[3 * t + c]; }
   double acc = 0.0;
 #pragma unroll
-  for (int t = 0; t < NFP; ++t) {
-    const double w = Li[kMaxFree * t + s], x = v[3 * t + c];
-    acc += (t >= s) ? w * x : 0.0;
-  }
+  for (int t = 0; t < NFP; ++t) acc += w[t] * x[t];
   return T15 * acc;
 }
 
@@ -220,6 +222,59 @@ __device__ __forceinline__ bool stage_rows(double* dst, const double* __restrict
     }
   }
   return bad;
+}
+
+// Sum of x[i] * v[i], i < n: x a per-lane LDS row, v an LDS vector; every
+// load is issued before the first product (the scheduler would otherwise
+// keep only a few in flight at this register pressure).
+template <int n>
+__device__ __forceinline__ double dot_row(const double* x, const double* v) {
+  double a[n], b[n];
+#pragma unroll
+  for (int i = 0; i < n; ++i) { a[i] = x[i]; b[i] = v[i]; }
+  __builtin_amdgcn_sched_barrier(0);
+  double acc = 0.0;
+#pragma unroll
+  for (int i = 0; i < n; ++i) acc += a[i] * b[i];
+  return acc;
+}
+// acc - sum over k < q of col[k * stride] * v[k] (q uniform), subtracted in
+// order, loads issued six at a time (indices past q read entry q - 1 and are
+// not used).
+__device__ __forceinline__ double colsub_q(double acc, const double* col, int stride, const double* v, int q) {
+  for (int k0 = 0; k0 < q; k0 += 6) {
+    double a[6], b[6];
+#pragma unroll
+    for (int u = 0; u < 6; ++u) {
+      const int k = k0 + u < q ? k0 + u : q - 1;
+      a[u] = col[k * stride];
+      b[u] = v[k];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < 6; ++u)
+      if (k0 + u < q) acc -= a[u] * b[u];
+  }
+  return acc;
+}
+// Sum over lane <= k < q of row[k] * v[k] (the upper-triangular part of a
+// row), in order, loads issued six at a time.
+__device__ __forceinline__ double rowsum_upper_q(const double* row, const double* v, int lane, int q) {
+  double acc = 0.0;
+  for (int k0 = 0; k0 < q; k0 += 6) {
+    double a[6], b[6];
+#pragma unroll
+    for (int u = 0; u < 6; ++u) {
+      const int k = k0 + u < q ? k0 + u : q - 1;
+      a[u] = row[k];
+      b[u] = v[k];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < 6; ++u)
+      if (k0 + u < q && k0 + u >= lane) acc += a[u] * b[u];
+  }
+  return acc;
 }
 
 // ==========================================================================
@@ -319,12 +374,12 @@ __device__ void solve_instance(const SolveArgs& A, const InstDesc& idesc, char* 
     const double gv = fa0 * in.dg[0] + fa1 * in.dg[1] + fa2 * in.dg[2];
     fixed_viol = (0.0 > fu) || (gv > fu);
   }
-  double fdn[NFP];
-#pragma unroll
-  for (int s = 0; s < NFP; ++s) fdn[s] = 1.0 / (in.T15 * fan * sqrt(K.kappa[s]));
+  // face-row scaling on point s: 1 / |L^-1 a| = ifan * rkappa[s]
+  const double ifan = 1.0 / (in.T15 * fan);
 
   // ---- difference rows: lane l < ND
   const bool dl = lane < ND;
+  const double sqT = sqrt(in.T), isT = 1.0 / sqT;
   int dk = 0, dc = 0;
   bool dvel = true;
   // a difference row holds its value in [dlo_of(), dbd]: [-dbd, dbd], or the
@@ -336,7 +391,7 @@ __device__ void solve_instance(const SolveArgs& A, const InstDesc& idesc, char* 
     if (lane < 3 * P) {
       dk = lane / 3; dc = lane - 3 * dk; dvel = true; dsc = in.sv; dbd = in.vmax;
       dcst = (dk == P - 1) ? in.sv * sel3(dc, in.dg[0], in.dg[1], in.dg[2]) : 0.0;
-      ddn = 1.0 / (K.wn_vel[dk] * sqrt(in.T));
+      ddn = K.rwn_vel[dk] * isT;
       if (pinl) {
         // pinned start velocity: the first derivative point equals x0[3+c];
         // its speed bound is then a constant test
@@ -347,7 +402,7 @@ __device__ void solve_instance(const SolveArgs& A, const InstDesc& idesc, char* 
       const int l2 = lane - 3 * P;
       dk = l2 / 3; dc = l2 - 3 * dk; dvel = false; dsc = in.sa; dbd = in.amax;
       dcst = (dk == P - 2) ? in.sa * sel3(dc, in.dg[0], in.dg[1], in.dg[2]) : 0.0;
-      ddn = sqrt(in.T) / K.wn_acc[dk];
+      ddn = sqT * K.rwn_acc[dk];
     }
   }
   // the velocity rows chained from both pinned ends bound every coordinate of
@@ -486,7 +541,8 @@ __device__ void solve_instance(const SolveArgs& A, const InstDesc& idesc, char* 
     const Real fa0r = Real(fa0), fa1r = Real(fa1), fa2r = Real(fa2);
 #pragma unroll
     for (int s = 0; s < NFP; ++s) {
-      ff[s] = Real(fdn[s]); fhi[s] = fl ? Real(fdn[s] * fu) : Real(kBigF);
+      const double fdn = ifan * K.rkappa[s];
+      ff[s] = Real(fdn); fhi[s] = fl ? Real(fdn * fu) : Real(kBigF);
       zf[s] = 0; yf[s] = 0;
     }
     const Real dd = Real(ddn);
@@ -688,20 +744,44 @@ __device__ void solve_instance(const SolveArgs& A, const InstDesc& idesc, char* 
   double Uw = box_bound();
 
   // --- owner helpers: key = 2*id + (side>0)
-  auto slot_of = [&](int id, int& own_lane, int& bit) {
+  auto slot_of = [&](int id_in, int& own_lane, int& bit) {   // id uniform
+    const int id = __builtin_amdgcn_readfirstlane(id_in);
     if (id < F) { const int s = id / nf; own_lane = id - s * nf; bit = s; }
     else if (id < RB) { own_lane = id - F; bit = NFP; }
     else { const int l = id - RB; own_lane = l & 63; bit = NFP + 1 + (l >> 6); }
   };
 
   // whitened normal of constraint (id, side) -> vA; also full-row bound pieces
-  auto build_normal = [&](int id, int side) {
+  // (L^-1 a restricted to the free variables; lane i = 3t + c): a face row
+  // has coefficients on one interior point, a difference row on two or three
+  // consecutive points of one coordinate, so their whitened normals are
+  // combinations of columns of L1inv; a reachable row is whitened from its
+  // LDS copy.  ``id`` is uniform.
+  auto build_normal = [&](int id_in, int side) {
+    const int id = __builtin_amdgcn_readfirstlane(id_in);
     if (vl) {
-      const int pt = vs + 1;
-      L.vC[lane] = in.coef(id, pt, vc, L.Af, L.Hd);
+      const double* Li = L.cL1i + kMaxFree * vs;   // row vs of L1inv
+      double w;
+      if (id < F) {
+        const int s = id / nf, j = id - s * nf;
+        w = in.T15 * Li[s] * L.Af[3 * j + vc];
+      } else if (id < RB) {
+        const int l = id - F;
+        const bool vel = l < 3 * P;
+        const int l2 = vel ? l : l - 3 * P, k = l2 / 3, cc = l2 - 3 * k;
+        double u;
+        if (vel) {   // sv (P_{k+1} - P_k): free points k and k - 1
+          u = in.sv * ((k <= NFP - 1 ? Li[k < NFP ? k : 0] : 0.0) - (k >= 1 ? Li[k >= 1 ? k - 1 : 0] : 0.0));
+        } else {     // sa (P_{k+2} - 2 P_{k+1} + P_k): free points k + 1, k, k - 1
+          u = in.sa * ((k + 1 <= NFP - 1 ? Li[k + 1 < NFP ? k + 1 : 0] : 0.0) - 2.0 * Li[k] +
+                       (k >= 1 ? Li[k >= 1 ? k - 1 : 0] : 0.0));
+        }
+        w = vc == cc ? in.T15 * u : 0.0;
+      } else {
+        w = whiten_at<P>(L.cL1i, in.T15, L.Hd + (id - RB) * HDS + 3, lane);
+      }
+      L.vA[lane] = double(side) * w;
     }
-    bsync<kWS>();
-    if (vl) L.vA[lane] = double(side) * whiten_at<P>(L.cL1i, in.T15, L.vC, lane);
     bsync<kWS>();
   };
 
@@ -710,44 +790,24 @@ __device__ void solve_instance(const SolveArgs& A, const InstDesc& idesc, char* 
   // re-orthogonalises only when the first lost more than half of |a|^2
   // (the Kahan-Parlett "twice is enough" test).
   auto project = [&](double& zz, double& aa) {
-    if (lane < q) {
-      double acc = 0.0;
-      for (int i = 0; i < N; ++i) acc += L.Q1[lane * NS + i] * L.vA[i];
-      L.vC[lane] = acc;
-    }
+    if (lane < q) L.vC[lane] = dot_row<N>(L.Q1 + lane * NS, L.vA);
     bsync<kWS>();
     double za = 0.0, zb = 0.0;
     if (vl) {
       za = L.vA[lane];
-      double acc = za;
-#pragma unroll
-      for (int k = 0; k < N; ++k) {
-        const double qk = L.Q1[k * NS + lane], ck = L.vC[k];
-        acc -= (k < q) ? qk * ck : 0.0;
-      }
-      L.vB[lane] = acc;
-      zb = acc;
+      zb = colsub_q(za, L.Q1 + lane, NS, L.vC, q);
+      L.vB[lane] = zb;
     }
     aa = wsum(za * za);
     zz = wsum(zb * zb);
     if (!(zz < 0.5 * aa) || q == 0) return;
     bsync<kWS>();
-    if (lane < q) {
-      double acc = 0.0;
-      for (int i = 0; i < N; ++i) acc += L.Q1[lane * NS + i] * L.vB[i];
-      L.vE[lane] = acc;
-    }
+    if (lane < q) L.vE[lane] = dot_row<N>(L.Q1 + lane * NS, L.vB);
     bsync<kWS>();
     double zc = 0.0;
     if (vl) {
-      double acc = L.vB[lane];
-#pragma unroll
-      for (int k = 0; k < N; ++k) {
-        const double qk = L.Q1[k * NS + lane], ek = L.vE[k];
-        acc -= (k < q) ? qk * ek : 0.0;
-      }
-      L.vB[lane] = acc;
-      zc = acc;
+      zc = colsub_q(L.vB[lane], L.Q1 + lane, NS, L.vE, q);
+      L.vB[lane] = zc;
     }
     if (lane < q) L.vC[lane] += L.vE[lane];
     zz = wsum(zc * zc);
@@ -756,15 +816,7 @@ __device__ void solve_instance(const SolveArgs& A, const InstDesc& idesc, char* 
 
   // r = R^-1 c, c in vC (lane i < q gets r_i)
   auto ri_times_c = [&]() -> double {
-    double acc = 0.0;
-    if (lane < q) {
-#pragma unroll
-      for (int k = 0; k < N; ++k) {
-        const double xk = L.Ri[lane * NS + k], ck = L.vC[k];
-        acc += (k >= lane && k < q) ? xk * ck : 0.0;
-      }
-    }
-    return acc;
+    return lane < q ? rowsum_upper_q(L.Ri + lane * NS, L.vC, lane, q) : 0.0;
   };
   // R^-1 rebuilt by back substitution after a downdate: lane j builds column
   // j (entries i <= j); each lane reads back only its own column
@@ -969,55 +1021,79 @@ __device__ void solve_instance(const SolveArgs& A, const InstDesc& idesc, char* 
   }
 
   // ---- main loop
-  // evaluate all rows on ybuf, return most violated inactive row
-  auto eval_rows = [&](double& best, int& key, double& splus, bool write_vals) {
-    best = -1.0; key = 0x7fffffff;
+  // Evaluate every owned row at the current point (row values to rowval) and
+  // return the most violated inactive row over the wavefront as (score, key).
+  // Each lane also keeps, for its own best candidate, the violation
+  // side * value - e_full and the row's e_full and c_full, which the owning
+  // lane hands to the others afterwards (no second evaluation).  The free
+  // entries of the point are uniform: they are loaded once, together with
+  // the lane's reachable-row coefficients, before any of them is used (the
+  // pinned entries of y~ are 0 at P_0 and the goal offset, whose product
+  // with a reachable row is the constant rcst).
+  auto eval_rows = [&](double& best, int& key, double& sv_b, double& e_b, double& c_b) {
+    best = -1.0; key = 0x7fffffff; sv_b = 0.0; e_b = 0.0; c_b = 0.0;
+    double y[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) y[i] = L.ybuf[3 + i];
+    // difference rows: lane-dependent entries, branch-free (a velocity lane
+    // reads its first entry twice and gives it weight 0)
+    const int di0 = 3 * dk + dc, di1 = di0 + 3, di2 = dvel ? di0 : di0 + 6;
+    const double yd0 = dl ? L.ybuf[di0] : 0.0, yd1 = dl ? L.ybuf[di1] : 0.0, yd2 = dl ? L.ybuf[di2] : 0.0;
+    // reachable row ``lane`` (row 0 stands in on lanes without one)
+    double hv[N];
+    {
+      const double* hr = L.Hd + (lane < r ? lane : 0) * HDS + 3;
+#pragma unroll
+      for (int i = 0; i < N; ++i) hv[i] = hr[i];
+    }
     if (fl) {
 #pragma unroll
       for (int s = 0; s < NFP; ++s) {
-        const int e = 3 * (s + 1);
-        const double v = fa0 * L.ybuf[e] + fa1 * L.ybuf[e + 1] + fa2 * L.ybuf[e + 2];
+        const double v = fa0 * y[3 * s] + fa1 * y[3 * s + 1] + fa2 * y[3 * s + 2];
         const int id = s * nf + lane;
-        if (write_vals) L.rowval[id] = v;
+        L.rowval[id] = v;
         const double viol = v - fu;
         if (!((act_bits >> s) & 1u) && viol > ftol * (1.0 + fabs(fu))) {
-          const double sc = viol * fdn[s];
-          if (sc > best) { best = sc; key = 2 * id + 1; }
+          const double sc = viol * (ifan * K.rkappa[s]);
+          if (sc > best) { best = sc; key = 2 * id + 1; sv_b = viol; e_b = fu; c_b = 0.0; }
         }
       }
     }
     if (dl) {
-      double v;
-      if (dvel) v = dsc * (L.ybuf[3 * (dk + 1) + dc] - L.ybuf[3 * dk + dc]);
-      else v = dsc * (L.ybuf[3 * (dk + 2) + dc] - 2.0 * L.ybuf[3 * (dk + 1) + dc] + L.ybuf[3 * dk + dc]);
-      if (write_vals) L.rowval[F + lane] = v;
+      const double v = dvel ? dsc * (yd1 - yd0) : dsc * (yd2 - 2.0 * yd1 + yd0);
+      L.rowval[F + lane] = v;
       if (!((act_bits >> NFP) & 1u)) {
         const double vu = v - dbd, vlo = dlo_of(dbd) - v, dtol = ftol * (1.0 + fabs(dbd));
-        if (vu > dtol && vu * ddn > best) { best = vu * ddn; key = 2 * (F + lane) + 1; }
-        if (vlo > dtol && vlo * ddn > best) { best = vlo * ddn; key = 2 * (F + lane); }
-      }
-    }
-#pragma unroll
-    for (int sl = 0; sl < 2; ++sl) {
-      const int l = lane + kWave * sl;
-      if (l < r) {
-        const double* hr = L.Hd + l * HDS;
-        double v = 0.0;
-        for (int e = 0; e < NC; ++e) v += hr[e] * L.ybuf[e];
-        if (write_vals) L.rowval[RB + l] = v;
-        const double viol = v - ru[sl];
-        if (!((act_bits >> (NFP + 1 + sl)) & 1u) && viol > ftol * (1.0 + fabs(ru[sl]))) {
-          const double sc = rdn[sl] > 0.0 ? viol * rdn[sl] : __builtin_huge_val();
-          if (sc > best) { best = sc; key = 2 * (RB + l) + 1; }
+        if (vu > dtol && vu * ddn > best) { best = vu * ddn; key = 2 * (F + lane) + 1; sv_b = vu; e_b = dbd; c_b = dcst; }
+        if (vlo > dtol && vlo * ddn > best) {
+          best = vlo * ddn; key = 2 * (F + lane); sv_b = vlo; e_b = -dlo_of(dbd); c_b = -dcst;
         }
       }
     }
-    wargmax(best, key);
-    splus = 0.0;
+    auto reach_row = [&](int sl, const double (&h)[N]) {
+      const int l = lane + kWave * sl;
+      double acc = 0.0;
+#pragma unroll
+      for (int i = 0; i < N; ++i) acc += h[i] * y[i];
+      const double v = acc + rcst[sl];
+      L.rowval[RB + l] = v;
+      const double viol = v - ru[sl];
+      if (!((act_bits >> (NFP + 1 + sl)) & 1u) && viol > ftol * (1.0 + fabs(ru[sl]))) {
+        const double sc = rdn[sl] > 0.0 ? viol * rdn[sl] : __builtin_huge_val();
+        if (sc > best) { best = sc; key = 2 * (RB + l) + 1; sv_b = viol; e_b = ru[sl]; c_b = rcst[sl]; }
+      }
+    };
+    if (lane < r) reach_row(0, hv);
+    if (r > kWave) {   // second reachable slot: rows 64..127
+      const double* hr = L.Hd + (lane + kWave < r ? lane + kWave : 0) * HDS + 3;
+#pragma unroll
+      for (int i = 0; i < N; ++i) hv[i] = hr[i];
+      if (lane + kWave < r) reach_row(1, hv);
+    }
   };
+  // x-space point from the whitened one; vD holds vw (written after every
+  // update of vw, ahead of a barrier)
   auto refresh_y = [&]() {
-    if (vl) L.vD[lane] = vw;
-    bsync<kWS>();
     if (vl) L.ybuf[3 + lane] = unwhiten_at<P>(L.cL1i, in.T15, L.vD, lane);
     bsync<kWS>();
   };
@@ -1054,46 +1130,28 @@ __device__ void solve_instance(const SolveArgs& A, const InstDesc& idesc, char* 
   };
   int bound_tries = 0;
 
+  if (vl) L.vD[lane] = vw;
+  bsync<kWS>();
+  // dual value of the current multipliers (objective 1/2 |v - v0|^2 plus the
+  // entering row's multiplier times its violation), carried along the steps:
+  // a step of length t adds t (s+ - t zz / 2)
+  double dual = q == 0 ? 0.0 : 0.5 * wsum(vl ? (vw - v0) * (vw - v0) : 0.0);
   bool certified_infeasible = false;
   while (true) {
     refresh_y();
-    double best;
+    double best, sv_b, e_b, c_b;
     int key;
-    double dummy;
-    eval_rows(best, key, dummy, true);   // the last pass leaves the solution's row values
+    eval_rows(best, key, sv_b, e_b, c_b);   // the last pass leaves the solution's row values
+    const int my_key = key;
+    wargmax(best, key);
     if (!(best > 0.0)) { status = kSolved; break; }
     if (steps >= max_steps || key < 0 || (key >> 1) >= m) { status = kPolishFailed; break; }
     const int id = key >> 1, side = (key & 1) ? 1 : -1;
-    // owner publishes violation, full-row bound and constant
-    {
-      int ol, bit;
-      slot_of(id, ol, bit);
-      if (lane == ol) {
-        double val, e_full, c_full;
-        if (bit < NFP) {
-          const int e = 3 * (bit + 1);
-          val = fa0 * L.ybuf[e] + fa1 * L.ybuf[e + 1] + fa2 * L.ybuf[e + 2];
-          e_full = fu; c_full = 0.0;
-        } else if (bit == NFP) {
-          val = dvel ? dsc * (L.ybuf[3 * (dk + 1) + dc] - L.ybuf[3 * dk + dc])
-                     : dsc * (L.ybuf[3 * (dk + 2) + dc] - 2.0 * L.ybuf[3 * (dk + 1) + dc] + L.ybuf[3 * dk + dc]);
-          e_full = side > 0 ? dbd : -dlo_of(dbd); c_full = double(side) * dcst;
-        } else {
-          const int sl = bit - NFP - 1;
-          const double* hr = L.Hd + (lane + kWave * sl) * HDS;
-          val = 0.0;
-          for (int e = 0; e < NC; ++e) val += hr[e] * L.ybuf[e];
-          e_full = sl == 0 ? ru[0] : ru[1];
-          c_full = sl == 0 ? rcst[0] : rcst[1];
-        }
-        L.scal[0] = double(side) * val - e_full;   // > 0
-        L.scal[1] = e_full;
-        L.scal[2] = c_full;
-      }
-    }
-    bsync<kWS>();
-    double splus = L.scal[0];
-    const double e_full = L.scal[1], c_full = L.scal[2];
+    // the lane whose candidate won hands over its violation (> 0), full-row
+    // bound and constant
+    const int owner = __builtin_ctzll(__ballot(my_key == key));
+    double splus = wave::bcast(sv_b, owner);
+    const double e_full = wave::bcast(e_b, owner), c_full = wave::bcast(c_b, owner);
     build_normal(id, side);
     double lamp = 0.0;
     bool added = false;
@@ -1146,15 +1204,15 @@ __device__ void solve_instance(const SolveArgs& A, const InstDesc& idesc, char* 
       }
       const double t = fmin(t1, t2);
       if (zfull && vl) vw -= t * L.vB[lane];
+      if (vl) L.vD[lane] = vw;
       if (lane < q) lamr -= t * rv;
       lamp += t;
+      dual += t * (splus - 0.5 * t * (zfull ? zz : 0.0));
       if (zfull) splus -= t * zz;
-      // dual value of the step's multipliers (the working-set rows are tight):
-      // once it passes the box bound, try the FP64 certificate
+      // once the dual value passes the bound of the objective, try the FP64
+      // certificate (which recomputes the dual value from the rows)
       if (bound_tries < 4) {
-        const double dv = vl ? vw - v0 : 0.0;
-        const double dval = 0.5 * wsum(dv * dv) + lamp * fmax(splus, 0.0);
-        if (dval > Uw * (1.0 + 1e-9) + 1e-12) {
+        if (dual > Uw * (1.0 + 1e-9) + 1e-12) {
           ++bound_tries;
           if (dual_bound_certified(id, side, e_full, c_full, lamp)) {
             certified_infeasible = true;
