@@ -1022,7 +1022,7 @@ __device__ void solve_instance(const SolveArgs& A, const InstDesc& idesc, char* 
 
   // ---- main loop
   // Evaluate every owned row at the current point (row values to rowval) and
-  // return the most violated inactive row over the wavefront as (score, key).
+  // return the lane's most violated inactive row as (score, key).
   // Each lane also keeps, for its own best candidate, the violation
   // side * value - e_full and the row's e_full and c_full, which the owning
   // lane hands to the others afterwards (no second evaluation).  The free
@@ -1142,14 +1142,15 @@ __device__ void solve_instance(const SolveArgs& A, const InstDesc& idesc, char* 
     double best, sv_b, e_b, c_b;
     int key;
     eval_rows(best, key, sv_b, e_b, c_b);   // the last pass leaves the solution's row values
-    const int my_key = key;
-    wargmax(best, key);
-    if (!(best > 0.0)) { status = kSolved; break; }
+    // the largest score; among equal scores the lowest lane's candidate
+    const double gbest = wmax(best);
+    if (!(gbest > 0.0)) { status = kSolved; break; }
+    const int owner = __builtin_ctzll(__ballot(best == gbest));
+    key = __builtin_amdgcn_readlane(key, owner);
     if (steps >= max_steps || key < 0 || (key >> 1) >= m) { status = kPolishFailed; break; }
     const int id = key >> 1, side = (key & 1) ? 1 : -1;
-    // the lane whose candidate won hands over its violation (> 0), full-row
-    // bound and constant
-    const int owner = __builtin_ctzll(__ballot(my_key == key));
+    // the owning lane hands over its violation (> 0), full-row bound and
+    // constant
     double splus = wave::bcast(sv_b, owner);
     const double e_full = wave::bcast(e_b, owner), c_full = wave::bcast(c_b, owner);
     build_normal(id, side);
@@ -1160,11 +1161,24 @@ __device__ void solve_instance(const SolveArgs& A, const InstDesc& idesc, char* 
       double zz, aa;
       project(zz, aa);
       const double rv = ri_times_c();   // r = R^-1 c
-      const double rmax = wmax((lane < q) ? fabs(rv) : 0.0);
+      // step to the first multiplier that reaches 0: the smallest lam_k / r_k
+      // over r_k > 1e-13 max |r|.  The arg-min over every r_k > 0 and the
+      // maximum are reduced together; only when the winner's r_k is below
+      // the threshold (rare) is the arg-min taken again over the others.
       double t1 = __builtin_huge_val();
       int kd = lane;
-      if (lane < q && rv > 1e-13 * rmax) t1 = lamr / rv;
-      wargmin(t1, kd);
+      if (q > 0) {
+        double rmax = (lane < q) ? fabs(rv) : 0.0;
+        if (lane < q && rv > 0.0) t1 = lamr / rv;
+        rmax = wmax(rmax);
+        wargmin(t1, kd);
+        if (t1 < __builtin_huge_val() && !(wave::bcast(rv, kd) > 1e-13 * rmax)) {
+          t1 = __builtin_huge_val();
+          kd = lane;
+          if (lane < q && rv > 1e-13 * rmax) t1 = lamr / rv;
+          wargmin(t1, kd);
+        }
+      }
       const bool zfull = zz > 1e-20 * aa;
       const double t2 = zfull ? splus / zz : __builtin_huge_val();
       if (!(t1 < 1e300) && !(t2 < 1e300)) {
@@ -1242,7 +1256,8 @@ __device__ void solve_instance(const SolveArgs& A, const InstDesc& idesc, char* 
 
   // ---- solution, KKT residuals, cost
   // ybuf and rowval hold the solution and its row values from the main
-  // loop's last pass (no row was violated there)
+  // loop's last pass (no row was violated there).  Every lane forms its
+  // partial values first; the reductions then run together.
   bsync<kWS>();
   // primal residual and scale over all rows (owners)
   double pres = 0.0, pscale = 0.0;
@@ -1268,39 +1283,46 @@ __device__ void solve_instance(const SolveArgs& A, const InstDesc& idesc, char* 
       pscale = fmax(pscale, fmax(fabs(v), fabs(ru[sl])));
     }
   }
-  pres = wmax(pres);
-  pscale = wmax(pscale);
   // (Q y~)_e for every full coefficient, cost = y~^T Q y~
-  double qy = 0.0;
+  double qy = 0.0, yq = 0.0;
   if (lane < NC) {
     const int pt = lane / 3, c = lane - 3 * (lane / 3);
 #pragma unroll
     for (int b = 0; b <= P; ++b) qy += L.cQ1[kMaxPts * pt + b] * L.ybuf[3 * b + c];
     qy *= in.iT3;
     L.qbuf[lane] = qy;
+    yq = qy * L.ybuf[lane];
   }
-  const double cost = wsum(lane < NC ? qy * L.ybuf[lane] : 0.0);
-  if (lane < q) L.lam[lane] = fmax(lamr, 0.0);
+  // complementarity
+  const double lam_own = fmax(lamr, 0.0);
+  double cres = 0.0, lmax = 0.0;
+  if (lane < q) {
+    L.lam[lane] = lam_own;
+    const int id = L.actid[lane];
+    const double slack = L.acte[lane] - double(L.actside[lane]) * L.rowval[id];
+    cres = lam_own * fabs(slack);
+    lmax = lam_own;
+  }
   bsync<kWS>();
   // stationarity on the free variables: 2 Q y~ + sum_k lam_k side_k a_k
   double st = 0.0, sq = 0.0, sac = 0.0;
   if (vl) {
     const int pt = vs + 1;
     sq = 2.0 * L.qbuf[3 + lane];
-    for (int k = 0; k < q; ++k) sac += L.lam[k] * double(L.actside[k]) * in.coef(L.actid[k], pt, vc, L.Af, L.Hd);
+    for (int k = 0; k < q; ++k) {
+      const int idk = __builtin_amdgcn_readfirstlane(L.actid[k]);
+      sac += L.lam[k] * double(L.actside[k]) * in.coef(idk, pt, vc, L.Af, L.Hd);
+    }
     st = sq + sac;
   }
-  const double dres = wmax(fabs(st)) / (1.0 + fmax(wmax(fabs(sq)), wmax(fabs(sac))));
-  // complementarity
-  double cres = 0.0, lmax = 0.0;
-  if (lane < q) {
-    const int id = L.actid[lane];
-    const double slack = L.acte[lane] - double(L.actside[lane]) * L.rowval[id];
-    cres = L.lam[lane] * fabs(slack);
-    lmax = L.lam[lane];
-  }
+  pres = wmax(pres);
+  pscale = wmax(pscale);
+  const double cost = wsum(yq);
+  const double stm = wmax(fabs(st)), sqm = wmax(fabs(sq)), sacm = wmax(fabs(sac));
   lmax = wmax(lmax);
-  cres = wmax(cres) / (1.0 + lmax);
+  cres = wmax(cres);
+  const double dres = stm / (1.0 + fmax(sqm, sacm));
+  cres = cres / (1.0 + lmax);
   const double kkt = fmax(fmax(fmax(pres, 0.0) / (1.0 + pscale), dres), cres);
   const bool ok = kkt <= A.kkt_tol && isfinite(kkt) && isfinite(cost);
   if (lane < NC) A.P_out[3 * in.po + lane] = L.ybuf[lane] + sel3(lane - 3 * (lane / 3), in.P0[0], in.P0[1], in.P0[2]);
