@@ -752,13 +752,15 @@ __device__ void solve_instance(const SolveArgs& A, const InstDesc& idesc, char* 
   };
 
   // whitened normal of constraint (id, side) -> vA; also full-row bound pieces
-  // (L^-1 a restricted to the free variables; lane i = 3t + c): a face row
+  // (L^-1 a restricted to the free variables; lane i = 3t + c, to vA and
+  // returned in the lane's register, 0 on lanes i >= N): a face row
   // has coefficients on one interior point, a difference row on two or three
   // consecutive points of one coordinate, so their whitened normals are
   // combinations of columns of L1inv; a reachable row is whitened from its
   // LDS copy.  ``id`` is uniform.
-  auto build_normal = [&](int id_in, int side) {
+  auto build_normal = [&](int id_in, int side) -> double {
     const int id = __builtin_amdgcn_readfirstlane(id_in);
+    double a = 0.0;
     if (vl) {
       const double* Li = L.cL1i + kMaxFree * vs;   // row vs of L1inv
       double w;
@@ -780,44 +782,40 @@ __device__ void solve_instance(const SolveArgs& A, const InstDesc& idesc, char* 
       } else {
         w = whiten_at<P>(L.cL1i, in.T15, L.Hd + (id - RB) * HDS + 3, lane);
       }
-      L.vA[lane] = double(side) * w;
+      a = double(side) * w;
+      L.vA[lane] = a;
     }
     bsync<kWS>();
+    return a;
   };
 
-  // c = Q1^T a, z = a - Q1 c by classical Gram-Schmidt; a in vA, z -> vB,
-  // c -> vC (first q entries), zz = |z|^2, aa = |a|^2.  A second pass
-  // re-orthogonalises only when the first lost more than half of |a|^2
-  // (the Kahan-Parlett "twice is enough" test).
-  auto project = [&](double& zz, double& aa) {
-    if (lane < q) L.vC[lane] = dot_row<N>(L.Q1 + lane * NS, L.vA);
+  // c = Q1 a, z = a - Q1^T c by classical Gram-Schmidt (a: vA in LDS and
+  // a_own, the lane's entry), then r = R^-1 c; lane i < N keeps z_i, lane
+  // k < q keeps c_k and r_k (c also in vC).  A second pass re-orthogonalises
+  // only when the first lost more than half of |a|^2 (the Kahan-Parlett
+  // "twice is enough" test).
+  auto project = [&](double a_own, double& zz, double& aa, double& z_own, double& r_own, double& c_own) {
+    c_own = lane < q ? dot_row<N>(L.Q1 + lane * NS, L.vA) : 0.0;
+    if (lane < q) L.vC[lane] = c_own;
     bsync<kWS>();
-    double za = 0.0, zb = 0.0;
-    if (vl) {
-      za = L.vA[lane];
-      zb = colsub_q(za, L.Q1 + lane, NS, L.vC, q);
-      L.vB[lane] = zb;
+    z_own = vl ? colsub_q(a_own, L.Q1 + lane, NS, L.vC, q) : 0.0;
+    aa = wsum(a_own * a_own);
+    zz = wsum(z_own * z_own);
+    if (zz < 0.5 * aa && q > 0) {
+      if (vl) L.vB[lane] = z_own;
+      bsync<kWS>();
+      const double e_own = lane < q ? dot_row<N>(L.Q1 + lane * NS, L.vB) : 0.0;
+      if (lane < q) L.vE[lane] = e_own;
+      bsync<kWS>();
+      z_own = vl ? colsub_q(z_own, L.Q1 + lane, NS, L.vE, q) : 0.0;
+      c_own += e_own;
+      if (lane < q) L.vC[lane] = c_own;
+      zz = wsum(z_own * z_own);
+      bsync<kWS>();
     }
-    aa = wsum(za * za);
-    zz = wsum(zb * zb);
-    if (!(zz < 0.5 * aa) || q == 0) return;
-    bsync<kWS>();
-    if (lane < q) L.vE[lane] = dot_row<N>(L.Q1 + lane * NS, L.vB);
-    bsync<kWS>();
-    double zc = 0.0;
-    if (vl) {
-      zc = colsub_q(L.vB[lane], L.Q1 + lane, NS, L.vE, q);
-      L.vB[lane] = zc;
-    }
-    if (lane < q) L.vC[lane] += L.vE[lane];
-    zz = wsum(zc * zc);
-    bsync<kWS>();
+    r_own = lane < q ? rowsum_upper_q(L.Ri + lane * NS, L.vC, lane, q) : 0.0;
   };
 
-  // r = R^-1 c, c in vC (lane i < q gets r_i)
-  auto ri_times_c = [&]() -> double {
-    return lane < q ? rowsum_upper_q(L.Ri + lane * NS, L.vC, lane, q) : 0.0;
-  };
   // R^-1 rebuilt by back substitution after a downdate: lane j builds column
   // j (entries i <= j); each lane reads back only its own column
   auto ri_rebuild = [&]() {
@@ -834,12 +832,14 @@ __device__ void solve_instance(const SolveArgs& A, const InstDesc& idesc, char* 
   };
 
   // append the projected direction as a new basis column (R gets c and |z|;
-  // R^-1 gets -R^-1 c / |z| and 1/|z|, with rv = R^-1 c on lanes < q)
-  auto append = [&](double nz, int id, int side, double e_full, double c_full, double rv) {
+  // R^-1 gets -R^-1 c / |z| and 1/|z|, with rv = R^-1 c and c_own = c on
+  // lanes < q, z_own = z on lanes < N)
+  auto append = [&](double nz, int id, int side, double e_full, double c_full, double rv, double z_own,
+                    double c_own) {
     const double inz = 1.0 / nz;
-    if (vl) L.Q1[q * NS + lane] = L.vB[lane] * inz;
+    if (vl) L.Q1[q * NS + lane] = z_own * inz;
     if (lane < q) {
-      L.Rm[lane * NS + q] = L.vC[lane];
+      L.Rm[lane * NS + q] = c_own;
       L.Ri[lane * NS + q] = -rv * inz;
     }
     if (lane == 0) {
@@ -977,10 +977,10 @@ __device__ void solve_instance(const SolveArgs& A, const InstDesc& idesc, char* 
     }
     bsync<kWS>();
     const double e_full = L.scal[0], c_full = L.scal[1];
-    build_normal(id, side);
-    double zz, aa;
-    project(zz, aa);
-    if (zz > 1e-16 * aa && q < N) append(sqrt(zz), id, side, e_full, c_full, ri_times_c());
+    const double a_own = build_normal(id, side);
+    double zz, aa, z_own, r_own, c_own;
+    project(a_own, zz, aa, z_own, r_own, c_own);
+    if (zz > 1e-16 * aa && q < N) append(sqrt(zz), id, side, e_full, c_full, r_own, z_own, c_own);
   }
   if (q == 0) {
     // no warm start: the unconstrained minimiser
@@ -1153,14 +1153,13 @@ __device__ void solve_instance(const SolveArgs& A, const InstDesc& idesc, char* 
     // constant
     double splus = wave::bcast(sv_b, owner);
     const double e_full = wave::bcast(e_b, owner), c_full = wave::bcast(c_b, owner);
-    build_normal(id, side);
+    const double a_own = build_normal(id, side);
     double lamp = 0.0;
     bool added = false;
     while (!added) {
       ++steps;
-      double zz, aa;
-      project(zz, aa);
-      const double rv = ri_times_c();   // r = R^-1 c
+      double zz, aa, z_own, rv, c_own;   // |z|^2, |a|^2, z_i, r = R^-1 c and c on lanes < q
+      project(a_own, zz, aa, z_own, rv, c_own);
       // step to the first multiplier that reaches 0: the smallest lam_k / r_k
       // over r_k > 1e-13 max |r|.  The arg-min over every r_k > 0 and the
       // maximum are reduced together; only when the winner's r_k is below
@@ -1217,7 +1216,7 @@ __device__ void solve_instance(const SolveArgs& A, const InstDesc& idesc, char* 
         break;
       }
       const double t = fmin(t1, t2);
-      if (zfull && vl) vw -= t * L.vB[lane];
+      if (zfull && vl) vw -= t * z_own;
       if (vl) L.vD[lane] = vw;
       if (lane < q) lamr -= t * rv;
       lamp += t;
@@ -1236,7 +1235,7 @@ __device__ void solve_instance(const SolveArgs& A, const InstDesc& idesc, char* 
         }
       }
       if (t2 <= t1) {
-        append(sqrt(zz), id, side, e_full, c_full, rv);
+        append(sqrt(zz), id, side, e_full, c_full, rv, z_own, c_own);
         if (lane == q - 1) lamr = lamp;
         added = true;
       } else {

@@ -70,6 +70,21 @@ __device__ __forceinline__ double reduce_f64(double v, Op op) {
 __device__ __forceinline__ double sum(double v) {
   return reduce_f64(v, [](double a, double b) { return a + b; });
 }
+// four sums at once (the stages of the four trees interleave)
+__device__ __forceinline__ void sum4(double (&v)[4]) {
+#pragma unroll
+  for (int u = 0; u < 4; ++u) v[u] = v[u] + dpp_f64<kXor1>(v[u]);
+#pragma unroll
+  for (int u = 0; u < 4; ++u) v[u] = v[u] + dpp_f64<kXor2>(v[u]);
+#pragma unroll
+  for (int u = 0; u < 4; ++u) v[u] = v[u] + dpp_f64<kHalfMirror>(v[u]);
+#pragma unroll
+  for (int u = 0; u < 4; ++u) v[u] = v[u] + dpp_f64<kMirror>(v[u]);
+#pragma unroll
+  for (int u = 0; u < 4; ++u) { const PairD p = swap_f64(v[u], false); v[u] = p.a + p.b; }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) { const PairD p = swap_f64(v[u], true); v[u] = p.a + p.b; }
+}
 __device__ __forceinline__ double max(double v) {
   return reduce_f64(v, [](double a, double b) { return fmax(a, b); });
 }
