@@ -167,14 +167,24 @@ struct Inst {
   }
 };
 
+// The value of x, opaque to the optimiser at this point: values derived from
+// it (lane-dependent addresses and indices) are formed where they are used
+// instead of being hoisted out of the polish loop and held in registers for
+// its whole length (the loop runs at the 256-register limit).
+__device__ __forceinline__ int opaque(int x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
 // whitening: (L^-1 a)_i for var i = 3s + c, a given on the free vars in ``a``;
 // Li = rows of L1inv (stride kMaxFree, in LDS or constant memory; lower
 // triangular with explicit zeros above the diagonal, so the full row can be
 // summed: a is finite).  Fixed trip count, every load issued before the
 // first product.
 template <int P>
-__device__ __forceinline__ double whiten_at(const double* Li, double T15, const double* a, int i) {
+__device__ __forceinline__ double whiten_at(const double* Li, double T15, const double* a, int i_in) {
   constexpr int NFP = P - 1;
+  const int i = opaque(i_in);
   const int s = i / 3, c = i - 3 * (i / 3);
   double w[NFP], x[NFP];
 #pragma unroll
@@ -186,8 +196,9 @@ __device__ __forceinline__ double whiten_at(const double* Li, double T15, const 
 }
 // un-whitening: (L^-T v)_i (column s of L1inv, zero above row s)
 template <int P>
-__device__ __forceinline__ double unwhiten_at(const double* Li, double T15, const double* v, int i) {
+__device__ __forceinline__ double unwhiten_at(const double* Li, double T15, const double* v, int i_in) {
   constexpr int NFP = P - 1;
+  const int i = opaque(i_in);
   const int s = i / 3, c = i - 3 * (i / 3);
   double w[NFP], x[NFP];
 #pragma unroll
@@ -859,6 +870,7 @@ __device__ void solve_instance(const SolveArgs& A, const InstDesc& idesc, char* 
   // Givens rotations applied to R rows and Q1 columns, shift active data
   auto drop = [&](int kd) {
     constexpr int EPL = (N * N + kWave - 1) / kWave;
+    const int ln = opaque(lane);
     {
       int own, bit;
       slot_of(L.actid[kd], own, bit);
@@ -867,7 +879,7 @@ __device__ void solve_instance(const SolveArgs& A, const InstDesc& idesc, char* 
     double tmp[EPL];
 #pragma unroll
     for (int u = 0; u < EPL; ++u) {
-      const int e = lane + kWave * u;
+      const int e = ln + kWave * u;
       const int row = e / N, col = e - N * (e / N);
       tmp[u] = (e < N * N && row < q && col >= kd && col < q - 1) ? L.Rm[row * NS + col + 1] : 0.0;
     }
@@ -880,7 +892,7 @@ __device__ void solve_instance(const SolveArgs& A, const InstDesc& idesc, char* 
     bsync<kWS>();
 #pragma unroll
     for (int u = 0; u < EPL; ++u) {
-      const int e = lane + kWave * u;
+      const int e = ln + kWave * u;
       const int row = e / N, col = e - N * (e / N);
       if (e < N * N && row < q && col >= kd && col < q - 1) L.Rm[row * NS + col] = tmp[u];
     }
@@ -1031,6 +1043,7 @@ __device__ void solve_instance(const SolveArgs& A, const InstDesc& idesc, char* 
   // pinned entries of y~ are 0 at P_0 and the goal offset, whose product
   // with a reachable row is the constant rcst).
   auto eval_rows = [&](double& best, int& key, double& sv_b, double& e_b, double& c_b) {
+    const int ln = opaque(lane);   // addresses formed here, not held across the loop
     best = -1.0; key = 0x7fffffff; sv_b = 0.0; e_b = 0.0; c_b = 0.0;
     double y[N];
 #pragma unroll
@@ -1042,7 +1055,7 @@ __device__ void solve_instance(const SolveArgs& A, const InstDesc& idesc, char* 
     // reachable row ``lane`` (row 0 stands in on lanes without one)
     double hv[N];
     {
-      const double* hr = L.Hd + (lane < r ? lane : 0) * HDS + 3;
+      const double* hr = L.Hd + (ln < r ? ln : 0) * HDS + 3;
 #pragma unroll
       for (int i = 0; i < N; ++i) hv[i] = hr[i];
     }
@@ -1051,7 +1064,7 @@ __device__ void solve_instance(const SolveArgs& A, const InstDesc& idesc, char* 
       for (int s = 0; s < NFP; ++s) {
         const double v = fa0 * y[3 * s] + fa1 * y[3 * s + 1] + fa2 * y[3 * s + 2];
         const int id = s * nf + lane;
-        L.rowval[id] = v;
+        L.rowval[s * nf + ln] = v;
         const double viol = v - fu;
         if (!((act_bits >> s) & 1u) && viol > ftol * (1.0 + fabs(fu))) {
           const double sc = viol * (ifan * K.rkappa[s]);
@@ -1061,7 +1074,7 @@ __device__ void solve_instance(const SolveArgs& A, const InstDesc& idesc, char* 
     }
     if (dl) {
       const double v = dvel ? dsc * (yd1 - yd0) : dsc * (yd2 - 2.0 * yd1 + yd0);
-      L.rowval[F + lane] = v;
+      L.rowval[F + ln] = v;
       if (!((act_bits >> NFP) & 1u)) {
         const double vu = v - dbd, vlo = dlo_of(dbd) - v, dtol = ftol * (1.0 + fabs(dbd));
         if (vu > dtol && vu * ddn > best) { best = vu * ddn; key = 2 * (F + lane) + 1; sv_b = vu; e_b = dbd; c_b = dcst; }
@@ -1072,11 +1085,12 @@ __device__ void solve_instance(const SolveArgs& A, const InstDesc& idesc, char* 
     }
     auto reach_row = [&](int sl, const double (&h)[N]) {
       const int l = lane + kWave * sl;
+      const int lo = ln + kWave * sl;
       double acc = 0.0;
 #pragma unroll
       for (int i = 0; i < N; ++i) acc += h[i] * y[i];
       const double v = acc + rcst[sl];
-      L.rowval[RB + l] = v;
+      L.rowval[RB + lo] = v;
       const double viol = v - ru[sl];
       if (!((act_bits >> (NFP + 1 + sl)) & 1u) && viol > ftol * (1.0 + fabs(ru[sl]))) {
         const double sc = rdn[sl] > 0.0 ? viol * rdn[sl] : __builtin_huge_val();
@@ -1085,7 +1099,7 @@ __device__ void solve_instance(const SolveArgs& A, const InstDesc& idesc, char* 
     };
     if (lane < r) reach_row(0, hv);
     if (r > kWave) {   // second reachable slot: rows 64..127
-      const double* hr = L.Hd + (lane + kWave < r ? lane + kWave : 0) * HDS + 3;
+      const double* hr = L.Hd + (ln + kWave < r ? ln + kWave : 0) * HDS + 3;
 #pragma unroll
       for (int i = 0; i < N; ++i) hv[i] = hr[i];
       if (lane + kWave < r) reach_row(1, hv);
