@@ -802,9 +802,12 @@ __device__ void solve_instance(const SolveArgs& A, const InstDesc& idesc, char* 
 
   // c = Q1 a, z = a - Q1^T c by classical Gram-Schmidt (a: vA in LDS and
   // a_own, the lane's entry), then r = R^-1 c; lane i < N keeps z_i, lane
-  // k < q keeps c_k and r_k (c also in vC).  A second pass re-orthogonalises
-  // only when the first lost more than half of |a|^2 (the Kahan-Parlett
-  // "twice is enough" test).
+  // k < q keeps c_k and r_k (c also in vC).  One pass leaves z orthogonal to
+  // the basis up to about eps |a| / |z|; a second pass re-orthogonalises when
+  // |z|^2 < 1e-2 |a|^2, i.e. when that loss could exceed about 10 eps (the
+  // "twice is enough" threshold of 1/2 would take it on nearly half of the
+  // steps here: face rows on neighbouring points are close in the whitened
+  // metric).
   auto project = [&](double a_own, double& zz, double& aa, double& z_own, double& r_own, double& c_own) {
     c_own = lane < q ? dot_row<N>(L.Q1 + lane * NS, L.vA) : 0.0;
     if (lane < q) L.vC[lane] = c_own;
@@ -812,7 +815,7 @@ __device__ void solve_instance(const SolveArgs& A, const InstDesc& idesc, char* 
     z_own = vl ? colsub_q(a_own, L.Q1 + lane, NS, L.vC, q) : 0.0;
     aa = wsum(a_own * a_own);
     zz = wsum(z_own * z_own);
-    if (zz < 0.5 * aa && q > 0) {
+    if (zz < 1e-2 * aa && q > 0) {
       if (vl) L.vB[lane] = z_own;
       bsync<kWS>();
       const double e_own = lane < q ? dot_row<N>(L.Q1 + lane * NS, L.vB) : 0.0;
