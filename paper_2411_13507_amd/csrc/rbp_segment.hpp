@@ -129,44 +129,6 @@ __device__ Lds<Real> carve(char* s, const LdsDims& D) {
 // Stride (elements) of the transposed reachable block H^T (free columns).
 __device__ __forceinline__ int hft_stride(const LdsDims& D) { return D.r_cap | 1; }
 
-// --------------------------------------------------------------------------
-// Instance description shared by the forward and backward passes.
-// --------------------------------------------------------------------------
-template <int P>
-struct Inst {
-  static constexpr int NFP = P - 1;       // interior control points
-  static constexpr int N = 3 * NFP;       // free variables
-  static constexpr int NC = 3 * (P + 1);  // coefficients of a full row
-  static constexpr int ND = 6 * P - 3;    // difference rows (velocity, acceleration)
-  // odd row strides (in doubles) of the LDS copies read one row per lane,
-  // so that a lane-strided 64-bit access touches distinct banks
-  static constexpr int NS = N | 1;        // basis Q1 and factor R
-  static constexpr int HDS = NC | 1;      // reachable rows
-  double T, T15, iT3, sv, sa, vmax, amax;
-  double x0[6], P0[3], dg[3];
-  int nf, r, F, RB, m, f0;
-  int64_t r0, hb, po;
-
-  // coefficient of row ``id`` on full-vector entry e = 3*pt + c (pt = 0..P)
-  __device__ double coef(int id, int pt, int c, const double* Af, const double* Hd) const {
-    if (id < F) {
-      const int s = id / nf, j = id - s * nf;
-      return (pt == s + 1) ? Af[3 * j + c] : 0.0;
-    }
-    if (id < F + 3 * P) {
-      const int l = id - F, k = l / 3, cc = l - 3 * (l / 3);
-      if (cc != c) return 0.0;
-      return sv * (double(pt == k + 1) - double(pt == k));
-    }
-    if (id < RB) {
-      const int l = id - F - 3 * P, k = l / 3, cc = l - 3 * (l / 3);
-      if (cc != c) return 0.0;
-      return sa * (double(pt == k + 2) - 2.0 * double(pt == k + 1) + double(pt == k));
-    }
-    return Hd[(id - RB) * HDS + 3 * pt + c];
-  }
-};
-
 // The value of x, opaque to the optimiser at this point: values derived from
 // it (lane-dependent addresses and indices) are formed where they are used
 // instead of being hoisted out of the polish loop and held in registers for
@@ -208,6 +170,74 @@ __device__ __forceinline__ double unwhiten_at(const double* Li, double T15, cons
   for (int t = 0; t < NFP; ++t) acc += w[t] * x[t];
   return T15 * acc;
 }
+
+// --------------------------------------------------------------------------
+// Instance description shared by the forward and backward passes.
+// --------------------------------------------------------------------------
+template <int P>
+struct Inst {
+  static constexpr int NFP = P - 1;       // interior control points
+  static constexpr int N = 3 * NFP;       // free variables
+  static constexpr int NC = 3 * (P + 1);  // coefficients of a full row
+  static constexpr int ND = 6 * P - 3;    // difference rows (velocity, acceleration)
+  // odd row strides (in doubles) of the LDS copies read one row per lane,
+  // so that a lane-strided 64-bit access touches distinct banks
+  static constexpr int NS = N | 1;        // basis Q1 and factor R
+  static constexpr int HDS = NC | 1;      // reachable rows
+  double T, T15, iT3, sv, sa, vmax, amax;
+  double x0[6], P0[3], dg[3];
+  int nf, r, F, RB, m, f0;
+  int64_t r0, hb, po;
+
+  // coefficient of row ``id`` on full-vector entry e = 3*pt + c (pt = 0..P)
+  __device__ double coef(int id, int pt, int c, const double* Af, const double* Hd) const {
+    if (id < F) {
+      const int s = id / nf, j = id - s * nf;
+      return (pt == s + 1) ? Af[3 * j + c] : 0.0;
+    }
+    if (id < F + 3 * P) {
+      const int l = id - F, k = l / 3, cc = l - 3 * (l / 3);
+      if (cc != c) return 0.0;
+      return sv * (double(pt == k + 1) - double(pt == k));
+    }
+    if (id < RB) {
+      const int l = id - F - 3 * P, k = l / 3, cc = l - 3 * (l / 3);
+      if (cc != c) return 0.0;
+      return sa * (double(pt == k + 2) - 2.0 * double(pt == k + 1) + double(pt == k));
+    }
+    return Hd[(id - RB) * HDS + 3 * pt + c];
+  }
+
+  // Entry i = 3t + c (t < P - 1) of the whitened normal L^-1 a of row ``id``
+  // (uniform), a restricted to the free variables.  A face row has
+  // coefficients on one interior point and a difference row on two or three
+  // consecutive points of one coordinate, so theirs are combinations of
+  // columns of L1inv (Li = row t of L1inv); a reachable row is whitened from
+  // its LDS copy (Li0 = L1inv, row stride kMaxFree).
+  __device__ double whitened(int id, int t, int c, int i, const double* Li0, const double* Af,
+                             const double* Hd) const {
+    constexpr int NFP = P - 1;
+    const double* Li = Li0 + kMaxFree * t;
+    if (id < F) {
+      const int s = id / nf, j = id - s * nf;
+      return T15 * Li[s] * Af[3 * j + c];
+    }
+    if (id < RB) {
+      const int l = id - F;
+      const bool vel = l < 3 * P;
+      const int l2 = vel ? l : l - 3 * P, k = l2 / 3, cc = l2 - 3 * k;
+      double u;
+      if (vel) {   // sv (P_{k+1} - P_k): free points k and k - 1
+        u = sv * ((k <= NFP - 1 ? Li[k < NFP ? k : 0] : 0.0) - (k >= 1 ? Li[k >= 1 ? k - 1 : 0] : 0.0));
+      } else {     // sa (P_{k+2} - 2 P_{k+1} + P_k): free points k + 1, k, k - 1
+        u = sa * ((k + 1 <= NFP - 1 ? Li[k + 1 < NFP ? k + 1 : 0] : 0.0) - 2.0 * Li[k] +
+                  (k >= 1 ? Li[k >= 1 ? k - 1 : 0] : 0.0));
+      }
+      return c == cc ? T15 * u : 0.0;
+    }
+    return whiten_at<P>(Li0, T15, Hd + (id - RB) * HDS + 3, i);
+  }
+};
 
 // Copy n doubles (rows of RL values) from global memory into LDS rows of
 // stride LD, with eight loads in flight per lane before the first store (the
@@ -762,38 +792,13 @@ __device__ void solve_instance(const SolveArgs& A, const InstDesc& idesc, char* 
     else { const int l = id - RB; own_lane = l & 63; bit = NFP + 1 + (l >> 6); }
   };
 
-  // whitened normal of constraint (id, side) -> vA; also full-row bound pieces
-  // (L^-1 a restricted to the free variables; lane i = 3t + c, to vA and
-  // returned in the lane's register, 0 on lanes i >= N): a face row
-  // has coefficients on one interior point, a difference row on two or three
-  // consecutive points of one coordinate, so their whitened normals are
-  // combinations of columns of L1inv; a reachable row is whitened from its
-  // LDS copy.  ``id`` is uniform.
+  // whitened normal of constraint (id, side): lane i < N gets entry i (also
+  // to vA), lanes i >= N get 0.  ``id`` is uniform.
   auto build_normal = [&](int id_in, int side) -> double {
     const int id = __builtin_amdgcn_readfirstlane(id_in);
     double a = 0.0;
     if (vl) {
-      const double* Li = L.cL1i + kMaxFree * vs;   // row vs of L1inv
-      double w;
-      if (id < F) {
-        const int s = id / nf, j = id - s * nf;
-        w = in.T15 * Li[s] * L.Af[3 * j + vc];
-      } else if (id < RB) {
-        const int l = id - F;
-        const bool vel = l < 3 * P;
-        const int l2 = vel ? l : l - 3 * P, k = l2 / 3, cc = l2 - 3 * k;
-        double u;
-        if (vel) {   // sv (P_{k+1} - P_k): free points k and k - 1
-          u = in.sv * ((k <= NFP - 1 ? Li[k < NFP ? k : 0] : 0.0) - (k >= 1 ? Li[k >= 1 ? k - 1 : 0] : 0.0));
-        } else {     // sa (P_{k+2} - 2 P_{k+1} + P_k): free points k + 1, k, k - 1
-          u = in.sa * ((k + 1 <= NFP - 1 ? Li[k + 1 < NFP ? k + 1 : 0] : 0.0) - 2.0 * Li[k] +
-                       (k >= 1 ? Li[k >= 1 ? k - 1 : 0] : 0.0));
-        }
-        w = vc == cc ? in.T15 * u : 0.0;
-      } else {
-        w = whiten_at<P>(L.cL1i, in.T15, L.Hd + (id - RB) * HDS + 3, lane);
-      }
-      a = double(side) * w;
+      a = double(side) * in.whitened(id, vs, vc, lane, L.cL1i, L.Af, L.Hd);
       L.vA[lane] = a;
     }
     bsync<kWS>();
@@ -1402,6 +1407,7 @@ __device__ void backward_instance(const BackArgs& A, const InstDesc& idesc, char
     return;
   }
   for (int e = lane; e < nf * 3; e += kWave) L.Af[e] = A.A_face[3 * (int64_t)in.f0 + e];
+  for (int e = lane; e < kMaxFree * kMaxFree; e += kWave) L.cL1i[e] = (&K.L1inv[0][0])[e];
   const int64_t sb = (int64_t)inst * A.st_stride;
   if (lane < q) {
     L.actid[lane] = A.st_id[sb + lane];
@@ -1437,51 +1443,48 @@ __device__ void backward_instance(const BackArgs& A, const InstDesc& idesc, char
   __syncthreads();
   const bool vl = lane < N;
   const int vs = lane / 3, vc = lane - 3 * (lane / 3);
-  // QR of the whitened active normals, in stored order
+  // QR of the whitened active normals, in stored order, by classical
+  // Gram-Schmidt (second pass when |z|^2 < 1e-2 |a|^2, as in the forward
+  // pass)
   bool dep = false;
   for (int k = 0; k < q; ++k) {
-    const int id = L.actid[k], side = L.actside[k];
-    if (vl) L.vC[lane] = in.coef(id, vs + 1, vc, L.Af, L.Hd);
+    const int id = __builtin_amdgcn_readfirstlane(L.actid[k]);
+    const int side = L.actside[k];
+    const double a = vl ? double(side) * in.whitened(id, vs, vc, lane, L.cL1i, L.Af, L.Hd) : 0.0;
+    if (vl) L.vA[lane] = a;
     __syncthreads();
-    if (vl) L.vA[lane] = double(side) * whiten_at<P>(&K.L1inv[0][0], in.T15, L.vC, lane);
+    double c = lane < k ? dot_row<N>(L.Q1 + lane * NS, L.vA) : 0.0;
+    if (lane < k) L.vE[lane] = c;
     __syncthreads();
-    for (int pass = 0; pass < 2; ++pass) {
-      if (lane < k) {
-        double acc = 0.0;
-        for (int i = 0; i < N; ++i) acc += L.Q1[lane * NS + i] * L.vA[i];
-        L.vE[lane] = acc;
-      }
+    double z = vl ? colsub_q(a, L.Q1 + lane, NS, L.vE, k) : 0.0;
+    const double aa = wsum(a * a);
+    double zz = wsum(z * z);
+    if (zz < 1e-2 * aa && k > 0) {
+      if (vl) L.vB[lane] = z;
       __syncthreads();
-      if (vl) {
-        double acc = L.vA[lane];
-        for (int j = 0; j < k; ++j) acc -= L.Q1[j * NS + lane] * L.vE[j];
-        L.vB[lane] = acc;
-      }
-      if (lane < k) {
-        if (pass == 0) L.Rm[lane * NS + k] = L.vE[lane];
-        else L.Rm[lane * NS + k] += L.vE[lane];
-      }
+      const double e = lane < k ? dot_row<N>(L.Q1 + lane * NS, L.vB) : 0.0;
+      if (lane < k) L.vE[lane] = e;
       __syncthreads();
-      if (vl) L.vA[lane] = L.vB[lane];
-      __syncthreads();
+      z = vl ? colsub_q(z, L.Q1 + lane, NS, L.vE, k) : 0.0;
+      c += e;
+      zz = wsum(z * z);
     }
-    const double zz = wsum(vl ? L.vA[lane] * L.vA[lane] : 0.0);
     const double nz = sqrt(zz);
     dep |= !(nz > 1e-10);
     const double nzs = nz > 1e-300 ? nz : 1e-300;
-    if (vl) L.Q1[k * NS + lane] = L.vA[lane] / nzs;
+    if (lane < k) L.Rm[lane * NS + k] = c;
+    if (vl) L.Q1[k * NS + lane] = z / nzs;
     if (lane == 0) L.Rm[k * NS + k] = nzs;
     __syncthreads();
   }
   // whitened upstream gradient on the free variables
   if (vl) L.vD[lane] = L.qbuf[3 + lane];
   __syncthreads();
-  double gh = vl ? whiten_at<P>(&K.L1inv[0][0], in.T15, L.vD, lane) : 0.0;
+  double gh = vl ? whiten_at<P>(L.cL1i, in.T15, L.vD, lane) : 0.0;
   if (vl) L.vA[lane] = gh;
   __syncthreads();
   // c = Q1^T gh ; omega = R^-1 c ; xi = gh - Q1 c ; w = L^-T xi
-  double cv = 0.0;
-  if (lane < q) for (int i = 0; i < N; ++i) cv += L.Q1[lane * NS + i] * L.vA[i];
+  const double cv = lane < q ? dot_row<N>(L.Q1 + lane * NS, L.vA) : 0.0;
   if (lane < q) L.vE[lane] = cv;
   __syncthreads();
   double om = cv;
@@ -1490,13 +1493,9 @@ __device__ void backward_instance(const BackArgs& A, const InstDesc& idesc, char
     if (lane == k) om = ok;
     else if (lane < k) om -= L.Rm[lane * NS + k] * ok;
   }
-  if (vl) {
-    double acc = L.vA[lane];
-    for (int k = 0; k < q; ++k) acc -= L.Q1[k * NS + lane] * L.vE[k];
-    L.vB[lane] = acc;
-  }
+  if (vl) L.vB[lane] = colsub_q(gh, L.Q1 + lane, NS, L.vE, q);
   __syncthreads();
-  if (vl) L.vC[lane] = unwhiten_at<P>(&K.L1inv[0][0], in.T15, L.vB, lane);   // w on the free vars
+  if (vl) L.vC[lane] = unwhiten_at<P>(L.cL1i, in.T15, L.vB, lane);   // w on the free vars
   // combined row weights  Omega_k = omega_k - gf lam_k
   if (lane < q) L.vD[lane] = om - gf * L.lam[lane];
   __syncthreads();
