@@ -1398,7 +1398,21 @@ __device__ void backward_instance(const BackArgs& A, const InstDesc& idesc, char
   in.sa = double(P) * (P - 1) / (in.T * in.T);
   const int64_t fo = idesc.fo;
   const int nf = in.nf, r = in.r;
-  const int q = (A.status[inst] == kSolved) ? A.st_q[inst] : -1;
+  // every global load of the prologue depends only on the descriptor: all
+  // are issued before the first wait (the stored active set is read on
+  // every lane below its stride, whatever q turns out to be)
+  const int64_t sb = (int64_t)inst * A.st_stride;
+  const int st = A.status[inst];
+  const int qs = A.st_q[inst];
+  int sid = 0, sside = 0;
+  double slam = 0.0;
+  if (lane < A.st_stride) { sid = A.st_id[sb + lane]; sside = A.st_side[sb + lane]; slam = A.st_lam[sb + lane]; }
+  double P0[3];
+  for (int c = 0; c < 3; ++c) P0[c] = A.x0[6 * (int64_t)inst + c];
+  const double psol = lane < NC ? A.P_sol[3 * in.po + lane] : 0.0;
+  const double gpv = (lane < NC && A.grad_P) ? A.grad_P[3 * in.po + lane] : 0.0;
+  const double gf = A.grad_cost ? A.grad_cost[inst] : 0.0;
+  const int q = st == kSolved ? qs : -1;
   if (q < 0) {
     if (lane < 6) A.grad_x0[6 * (int64_t)inst + lane] = 0.0;
     if (lane < 3) A.grad_goal[3 * (int64_t)inst + lane] = 0.0;
@@ -1408,23 +1422,30 @@ __device__ void backward_instance(const BackArgs& A, const InstDesc& idesc, char
   }
   for (int e = lane; e < nf * 3; e += kWave) L.Af[e] = A.A_face[3 * (int64_t)in.f0 + e];
   for (int e = lane; e < kMaxFree * kMaxFree; e += kWave) L.cL1i[e] = (&K.L1inv[0][0])[e];
-  const int64_t sb = (int64_t)inst * A.st_stride;
   if (lane < q) {
-    L.actid[lane] = A.st_id[sb + lane];
-    L.actside[lane] = A.st_side[sb + lane];
-    L.lam[lane] = A.st_lam[sb + lane];
+    L.actid[lane] = sid;
+    L.actside[lane] = sside;
+    L.lam[lane] = slam;
   }
-  __syncthreads();
+  // solution in the shifted frame; upstream gradient on the full control
+  // points -> qbuf (reused)
+  if (lane < NC) {
+    L.ybuf[lane] = psol - sel3(lane - 3 * (lane / 3), P0[0], P0[1], P0[2]);
+    L.qbuf[lane] = gpv;
+  }
   // only the active reachable rows enter the adjoint: stage those (the
-  // others are never read), four loads in flight per lane
+  // others are never read), four loads in flight per lane; the row id of
+  // active row k comes from lane k's register
   for (int base = 0; base < q * NC; base += 4 * kWave) {
     double v[4];
     int dst[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int t = base + u * kWave + lane;
-      const int k = t / NC, e = t - NC * (t / NC);
-      const int id = t < q * NC ? L.actid[k] : -1;
+      const bool live = t < q * NC;
+      const int k = live ? t / NC : 0, e = t - NC * (t / NC);
+      const int idk = __shfl(sid, k, kWave);
+      const int id = live ? idk : -1;
       const bool take = id >= in.RB;
       dst[u] = take ? (id - in.RB) * HDS + e : -1;
       v[u] = take ? A.H[in.hb + (int64_t)(id - in.RB) * NC + e] : 0.0;
@@ -1433,13 +1454,6 @@ __device__ void backward_instance(const BackArgs& A, const InstDesc& idesc, char
     for (int u = 0; u < 4; ++u)
       if (dst[u] >= 0) L.Hd[dst[u]] = v[u];
   }
-  // solution in the shifted frame
-  double P0[3];
-  for (int c = 0; c < 3; ++c) P0[c] = A.x0[6 * (int64_t)inst + c];
-  if (lane < NC) L.ybuf[lane] = A.P_sol[3 * in.po + lane] - sel3(lane - 3 * (lane / 3), P0[0], P0[1], P0[2]);
-  const double gf = A.grad_cost ? A.grad_cost[inst] : 0.0;
-  // upstream gradient on the full control points -> qbuf (reused)
-  if (lane < NC) L.qbuf[lane] = A.grad_P ? A.grad_P[3 * in.po + lane] : 0.0;
   __syncthreads();
   const bool vl = lane < N;
   const int vs = lane / 3, vc = lane - 3 * (lane / 3);
