@@ -45,7 +45,7 @@ LdsDims make_dims(int pmax, int r_cap, int nf_cap, int real_bytes, bool admm) {
   d.o_Af = take(d.nf_cap * 3 * 8);
   d.o_rowval = take(d.m_cap * 8);
   d.o_ybuf = take(2 * d.ncol * 8);
-  d.o_vec = take(7 * d.nmax * 8);   // vA..vE, then the feasible box (lo, hi)
+  d.o_vec = take(5 * d.nmax * 8);   // vA..vE
   d.o_scal = take(16 * 8);
   d.o_acte = take(2 * d.nmax * 8);
   d.o_lam = take(d.nmax * 8);

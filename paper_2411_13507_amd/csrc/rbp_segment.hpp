@@ -81,7 +81,6 @@ __device__ __forceinline__ double sel3(int c, double a, double b, double d) {
 template <typename Real>
 struct Lds {
   double *Hd, *Af, *rowval, *ybuf, *qbuf, *vA, *vB, *vC, *vD, *vE, *scal, *acte, *actc, *lam;
-  double *blo, *bhi;               // box that holds every feasible point (free variables)
   int *actid, *actside;
   Real *HfT, *Aff, *vbuf, *xb1, *xb2, *Kx;
   double *Q1, *Rm;
@@ -102,8 +101,6 @@ __device__ Lds<Real> carve(char* s, const LdsDims& D) {
   L.vC = L.vB + D.nmax;
   L.vD = L.vC + D.nmax;
   L.vE = L.vD + D.nmax;
-  L.blo = L.vE + D.nmax;
-  L.bhi = L.blo + D.nmax;
   L.scal = (double*)(s + D.o_scal);
   L.acte = (double*)(s + D.o_acte);
   L.actc = L.acte + D.nmax;
@@ -735,13 +732,17 @@ __device__ void solve_instance(const SolveArgs& A, const InstDesc& idesc, char* 
     }
     v0 = -in.T15 * 2.0 * in.iT3 * sel3(vc, in.dg[0], in.dg[1], in.dg[2]) * acc;
   }
-  // Box that holds every feasible x, in LDS (blo, bhi): the velocity rows
-  // chained from both pinned ends.
+  // Box that holds every feasible x: the velocity rows chained from both
+  // pinned ends.  bc, bw: offset of its centre from the unconstrained
+  // minimiser x_u = L^-T v0 (the straight line at constant speed: point k at
+  // (k / p) dg) and its half-widths.
+  double bc = 0.0, bw = 0.0;
   if (vl) {
     const int k = vs + 1;
     const double vv = in.vmax * in.T / P, dgc = sel3(vc, in.dg[0], in.dg[1], in.dg[2]);
-    L.blo[lane] = fmax(-k * vv, dgc - (P - k) * vv);
-    L.bhi[lane] = fmin(k * vv, dgc + (P - k) * vv);
+    const double lo = fmax(-k * vv, dgc - (P - k) * vv), hi = fmin(k * vv, dgc + (P - k) * vv);
+    bc = 0.5 * (lo + hi) - (double(k) / P) * dgc;
+    bw = fmax(0.5 * (hi - lo), 0.0);
   }
   // Upper bound of the whitened objective 1/2 |L^T x - v0|^2 over the
   // feasible points; a dual value above it proves that none exists (weak
@@ -757,15 +758,6 @@ __device__ void solve_instance(const SolveArgs& A, const InstDesc& idesc, char* 
   //    (P = 2 Q_ff).
   // The smaller is returned.
   auto box_bound = [&]() -> double {
-    double bc = 0.0, bw = 0.0;
-    if (vl) L.vD[lane] = v0;
-    bsync<kWS>();
-    if (vl) {
-      const double lo = L.blo[lane], hi = L.bhi[lane];
-      bc = 0.5 * (lo + hi) - unwhiten_at<P>(L.cL1i, in.T15, L.vD, lane);
-      bw = fmax(0.5 * (hi - lo), 0.0);
-    }
-    bsync<kWS>();
     if (vl) { L.vD[lane] = bc; L.vE[lane] = bw; }
     bsync<kWS>();
     double pc = 0.0, pw = 0.0;
