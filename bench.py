@@ -299,17 +299,21 @@ def extra_workloads(reps=3, admm_iters=-1, edges=None, main_opts=None):
                           "edges_cut": int((cres.n_collide.cpu().numpy() > 0).sum())}
     cg.close()
     del cres, Pc
-    # the same edges against 200 boxes and 100 convex polytopes (4-16 faces)
+    # the same edges against 200 boxes and 100 convex polytopes (8-16 faces):
+    # codes and per-edge counts (as above), and separately with the step and
+    # the Cut-QP values of the undecided pairs
     cbp = gen.gen_cut(n_poly=100)
     cgp = CutGPU(cbp, cbp.n_edges, device="cuda:0")
     Pcp = torch.as_tensor(cbp.P, device=dev)
     cresp = cgp.alloc()
     t = time_launches(lambda: cgp.run(Pcp, out=cresp, with_step=False, with_dist=False), reps, stream)
+    t_val = time_launches(lambda: cgp.run(Pcp, out=cresp), reps, stream)
     cgp.run(Pcp, out=cresp)
     n_qp = cgp.qp_count()
     stp = cresp.step.cpu().numpy()
     n_pairs = cbp.n_edges * cbp.n_obstacles
-    out["cut50k_o200_p100"] = {"ms": t * 1e3, "pairs_per_s": n_pairs / t, "edges": cbp.n_edges,
+    out["cut50k_o200_p100"] = {"ms": t * 1e3, "pairs_per_s": n_pairs / t, "ms_with_values": t_val * 1e3,
+                               "edges": cbp.n_edges,
                                "boxes": cbp.n_boxes, "polytopes": cbp.n_polytopes,
                                "polytope_pairs_by_step": np.bincount(stp[cbp.n_boxes:].ravel(), minlength=4)[1:].tolist(),
                                "qp_pairs": n_qp, "edges_cut": int((cresp.n_collide.cpu().numpy() > 0).sum())}

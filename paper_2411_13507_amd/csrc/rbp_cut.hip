@@ -472,7 +472,9 @@ __global__ __launch_bounds__(kCutBlock) void cut_qp_kernel(CutArgs A) {
       };
       V3 v;
       d2 = gjk_dist2(support, sub(pts[0], V3{A.pv[3 * v0], A.pv[3 * v0 + 1], A.pv[3 * v0 + 2]}), zero2, v);
-      value = d2 > 0.0 ? cut_qp_value<NP>(pts, A.pob_A, A.pob_b, A.pob_off[jp], A.pob_off[jp + 1]) : 0.0;
+      // the value only when it is asked for (the decision needs d2 alone)
+      value = (A.qp_dist2 && d2 > 0.0) ? cut_qp_value<NP>(pts, A.pob_A, A.pob_b, A.pob_off[jp], A.pob_off[jp + 1])
+                                       : 0.0;
     }
     const int64_t q = (int64_t)o * A.n_edges + e;
     const int code = d2 > 0.0 ? 1 : 0;
