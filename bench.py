@@ -61,16 +61,19 @@ def algorithmic_flops(b, iters):
     return np.where(K > 0, setup, 0) + K * admm_it + S * polish_step + final
 
 
-def algorithmic_bytes(b, q_mean=8, store=True):
+def algorithmic_bytes(b, q_mean=3, store=True):
     """HBM bytes per instance of the forward kernel: problem data read once,
-    outputs (and, when kept for the backward pass, the active set) written
-    once."""
+    outputs written once and, when kept for the backward pass, the final
+    working set (q_mean rows: ids, sides, multipliers) and its factor (q_mean
+    rows of Q1 over the 3(p-1) free variables and the upper triangle of R)."""
     p, nf, r = instance_sizes(b)
     if getattr(b, "reach_idx", None) is None:
         reads = 8 * r * 3 * (p + 1) + 48 * r + 8 * r + 72 + 8 + 44 + 32 * nf
     else:                                    # shared blocks: read once per launch, not per instance
         reads = 72 + 8 + 44 + 32 * nf + 4 + (8 * b.H.size + 56 * b.h0.size) / max(b.n, 1)
-    writes = 24 * (p + 1) + 16 + 4 + 8 + 4 + (16 * q_mean if store else 0)
+    n = 3 * (p - 1)
+    kept = 16 * q_mean + 8 * (q_mean * n + q_mean * (q_mean + 1) / 2)
+    writes = 24 * (p + 1) + 16 + 4 + 8 + 4 + (kept if store else 0)
     return reads + writes
 
 

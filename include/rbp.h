@@ -161,7 +161,9 @@ void rbp_default_opts(rbp_solve_opts* o);
  * Validates the description (index arrays are copied to the host; the call
  * synchronises `stream`), computes per-instance output offsets and a work
  * order, uploads the per-degree constant tables to the current device and
- * allocates the forward state.  On success *out owns the new batch.
+ * allocates the forward state kept for rbp_backward (per instance: the final
+ * working set and its factor, 2 (3(pmax-1))^2 doubles, with pmax the largest
+ * degree).  On success *out owns the new batch.
  * Errors: RBP_E_INVALID (null pointers, vmax/amax <= 0), RBP_E_SHAPE (offsets
  * not monotone, sizes or degrees out of range, H_off inconsistent with the
  * degrees and row counts), RBP_E_ALLOC, RBP_E_DEVICE.
@@ -201,7 +203,8 @@ int rbp_solve_batch(rbp_batch* batch, const double* x0, const double* goal, cons
 /*
  * Vector-Jacobian product of the last forward pass (which must have run with
  * store_for_backward) for the loss  l = sum_i grad_P_i . P*_i + grad_cost_i f*_i,
- * by implicit differentiation of the KKT system on the polished active set.
+ * by implicit differentiation of the KKT system on the polished active set
+ * (with the QR factor of its whitened normals that the forward pass kept).
  *   grad_P    [3 * points_total] or NULL (zero)
  *   grad_cost [N] or NULL (zero)
  *   grad_x0   [N][6], grad_goal [N][3]

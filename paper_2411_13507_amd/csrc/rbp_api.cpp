@@ -37,6 +37,7 @@ struct rbp_batch {
   int32_t* st_id = nullptr;
   int32_t* st_side = nullptr;
   double* st_lam = nullptr;
+  double* st_qr = nullptr;      // factor of the final working set (Q1 rows, R rows)
   double* fw_P = nullptr;
   int32_t* fw_status = nullptr;
   double* fw_x0 = nullptr;
@@ -75,7 +76,7 @@ int dalloc(T** p, size_t n) {
 void free_batch(rbp_batch* b) {
   if (!b) return;
   void* ptrs[] = {b->d_pt_off, b->d_face_off, b->d_order, b->d_desc, b->st_q, b->st_id, b->st_side,
-                  b->st_lam, b->fw_P, b->fw_status, b->fw_x0, b->fw_goal, b->fw_bface};
+                  b->st_lam, b->st_qr, b->fw_P, b->fw_status, b->fw_x0, b->fw_goal, b->fw_bface};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete b;
@@ -244,7 +245,8 @@ int rbp_build_batch(const rbp_problem_desc* d, hipStream_t stream, rbp_batch** o
   if ((rc = dalloc(&b->d_pt_off, n1 + 1)) || (rc = dalloc(&b->d_face_off, n1 + 1)) ||
       (rc = dalloc(&b->d_order, n1)) || (rc = dalloc(&b->d_desc, n1)) || (rc = dalloc(&b->st_q, n1)) ||
       (rc = dalloc(&b->st_id, n1 * b->nmax)) || (rc = dalloc(&b->st_side, n1 * b->nmax)) ||
-      (rc = dalloc(&b->st_lam, n1 * b->nmax)) || (rc = dalloc(&b->fw_P, size_t(3 * b->pt_total))) ||
+      (rc = dalloc(&b->st_lam, n1 * b->nmax)) || (rc = dalloc(&b->st_qr, n1 * 2 * b->nmax * b->nmax)) ||
+      (rc = dalloc(&b->fw_P, size_t(3 * b->pt_total))) ||
       (rc = dalloc(&b->fw_status, n1)) || (rc = dalloc(&b->fw_x0, 6 * n1)) ||
       (rc = dalloc(&b->fw_goal, 3 * n1)) || (rc = dalloc(&b->fw_bface, size_t(std::max<int64_t>(b->F_total, 1))))) {
     free_batch(b);
@@ -299,7 +301,7 @@ int rbp_solve_batch(rbp_batch* b, const double* x0, const double* goal, const do
   a.x0 = x0; a.goal = goal; a.pt_off = b->d_pt_off;
   a.P_out = P_out; a.cost_out = cost_out; a.status_out = status_out; a.kkt_out = kkt_out; a.iters_out = iters_out;
   a.store = o.store_for_backward ? 1 : 0;
-  a.st_q = b->st_q; a.st_id = b->st_id; a.st_side = b->st_side; a.st_lam = b->st_lam;
+  a.st_q = b->st_q; a.st_id = b->st_id; a.st_side = b->st_side; a.st_lam = b->st_lam; a.st_qr = b->st_qr;
   a.st_stride = b->nmax;
   a.admm_iters = o.admm_iters; a.rho = o.rho; a.alpha = o.alpha;
   a.max_steps = o.max_polish_steps; a.feas_tol = o.feas_tol; a.kkt_tol = o.kkt_tol;
@@ -366,7 +368,7 @@ int rbp_backward(rbp_batch* b, const double* grad_P, const double* grad_cost, do
   a.vmax = d.vmax; a.amax = d.amax;
   a.x0 = b->fw_x0; a.goal = b->fw_goal; a.pt_off = b->d_pt_off; a.face_off = b->d_face_off;
   a.P_sol = b->fw_P; a.status = b->fw_status;
-  a.st_q = b->st_q; a.st_id = b->st_id; a.st_side = b->st_side; a.st_lam = b->st_lam;
+  a.st_q = b->st_q; a.st_id = b->st_id; a.st_side = b->st_side; a.st_lam = b->st_lam; a.st_qr = b->st_qr;
   a.grad_P = grad_P; a.grad_cost = grad_cost;
   a.grad_x0 = grad_x0; a.grad_goal = grad_goal; a.grad_b = grad_b; a.flags = flags_out;
   a.order = b->d_order;

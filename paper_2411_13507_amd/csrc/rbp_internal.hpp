@@ -76,6 +76,7 @@ struct SolveArgs {
   int32_t* st_id;            // [N * nmax] row ids
   int32_t* st_side;          // [N * nmax] sides
   double* st_lam;            // [N * st_stride] multipliers
+  double* st_qr;             // [N * 2 st_stride^2] final Q1 rows, then R rows (stride st_stride)
   int st_stride;             // entries per instance in st_id / st_side / st_lam
   // options
   int admm_iters;
@@ -115,6 +116,7 @@ struct BackArgs {
   const int32_t* st_id;
   const int32_t* st_side;
   const double* st_lam;
+  const double* st_qr;
   const double* grad_P;      // nullable
   const double* grad_cost;   // nullable
   double* grad_x0;

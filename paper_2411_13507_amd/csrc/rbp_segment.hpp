@@ -1352,6 +1352,23 @@ __device__ void solve_instance(const SolveArgs& A, const InstDesc& idesc, char* 
     A.st_side[b + lane] = L.actside[lane];
     A.st_lam[b + lane] = L.lam[lane];
   }
+  // the factor of the final working set (rows k < q of Q1 and of R, stride
+  // st_stride) for the backward pass, element-parallel
+  if (A.store) {
+    constexpr int EPL = (N * N + kWave - 1) / kWave;
+    const int S = A.st_stride;
+    double* qr = A.st_qr + (int64_t)inst * 2 * S * S;
+    const int ln = opaque(lane);
+#pragma unroll
+    for (int u = 0; u < EPL; ++u) {
+      const int e = ln + kWave * u;
+      const int k = e / N, i = e - N * (e / N);
+      if (k < q) {
+        qr[k * S + i] = L.Q1[k * NS + i];
+        if (i >= k && i < q) qr[S * S + k * S + i] = L.Rm[k * NS + i];
+      }
+    }
+  }
 }
 
 // ==========================================================================
@@ -1425,17 +1442,18 @@ __device__ void backward_instance(const BackArgs& A, const InstDesc& idesc, char
     L.ybuf[lane] = psol - sel3(lane - 3 * (lane / 3), P0[0], P0[1], P0[2]);
     L.qbuf[lane] = gpv;
   }
-  // only the active reachable rows enter the adjoint: stage those (the
-  // others are never read), four loads in flight per lane; the row id of
+  // the adjoint needs the active reachable rows only on the pinned points
+  // (their coefficients on P_0 and P_p): six entries per row; the row id of
   // active row k comes from lane k's register
-  for (int base = 0; base < q * NC; base += 4 * kWave) {
-    double v[4];
-    int dst[4];
+  for (int base = 0; base < q * 6; base += 2 * kWave) {
+    double v[2];
+    int dst[2];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < 2; ++u) {
       const int t = base + u * kWave + lane;
-      const bool live = t < q * NC;
-      const int k = live ? t / NC : 0, e = t - NC * (t / NC);
+      const bool live = t < q * 6;
+      const int k = live ? t / 6 : 0, j = t - 6 * (t / 6);
+      const int e = j < 3 ? j : 3 * P + j - 3;
       const int idk = __shfl(sid, k, kWave);
       const int id = live ? idk : -1;
       const bool take = id >= in.RB;
@@ -1443,46 +1461,30 @@ __device__ void backward_instance(const BackArgs& A, const InstDesc& idesc, char
       v[u] = take ? A.H[in.hb + (int64_t)(id - in.RB) * NC + e] : 0.0;
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < 2; ++u)
       if (dst[u] >= 0) L.Hd[dst[u]] = v[u];
+  }
+  // the factor of the final working set (rows k < q of Q1 and R)
+  {
+    constexpr int EPL = (N * N + kWave - 1) / kWave;
+    const int S = A.st_stride;
+    const double* qr = A.st_qr + (int64_t)inst * 2 * S * S;
+#pragma unroll
+    for (int u = 0; u < EPL; ++u) {
+      const int e = lane + kWave * u;
+      const int k = e / N, i = e - N * (e / N);
+      if (k < q) {
+        L.Q1[k * NS + i] = qr[k * S + i];
+        if (i >= k && i < q) L.Rm[k * NS + i] = qr[S * S + k * S + i];
+      }
+    }
   }
   __syncthreads();
   const bool vl = lane < N;
   const int vs = lane / 3, vc = lane - 3 * (lane / 3);
-  // QR of the whitened active normals, in stored order, by classical
-  // Gram-Schmidt (second pass when |z|^2 < 1e-2 |a|^2, as in the forward
-  // pass)
-  bool dep = false;
-  for (int k = 0; k < q; ++k) {
-    const int id = __builtin_amdgcn_readfirstlane(L.actid[k]);
-    const int side = L.actside[k];
-    const double a = vl ? double(side) * in.whitened(id, vs, vc, lane, L.cL1i, L.Af, L.Hd) : 0.0;
-    if (vl) L.vA[lane] = a;
-    __syncthreads();
-    double c = lane < k ? dot_row<N>(L.Q1 + lane * NS, L.vA) : 0.0;
-    if (lane < k) L.vE[lane] = c;
-    __syncthreads();
-    double z = vl ? colsub_q(a, L.Q1 + lane, NS, L.vE, k) : 0.0;
-    const double aa = wsum(a * a);
-    double zz = wsum(z * z);
-    if (zz < 1e-2 * aa && k > 0) {
-      if (vl) L.vB[lane] = z;
-      __syncthreads();
-      const double e = lane < k ? dot_row<N>(L.Q1 + lane * NS, L.vB) : 0.0;
-      if (lane < k) L.vE[lane] = e;
-      __syncthreads();
-      z = vl ? colsub_q(z, L.Q1 + lane, NS, L.vE, k) : 0.0;
-      c += e;
-      zz = wsum(z * z);
-    }
-    const double nz = sqrt(zz);
-    dep |= !(nz > 1e-10);
-    const double nzs = nz > 1e-300 ? nz : 1e-300;
-    if (lane < k) L.Rm[lane * NS + k] = c;
-    if (vl) L.Q1[k * NS + lane] = z / nzs;
-    if (lane == 0) L.Rm[k * NS + k] = nzs;
-    __syncthreads();
-  }
+  // the factor of the active normals (whitened, in stored order), kept by
+  // the forward pass; a diagonal entry near 0 flags dependent active rows
+  const bool dep = wany(lane < q && !(L.Rm[lane * NS + lane] > 1e-10));
   // whitened upstream gradient on the free variables
   if (vl) L.vD[lane] = L.qbuf[3 + lane];
   __syncthreads();
