@@ -38,11 +38,9 @@ struct rbp_batch {
   int32_t* st_side = nullptr;
   double* st_lam = nullptr;
   double* st_qr = nullptr;      // factor of the final working set (Q1 rows, R rows)
-  double* fw_P = nullptr;
+  double* fw_P = nullptr;        // forward results kept for backward (written by the solve kernels)
   int32_t* fw_status = nullptr;
-  double* fw_x0 = nullptr;
-  double* fw_goal = nullptr;
-  double* fw_bface = nullptr;   // copy of the b_face actually used
+  double* fw_P0 = nullptr;      // start points
   int64_t F_total = 0;
   bool has_forward = false;
   int32_t fw_schedule = 0;      // schedule of the stored forward pass
@@ -76,7 +74,7 @@ int dalloc(T** p, size_t n) {
 void free_batch(rbp_batch* b) {
   if (!b) return;
   void* ptrs[] = {b->d_pt_off, b->d_face_off, b->d_order, b->d_desc, b->st_q, b->st_id, b->st_side,
-                  b->st_lam, b->st_qr, b->fw_P, b->fw_status, b->fw_x0, b->fw_goal, b->fw_bface};
+                  b->st_lam, b->st_qr, b->fw_P, b->fw_status, b->fw_P0};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete b;
@@ -247,8 +245,7 @@ int rbp_build_batch(const rbp_problem_desc* d, hipStream_t stream, rbp_batch** o
       (rc = dalloc(&b->st_id, n1 * b->nmax)) || (rc = dalloc(&b->st_side, n1 * b->nmax)) ||
       (rc = dalloc(&b->st_lam, n1 * b->nmax)) || (rc = dalloc(&b->st_qr, n1 * 2 * b->nmax * b->nmax)) ||
       (rc = dalloc(&b->fw_P, size_t(3 * b->pt_total))) ||
-      (rc = dalloc(&b->fw_status, n1)) || (rc = dalloc(&b->fw_x0, 6 * n1)) ||
-      (rc = dalloc(&b->fw_goal, 3 * n1)) || (rc = dalloc(&b->fw_bface, size_t(std::max<int64_t>(b->F_total, 1))))) {
+      (rc = dalloc(&b->fw_status, n1)) || (rc = dalloc(&b->fw_P0, 3 * n1))) {
     free_batch(b);
     return rc;
   }
@@ -301,6 +298,7 @@ int rbp_solve_batch(rbp_batch* b, const double* x0, const double* goal, const do
   a.x0 = x0; a.goal = goal; a.pt_off = b->d_pt_off;
   a.P_out = P_out; a.cost_out = cost_out; a.status_out = status_out; a.kkt_out = kkt_out; a.iters_out = iters_out;
   a.store = o.store_for_backward ? 1 : 0;
+  if (a.store) { a.fw_P = b->fw_P; a.fw_status = b->fw_status; a.fw_P0 = b->fw_P0; }
   a.st_q = b->st_q; a.st_id = b->st_id; a.st_side = b->st_side; a.st_lam = b->st_lam; a.st_qr = b->st_qr;
   a.st_stride = b->nmax;
   a.admm_iters = o.admm_iters; a.rho = o.rho; a.alpha = o.alpha;
@@ -338,17 +336,7 @@ int rbp_solve_batch(rbp_batch* b, const double* x0, const double* goal, const do
   if (e != hipSuccess) return RBP_E_DEVICE;
   b->last_stream = stream;
   b->fw_schedule = o.schedule;
-  if (o.store_for_backward) {
-    const size_t n1 = size_t(b->N);
-    if (hipMemcpyAsync(b->fw_P, P_out, size_t(3 * b->pt_total) * sizeof(double), hipMemcpyDeviceToDevice, stream) ||
-        hipMemcpyAsync(b->fw_status, status_out, n1 * sizeof(int32_t), hipMemcpyDeviceToDevice, stream) ||
-        hipMemcpyAsync(b->fw_x0, x0, 6 * n1 * sizeof(double), hipMemcpyDeviceToDevice, stream) ||
-        hipMemcpyAsync(b->fw_goal, goal, 3 * n1 * sizeof(double), hipMemcpyDeviceToDevice, stream) ||
-        (b->F_total > 0 &&
-         hipMemcpyAsync(b->fw_bface, bf, size_t(b->F_total) * sizeof(double), hipMemcpyDeviceToDevice, stream)))
-      return RBP_E_DEVICE;
-    b->has_forward = true;
-  }
+  if (o.store_for_backward) b->has_forward = true;
   return RBP_OK;
 }
 
@@ -361,12 +349,12 @@ int rbp_backward(rbp_batch* b, const double* grad_P, const double* grad_cost, do
   const rbp_problem_desc& d = b->desc;
   rbp::BackArgs a{};
   a.N = b->N;
-  a.degree = d.degree; a.T = d.T; a.poly_off = d.poly_off; a.A_face = d.A_face; a.b_face = b->fw_bface;
+  a.degree = d.degree; a.T = d.T; a.poly_off = d.poly_off; a.A_face = d.A_face;
   a.poly_idx = d.poly_idx; a.reach_off = d.reach_off; a.H_off = d.H_off; a.H = d.H; a.G = d.G;
   a.reach_idx = d.reach_idx;
   a.pin_v0 = d.pin_start_velocity;
   a.vmax = d.vmax; a.amax = d.amax;
-  a.x0 = b->fw_x0; a.goal = b->fw_goal; a.pt_off = b->d_pt_off; a.face_off = b->d_face_off;
+  a.P0 = b->fw_P0; a.pt_off = b->d_pt_off; a.face_off = b->d_face_off;
   a.P_sol = b->fw_P; a.status = b->fw_status;
   a.st_q = b->st_q; a.st_id = b->st_id; a.st_side = b->st_side; a.st_lam = b->st_lam; a.st_qr = b->st_qr;
   a.grad_P = grad_P; a.grad_cost = grad_cost;

@@ -78,6 +78,10 @@ struct SolveArgs {
   double* st_lam;            // [N * st_stride] multipliers
   double* st_qr;             // [N * 2 st_stride^2] final Q1 rows, then R rows (stride st_stride)
   int st_stride;             // entries per instance in st_id / st_side / st_lam
+  // forward results kept for the backward pass (written when store is set)
+  double* fw_P;              // [3 * points_total] control points
+  int32_t* fw_status;        // [N]
+  double* fw_P0;             // [N][3] start points
   // options
   int admm_iters;
   float rho, alpha;
@@ -97,7 +101,6 @@ struct BackArgs {
   const double* T;
   const int32_t* poly_off;
   const double* A_face;
-  const double* b_face;
   const int32_t* poly_idx;
   const int64_t* reach_off;
   const int64_t* H_off;
@@ -106,8 +109,7 @@ struct BackArgs {
   const double* H;
   const double* G;
   double vmax, amax;
-  const double* x0;
-  const double* goal;
+  const double* P0;          // [N][3] start points of the forward pass
   const int64_t* pt_off;
   const int64_t* face_off;   // per-instance offset of its faces in grad_b
   const double* P_sol;       // forward solution (control points)

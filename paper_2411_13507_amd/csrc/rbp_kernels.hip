@@ -16,7 +16,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void so
   if (b >= A.N) return;
   const InstDesc dsc = A.desc[b];
   if (dsc.p == P) solve_instance<P, Real, kAdmm>(A, dsc, smem);
-  else if (threadIdx.x == 0) A.status_out[dsc.inst] = kInvalid;
+  else if (threadIdx.x == 0) { A.status_out[dsc.inst] = kInvalid; if (A.store) A.fw_status[dsc.inst] = kInvalid; }
 }
 
 // One launch per group of the work order (same degree P): block b handles

@@ -23,7 +23,7 @@ __global__ __launch_bounds__(64 * WPG) __attribute__((amdgpu_waves_per_eu(WPE)))
   // (one wavefront: the LDS base stays a constant)
   char* my = WPG == 1 ? smem : smem + size_t(w) * size_t(A.dims.bytes);
   if (dsc.p == P) solve_instance<P, float, kAdmm, (WPG > 1), 10 * WPG + WPE>(A, dsc, my);
-  else if ((threadIdx.x & (kWave - 1)) == 0) A.status_out[dsc.inst] = kInvalid;
+  else if ((threadIdx.x & (kWave - 1)) == 0) { A.status_out[dsc.inst] = kInvalid; if (A.store) A.fw_status[dsc.inst] = kInvalid; }
 }
 
 // The whole batch in one launch: block b solves order[b] whatever its degree
@@ -43,7 +43,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void so
     case 7: solve_instance<7, float, kAdmm, false, 99>(A, dsc, smem); break;
     case 8: solve_instance<8, float, kAdmm, false, 99>(A, dsc, smem); break;
     case 9: solve_instance<9, float, kAdmm, false, 99>(A, dsc, smem); break;
-    default: if (threadIdx.x == 0) A.status_out[dsc.inst] = kInvalid; break;
+    default: if (threadIdx.x == 0) { A.status_out[dsc.inst] = kInvalid; if (A.store) A.fw_status[dsc.inst] = kInvalid; } break;
   }
 }
 

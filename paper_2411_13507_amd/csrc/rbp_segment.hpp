@@ -366,7 +366,7 @@ __device__ void solve_instance(const SolveArgs& A, const InstDesc& idesc, char* 
       A.status_out[inst] = status;
       A.kkt_out[inst] = __builtin_nan("");
       if (A.iters_out) { A.iters_out[2 * inst] = 0; A.iters_out[2 * inst + 1] = 0; }
-      if (A.store) A.st_q[inst] = 0;
+      if (A.store) { A.st_q[inst] = 0; A.fw_status[inst] = status; }
     }
   };
 
@@ -1338,10 +1338,16 @@ __device__ void solve_instance(const SolveArgs& A, const InstDesc& idesc, char* 
   cres = cres / (1.0 + lmax);
   const double kkt = fmax(fmax(fmax(pres, 0.0) / (1.0 + pscale), dres), cres);
   const bool ok = kkt <= A.kkt_tol && isfinite(kkt) && isfinite(cost);
-  if (lane < NC) A.P_out[3 * in.po + lane] = L.ybuf[lane] + sel3(lane - 3 * (lane / 3), in.P0[0], in.P0[1], in.P0[2]);
+  if (lane < NC) {
+    const double pv = L.ybuf[lane] + sel3(lane - 3 * (lane / 3), in.P0[0], in.P0[1], in.P0[2]);
+    A.P_out[3 * in.po + lane] = pv;
+    if (A.store) A.fw_P[3 * in.po + lane] = pv;
+  }
+  if (A.store && lane < 3) A.fw_P0[3 * (int64_t)inst + lane] = sel3(lane, in.P0[0], in.P0[1], in.P0[2]);
   if (lane == 0) {
     A.cost_out[inst] = cost;
     A.status_out[inst] = ok ? kSolved : kNumerical;
+    if (A.store) A.fw_status[inst] = ok ? kSolved : kNumerical;
     A.kkt_out[inst] = kkt;
     if (A.iters_out) { A.iters_out[2 * inst] = K_admm; A.iters_out[2 * inst + 1] = steps; }
     if (A.store) A.st_q[inst] = q;
@@ -1417,7 +1423,7 @@ __device__ void backward_instance(const BackArgs& A, const InstDesc& idesc, char
   double slam = 0.0;
   if (lane < A.st_stride) { sid = A.st_id[sb + lane]; sside = A.st_side[sb + lane]; slam = A.st_lam[sb + lane]; }
   double P0[3];
-  for (int c = 0; c < 3; ++c) P0[c] = A.x0[6 * (int64_t)inst + c];
+  for (int c = 0; c < 3; ++c) P0[c] = A.P0[3 * (int64_t)inst + c];
   const double psol = lane < NC ? A.P_sol[3 * in.po + lane] : 0.0;
   const double gpv = (lane < NC && A.grad_P) ? A.grad_P[3 * in.po + lane] : 0.0;
   const double gf = A.grad_cost ? A.grad_cost[inst] : 0.0;
