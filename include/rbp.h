@@ -140,6 +140,12 @@ typedef struct rbp_solve_opts {
                                  the kernel, LDS sized for the largest
                                  instance).  The backward pass follows the
                                  schedule of the forward pass it differentiates */
+  int32_t debug_fill_lds;     /* 1: every segment workgroup fills its LDS with
+                                 NaN before use (forward pass and the backward
+                                 pass of that forward), so a read of a value
+                                 never written shows up in the outputs; 0 for
+                                 normal runs.  Ignored by rbp_solve_chains    */
+  int32_t reserved;           /* must be 0                                     */
 } rbp_solve_opts;
 
 /* Sizes of the variable-length outputs of a batch (host struct). */

@@ -74,6 +74,7 @@ class SolveOpts(ctypes.Structure):
         ("max_polish_steps", ctypes.c_int32), ("feas_tol", ctypes.c_double),
         ("kkt_tol", ctypes.c_double), ("store_for_backward", ctypes.c_int32), ("plain", ctypes.c_int32),
         ("launch_shape", ctypes.c_int32), ("schedule", ctypes.c_int32),
+        ("debug_fill_lds", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
 

@@ -92,7 +92,41 @@ def build(verbose: bool = False) -> str:
     os.replace(tmp, LIB)
     with open(RESOURCES, "w") as fh:
         fh.write(_resource_table("\n".join(remarks)))
+    build_abi_check([o for o, _ in results if not o.endswith("rbp_api.cpp.o")], verbose)
     return LIB
+
+
+ABI_CHECK = os.path.join(HERE, "abi_asan_check")
+ABI_DRIVER = os.path.join(os.path.dirname(HERE), "tests", "abi_asan_driver.cpp")
+
+
+def build_abi_check(device_objs, verbose: bool = False):
+    """AddressSanitizer build of the library's host code (argument validation
+    and set-up behind the C ABI) with the driver in tests/ that exercises it:
+    both compiled by g++ with -fsanitize=address (host code only), linked with
+    the library's device objects.  A GPU test runs it.  Returns its path, or
+    None where no g++ is found or the driver is absent."""
+    gxx = shutil.which("g++")
+    if not gxx or not os.path.exists(ABI_DRIVER):
+        return None
+    rocm = os.path.dirname(os.path.dirname(os.path.realpath(hipcc())))
+    objdir = os.path.join(HERE, "_build")
+    flags = ["-std=c++17", "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address",
+             "-D__HIP_PLATFORM_AMD__", "-I" + os.path.join(rocm, "include")]
+    api_o, drv_o = os.path.join(objdir, "rbp_api_asan.o"), os.path.join(objdir, "abi_asan_driver.o")
+    steps = [[gxx, *flags, "-c", "-o", api_o, os.path.join(CSRC, "rbp_api.cpp")],
+             [gxx, *flags, "-c", "-o", drv_o, ABI_DRIVER],
+             [gxx, "-fsanitize=address", "-o", ABI_CHECK + ".tmp", drv_o, api_o, *device_objs,
+              "-L" + os.path.join(rocm, "lib"), "-lamdhip64", "-Wl,-rpath," + os.path.join(rocm, "lib")]]
+    for cmd in steps:
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        res = subprocess.run(cmd, capture_output=True, text=True)
+        if res.returncode != 0:
+            sys.stderr.write(res.stdout + res.stderr)
+            raise RuntimeError(f"AddressSanitizer build of the ABI check failed with exit code {res.returncode}")
+    os.replace(ABI_CHECK + ".tmp", ABI_CHECK)
+    return ABI_CHECK
 
 
 if __name__ == "__main__":

@@ -44,6 +44,7 @@ struct rbp_batch {
   int64_t F_total = 0;
   bool has_forward = false;
   int32_t fw_schedule = 0;      // schedule of the stored forward pass
+  int32_t fw_debug_fill = 0;    // its LDS NaN fill (the backward pass follows it)
   hipStream_t last_stream = nullptr;
 };
 
@@ -104,6 +105,8 @@ void rbp_default_opts(rbp_solve_opts* o) {
   o->plain = 0;
   o->launch_shape = 0;
   o->schedule = 0;
+  o->debug_fill_lds = 0;
+  o->reserved = 0;
 }
 
 const char* rbp_status_string(int code) {
@@ -280,7 +283,7 @@ int rbp_solve_batch(rbp_batch* b, const double* x0, const double* goal, const do
   if (opts_in) o = *opts_in;
   if (o.admm_iters < 0 || !(o.rho > 0.0f) || !(o.alpha > 0.0f) || !(o.alpha < 2.0f) || o.max_polish_steps < 0 ||
       !(o.feas_tol > 0.0) || !(o.kkt_tol > 0.0) || o.launch_shape < 0 || o.launch_shape > 2 ||
-      o.schedule < 0 || o.schedule > 1)
+      o.schedule < 0 || o.schedule > 1 || o.debug_fill_lds < 0 || o.debug_fill_lds > 1 || o.reserved != 0)
     return RBP_E_INVALID;
   b->has_forward = false;
   if (b->N == 0) return RBP_OK;
@@ -298,6 +301,7 @@ int rbp_solve_batch(rbp_batch* b, const double* x0, const double* goal, const do
   a.x0 = x0; a.goal = goal; a.pt_off = b->d_pt_off;
   a.P_out = P_out; a.cost_out = cost_out; a.status_out = status_out; a.kkt_out = kkt_out; a.iters_out = iters_out;
   a.store = o.store_for_backward ? 1 : 0;
+  a.debug_fill = o.debug_fill_lds;
   if (a.store) { a.fw_P = b->fw_P; a.fw_status = b->fw_status; a.fw_P0 = b->fw_P0; }
   a.st_q = b->st_q; a.st_id = b->st_id; a.st_side = b->st_side; a.st_lam = b->st_lam; a.st_qr = b->st_qr;
   a.st_stride = b->nmax;
@@ -336,6 +340,7 @@ int rbp_solve_batch(rbp_batch* b, const double* x0, const double* goal, const do
   if (e != hipSuccess) return RBP_E_DEVICE;
   b->last_stream = stream;
   b->fw_schedule = o.schedule;
+  b->fw_debug_fill = o.debug_fill_lds;
   if (o.store_for_backward) b->has_forward = true;
   return RBP_OK;
 }
@@ -362,6 +367,7 @@ int rbp_backward(rbp_batch* b, const double* grad_P, const double* grad_cost, do
   a.order = b->d_order;
   a.desc = b->d_desc;
   a.st_stride = b->nmax;
+  a.debug_fill = b->fw_debug_fill;
   if (b->fw_schedule == 1) {
     a.dims = rbp::make_dims(b->pmax, b->rmax, b->nfmax, 8, false);
     a.inst_base = 0;

@@ -72,6 +72,7 @@ struct SolveArgs {
   int32_t* iters_out;        // nullable, 2 per instance: ADMM iterations, polish steps
   // state kept for the backward pass
   int store;
+  int debug_fill;            // 1: fill the workgroup's LDS with NaN first
   int32_t* st_q;             // active count per instance
   int32_t* st_id;            // [N * nmax] row ids
   int32_t* st_side;          // [N * nmax] sides
@@ -96,6 +97,7 @@ struct BackArgs {
   const int32_t* order;      // work order (nullable): block b handles order[inst_base + b]
   const InstDesc* desc;      // [N] descriptors in work-order position
   int inst_base;
+  int debug_fill;            // 1: fill the workgroup's LDS with NaN first
   int st_stride;
   const int32_t* degree;
   const double* T;

@@ -382,6 +382,13 @@ __device__ void solve_instance(const SolveArgs& A, const InstDesc& idesc, char* 
     for (int e = 0; e < 6; ++e) g_in[sl][e] = on ? A.G[6 * (in.r0 + l) + e] : 0.0;
   }
 
+  // debug option: poison the workgroup's LDS first, so that a read of a
+  // value never written turns the outputs into NaN
+  if (A.debug_fill) {
+    double* w = reinterpret_cast<double*>(smem);
+    for (int e = lane; e < D.bytes / 8; e += kWave) w[e] = __builtin_nan("");
+    bsync<kWS>();
+  }
   // ---- stage instance data in LDS
   bad |= stage_rows<NC, HDS>(L.Hd, A.H + in.hb, r * NC, lane);
   for (int e = lane; e < nf * 3; e += kWave) L.Af[e] = A.A_face[3 * (int64_t)in.f0 + e];
@@ -1434,6 +1441,11 @@ __device__ void backward_instance(const BackArgs& A, const InstDesc& idesc, char
     for (int j = lane; j < nf; j += kWave) A.grad_b[fo + j] = 0.0;
     if (A.flags && lane == 0) A.flags[inst] = 0;
     return;
+  }
+  if (A.debug_fill) {   // debug option: poison the LDS first (see the forward pass)
+    double* w = reinterpret_cast<double*>(smem);
+    for (int e = lane; e < D.bytes / 8; e += kWave) w[e] = __builtin_nan("");
+    __syncthreads();
   }
   for (int e = lane; e < nf * 3; e += kWave) L.Af[e] = A.A_face[3 * (int64_t)in.f0 + e];
   for (int e = lane; e < kMaxFree * kMaxFree; e += kWave) L.cL1i[e] = (&K.L1inv[0][0])[e];
