@@ -24,6 +24,15 @@ struct rbp_batch {
   // launch whose LDS is sized by the group's own largest instance
   struct Group { int32_t p, start, count, rmax, nfmax; };
   std::vector<Group> groups;
+  // groups of a grouped launch run on kLanes streams at once (the caller's
+  // and kLanes - 1 of the batch's own, forked from and joined back into the
+  // caller's with events), assigned longest estimated cost first to the
+  // least loaded stream, so that no group waits for the tail of another
+  static constexpr int kLanes = 4;
+  std::vector<int32_t> group_lane;
+  hipStream_t side[kLanes - 1] = {};
+  hipEvent_t ev_fork = nullptr;
+  hipEvent_t ev_join[kLanes - 1] = {};
   std::vector<int32_t> degree_host;
   int64_t pt_total = 0, face_total = 0;
   int64_t* d_pt_off = nullptr;
@@ -74,11 +83,38 @@ int dalloc(T** p, size_t n) {
 
 void free_batch(rbp_batch* b) {
   if (!b) return;
+  for (int k = 0; k < rbp_batch::kLanes - 1; ++k) {
+    if (b->side[k]) { (void)hipStreamSynchronize(b->side[k]); (void)hipStreamDestroy(b->side[k]); }
+    if (b->ev_join[k]) (void)hipEventDestroy(b->ev_join[k]);
+  }
+  if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
   void* ptrs[] = {b->d_pt_off, b->d_face_off, b->d_order, b->d_desc, b->st_q, b->st_id, b->st_side,
                   b->st_lam, b->st_qr, b->fw_P, b->fw_status, b->fw_P0};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete b;
+}
+
+// Fork the batch's side streams from `stream` (they wait for everything
+// queued on it so far); true when there are side streams and it worked.
+bool fork_lanes(rbp_batch* b, hipStream_t stream) {
+  if (b->groups.size() <= 1 || !b->ev_fork) return false;
+  if (hipEventRecord(b->ev_fork, stream) != hipSuccess) return false;
+  for (int l = 0; l < rbp_batch::kLanes - 1; ++l)
+    if (hipStreamWaitEvent(b->side[l], b->ev_fork, 0) != hipSuccess) return false;
+  return true;
+}
+// Join the side streams back into `stream` (it waits for their work).
+bool join_lanes(rbp_batch* b, hipStream_t stream) {
+  for (int l = 0; l < rbp_batch::kLanes - 1; ++l)
+    if (hipEventRecord(b->ev_join[l], b->side[l]) != hipSuccess ||
+        hipStreamWaitEvent(stream, b->ev_join[l], 0) != hipSuccess)
+      return false;
+  return true;
+}
+hipStream_t lane_stream(const rbp_batch* b, size_t group, hipStream_t stream) {
+  const int l = b->groups.size() > 1 ? b->group_lane[group] : 0;
+  return l == 0 ? stream : b->side[l - 1];
 }
 
 template <typename T>
@@ -206,18 +242,43 @@ int rbp_build_batch(const rbp_problem_desc* d, hipStream_t stream, rbp_batch** o
       const int ra = rclass(a), rc2 = rclass(c);
       return ra != rc2 ? ra < rc2 : cost[a] > cost[c];
     });
+    std::vector<int64_t> gcost;
     for (int k = 0; k < N; ++k) {
       const int i = order[k];
       const int32_t r = int32_t(roff[blk(i) + 1] - roff[blk(i)]);
       const int32_t nf = poff[pidx[i] + 1] - poff[pidx[i]];
-      if (b->groups.empty() || b->groups.back().p != deg[i] || rclass(order[b->groups.back().start]) != rclass(i))
+      if (b->groups.empty() || b->groups.back().p != deg[i] || rclass(order[b->groups.back().start]) != rclass(i)) {
         b->groups.push_back({deg[i], k, 0, 0, 1});
+        gcost.push_back(0);
+      }
       rbp_batch::Group& g = b->groups.back();
       ++g.count;
       g.rmax = std::max(g.rmax, r);
       g.nfmax = std::max(g.nfmax, nf);
+      gcost.back() += cost[i];
     }
     b->degree_host = deg;
+    // streams of the groups: longest processing time first onto the least
+    // loaded stream
+    b->group_lane.assign(b->groups.size(), 0);
+    if (b->groups.size() > 1) {
+      std::vector<int> byc(b->groups.size());
+      std::iota(byc.begin(), byc.end(), 0);
+      std::stable_sort(byc.begin(), byc.end(), [&](int x, int y) { return gcost[size_t(x)] > gcost[size_t(y)]; });
+      int64_t load[rbp_batch::kLanes] = {};
+      for (int gi : byc) {
+        int best = 0;
+        for (int l = 1; l < rbp_batch::kLanes; ++l)
+          if (load[l] < load[best]) best = l;
+        b->group_lane[size_t(gi)] = best;
+        load[best] += gcost[size_t(gi)];
+      }
+      bool ok = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) == hipSuccess;
+      for (int l = 0; ok && l < rbp_batch::kLanes - 1; ++l)
+        ok = hipStreamCreateWithFlags(&b->side[l], hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&b->ev_join[l], hipEventDisableTiming) == hipSuccess;
+      if (!ok) { free_batch(b); return RBP_E_DEVICE; }
+    }
   }
   // descriptors in work-order position and the inverse permutation
   std::vector<rbp::InstDesc> desc(static_cast<size_t>(N));
@@ -325,17 +386,21 @@ int rbp_solve_batch(rbp_batch* b, const double* x0, const double* goal, const do
     e = rbp::launch_solve_all(a, b->N, stream);
   } else {
     a.order = b->d_order;
+    const bool fork = fork_lanes(b, stream);
+    if (b->groups.size() > 1 && !fork) return RBP_E_DEVICE;
     for (size_t k = 0; k < b->groups.size() && e == hipSuccess; ++k) {
       const rbp_batch::Group& g = b->groups[k];
+      const hipStream_t gs = lane_stream(b, k, stream);
       a.dims = rbp::make_dims(g.p, g.rmax, g.nfmax, 4, o.admm_iters > 0);
       a.inst_base = g.start;
       a.N = g.start + g.count;
       // two instances per workgroup only while both slices fit the LDS
       int shape = o.launch_shape;
       if (rbp::kShapeWaves[shape] * size_t(a.dims.bytes) > kLdsBytes) shape = rbp::kShapeW1E2;
-      e = shape == rbp::kShapeW1E2 ? rbp::launch_solve(a, g.count, stream, false, g.p)
-                                   : rbp::launch_solve_shape(a, g.count, stream, g.p, shape);
+      e = shape == rbp::kShapeW1E2 ? rbp::launch_solve(a, g.count, gs, false, g.p)
+                                   : rbp::launch_solve_shape(a, g.count, gs, g.p, shape);
     }
+    if (fork && !join_lanes(b, stream) && e == hipSuccess) e = hipErrorUnknown;
   }
   if (e != hipSuccess) return RBP_E_DEVICE;
   b->last_stream = stream;
@@ -375,13 +440,18 @@ int rbp_backward(rbp_batch* b, const double* grad_P, const double* grad_cost, do
     b->last_stream = stream;
     return RBP_OK;
   }
-  for (size_t k = 0; k < b->groups.size(); ++k) {
+  const bool fork = fork_lanes(b, stream);
+  if (b->groups.size() > 1 && !fork) return RBP_E_DEVICE;
+  hipError_t e = hipSuccess;
+  for (size_t k = 0; k < b->groups.size() && e == hipSuccess; ++k) {
     const rbp_batch::Group& g = b->groups[k];
     a.dims = rbp::make_dims(g.p, g.rmax, g.nfmax, 8, false);
     a.inst_base = g.start;
     a.N = g.start + g.count;
-    if (rbp::launch_backward(a, g.count, stream, g.p) != hipSuccess) return RBP_E_DEVICE;
+    e = rbp::launch_backward(a, g.count, lane_stream(b, k, stream), g.p);
   }
+  if (fork && !join_lanes(b, stream) && e == hipSuccess) e = hipErrorUnknown;
+  if (e != hipSuccess) return RBP_E_DEVICE;
   b->last_stream = stream;
   return RBP_OK;
 }
