@@ -64,15 +64,16 @@ def algorithmic_flops(b, iters):
 def algorithmic_bytes(b, q_mean=3, store=True):
     """HBM bytes per instance of the forward kernel: problem data read once,
     outputs written once and, when kept for the backward pass, the final
-    working set (q_mean rows: ids, sides, multipliers) and its factor (q_mean
-    rows of Q1 over the 3(p-1) free variables and the upper triangle of R)."""
+    working set (q_mean rows: ids, sides, multipliers), its factor (q_mean
+    rows of Q1 over the 3(p-1) free variables and the upper triangle of R) and
+    the six multipliers of the pinned start and goal coordinates."""
     p, nf, r = instance_sizes(b)
     if getattr(b, "reach_idx", None) is None:
         reads = 8 * r * 3 * (p + 1) + 48 * r + 8 * r + 72 + 8 + 44 + 32 * nf
     else:                                    # shared blocks: read once per launch, not per instance
         reads = 72 + 8 + 44 + 32 * nf + 4 + (8 * b.H.size + 56 * b.h0.size) / max(b.n, 1)
     n = 3 * (p - 1)
-    kept = 16 * q_mean + 8 * (q_mean * n + q_mean * (q_mean + 1) / 2)
+    kept = 16 * q_mean + 8 * (q_mean * n + q_mean * (q_mean + 1) / 2) + 48
     writes = 24 * (p + 1) + 16 + 4 + 8 + 4 + (kept if store else 0)
     return reads + writes
 

@@ -168,8 +168,8 @@ void rbp_default_opts(rbp_solve_opts* o);
  * synchronises `stream`), computes per-instance output offsets and a work
  * order, uploads the per-degree constant tables to the current device and
  * allocates the forward state kept for rbp_backward (per instance: the final
- * working set and its factor, 2 (3(pmax-1))^2 doubles, with pmax the largest
- * degree).  On success *out owns the new batch.
+ * working set, its factor in a slot of 2 (3(pmax-1))^2 doubles, with pmax the
+ * largest degree, and the multipliers of the pinned coordinates).  On success *out owns the new batch.
  * Errors: RBP_E_INVALID (null pointers, vmax/amax <= 0), RBP_E_SHAPE (offsets
  * not monotone, sizes or degrees out of range, H_off inconsistent with the
  * degrees and row counts), RBP_E_ALLOC, RBP_E_DEVICE.

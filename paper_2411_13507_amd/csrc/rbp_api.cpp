@@ -47,9 +47,8 @@ struct rbp_batch {
   int32_t* st_side = nullptr;
   double* st_lam = nullptr;
   double* st_qr = nullptr;      // factor of the final working set (Q1 rows, R rows)
-  double* fw_P = nullptr;        // forward results kept for backward (written by the solve kernels)
-  int32_t* fw_status = nullptr;
-  double* fw_P0 = nullptr;      // start points
+  int32_t* fw_status = nullptr;  // forward results kept for backward (written by the solve kernels)
+  double* fw_nu = nullptr;      // multipliers of the pinned start and goal coordinates
   int64_t F_total = 0;
   bool has_forward = false;
   int32_t fw_schedule = 0;      // schedule of the stored forward pass
@@ -89,7 +88,7 @@ void free_batch(rbp_batch* b) {
   }
   if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
   void* ptrs[] = {b->d_pt_off, b->d_face_off, b->d_order, b->d_desc, b->st_q, b->st_id, b->st_side,
-                  b->st_lam, b->st_qr, b->fw_P, b->fw_status, b->fw_P0};
+                  b->st_lam, b->st_qr, b->fw_status, b->fw_nu};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete b;
@@ -308,8 +307,7 @@ int rbp_build_batch(const rbp_problem_desc* d, hipStream_t stream, rbp_batch** o
       (rc = dalloc(&b->d_order, n1)) || (rc = dalloc(&b->d_desc, n1)) || (rc = dalloc(&b->st_q, n1)) ||
       (rc = dalloc(&b->st_id, n1 * b->nmax)) || (rc = dalloc(&b->st_side, n1 * b->nmax)) ||
       (rc = dalloc(&b->st_lam, n1 * b->nmax)) || (rc = dalloc(&b->st_qr, n1 * 2 * b->nmax * b->nmax)) ||
-      (rc = dalloc(&b->fw_P, size_t(3 * b->pt_total))) ||
-      (rc = dalloc(&b->fw_status, n1)) || (rc = dalloc(&b->fw_P0, 3 * n1))) {
+      (rc = dalloc(&b->fw_status, n1)) || (rc = dalloc(&b->fw_nu, 6 * n1))) {
     free_batch(b);
     return rc;
   }
@@ -363,7 +361,7 @@ int rbp_solve_batch(rbp_batch* b, const double* x0, const double* goal, const do
   a.P_out = P_out; a.cost_out = cost_out; a.status_out = status_out; a.kkt_out = kkt_out; a.iters_out = iters_out;
   a.store = o.store_for_backward ? 1 : 0;
   a.debug_fill = o.debug_fill_lds;
-  if (a.store) { a.fw_P = b->fw_P; a.fw_status = b->fw_status; a.fw_P0 = b->fw_P0; }
+  if (a.store) { a.fw_status = b->fw_status; a.fw_nu = b->fw_nu; }
   a.st_q = b->st_q; a.st_id = b->st_id; a.st_side = b->st_side; a.st_lam = b->st_lam; a.st_qr = b->st_qr;
   a.st_stride = b->nmax;
   a.admm_iters = o.admm_iters; a.rho = o.rho; a.alpha = o.alpha;
@@ -424,8 +422,8 @@ int rbp_backward(rbp_batch* b, const double* grad_P, const double* grad_cost, do
   a.reach_idx = d.reach_idx;
   a.pin_v0 = d.pin_start_velocity;
   a.vmax = d.vmax; a.amax = d.amax;
-  a.P0 = b->fw_P0; a.pt_off = b->d_pt_off; a.face_off = b->d_face_off;
-  a.P_sol = b->fw_P; a.status = b->fw_status;
+  a.nu = b->fw_nu; a.pt_off = b->d_pt_off; a.face_off = b->d_face_off;
+  a.status = b->fw_status;
   a.st_q = b->st_q; a.st_id = b->st_id; a.st_side = b->st_side; a.st_lam = b->st_lam; a.st_qr = b->st_qr;
   a.grad_P = grad_P; a.grad_cost = grad_cost;
   a.grad_x0 = grad_x0; a.grad_goal = grad_goal; a.grad_b = grad_b; a.flags = flags_out;

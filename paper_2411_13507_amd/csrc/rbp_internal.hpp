@@ -77,12 +77,11 @@ struct SolveArgs {
   int32_t* st_id;            // [N * nmax] row ids
   int32_t* st_side;          // [N * nmax] sides
   double* st_lam;            // [N * st_stride] multipliers
-  double* st_qr;             // [N * 2 st_stride^2] final Q1 rows, then R rows (stride st_stride)
+  double* st_qr;             // [N * 2 st_stride^2] final factor: q rows of Q1, then the q x q R block
   int st_stride;             // entries per instance in st_id / st_side / st_lam
   // forward results kept for the backward pass (written when store is set)
-  double* fw_P;              // [3 * points_total] control points
   int32_t* fw_status;        // [N]
-  double* fw_P0;             // [N][3] start points
+  double* fw_nu;             // [N][6] multipliers of the pinned start and goal coordinates
   // options
   int admm_iters;
   float rho, alpha;
@@ -111,10 +110,9 @@ struct BackArgs {
   const double* H;
   const double* G;
   double vmax, amax;
-  const double* P0;          // [N][3] start points of the forward pass
   const int64_t* pt_off;
   const int64_t* face_off;   // per-instance offset of its faces in grad_b
-  const double* P_sol;       // forward solution (control points)
+  const double* nu;          // [N][6] multipliers of the pinned coordinates (forward pass)
   const int32_t* status;
   const int32_t* st_q;
   const int32_t* st_id;

@@ -1325,16 +1325,22 @@ __device__ void solve_instance(const SolveArgs& A, const InstDesc& idesc, char* 
   }
   bsync<kWS>();
   // stationarity on the free variables: 2 Q y~ + sum_k lam_k side_k a_k
-  double st = 0.0, sq = 0.0, sac = 0.0;
+  // lanes 0..5 also form the multipliers of the pinned coordinates (start
+  // point, then goal):  nu = -(2 (Q y~)_pinned + sum_k lam_k side_k a_k,pinned)
+  double st = 0.0, sq = 0.0, sac = 0.0, spin = 0.0;
+  const int ppt = lane < 3 ? 0 : P, pc = lane - 3 * (lane / 3);
   if (vl) {
     const int pt = vs + 1;
     sq = 2.0 * L.qbuf[3 + lane];
     for (int k = 0; k < q; ++k) {
       const int idk = __builtin_amdgcn_readfirstlane(L.actid[k]);
-      sac += L.lam[k] * double(L.actside[k]) * in.coef(idk, pt, vc, L.Af, L.Hd);
+      const double ls = L.lam[k] * double(L.actside[k]);
+      sac += ls * in.coef(idk, pt, vc, L.Af, L.Hd);
+      if (A.store) spin += ls * in.coef(idk, ppt, pc, L.Af, L.Hd);
     }
     st = sq + sac;
   }
+  if (A.store && lane < 6) A.fw_nu[6 * (int64_t)inst + lane] = -(2.0 * L.qbuf[3 * ppt + pc] + spin);
   pres = wmax(pres);
   pscale = wmax(pscale);
   const double cost = wsum(yq);
@@ -1348,9 +1354,7 @@ __device__ void solve_instance(const SolveArgs& A, const InstDesc& idesc, char* 
   if (lane < NC) {
     const double pv = L.ybuf[lane] + sel3(lane - 3 * (lane / 3), in.P0[0], in.P0[1], in.P0[2]);
     A.P_out[3 * in.po + lane] = pv;
-    if (A.store) A.fw_P[3 * in.po + lane] = pv;
   }
-  if (A.store && lane < 3) A.fw_P0[3 * (int64_t)inst + lane] = sel3(lane, in.P0[0], in.P0[1], in.P0[2]);
   if (lane == 0) {
     A.cost_out[inst] = cost;
     A.status_out[inst] = ok ? kSolved : kNumerical;
@@ -1365,8 +1369,9 @@ __device__ void solve_instance(const SolveArgs& A, const InstDesc& idesc, char* 
     A.st_side[b + lane] = L.actside[lane];
     A.st_lam[b + lane] = L.lam[lane];
   }
-  // the factor of the final working set (rows k < q of Q1 and of R, stride
-  // st_stride) for the backward pass, element-parallel
+  // the factor of the final working set for the backward pass, packed:
+  // rows k < q of Q1 (N entries each), then the q x q block of R (upper
+  // triangle written), element-parallel
   if (A.store) {
     constexpr int EPL = (N * N + kWave - 1) / kWave;
     const int S = A.st_stride;
@@ -1377,8 +1382,8 @@ __device__ void solve_instance(const SolveArgs& A, const InstDesc& idesc, char* 
       const int e = ln + kWave * u;
       const int k = e / N, i = e - N * (e / N);
       if (k < q) {
-        qr[k * S + i] = L.Q1[k * NS + i];
-        if (i >= k && i < q) qr[S * S + k * S + i] = L.Rm[k * NS + i];
+        qr[k * N + i] = L.Q1[k * NS + i];
+        if (i >= k && i < q) qr[q * N + k * q + i] = L.Rm[k * NS + i];
       }
     }
   }
@@ -1429,9 +1434,7 @@ __device__ void backward_instance(const BackArgs& A, const InstDesc& idesc, char
   int sid = 0, sside = 0;
   double slam = 0.0;
   if (lane < A.st_stride) { sid = A.st_id[sb + lane]; sside = A.st_side[sb + lane]; slam = A.st_lam[sb + lane]; }
-  double P0[3];
-  for (int c = 0; c < 3; ++c) P0[c] = A.P0[3 * (int64_t)inst + c];
-  const double psol = lane < NC ? A.P_sol[3 * in.po + lane] : 0.0;
+  const double nu = lane < 6 ? A.nu[6 * (int64_t)inst + lane] : 0.0;
   const double gpv = (lane < NC && A.grad_P) ? A.grad_P[3 * in.po + lane] : 0.0;
   const double gf = A.grad_cost ? A.grad_cost[inst] : 0.0;
   const int q = st == kSolved ? qs : -1;
@@ -1454,12 +1457,8 @@ __device__ void backward_instance(const BackArgs& A, const InstDesc& idesc, char
     L.actside[lane] = sside;
     L.lam[lane] = slam;
   }
-  // solution in the shifted frame; upstream gradient on the full control
-  // points -> qbuf (reused)
-  if (lane < NC) {
-    L.ybuf[lane] = psol - sel3(lane - 3 * (lane / 3), P0[0], P0[1], P0[2]);
-    L.qbuf[lane] = gpv;
-  }
+  // upstream gradient on the full control points -> qbuf (reused)
+  if (lane < NC) L.qbuf[lane] = gpv;
   // the adjoint needs the active reachable rows only on the pinned points
   // (their coefficients on P_0 and P_p): six entries per row; the row id of
   // active row k comes from lane k's register
@@ -1482,7 +1481,8 @@ __device__ void backward_instance(const BackArgs& A, const InstDesc& idesc, char
     for (int u = 0; u < 2; ++u)
       if (dst[u] >= 0) L.Hd[dst[u]] = v[u];
   }
-  // the factor of the final working set (rows k < q of Q1 and R)
+  // the factor of the final working set (packed by the forward pass: rows
+  // k < q of Q1, then the q x q block of R)
   {
     constexpr int EPL = (N * N + kWave - 1) / kWave;
     const int S = A.st_stride;
@@ -1492,8 +1492,8 @@ __device__ void backward_instance(const BackArgs& A, const InstDesc& idesc, char
       const int e = lane + kWave * u;
       const int k = e / N, i = e - N * (e / N);
       if (k < q) {
-        L.Q1[k * NS + i] = qr[k * S + i];
-        if (i >= k && i < q) L.Rm[k * NS + i] = qr[S * S + k * S + i];
+        L.Q1[k * NS + i] = qr[k * N + i];
+        if (i >= k && i < q) L.Rm[k * NS + i] = qr[q * N + k * q + i];
       }
     }
   }
@@ -1525,24 +1525,21 @@ __device__ void backward_instance(const BackArgs& A, const InstDesc& idesc, char
   // combined row weights  Omega_k = omega_k - gf lam_k
   if (lane < q) L.vD[lane] = om - gf * L.lam[lane];
   __syncthreads();
-  // pinned rows: omega_E and nu, per coordinate (lanes 0..5: e = start c / goal c)
+  // pinned rows: omega_E per coordinate (lanes 0..5: e = start c / goal c);
+  // nu of the same coordinate was formed by the forward pass
   if (lane < 6) {
     const int c = lane % 3;
     const int pt = lane < 3 ? 0 : P;
-    // (2 Q)_{pt, free} w and 2 (Q y~)_pt
-    double qw = 0.0, qyv = 0.0;
+    // (2 Q)_{pt, free} w
+    double qw = 0.0;
     for (int s = 0; s < NFP; ++s) qw += K.Q1[pt][s + 1] * L.vC[3 * s + c];
-    for (int b = 0; b <= P; ++b) qyv += K.Q1[pt][b] * L.ybuf[3 * b + c];
     qw *= 2.0 * in.iT3;
-    qyv *= 2.0 * in.iT3;
-    double cw = 0.0, cl = 0.0;
+    double cw = 0.0;
     for (int k = 0; k < q; ++k) {
       const double a = double(L.actside[k]) * in.coef(L.actid[k], pt, c, L.Af, L.Hd);
       cw += a * (L.vD[k] + gf * L.lam[k]);   // omega_k
-      cl += a * L.lam[k];
     }
     const double omE = L.qbuf[3 * pt + c] - qw - cw;
-    const double nu = -(qyv + cl);
     L.scal[lane] = omE - gf * nu;
   }
   __syncthreads();
