@@ -314,8 +314,10 @@ void rbp_destroy_chains(rbp_chains* chains);
  * polytope it is min over conv(P) of |(A x - b)_+|^2.  Step 3 decides
  * free / may collide by the distance between conv(P) and O (GJK: zero
  * exactly when the Cut-QP optimum is zero; below 1e-24 max(1, |P|)^2 counts
- * as zero) and computes the optimum itself by accelerated projected gradient
- * on the weights, stopped by the Lagrange-dual gap.
+ * as zero).  When qp_dist2 is given, a second pass computes the optimum of
+ * each undecided polytope pair exactly (Newton steps over the pieces of the
+ * objective, each piece minimised by Wolfe's minimum-norm-point method),
+ * certified by the Lagrange-dual gap.
  * ------------------------------------------------------------------------ */
 #define RBP_CUT_MAX_POLY_ROWS 32   /* halfspaces per polytope obstacle            */
 #define RBP_CUT_MAX_POLY_VERTS 64  /* vertices per polytope obstacle              */

@@ -16,8 +16,9 @@
 // Gilbert-Johnson-Keerthi iteration on the Minkowski difference (support
 // points in closed form for a box, over the vertex table for a polytope),
 // in FP64; the distance is zero exactly when the Cut-QP optimum is.  For a
-// polytope the optimum itself is then computed by accelerated projected
-// gradient on the convex weights, stopped by the Lagrange-dual gap.
+// polytope the optimum itself is then computed, when asked for, by a second
+// pass with one wavefront per pair (Newton steps over the pieces of the
+// objective, each piece minimised exactly; see cut_value_kernel).
 //
 // Work split: steps 1-2 run for every pair, one thread per (edge, chunk of
 // obstacles), control points in registers and the current obstacle read
@@ -34,6 +35,7 @@
 #include <cstdint>
 
 #include "rbp_internal.hpp"
+#include "rbp_wave.hpp"
 
 namespace rbp {
 namespace {
@@ -314,101 +316,267 @@ __device__ double gjk_dist2(Support support, V3 w0, double zero2, V3& v) {
   return vv > zero2 ? vv : 0.0;
 }
 
-// Euclidean projection of v onto the simplex {lam >= 0, sum lam = 1}: the
-// threshold is max over k of (sum of the k largest entries - 1) / k, taken
-// here over the sets {i : v_i >= v_j} (no sorting, constant indices).
-template <int NP>
-__device__ __forceinline__ void project_simplex(const double (&v)[NP], double (&out)[NP]) {
-  double theta = -__builtin_huge_val();
-#pragma unroll
-  for (int j = 0; j < NP; ++j) {
-    double sum = 0.0, cnt = 0.0;
-#pragma unroll
-    for (int i = 0; i < NP; ++i) {
-      const bool in = v[i] >= v[j];
-      sum += in ? v[i] : 0.0;
-      cnt += in ? 1.0 : 0.0;
-    }
-    theta = fmax(theta, (sum - 1.0) / cnt);
-  }
-#pragma unroll
-  for (int i = 0; i < NP; ++i) out[i] = fmax(v[i] - theta, 0.0);
+// ---- Cut-QP value of a polytope pair (one wavefront per pair)
+//
+// With the slacks eliminated (for fixed weights the best slack of a row is
+// its violation) the Cut-QP optimum is  f* = min over x in conv(P) of
+// f(x) = |(A x - b)_+|^2, a convex piecewise quadratic; on the rows S
+// violated at x it equals q_S(x) = |A_S x - b_S|^2.  Each outer step
+//   1. evaluates f and the Lagrange-dual bound h(mu) = min_j mu . (A P_j - b)
+//      - |mu|^2 / 4 <= f* at mu = 2 (A x - b)_+, and stops when f - h is at
+//      most 1e-11 f or f no longer decreases;
+//   2. minimises q_S over conv(P) exactly (Wolfe's minimum-norm-point method:
+//      q_S(P^T lam) is the squared norm of sum_j lam_j w_j with
+//      w_j = A_S P_j - b_S, whose Gram matrix follows from the moments
+//      H = A_S^T A_S, g = A_S^T b_S, c = |b_S|^2);
+//   3. moves to the minimiser of f on the segment towards that point (f is a
+//      convex piecewise quadratic along it: safeguarded Newton on its slope,
+//      exact once the segment's violated rows are found).
+// Once S is the violated set of the optimum, step 2 lands on it.  The rows
+// are spread one per lane (at most 32); x and the moments are uniform.
+
+// 3 x 3 symmetric matrix as (xx, xy, xz, yy, yz, zz)
+__device__ __forceinline__ V3 sym_mul(const double (&H)[6], V3 v) {
+  return {H[0] * v.x + H[1] * v.y + H[2] * v.z, H[1] * v.x + H[3] * v.y + H[4] * v.z,
+          H[2] * v.x + H[4] * v.y + H[5] * v.z};
 }
 
-// Cut-QP optimum for the polytope rows r0..r1-1 of (Ar, br): the minimum over
-// the convex weights lam of f = |(A P^T lam - b)_+|^2, by projected gradient
-// with Nesterov momentum (step 1/L with L = 2 |A|_F^2 sum_k |P_k - mean|^2,
-// a bound of the curvature along the simplex; momentum restarted when f
-// rises), stopped when f is within 1e-10 f of the Lagrange-dual bound
-// h(mu) = min_k mu . (A P_k - b) - |mu|^2 / 4 at mu = 2 (A x - b)_+, or after
-// 4,000 steps.  Returns the smallest f seen (an upper bound of the optimum).
+// Wolfe's minimum-norm-point method for min over the simplex of
+// q(x) = x^T H x - 2 g^T x + c, x = sum_j lam_j P_j, H positive
+// semidefinite.  q is the squared norm of sum_j lam_j w_j for points w_j of
+// an affine space of dimension at most 3, so the corral (the affinely
+// independent points carrying the current weights) holds at most four; its
+// points, weights and indices stay in registers.  Returns the minimiser x.
 template <int NP>
-__device__ double cut_qp_value(const V3 (&pts)[NP], const double* __restrict__ Ar, const double* __restrict__ br,
-                               int r0, int r1) {
-  V3 pm{0.0, 0.0, 0.0};
+__device__ V3 min_norm_point(const V3 (&pts)[NP], const double (&H)[6], V3 g, double c) {
+  V3 cp[4];
+  int cid[4];
+  double al[4];
+  // start at the vertex with the smallest q
+  double qbest = __builtin_huge_val(), dmax = 0.0;
+  cp[0] = pts[0];
+  cid[0] = 0;
 #pragma unroll
-  for (int k = 0; k < NP; ++k) pm = axpy(1.0 / NP, pts[k], pm);
-  double sp = 0.0;
+  for (int k = 0; k < NP; ++k) {
+    const double qk = dot(pts[k], sym_mul(H, pts[k])) - 2.0 * dot(g, pts[k]) + c;
+    dmax = fmax(dmax, fabs(qk));
+    if (qk < qbest) { qbest = qk; cp[0] = pts[k]; cid[0] = k; }
+  }
 #pragma unroll
-  for (int k = 0; k < NP; ++k) { const V3 d = sub(pts[k], pm); sp += dot(d, d); }
-  double sa = 0.0;
-  for (int r = r0; r < r1; ++r) sa += Ar[3 * r] * Ar[3 * r] + Ar[3 * r + 1] * Ar[3 * r + 1] + Ar[3 * r + 2] * Ar[3 * r + 2];
-  // f, the row-weighted gradient A^T (A x - b)_+ and (A x - b)_+ . b at x
-  auto eval = [&](V3 x, V3& gr, double& rb) -> double {
-    double f = 0.0;
-    gr = V3{0.0, 0.0, 0.0};
-    rb = 0.0;
-    for (int r = r0; r < r1; ++r) {
-      const V3 a{Ar[3 * r], Ar[3 * r + 1], Ar[3 * r + 2]};
-      const double s = fmax(dot(a, x) - br[r], 0.0);
-      f += s * s;
-      gr = axpy(s, a, gr);
-      rb += s * br[r];
-    }
-    return f;
-  };
-  double lam[NP], y[NP];
+  for (int i = 0; i < 4; ++i) al[i] = i == 0 ? 1.0 : 0.0;
 #pragma unroll
-  for (int k = 0; k < NP; ++k) { lam[k] = 1.0 / NP; y[k] = lam[k]; }
-  auto point = [&](const double (&l)[NP]) -> V3 {
+  for (int i = 1; i < 4; ++i) { cp[i] = cp[0]; cid[i] = -1; }
+  int nc = 1;
+  auto point = [&]() {
     V3 x{0.0, 0.0, 0.0};
 #pragma unroll
-    for (int k = 0; k < NP; ++k) x = axpy(l[k], pts[k], x);
+    for (int i = 0; i < 4; ++i) x = axpy(i < nc ? al[i] : 0.0, cp[i], x);
     return x;
   };
-  V3 gr;
-  double rb;
-  double fbest = eval(point(lam), gr, rb);
-  if (!(sp > 0.0) || !(sa > 0.0) || fbest == 0.0) return fbest;
-  const double inv_l = 1.0 / (2.0 * sa * sp);
-  double t = 1.0, fprev = fbest;
-  for (int it = 0; it < 4000; ++it) {
-    (void)eval(point(y), gr, rb);
-    double z[NP], ln[NP];
+  bool done = false;
+  for (int major = 0; major < 16 && !done; ++major) {
+    const V3 x = point();
+    const V3 v = sub(sym_mul(H, x), g);   // x_w . w_j = v . P_j - g . x + c
+    const double gx = dot(g, x);
+    const double xx = dot(v, x) - gx + c;
+    double best = __builtin_huge_val();
+    int jb = -1;
+    V3 pb = pts[0];
 #pragma unroll
-    for (int k = 0; k < NP; ++k) z[k] = y[k] - 2.0 * dot(gr, pts[k]) * inv_l;
-    project_simplex<NP>(z, ln);
-    const double f = eval(point(ln), gr, rb);
-    double mn = __builtin_huge_val();
-#pragma unroll
-    for (int k = 0; k < NP; ++k) mn = fmin(mn, dot(gr, pts[k]));
-    const double h = 2.0 * mn - 2.0 * rb - f;
-    fbest = fmin(fbest, f);
-    if (f - h <= 1e-10 * f) break;
-    if (f > fprev) {                       // restart the momentum
-      t = 1.0;
-#pragma unroll
-      for (int k = 0; k < NP; ++k) { y[k] = ln[k]; lam[k] = ln[k]; }
-    } else {
-      const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
-      const double beta = (t - 1.0) / tn;
-#pragma unroll
-      for (int k = 0; k < NP; ++k) { y[k] = ln[k] + beta * (ln[k] - lam[k]); lam[k] = ln[k]; }
-      t = tn;
+    for (int k = 0; k < NP; ++k) {
+      const double vk = dot(v, pts[k]);
+      if (vk < best) { best = vk; jb = k; pb = pts[k]; }
     }
-    fprev = f;
+    if (best - gx + c >= xx - 1e-14 * dmax) break;     // x is optimal
+    bool dup = false;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) dup |= (i < nc) & (cid[i] == jb);
+    if (dup || nc == 4) break;                         // no independent point left (rounding)
+#pragma unroll
+    for (int i = 1; i < 4; ++i)
+      if (i == nc) { cp[i] = pb; cid[i] = jb; al[i] = 0.0; }
+    ++nc;
+    // minor cycles: the affine minimiser of the corral, clipped back into
+    // its hull while it has a weight <= 0
+    for (int minor = 0; minor < 4; ++minor) {
+      // y minimises q(cp0 + sum_i y_i (cp_i - cp0)): [D^T H D] y = -D^T (H cp0 - g)
+      const int n = nc - 1;
+      V3 D[3];
+      double M[3][3], y[3];
+      const V3 r0 = sub(sym_mul(H, cp[0]), g);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) D[i] = sub(cp[i + 1], cp[0]);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const V3 HDi = sym_mul(H, D[i]);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) M[i][j] = (i < n && j < n) ? dot(D[j], HDi) : (i == j ? 1.0 : 0.0);
+        y[i] = i < n ? -dot(D[i], r0) : 0.0;
+      }
+      // symmetric elimination (no pivoting: M is positive definite when the
+      // corral is affinely independent); a pivot that vanishes against its
+      // diagonal entry means it is not
+      double d0[3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) d0[i] = M[i][i];
+      bool sing = false;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        sing |= !(M[k][k] > 1e-12 * d0[k]) | !(d0[k] > 0.0);
+        const double piv = M[k][k] > 0.0 ? M[k][k] : 1.0;
+#pragma unroll
+        for (int i = k + 1; i < 3; ++i) {
+          const double l = M[i][k] / piv;
+#pragma unroll
+          for (int j = k + 1; j < 3; ++j) M[i][j] -= l * M[k][j];
+          y[i] -= l * y[k];
+        }
+      }
+#pragma unroll
+      for (int k = 2; k >= 0; --k) {
+        double acc = y[k];
+#pragma unroll
+        for (int j = k + 1; j < 3; ++j) acc -= M[k][j] * y[j];
+        y[k] = acc / (M[k][k] > 0.0 ? M[k][k] : 1.0);
+      }
+      if (sing) {                                       // drop the last point, stop
+        --nc;
+        done = true;
+        break;
+      }
+      double be[4];
+      be[0] = 1.0;
+#pragma unroll
+      for (int i = 1; i < 4; ++i) { be[i] = i < nc ? y[i - 1] : 0.0; be[0] -= be[i]; }
+      bool inside = true;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) inside &= (i >= nc) | (be[i] > 0.0);
+      if (inside) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) al[i] = be[i];
+        break;
+      }
+      // largest step from al towards be that keeps every weight >= 0
+      double th = 1.0;
+      int kd = 0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        if (i < nc && be[i] <= 0.0) {
+          const double ti = al[i] / (al[i] - be[i]);
+          if (ti < th) { th = ti; kd = i; }
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) al[i] = (1.0 - th) * al[i] + th * be[i];
+      // remove corral point kd (its weight is now 0)
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+        if (i >= kd) { cp[i] = cp[i + 1]; cid[i] = cid[i + 1]; al[i] = al[i + 1]; }
+      --nc;
+      double sa = 0.0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) { al[i] = i < nc ? fmax(al[i], 0.0) : 0.0; sa += al[i]; }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) al[i] /= sa;
+      if (nc == 1) break;
+    }
   }
-  return fbest;
+  return point();
+}
+
+template <int NP>
+__global__ __launch_bounds__(kCutBlock) void cut_value_kernel(CutArgs A) {
+  const unsigned long long cnt = *A.counter;
+  const int64_t n = (int64_t)(cnt < (unsigned long long)A.list_cap ? cnt : (unsigned long long)A.list_cap);
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wv = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (kCutBlock / kWave) + threadIdx.x / kWave));
+  const int64_t nw = (int64_t)gridDim.x * (kCutBlock / kWave);
+  for (int64_t t = wv; t < n; t += nw) {
+    const int64_t ent = A.list[t];
+    const int o = (int)(ent >> 32), e = (int)(ent & 0xffffffffll);
+    if (o < A.n_box) continue;
+    const int64_t qi = (int64_t)o * A.n_edges + e;
+    if (!(A.qp_dist2[qi] > 0.0)) continue;   // conv(P) meets O: the optimum is 0
+    const int jp = o - A.n_box;
+    const int r0 = A.pob_off[jp], m = A.pob_off[jp + 1] - r0;
+    // row of this lane (idle lanes: 0 . x - 1 < 0, never violated)
+    const bool rl = lane < m;
+    const V3 a = rl ? V3{A.pob_A[3 * (r0 + lane)], A.pob_A[3 * (r0 + lane) + 1], A.pob_A[3 * (r0 + lane) + 2]}
+                    : V3{0.0, 0.0, 0.0};
+    const double bk = rl ? A.pob_b[r0 + lane] : 1.0;
+    V3 pts[NP];
+    V3 x{0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      const int64_t b = (int64_t)e * (3 * NP) + 3 * k;
+      pts[k] = {A.P[b], A.P[b + 1], A.P[b + 2]};
+      x = axpy(1.0 / NP, pts[k], x);
+    }
+    double fbest = __builtin_huge_val(), fprev = __builtin_huge_val();
+    for (int it = 0; it < 32; ++it) {
+      const double r = dot(a, x) - bk;
+      const double rp = fmax(r, 0.0);
+      double s4[4] = {rp * rp, rp * a.x, rp * a.y, rp * a.z};
+      wave::sum4(s4);
+      const double f = s4[0];
+      const double beta = wave::sum(rp * bk);
+      fbest = fmin(fbest, f);
+      if (!(f > 0.0) || !(f < fprev)) break;
+      fprev = f;
+      const V3 u{s4[1], s4[2], s4[3]};
+      double mn = __builtin_huge_val();
+#pragma unroll
+      for (int k = 0; k < NP; ++k) mn = fmin(mn, dot(u, pts[k]));
+      const double h = 2.0 * (mn - beta) - f;
+      if (f - h <= 1e-11 * f) break;
+      // moments of the violated rows
+      const double sw = r > 0.0 ? 1.0 : 0.0;
+      double m1[4] = {sw * a.x * a.x, sw * a.x * a.y, sw * a.x * a.z, sw * a.y * a.y};
+      double m2[4] = {sw * a.y * a.z, sw * a.z * a.z, sw * bk * a.x, sw * bk * a.y};
+      double m3[4] = {sw * bk * a.z, sw * bk * bk, 0.0, 0.0};
+      wave::sum4(m1);
+      wave::sum4(m2);
+      wave::sum4(m3);
+      const double H[6] = {m1[0], m1[1], m1[2], m1[3], m2[0], m2[1]};
+      const V3 xs = min_norm_point<NP>(pts, H, V3{m2[2], m2[3], m3[0]}, m3[1]);
+      // half the slope of f at x along xs - x is u . (xs - x): stop unless it
+      // descends
+      if (!(dot(u, sub(xs, x)) < 0.0)) break;
+      // line search on f along x + t (xs - x), t in [0, 1]: half its slope
+      // is sum_k (r_k + t d_k)_+ d_k, nondecreasing in t
+      const double dk = dot(a, sub(xs, x));
+      auto slope = [&](double t, double& s2) {
+        const double rt = r + t * dk;
+        double v2[2] = {rt > 0.0 ? rt * dk : 0.0, rt > 0.0 ? dk * dk : 0.0};
+        // two sums, interleaved through the same stages
+        double v4[4] = {v2[0], v2[1], 0.0, 0.0};
+        wave::sum4(v4);
+        s2 = v4[1];
+        return v4[0];
+      };
+      double s2;
+      double t = 1.0;
+      const double g1 = slope(1.0, s2);
+      if (g1 > 0.0) {
+        double lo = 0.0, hi = 1.0;
+        // the piece at t = 1 is linear: its root is the Newton point
+        double tn = s2 > 0.0 ? 1.0 - g1 / s2 : 0.5;
+        for (int ls = 0; ls < 40; ++ls) {
+          t = (tn > lo && tn < hi) ? tn : 0.5 * (lo + hi);
+          double q2;
+          const double gt = slope(t, q2);
+          if (gt == 0.0) break;
+          if (gt > 0.0) hi = t; else lo = t;
+          if (!(hi - lo > 1e-15)) break;
+          tn = q2 > 0.0 ? t - gt / q2 : 0.5 * (lo + hi);
+          if (tn == t) break;
+        }
+      }
+      if (!(t > 0.0)) break;
+      x = axpy(t, sub(xs, x), x);
+    }
+    if (lane == 0) A.qp_dist2[qi] = fbest;
+  }
 }
 
 // Step 3 for every listed pair: squared distance between conv(P) and the box.
@@ -472,9 +640,9 @@ __global__ __launch_bounds__(kCutBlock) void cut_qp_kernel(CutArgs A) {
       };
       V3 v;
       d2 = gjk_dist2(support, sub(pts[0], V3{A.pv[3 * v0], A.pv[3 * v0 + 1], A.pv[3 * v0 + 2]}), zero2, v);
-      // the value only when it is asked for (the decision needs d2 alone)
-      value = (A.qp_dist2 && d2 > 0.0) ? cut_qp_value<NP>(pts, A.pob_A, A.pob_b, A.pob_off[jp], A.pob_off[jp + 1])
-                                       : 0.0;
+      // 0 when conv(P) meets O; otherwise the value pass overwrites it with
+      // the Cut-QP optimum
+      value = d2;
     }
     const int64_t q = (int64_t)o * A.n_edges + e;
     const int code = d2 > 0.0 ? 1 : 0;
@@ -495,6 +663,8 @@ hipError_t launch_cut_p(const CutArgs& a, hipStream_t s, int qp_blocks) {
     hipLaunchKernelGGL((cut_prefilter_kernel<P, true>), dim3(gx, (n_poly + kObsChunk - 1) / kObsChunk),
                        dim3(kCutBlock), 0, s, a);
   hipLaunchKernelGGL((cut_qp_kernel<P>), dim3(qp_blocks), dim3(kCutBlock), 0, s, a);
+  if (a.qp_dist2 && n_poly > 0)
+    hipLaunchKernelGGL((cut_value_kernel<P + 1>), dim3(qp_blocks), dim3(kCutBlock), 0, s, a);
   return hipGetLastError();
 }
 

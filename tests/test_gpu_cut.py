@@ -253,6 +253,19 @@ def test_polytopes_full_size_sampled(gpu_available):
     assert np.array_equal(out["n_collide"], (out["code"] == 0).sum(axis=0))
 
 
+@pytest.mark.parametrize("p", [1, 2, 5, 9])
+def test_polytope_values_every_degree(gpu_available, p):
+    """The Cut-QP value pass (one wavefront per pair) for every curve degree it
+    is instantiated for: every polytope pair of a small graph that reaches
+    step 3 lies in the oracle's primal/dual enclosure."""
+    b = gen.gen_cut(n_nodes=400, k_nn=8, n_obst=4, n_poly=24, p=p)
+    print(f"case: degree {p}, {b.n_edges} edges x {b.n_boxes} boxes + {b.n_polytopes} polytopes", flush=True)
+    out = run_gpu(b)
+    qo, qe = np.nonzero(out["step"][b.n_boxes:] == 3)
+    kinds = check_poly(b, out, [(b.n_boxes + int(o), int(e)) for o, e in zip(qo, qe)], f"poly-qp p={p}")
+    assert kinds.get("qp", 0) > 0
+
+
 def test_box_given_as_polytope_matches_the_box(gpu_available):
     """A box written as six unit rows gives the box's codes wherever the
     plane test is not within rounding, and the same Cut-QP optimum (the
