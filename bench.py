@@ -343,6 +343,18 @@ def extra_workloads(reps=3, admm_iters=-1, edges=None, main_opts=None):
     out["adjacent_hyperplanes_5000x200"] = {"ms": t_h * 1e3, "nodes": int(gb_.V.shape[0]),
                                             "obstacles": int(gb_.box_lo.shape[0])}
     gg.close()
+    chains_workload(out, reps, stream)
+    mpc_workload(out, reps, stream)
+    return out
+
+
+def chains_workload(out, reps, stream):
+    """8,192 paths of 4-12 joined degree-7 segments, forward (polish only)."""
+    import torch
+    from paper_2411_13507_amd import _lib
+    from paper_2411_13507_amd.api import ChainBatchGPU
+    from workloads import gen
+    dev = torch.device("cuda", 0)
     c = gen.generate_chains(8192)
     cb = ChainBatchGPU(c, device="cuda:0")
     x0, goal = torch.as_tensor(c.x0, device=dev), torch.as_tensor(c.goal, device=dev)
@@ -363,6 +375,13 @@ def extra_workloads(reps=3, admm_iters=-1, edges=None, main_opts=None):
                           "status_counts": np.bincount(st, minlength=6).tolist(), "admm_iters": 0,
                           "polish_steps_mean": float(r.iters.cpu().numpy()[:, 1].mean())}
     cb.close()
+
+
+def mpc_workload(out, reps, stream):
+    """4,096 MPC refinements of 50 steps (eq. MPC)."""
+    import torch
+    from workloads import gen
+    dev = torch.device("cuda", 0)
     # MPC refinement (eq. MPC): 4,096 independent 50-step horizons, one
     # separating plane per step, 16 reachable rows per step
     from paper_2411_13507_amd.api import MpcGPU
@@ -380,7 +399,6 @@ def extra_workloads(reps=3, admm_iters=-1, edges=None, main_opts=None):
                           "ipm_iters_mean": float(its.mean()), "ipm_iters_max": int(its.max()),
                           "alu_tflops": flops / t / 1e12, "alu_frac": flops / t / 1e12 / PEAK_VALU_TFLOPS}
     mg.close()
-    return out
 
 
 def main():
@@ -394,6 +412,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--workload", choices=["chains", "mpc"], default=None,
+                    help="only time this one workload of the extras and print its record (for profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device-to-device copy (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -405,6 +425,15 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": x.numel() * 8, "copy_bytes_written": y.numel() * 8, "launches": 3}))
+        return
+    if args.workload is not None and args.gpus == 1:
+        import torch
+        dev = torch.device("cuda", 0)
+        torch.cuda.set_device(dev)
+        rec = {}
+        fn = {"chains": chains_workload, "mpc": mpc_workload}[args.workload]
+        fn(rec, max(args.steps, 1), torch.cuda.current_stream(dev))
+        print(json.dumps(rec))
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); instances are independent, "
