@@ -279,9 +279,10 @@ int rbp_chains_get_sizes(const rbp_chains* chains, rbp_batch_sizes* out);
  * a Farkas vector, or a dual value of the polish's multipliers above every
  * objective value in the box that the chained velocity rows give (weak
  * duality).  Two launches on the stream: every path first runs with a small
- * working set; the few whose working set outgrows it are solved again by a
- * second launch at the full size, which also rewrites their outputs (until
- * it has run, status_out may hold an internal value).
+ * working set; the few whose working set outgrows it are finished by a
+ * second launch at the full size, which continues from the working set the
+ * first held and rewrites their outputs (until it has run, status_out may
+ * hold an internal value).
  *   x0 [N][6], goal [N][3]; opts as for rbp_solve_batch (plain and
  *   store_for_backward are ignored);
  *   P_out [3 points_total]: the control points of every segment (NaN unless

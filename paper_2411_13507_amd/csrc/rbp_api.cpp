@@ -460,6 +460,8 @@ struct rbp_chains {
   int32_t N = 0, s_max = 1, nf_max = 1, r_max = 0;
   int64_t pt_total = 0;
   int32_t* d_order = nullptr;
+  int32_t* ws_keys = nullptr;   // working set of each path at its first-pass overflow
+  int32_t* ws_meta = nullptr;   // its row count and the polish steps taken
   // work order, most segments first (longest paths start first, so the
   // launch's tail is short); the launch groups hold LDS sizes (one group:
   // separate launches per segment count were slower, each waiting out its
@@ -486,6 +488,12 @@ int ensure_chain_constants(int device) {
 // working-set rows of the first path pass: at 12 segments of degree 7 its LDS
 // (about 50 KB) leaves three paths resident per CU, against one at the full cap
 constexpr int kChainFirstPassRows = 32;
+
+void free_chains(rbp_chains* c) {
+  for (int32_t* p : {c->d_order, c->ws_keys, c->ws_meta})
+    if (p) (void)hipFree(p);
+  delete c;
+}
 
 int chain_q_cap(int p, int s_max) {
   const int n = 3 * ((p - 1) + (s_max - 1) * (p - 2));
@@ -565,11 +573,15 @@ int rbp_build_chains(const rbp_chain_desc* d, hipStream_t stream, rbp_chains** o
     }
   }
   c->pt_total = int64_t(p + 1) * nseg;
-  if ((rc = dalloc(&c->d_order, size_t(std::max(N, 1))))) { delete c; return rc; }
+  const size_t n1 = size_t(std::max(N, 1));
+  if ((rc = dalloc(&c->d_order, n1)) || (rc = dalloc(&c->ws_keys, n1 * kChainFirstPassRows)) ||
+      (rc = dalloc(&c->ws_meta, 2 * n1))) {
+    free_chains(c);
+    return rc;
+  }
   if (N > 0 && (hipMemcpyAsync(c->d_order, order.data(), size_t(N) * 4, hipMemcpyHostToDevice, stream) ||
                 hipStreamSynchronize(stream))) {
-    (void)hipFree(c->d_order);
-    delete c;
+    free_chains(c);
     return RBP_E_DEVICE;
   }
   c->last_stream = stream;
@@ -604,13 +616,15 @@ int rbp_solve_chains(rbp_chains* c, const double* x0, const double* goal, const 
   a.seg_off = d.seg_off; a.poly_off = d.poly_off; a.A_face = d.A_face; a.b_face = d.b_face;
   a.poly_idx = d.poly_idx; a.reach_off = d.reach_off; a.H_off = d.H_off; a.H = d.H; a.h0 = d.h0; a.G = d.G;
   a.x0 = x0; a.goal = goal; a.order = c->d_order;
+  a.ws_keys = c->ws_keys; a.ws_meta = c->ws_meta; a.ws_stride = kChainFirstPassRows;
   a.P_out = P_out; a.cost_out = cost_out; a.status_out = status_out; a.kkt_out = kkt_out; a.iters_out = iters_out;
   a.admm_iters = o.admm_iters; a.rho = o.rho; a.alpha = o.alpha; a.max_steps = o.max_polish_steps;
   a.feas_tol = o.feas_tol; a.kkt_tol = o.kkt_tol;
   for (const rbp_chains::Group& g : c->groups) {
     // a first pass with a small working-set cap keeps LDS per path low (more
     // paths resident per CU); the few paths whose working set outgrows it are
-    // solved again by a full-cap pass, which skips every other path
+    // finished by a full-cap pass, which continues from the working set the
+    // first pass held and skips every other path
     const int q_full = chain_q_cap(d.degree, g.s_max);
     const int q_first = std::min(q_full, kChainFirstPassRows);
     const bool admm = o.admm_iters > 0;
@@ -634,8 +648,7 @@ void rbp_destroy_chains(rbp_chains* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   if (c->last_stream) (void)hipStreamSynchronize(c->last_stream);
-  if (c->d_order) (void)hipFree(c->d_order);
-  delete c;
+  free_chains(c);
 }
 
 void rbp_destroy_batch(rbp_batch* b) {

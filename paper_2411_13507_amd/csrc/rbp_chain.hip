@@ -465,7 +465,7 @@ __device__ __forceinline__ void chain_instance(const ChainArgs& A, const int ch,
   // ======================================================================
   const int K_admm = A.admm_iters;
   int ncand = 0;
-  if (K_admm > 0) {
+  if (K_admm > 0 && !A.retry_only) {
     const float rho = A.rho, alpha = A.alpha, irho = 1.0f / A.rho;
     // K = G (x) I3 + rho * sum_s embed(M_s^T C_s M_s); band storage Kb[i][d] = K[i][i-d]
     for (int e = lane; e < n * (BW + 1); e += kWave) {
@@ -1049,7 +1049,16 @@ __device__ __forceinline__ void chain_instance(const ChainArgs& A, const int ch,
   };
   auto nplus_dot = [&](int slot, const double* v) -> double { return ndot(slot, v); };
 
-  // ---- warm start from the ADMM proposals
+  // the full pass continues from the working set the reduced-cap pass held
+  // when it overflowed (the same rows in the same order: appending them and
+  // solving for their multipliers restores its iterate)
+  if (A.retry_only) {
+    ncand = A.ws_meta[2 * ch];
+    steps = A.ws_meta[2 * ch + 1];
+    for (int t = lane; t < ncand; t += kWave) L.cand[t] = A.ws_keys[(int64_t)ch * A.ws_stride + t];
+    __syncthreads();
+  }
+  // ---- warm start from the ADMM proposals (or the stored working set)
   for (int t = 0; t < ncand && q < QC - 1; ++t) {
     const int key = L.cand[t];
     const int id = key >> 1, side = (key & 1) ? 1 : -1;
@@ -1158,7 +1167,13 @@ __device__ __forceinline__ void chain_instance(const ChainArgs& A, const int ch,
     }
     wave::argmax(best, key);
     if (!(best > 0.0)) { status = kSolved; break; }
-    if (q >= QC - 1 && QC < A.q_full) { status = kRetry; break; }
+    if (q >= QC - 1 && QC < A.q_full) {
+      for (int k = lane; k < q; k += kWave)
+        A.ws_keys[(int64_t)ch * A.ws_stride + k] = 2 * L.actid[k] + (L.actside[k] > 0 ? 1 : 0);
+      if (lane == 0) { A.ws_meta[2 * ch] = q; A.ws_meta[2 * ch + 1] = steps; }
+      status = kRetry;
+      break;
+    }
     if (steps >= max_steps || key < 0 || (key >> 1) >= m || q >= QC - 1) { status = kPolishFailed; break; }
     const int id = key >> 1, side = (key & 1) ? 1 : -1;
     const int sp = seg_of(id);

@@ -168,6 +168,11 @@ struct ChainArgs {
   ChainDims dims;
   int q_full;       // working-set cap of the full pass; a smaller dims.q_cap marks overflows for retry
   int retry_only;   // solve only the paths a reduced-cap pass marked for retry
+  // working set of a path at its overflow (written by the reduced-cap pass,
+  // read by the full pass, which continues from it): row keys 2 id + (side > 0)
+  int32_t* ws_keys;  // [N][ws_stride]
+  int32_t* ws_meta;  // [N][2]: rows, polish steps taken
+  int ws_stride;
 };
 
 // ---- cutting graph edges against box obstacles (rbp_cut.hip)
