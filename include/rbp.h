@@ -278,11 +278,14 @@ int rbp_chains_get_sizes(const rbp_chains* chains, rbp_batch_sizes* out);
  * solves.  Infeasibility is reported only with a certificate checked in FP64:
  * a Farkas vector, or a dual value of the polish's multipliers above every
  * objective value in the box that the chained velocity rows give (weak
- * duality).  Two launches on the stream: every path first runs with a small
- * working set; the few whose working set outgrows it are finished by a
- * second launch at the full size, which continues from the working set the
- * first held and rewrites their outputs (until it has run, status_out may
- * hold an internal value).
+ * duality).  Paths are launched in groups by segment count; each group runs
+ * twice: every path first with a small working set, then the few whose
+ * working set outgrew it at the full size, continuing from the working set
+ * the first launch held (their outputs are rewritten; until then status_out
+ * may hold an internal value).  The groups run on the caller's stream and
+ * three streams of the batch, forked from `stream` and joined back into it,
+ * so all work is ordered after what `stream` holds and before what it gets
+ * next (graph capture on `stream` takes all of it).
  *   x0 [N][6], goal [N][3]; opts as for rbp_solve_batch (plain and
  *   store_for_backward are ignored);
  *   P_out [3 points_total]: the control points of every segment (NaN unless

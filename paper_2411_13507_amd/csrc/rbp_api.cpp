@@ -241,6 +241,8 @@ int rbp_build_batch(const rbp_problem_desc* d, hipStream_t stream, rbp_batch** o
       const int ra = rclass(a), rc2 = rclass(c);
       return ra != rc2 ? ra < rc2 : cost[a] > cost[c];
     });
+    // estimated work of a path: its polish steps and the cost of one both
+    // grow with its segment count
     std::vector<int64_t> gcost;
     for (int k = 0; k < N; ++k) {
       const int i = order[k];
@@ -462,12 +464,18 @@ struct rbp_chains {
   int32_t* d_order = nullptr;
   int32_t* ws_keys = nullptr;   // working set of each path at its first-pass overflow
   int32_t* ws_meta = nullptr;   // its row count and the polish steps taken
-  // work order, most segments first (longest paths start first, so the
-  // launch's tail is short); the launch groups hold LDS sizes (one group:
-  // separate launches per segment count were slower, each waiting out its
-  // own tail)
+  // work order, most segments first (longest paths start first, so a
+  // launch's tail is short); launch groups by ranges of segment counts, each
+  // with its own LDS size, run on kLanes streams at once (the caller's and
+  // kLanes - 1 of the batch's own, forked and joined with events), assigned
+  // longest estimated work first to the least loaded stream
   struct Group { int32_t start, count, s_max, nf_max, r_max; };
   std::vector<Group> groups;
+  static constexpr int kLanes = 4;
+  std::vector<int32_t> group_lane;
+  hipStream_t side[kLanes - 1] = {};
+  hipEvent_t ev_fork = nullptr;
+  hipEvent_t ev_join[kLanes - 1] = {};
   hipStream_t last_stream = nullptr;
 };
 
@@ -490,9 +498,27 @@ int ensure_chain_constants(int device) {
 constexpr int kChainFirstPassRows = 32;
 
 void free_chains(rbp_chains* c) {
+  for (int k = 0; k < rbp_chains::kLanes - 1; ++k) {
+    if (c->side[k]) { (void)hipStreamSynchronize(c->side[k]); (void)hipStreamDestroy(c->side[k]); }
+    if (c->ev_join[k]) (void)hipEventDestroy(c->ev_join[k]);
+  }
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
   for (int32_t* p : {c->d_order, c->ws_keys, c->ws_meta})
     if (p) (void)hipFree(p);
   delete c;
+}
+
+// launch groups of a path batch by segment count (S >= 12, 10-11, 8-9, 6-7,
+// up to 5): each group's LDS is sized for its longest path, so short paths
+// are resident four to a CU.  On the 8,192-path batch (4-12 segments) this
+// took 29.3 ms against 31.5 ms for one group; one group per count (34.9 ms)
+// or per three counts (33.7 ms) was slower: the groups share four streams,
+// and a stream waits out each of its groups' full-cap tails in turn.
+constexpr int kChainGroupMinS[] = {12, 10, 8, 6, 1};
+int chain_bucket(int S) {
+  int k = 0;
+  while (S < kChainGroupMinS[k]) ++k;
+  return k;
 }
 
 int chain_q_cap(int p, int s_max) {
@@ -559,17 +585,43 @@ int rbp_build_chains(const rbp_chain_desc* d, hipStream_t stream, rbp_chains** o
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
       return soff[a + 1] - soff[a] > soff[b + 1] - soff[b];
     });
+    // estimated work of a path: its polish steps and the cost of one both
+    // grow with its segment count
+    std::vector<int64_t> gcost;
     for (int k = 0; k < N; ++k) {
       const int i = order[k];
       const int32_t S = int32_t(soff[i + 1] - soff[i]);
-      if (c->groups.empty()) c->groups.push_back({k, 0, S, 1, 0});
+      if (c->groups.empty() || chain_bucket(c->groups.back().s_max) != chain_bucket(S)) {
+        c->groups.push_back({k, 0, S, 1, 0});
+        gcost.push_back(0);
+      }
       rbp_chains::Group& g = c->groups.back();
       ++g.count;
       g.s_max = std::max(g.s_max, S);
+      gcost.back() += int64_t(S) * S;
       for (int64_t s = soff[i]; s < soff[i + 1]; ++s) {
         g.r_max = std::max<int32_t>(g.r_max, int32_t(roff[s + 1] - roff[s]));
         g.nf_max = std::max<int32_t>(g.nf_max, poff[pidx[s] + 1] - poff[pidx[s]]);
       }
+    }
+    c->group_lane.assign(c->groups.size(), 0);
+    if (c->groups.size() > 1) {
+      std::vector<int> byc(c->groups.size());
+      std::iota(byc.begin(), byc.end(), 0);
+      std::stable_sort(byc.begin(), byc.end(), [&](int x, int y) { return gcost[size_t(x)] > gcost[size_t(y)]; });
+      int64_t load[rbp_chains::kLanes] = {};
+      for (int gi : byc) {
+        int best = 0;
+        for (int l = 1; l < rbp_chains::kLanes; ++l)
+          if (load[l] < load[best]) best = l;
+        c->group_lane[size_t(gi)] = best;
+        load[best] += gcost[size_t(gi)];
+      }
+      bool ok = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) == hipSuccess;
+      for (int l = 0; ok && l < rbp_chains::kLanes - 1; ++l)
+        ok = hipStreamCreateWithFlags(&c->side[l], hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&c->ev_join[l], hipEventDisableTiming) == hipSuccess;
+      if (!ok) { free_chains(c); return RBP_E_DEVICE; }
     }
   }
   c->pt_total = int64_t(p + 1) * nseg;
@@ -620,7 +672,19 @@ int rbp_solve_chains(rbp_chains* c, const double* x0, const double* goal, const 
   a.P_out = P_out; a.cost_out = cost_out; a.status_out = status_out; a.kkt_out = kkt_out; a.iters_out = iters_out;
   a.admm_iters = o.admm_iters; a.rho = o.rho; a.alpha = o.alpha; a.max_steps = o.max_polish_steps;
   a.feas_tol = o.feas_tol; a.kkt_tol = o.kkt_tol;
-  for (const rbp_chains::Group& g : c->groups) {
+  // fork the side streams from the caller's (they wait for its queued work),
+  // launch every group on its stream, join them back into the caller's
+  const bool fork = c->groups.size() > 1 && c->ev_fork;
+  if (fork) {
+    if (hipEventRecord(c->ev_fork, stream) != hipSuccess) return RBP_E_DEVICE;
+    for (int l = 0; l < rbp_chains::kLanes - 1; ++l)
+      if (hipStreamWaitEvent(c->side[l], c->ev_fork, 0) != hipSuccess) return RBP_E_DEVICE;
+  }
+  hipError_t e = hipSuccess;
+  for (size_t k = 0; k < c->groups.size() && e == hipSuccess; ++k) {
+    const rbp_chains::Group& g = c->groups[k];
+    const int l = fork ? c->group_lane[k] : 0;
+    const hipStream_t gs = l == 0 ? stream : c->side[l - 1];
     // a first pass with a small working-set cap keeps LDS per path low (more
     // paths resident per CU); the few paths whose working set outgrows it are
     // finished by a full-cap pass, which continues from the working set the
@@ -633,13 +697,19 @@ int rbp_solve_chains(rbp_chains* c, const double* x0, const double* goal, const 
     a.q_full = q_full;
     a.retry_only = 0;
     a.dims = rbp::make_chain_dims(d.degree, g.s_max, g.nf_max, g.r_max, q_first, admm);
-    if (rbp::launch_chains(a, stream) != hipSuccess) return RBP_E_DEVICE;
-    if (q_first < q_full) {
+    e = rbp::launch_chains(a, gs);
+    if (e == hipSuccess && q_first < q_full) {
       a.retry_only = 1;
       a.dims = rbp::make_chain_dims(d.degree, g.s_max, g.nf_max, g.r_max, q_full, admm);
-      if (rbp::launch_chains(a, stream) != hipSuccess) return RBP_E_DEVICE;
+      e = rbp::launch_chains(a, gs);
     }
   }
+  if (fork)
+    for (int l = 0; l < rbp_chains::kLanes - 1; ++l)
+      if (hipEventRecord(c->ev_join[l], c->side[l]) != hipSuccess ||
+          hipStreamWaitEvent(stream, c->ev_join[l], 0) != hipSuccess)
+        e = e == hipSuccess ? hipErrorUnknown : e;
+  if (e != hipSuccess) return RBP_E_DEVICE;
   c->last_stream = stream;
   return RBP_OK;
 }
