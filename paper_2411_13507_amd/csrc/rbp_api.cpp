@@ -25,9 +25,10 @@ struct rbp_batch {
   struct Group { int32_t p, start, count, rmax, nfmax; };
   std::vector<Group> groups;
   // groups of a grouped launch run on kLanes streams at once (the caller's
-  // and kLanes - 1 of the batch's own, forked from and joined back into the
-  // caller's with events), assigned longest estimated cost first to the
-  // least loaded stream, so that no group waits for the tail of another
+  // and the device's kLanes - 1 side streams, forked from and joined back
+  // into the caller's with events), assigned longest estimated cost first
+  // to the least loaded stream, so that no group waits for the tail of
+  // another
   static constexpr int kLanes = 4;
   std::vector<int32_t> group_lane;
   hipStream_t side[kLanes - 1] = {};
@@ -60,6 +61,30 @@ namespace {
 // LDS of one workgroup on gfx950
 constexpr size_t kLdsBytes = 160 * 1024;
 
+// The side streams of grouped launches: three per device, created once (at
+// the first batch built on it) and shared by every batch and path batch
+// of the process until it ends.  A device has few hardware queues (four by
+// default), and streams beyond that share them round-robin in creation
+// order: streams made per batch, after the caller's own, could land on the
+// caller's queue, and groups meant to run side by side would then run one
+// after another.  Made once and early, the three take consecutive queues.
+std::mutex g_side_mu;
+std::vector<std::pair<int, std::array<hipStream_t, 3>>> g_side;
+bool side_streams(int device, hipStream_t (&out)[3]) {
+  std::lock_guard<std::mutex> lk(g_side_mu);
+  for (const auto& e : g_side)
+    if (e.first == device) { for (int k = 0; k < 3; ++k) out[k] = e.second[k]; return true; }
+  std::array<hipStream_t, 3> st{};
+  for (int k = 0; k < 3; ++k)
+    if (hipStreamCreateWithFlags(&st[size_t(k)], hipStreamNonBlocking) != hipSuccess) {
+      for (int j = 0; j < k; ++j) (void)hipStreamDestroy(st[size_t(j)]);
+      return false;
+    }
+  g_side.emplace_back(device, st);
+  for (int k = 0; k < 3; ++k) out[k] = st[size_t(k)];
+  return true;
+}
+
 std::mutex g_const_mu;
 std::vector<int> g_const_done;
 
@@ -83,7 +108,7 @@ int dalloc(T** p, size_t n) {
 void free_batch(rbp_batch* b) {
   if (!b) return;
   for (int k = 0; k < rbp_batch::kLanes - 1; ++k) {
-    if (b->side[k]) { (void)hipStreamSynchronize(b->side[k]); (void)hipStreamDestroy(b->side[k]); }
+    if (b->side[k]) (void)hipStreamSynchronize(b->side[k]);   // shared: not destroyed
     if (b->ev_join[k]) (void)hipEventDestroy(b->ev_join[k]);
   }
   if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
@@ -177,6 +202,12 @@ int rbp_build_batch(const rbp_problem_desc* d, hipStream_t stream, rbp_batch** o
   }
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return RBP_E_DEVICE;
+  {
+    // the device's side streams are made at the first batch, whatever its
+    // groups, so that they are among the process's first streams
+    hipStream_t early[3];
+    if (!side_streams(dev, early)) return RBP_E_DEVICE;
+  }
   if (int rc = ensure_constants(dev)) return rc;
 
   // reachable blocks: one per instance, or a shared table indexed by reach_idx
@@ -274,10 +305,10 @@ int rbp_build_batch(const rbp_problem_desc* d, hipStream_t stream, rbp_batch** o
         b->group_lane[size_t(gi)] = best;
         load[best] += gcost[size_t(gi)];
       }
-      bool ok = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) == hipSuccess;
+      bool ok = side_streams(dev, b->side) &&
+                hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) == hipSuccess;
       for (int l = 0; ok && l < rbp_batch::kLanes - 1; ++l)
-        ok = hipStreamCreateWithFlags(&b->side[l], hipStreamNonBlocking) == hipSuccess &&
-             hipEventCreateWithFlags(&b->ev_join[l], hipEventDisableTiming) == hipSuccess;
+        ok = hipEventCreateWithFlags(&b->ev_join[l], hipEventDisableTiming) == hipSuccess;
       if (!ok) { free_batch(b); return RBP_E_DEVICE; }
     }
   }
@@ -467,8 +498,8 @@ struct rbp_chains {
   // work order, most segments first (longest paths start first, so a
   // launch's tail is short); launch groups by ranges of segment counts, each
   // with its own LDS size, run on kLanes streams at once (the caller's and
-  // kLanes - 1 of the batch's own, forked and joined with events), assigned
-  // longest estimated work first to the least loaded stream
+  // the device's kLanes - 1 side streams, forked and joined with events),
+  // assigned longest estimated work first to the least loaded stream
   struct Group { int32_t start, count, s_max, nf_max, r_max; };
   std::vector<Group> groups;
   static constexpr int kLanes = 4;
@@ -499,7 +530,7 @@ constexpr int kChainFirstPassRows = 32;
 
 void free_chains(rbp_chains* c) {
   for (int k = 0; k < rbp_chains::kLanes - 1; ++k) {
-    if (c->side[k]) { (void)hipStreamSynchronize(c->side[k]); (void)hipStreamDestroy(c->side[k]); }
+    if (c->side[k]) (void)hipStreamSynchronize(c->side[k]);   // shared: not destroyed
     if (c->ev_join[k]) (void)hipEventDestroy(c->ev_join[k]);
   }
   if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
@@ -539,6 +570,12 @@ int rbp_build_chains(const rbp_chain_desc* d, hipStream_t stream, rbp_chains** o
   if (N > 0 && d->n_poly < 1) return RBP_E_SHAPE;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return RBP_E_DEVICE;
+  {
+    // the device's side streams are made at the first batch, whatever its
+    // groups, so that they are among the process's first streams
+    hipStream_t early[3];
+    if (!side_streams(dev, early)) return RBP_E_DEVICE;
+  }
   if (int rc = ensure_chain_constants(dev)) return rc;
   std::vector<int64_t> soff;
   int rc = RBP_OK;
@@ -617,10 +654,10 @@ int rbp_build_chains(const rbp_chain_desc* d, hipStream_t stream, rbp_chains** o
         c->group_lane[size_t(gi)] = best;
         load[best] += gcost[size_t(gi)];
       }
-      bool ok = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) == hipSuccess;
+      bool ok = side_streams(dev, c->side) &&
+                hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) == hipSuccess;
       for (int l = 0; ok && l < rbp_chains::kLanes - 1; ++l)
-        ok = hipStreamCreateWithFlags(&c->side[l], hipStreamNonBlocking) == hipSuccess &&
-             hipEventCreateWithFlags(&c->ev_join[l], hipEventDisableTiming) == hipSuccess;
+        ok = hipEventCreateWithFlags(&c->ev_join[l], hipEventDisableTiming) == hipSuccess;
       if (!ok) { free_chains(c); return RBP_E_DEVICE; }
     }
   }
