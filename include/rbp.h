@@ -33,6 +33,14 @@
  *     is used.
  *   - A batch is not re-entrant: do not run two calls on one batch
  *     concurrently on different streams.
+ *   - Grouped launches (batches of several degrees or row classes, path
+ *     batches of several lengths) run their groups on the caller's stream and
+ *     on three side streams of the device, made at the first batch built on
+ *     it and shared by every batch until the process ends; the side streams
+ *     are forked from the caller's stream and joined back into it with
+ *     events, so every call stays ordered on the caller's stream (and can be
+ *     captured in a graph there).  Calls on different caller streams share
+ *     the side streams and may wait for each other.
  *   - Return value: RBP_OK (0) or a negative RBP_E_* code; nothing throws
  *     across this interface.  Per-instance outcomes are reported in
  *     status_out (RBP_SOLVED ... RBP_INVALID_INPUT).
@@ -282,10 +290,9 @@ int rbp_chains_get_sizes(const rbp_chains* chains, rbp_batch_sizes* out);
  * twice: every path first with a small working set, then the few whose
  * working set outgrew it at the full size, continuing from the working set
  * the first launch held (their outputs are rewritten; until then status_out
- * may hold an internal value).  The groups run on the caller's stream and
- * three streams of the batch, forked from `stream` and joined back into it,
- * so all work is ordered after what `stream` holds and before what it gets
- * next (graph capture on `stream` takes all of it).
+ * may hold an internal value).  The groups run on `stream` and the device's
+ * side streams (see the conventions at the top), ordered after what `stream`
+ * holds and before what it gets next.
  *   x0 [N][6], goal [N][3]; opts as for rbp_solve_batch (plain and
  *   store_for_backward are ignored);
  *   P_out [3 points_total]: the control points of every segment (NaN unless
