@@ -39,7 +39,8 @@ namespace {
 constexpr int kWave = 64;
 constexpr int kSolved = 0, kInfeasible = 1, kPolishFailed = 3, kNumerical = 4, kInvalid = 5;
 // internal: the working set outgrew a reduced-cap pass; the full-cap pass
-// that follows solves the path again and overwrites every output
+// that follows continues the path from the working set it stored and
+// overwrites every output
 constexpr int kRetry = 6;
 constexpr float kBigF = 1e30f;
 typedef float floatx16 __attribute__((ext_vector_type(16)));
