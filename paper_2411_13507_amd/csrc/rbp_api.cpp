@@ -465,7 +465,7 @@ int rbp_backward(rbp_batch* b, const double* grad_P, const double* grad_cost, do
   a.st_stride = b->nmax;
   a.debug_fill = b->fw_debug_fill;
   if (b->fw_schedule == 1) {
-    a.dims = rbp::make_dims(b->pmax, b->rmax, b->nfmax, 8, false);
+    a.dims = rbp::make_back_dims(b->pmax, b->nfmax);
     a.inst_base = 0;
     if (rbp::launch_backward_all(a, b->N, stream) != hipSuccess) return RBP_E_DEVICE;
     b->last_stream = stream;
@@ -476,7 +476,7 @@ int rbp_backward(rbp_batch* b, const double* grad_P, const double* grad_cost, do
   hipError_t e = hipSuccess;
   for (size_t k = 0; k < b->groups.size() && e == hipSuccess; ++k) {
     const rbp_batch::Group& g = b->groups[k];
-    a.dims = rbp::make_dims(g.p, g.rmax, g.nfmax, 8, false);
+    a.dims = rbp::make_back_dims(g.p, g.nfmax);
     a.inst_base = g.start;
     a.N = g.start + g.count;
     e = rbp::launch_backward(a, g.count, lane_stream(b, k, stream), g.p);

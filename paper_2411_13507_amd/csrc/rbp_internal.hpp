@@ -269,6 +269,8 @@ hipError_t launch_mpc(const MpcArgs& a, hipStream_t s);
 
 // admm = false: no room for the ADMM iteration (polish only)
 LdsDims make_dims(int pmax, int r_cap, int nf_cap, int real_bytes, bool admm);
+// LDS of the backward pass alone (its own, smaller carve: more waves resident)
+LdsDims make_back_dims(int pmax, int nf_cap);
 ChainDims make_chain_dims(int p, int s_cap, int nf_cap, int r_cap, int q_cap, bool admm);
 hipError_t upload_chain_constants(int device);
 hipError_t launch_chains(const ChainArgs& a, hipStream_t s);

@@ -78,6 +78,37 @@ LdsDims make_dims(int pmax, int r_cap, int nf_cap, int real_bytes, bool admm) {
   return d;
 }
 
+// The backward pass reads the faces, the factor of the final working set,
+// its ids, sides and multipliers, the coefficients of its reachable rows on
+// the pinned points (six per active row, packed by working-set slot in the
+// Hd region), the degree table L^-1 and a few vectors; everything else of the
+// forward carve aliases the start of the buffer and is never touched.
+LdsDims make_back_dims(int pmax, int nf_cap) {
+  LdsDims d{};
+  d.nmax = 3 * (pmax - 1);
+  d.ncol = 3 * (pmax + 1);
+  d.r_cap = 1;
+  d.nf_cap = nf_cap < 1 ? 1 : nf_cap;
+  d.m_cap = 1;
+  int o = 0;
+  auto take = [&](int bytes) { const int at = o; o += (bytes + 15) & ~15; return at; };
+  d.o_Hd = take(d.nmax * 6 * 8);
+  d.o_Af = take(d.nf_cap * 3 * 8);
+  d.o_ybuf = take(2 * d.ncol * 8);
+  d.o_vec = take(5 * d.nmax * 8);
+  d.o_scal = take(16 * 8);
+  d.o_lam = take(d.nmax * 8);
+  d.o_actid = take(d.nmax * 4);
+  d.o_actside = take(d.nmax * 4);
+  d.o_cst = take(kMaxFree * kMaxFree * 8);
+  d.o_Q1 = take(d.nmax * (d.nmax | 1) * 8);
+  d.o_R = take(d.nmax * (d.nmax | 1) * 8);
+  d.o_rowval = d.o_acte = d.o_Rd = d.o_Ri = 0;
+  d.o_region = d.o_Hf = d.o_Aff = d.o_vbuf = d.o_xb1 = d.o_xb2 = d.o_Kx = 0;
+  d.bytes = o;
+  return d;
+}
+
 hipError_t upload_constants(int device) {
   (void)device;
   DegConst host[kMaxDeg + 1];

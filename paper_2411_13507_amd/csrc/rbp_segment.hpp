@@ -1402,7 +1402,7 @@ __device__ void solve_instance(const SolveArgs& A, const InstDesc& idesc, char* 
 template <int P>
 __device__ void backward_instance(const BackArgs& A, const InstDesc& idesc, char* smem) {
   using I = Inst<P>;
-  constexpr int NFP = I::NFP, N = I::N, NC = I::NC, ND = I::ND, NS = I::NS, HDS = I::HDS;
+  constexpr int NFP = I::NFP, N = I::N, NC = I::NC, ND = I::ND, NS = I::NS;
   const int lane = threadIdx.x;
   const DegConst& K = c_deg[P];
   const LdsDims& D = A.dims;
@@ -1460,8 +1460,9 @@ __device__ void backward_instance(const BackArgs& A, const InstDesc& idesc, char
   // upstream gradient on the full control points -> qbuf (reused)
   if (lane < NC) L.qbuf[lane] = gpv;
   // the adjoint needs the active reachable rows only on the pinned points
-  // (their coefficients on P_0 and P_p): six entries per row; the row id of
-  // active row k comes from lane k's register
+  // (their coefficients on P_0 and P_p): six entries per row, packed by
+  // working-set slot (Hd[6 k + j]); the row id of active row k comes from
+  // lane k's register
   for (int base = 0; base < q * 6; base += 2 * kWave) {
     double v[2];
     int dst[2];
@@ -1474,7 +1475,7 @@ __device__ void backward_instance(const BackArgs& A, const InstDesc& idesc, char
       const int idk = __shfl(sid, k, kWave);
       const int id = live ? idk : -1;
       const bool take = id >= in.RB;
-      dst[u] = take ? (id - in.RB) * HDS + e : -1;
+      dst[u] = take ? 6 * k + j : -1;
       v[u] = take ? A.H[in.hb + (int64_t)(id - in.RB) * NC + e] : 0.0;
     }
 #pragma unroll
@@ -1536,7 +1537,9 @@ __device__ void backward_instance(const BackArgs& A, const InstDesc& idesc, char
     qw *= 2.0 * in.iT3;
     double cw = 0.0;
     for (int k = 0; k < q; ++k) {
-      const double a = double(L.actside[k]) * in.coef(L.actid[k], pt, c, L.Af, L.Hd);
+      const int idk = L.actid[k];
+      const double a = double(L.actside[k]) *
+                       (idk >= in.RB ? L.Hd[6 * k + (pt == 0 ? c : 3 + c)] : in.coef(idk, pt, c, L.Af, L.Hd));
       cw += a * (L.vD[k] + gf * L.lam[k]);   // omega_k
     }
     const double omE = L.qbuf[3 * pt + c] - qw - cw;
