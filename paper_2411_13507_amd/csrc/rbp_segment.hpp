@@ -1329,12 +1329,16 @@ __device__ void solve_instance(const SolveArgs& A, const InstDesc& idesc, char* 
   // point, then goal):  nu = -(2 (Q y~)_pinned + sum_k lam_k side_k a_k,pinned)
   double st = 0.0, sq = 0.0, sac = 0.0, spin = 0.0;
   const int ppt = lane < 3 ? 0 : P, pc = lane - 3 * (lane / 3);
+  // row k's id and signed multiplier from lane k's registers (no LDS round
+  // trip per row)
+  const int id_r = lane < q ? L.actid[lane] : 0;
+  const double ls_r = lane < q ? lam_own * double(L.actside[lane]) : 0.0;
   if (vl) {
     const int pt = vs + 1;
     sq = 2.0 * L.qbuf[3 + lane];
     for (int k = 0; k < q; ++k) {
-      const int idk = __builtin_amdgcn_readfirstlane(L.actid[k]);
-      const double ls = L.lam[k] * double(L.actside[k]);
+      const int idk = __builtin_amdgcn_readlane(id_r, k);
+      const double ls = wave::bcast(ls_r, k);
       sac += ls * in.coef(idk, pt, vc, L.Af, L.Hd);
       if (A.store) spin += ls * in.coef(idk, ppt, pc, L.Af, L.Hd);
     }
