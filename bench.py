@@ -249,43 +249,7 @@ def extra_workloads(reps=3, admm_iters=-1, edges=None, main_opts=None):
         # with the start velocity pinned (fwd + bwd with the headline options)
         out["edges50k_p7_shared_reach"] = _variant(gen.with_shared_reach(edges), main_opts, reps, stream)
         out["edges50k_p7_pinned_v0"] = _variant(gen.with_pinned_velocity(edges), main_opts, reps, stream)
-    b = gen.generate(2, 200_000)
-    gb = SegmentBatchGPU(b, device="cuda:0")
-    x0, goal = torch.as_tensor(b.x0, device=dev), torch.as_tensor(b.goal, device=dev)
-    res = gb.alloc_outputs()
-    from paper_2411_13507_amd import autotune
-    tuning = None
-    if admm_iters >= 0:
-        uo = _lib.default_opts()
-        uo.admm_iters = admm_iters
-    else:
-        uo = autotune.tune(b, sample=b.n, reps=2, use_cache=False)
-        tuning = autotune.tune.last
-    uo.store_for_backward = 0
-    # the tuned solve (every launch of its schedule) captured in one HIP graph
-    gb.solve(x0, goal, opts=uo, out=res)
-    torch.cuda.synchronize()
-    side = torch.cuda.Stream(device=dev)
-    side.wait_stream(stream)
-    with torch.cuda.stream(side):
-        gb.solve(x0, goal, opts=uo, out=res)
-    stream.wait_stream(side)
-    ugraph = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(ugraph):
-        gb.solve(x0, goal, opts=uo, out=res)
-    t = time_launches(ugraph.replay, reps, stream)
-    st = res.status.cpu().numpy()
-    kk = res.kkt.cpu().numpy()
-    ok = int(((st == 0) & (kk <= KKT_OK)).sum() + (st == 1).sum())
-    out["uneven200k_p3to9"] = {"fwd_ms": t * 1e3, "solves_per_s": ok / t, "instances": b.n, "launch": "hipgraph",
-                               "admm_iters": int(uo.admm_iters), "rho": round(float(uo.rho), 6),
-                               "schedule": int(uo.schedule), "launch_shape": int(uo.launch_shape),
-                               "status_counts": np.bincount(st, minlength=6).tolist(),
-                               "tuning_ms": None if tuning is None else {"admm/rho": tuning["ms"],
-                                                                         "launch": tuning["ms_launch"]}}
-    del ugraph
-    gb.close()
-    del b, gb, res
+    uneven_workload(out, reps, stream, admm_iters)
     # graph cut (Alg. 2 + Cut-QP): 50,000 edges x 200 box obstacles, codes and
     # per-edge collision counts (the cut graph)
     from paper_2411_13507_amd.api import CutGPU
@@ -346,6 +310,54 @@ def extra_workloads(reps=3, admm_iters=-1, edges=None, main_opts=None):
     chains_workload(out, reps, stream)
     mpc_workload(out, reps, stream)
     return out
+
+
+def uneven_workload(out, reps, stream, admm_iters=-1):
+    """The uneven batch: 200,000 segments of degree 3-9, 6-40 faces, 16-128
+    reachable rows, forward, with autotuned options (admm_iters < 0) captured
+    in one HIP graph."""
+    import torch
+    from paper_2411_13507_amd import _lib
+    from paper_2411_13507_amd.api import SegmentBatchGPU
+    from workloads import gen
+    dev = torch.device("cuda", 0)
+    b = gen.generate(2, 200_000)
+    gb = SegmentBatchGPU(b, device="cuda:0")
+    x0, goal = torch.as_tensor(b.x0, device=dev), torch.as_tensor(b.goal, device=dev)
+    res = gb.alloc_outputs()
+    from paper_2411_13507_amd import autotune
+    tuning = None
+    if admm_iters >= 0:
+        uo = _lib.default_opts()
+        uo.admm_iters = admm_iters
+    else:
+        uo = autotune.tune(b, sample=b.n, reps=2, use_cache=False)
+        tuning = autotune.tune.last
+    uo.store_for_backward = 0
+    # the tuned solve (every launch of its schedule) captured in one HIP graph
+    gb.solve(x0, goal, opts=uo, out=res)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream(device=dev)
+    side.wait_stream(stream)
+    with torch.cuda.stream(side):
+        gb.solve(x0, goal, opts=uo, out=res)
+    stream.wait_stream(side)
+    ugraph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(ugraph):
+        gb.solve(x0, goal, opts=uo, out=res)
+    t = time_launches(ugraph.replay, reps, stream)
+    st = res.status.cpu().numpy()
+    kk = res.kkt.cpu().numpy()
+    ok = int(((st == 0) & (kk <= KKT_OK)).sum() + (st == 1).sum())
+    out["uneven200k_p3to9"] = {"fwd_ms": t * 1e3, "solves_per_s": ok / t, "instances": b.n, "launch": "hipgraph",
+                               "admm_iters": int(uo.admm_iters), "rho": round(float(uo.rho), 6),
+                               "schedule": int(uo.schedule), "launch_shape": int(uo.launch_shape),
+                               "status_counts": np.bincount(st, minlength=6).tolist(),
+                               "tuning_ms": None if tuning is None else {"admm/rho": tuning["ms"],
+                                                                         "launch": tuning["ms_launch"]}}
+    del ugraph
+    gb.close()
+    del b, gb, res
 
 
 def chains_workload(out, reps, stream):
@@ -412,7 +424,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--workload", choices=["chains", "mpc"], default=None,
+    ap.add_argument("--workload", choices=["uneven", "chains", "mpc"], default=None,
                     help="only time this one workload of the extras and print its record (for profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device-to-device copy (HBM counter calibration) and exit")
@@ -431,8 +443,11 @@ def main():
         dev = torch.device("cuda", 0)
         torch.cuda.set_device(dev)
         rec = {}
-        fn = {"chains": chains_workload, "mpc": mpc_workload}[args.workload]
-        fn(rec, max(args.steps, 1), torch.cuda.current_stream(dev))
+        st = torch.cuda.current_stream(dev)
+        if args.workload == "uneven":
+            uneven_workload(rec, max(args.steps, 1), st, args.admm_iters)
+        else:
+            {"chains": chains_workload, "mpc": mpc_workload}[args.workload](rec, max(args.steps, 1), st)
         print(json.dumps(rec))
         return
     if args.gpus != 1:

@@ -31,6 +31,7 @@ struct rbp_batch {
   // another
   static constexpr int kLanes = 4;
   std::vector<int32_t> group_lane;
+  std::vector<int32_t> launch_order;   // groups by estimated cost, longest first
   hipStream_t side[kLanes - 1] = {};
   hipEvent_t ev_fork = nullptr;
   hipEvent_t ev_join[kLanes - 1] = {};
@@ -272,8 +273,9 @@ int rbp_build_batch(const rbp_problem_desc* d, hipStream_t stream, rbp_batch** o
       const int ra = rclass(a), rc2 = rclass(c);
       return ra != rc2 ? ra < rc2 : cost[a] > cost[c];
     });
-    // estimated work of a path: its polish steps and the cost of one both
-    // grow with its segment count
+    // estimated work of a group: its instances' cost, scaled by how few of
+    // its workgroups fit a CU (a group of large instances runs at low
+    // residency, so each instance takes longer)
     std::vector<int64_t> gcost;
     for (int k = 0; k < N; ++k) {
       const int i = order[k];
@@ -289,14 +291,23 @@ int rbp_build_batch(const rbp_problem_desc* d, hipStream_t stream, rbp_batch** o
       g.nfmax = std::max(g.nfmax, nf);
       gcost.back() += cost[i];
     }
+    for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+      const rbp_batch::Group& g = b->groups[gi];
+      const size_t bytes = size_t(rbp::make_dims(g.p, g.rmax, g.nfmax, 4, false).bytes);
+      const int64_t per_cu = std::max<int64_t>(1, std::min<int64_t>(8, int64_t(kLdsBytes / std::max<size_t>(bytes, 1))));
+      gcost[gi] = gcost[gi] * 8 / per_cu;
+    }
     b->degree_host = deg;
     // streams of the groups: longest processing time first onto the least
-    // loaded stream
+    // loaded stream, and launched in that order (each stream starts with its
+    // longest group)
     b->group_lane.assign(b->groups.size(), 0);
+    b->launch_order.resize(b->groups.size());
+    std::iota(b->launch_order.begin(), b->launch_order.end(), 0);
+    std::stable_sort(b->launch_order.begin(), b->launch_order.end(),
+                     [&](int x, int y) { return gcost[size_t(x)] > gcost[size_t(y)]; });
     if (b->groups.size() > 1) {
-      std::vector<int> byc(b->groups.size());
-      std::iota(byc.begin(), byc.end(), 0);
-      std::stable_sort(byc.begin(), byc.end(), [&](int x, int y) { return gcost[size_t(x)] > gcost[size_t(y)]; });
+      const std::vector<int32_t>& byc = b->launch_order;
       int64_t load[rbp_batch::kLanes] = {};
       for (int gi : byc) {
         int best = 0;
@@ -419,7 +430,8 @@ int rbp_solve_batch(rbp_batch* b, const double* x0, const double* goal, const do
     a.order = b->d_order;
     const bool fork = fork_lanes(b, stream);
     if (b->groups.size() > 1 && !fork) return RBP_E_DEVICE;
-    for (size_t k = 0; k < b->groups.size() && e == hipSuccess; ++k) {
+    for (size_t j = 0; j < b->groups.size() && e == hipSuccess; ++j) {
+      const size_t k = size_t(b->launch_order[j]);
       const rbp_batch::Group& g = b->groups[k];
       const hipStream_t gs = lane_stream(b, k, stream);
       a.dims = rbp::make_dims(g.p, g.rmax, g.nfmax, 4, o.admm_iters > 0);
@@ -474,7 +486,8 @@ int rbp_backward(rbp_batch* b, const double* grad_P, const double* grad_cost, do
   const bool fork = fork_lanes(b, stream);
   if (b->groups.size() > 1 && !fork) return RBP_E_DEVICE;
   hipError_t e = hipSuccess;
-  for (size_t k = 0; k < b->groups.size() && e == hipSuccess; ++k) {
+  for (size_t j = 0; j < b->groups.size() && e == hipSuccess; ++j) {
+    const size_t k = size_t(b->launch_order[j]);
     const rbp_batch::Group& g = b->groups[k];
     a.dims = rbp::make_back_dims(g.p, g.nfmax);
     a.inst_base = g.start;
